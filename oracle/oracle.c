@@ -1,0 +1,817 @@
+/*
+ * FP64 CPU oracle: the per-electron step of a PIC code with Monte-Carlo
+ * nonlinear Compton scattering (NCS) and bremsstrahlung, written step by step
+ * from Wan et al. (arXiv:1612.07592).
+ *
+ * TEST INFRASTRUCTURE ONLY: used by the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark; the product path never calls it.  It
+ * shares no code with the HIP library.
+ *
+ * Paper references used below:
+ *   Sec. II.A  - the quantum parameter eta and the NCS process (photon
+ *                emission handled "the same as EPOCH": optical depth plus
+ *                sampling from the quantum-synchrotron spectrum).
+ *   Sec. II.B  - Tsai cross-section, Eq. (1); collision probability Eq. (4);
+ *                the R1 < P_br test, the R2 energy draw, photon energy E*y and
+ *                photon direction v/|v|; dropping low-energy photons.
+ *   Sec. II.B (benchmark paragraph) - particle-only mode: field updater and
+ *                weighting switched off.
+ *   Sec. III   - laser and target set-up, absorbing boundaries, the
+ *                m_e c^2 photon cut.
+ * Where the paper is silent (pusher, shapes, recoil, RNG, interpolation) the
+ * readings are the ones listed in the design notes; each is marked READING.
+ *
+ * Every floating-point expression is written in a fixed left-to-right order
+ * and the file is compiled without FP contraction, so that an independent
+ * implementation of the same readings can reproduce it bit for bit (apart from
+ * libm rounding of log/exp/expm1/sin).
+ */
+#include "oracle.h"
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ---------------- Philox4x32-10 (Salmon et al., SC'11) ------------------ */
+/* Counter-based generator: 10 rounds of the Philox S-box on a 4x32-bit
+ * counter, with a 2x32-bit key bumped by the Weyl constants between rounds. */
+void or_philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+               uint32_t k0, uint32_t k1, uint32_t out[4]) {
+  const uint64_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  for (int r = 0; r < 10; ++r) {
+    uint64_t a = M0 * (uint64_t)c0;   /* multiplies the first counter word  */
+    uint64_t b = M1 * (uint64_t)c2;   /* multiplies the third counter word  */
+    uint32_t hi0 = (uint32_t)(a >> 32), lo0 = (uint32_t)a;
+    uint32_t hi1 = (uint32_t)(b >> 32), lo1 = (uint32_t)b;
+    uint32_t n0 = hi1 ^ c1 ^ k0;
+    uint32_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* u in (0,1) from one 32-bit word, exact in double. */
+static double u32(uint32_t r) { return ((double)r + 0.5) * 0x1p-32; }
+/* 52-bit uniform in (0,1) from two words, exact in double: needed because the
+ * per-step bremsstrahlung probability is far below 2^-32. */
+static double u52(uint32_t r0, uint32_t r1) {
+  uint64_t k = ((uint64_t)r0 << 20) | (uint64_t)(r1 >> 12);
+  return ((double)k + 0.5) * 0x1p-52;
+}
+
+/* ---------------------------- state --------------------------------------- */
+#define G 2 /* guard cells per side on active axes */
+
+struct or_sim {
+  or_config c;
+  /* tables (owned copies) */
+  int n_eta, n_xi, n_T, n_y;
+  double ln_eta0, dln_eta, idln_eta, ln_T0, dln_T, idln_T, k_cut, iny1;
+  double *h, *ln_xi, *ncs_cdf, *sigma, *br_cdf;
+  /* derived */
+  int dims, n[3], act[3], gg[3], sz[3];
+  double dx[3], idx[3], L[3], dt, invV, E_S, iES, K_N, K_BR, n_c;
+  double cm[3];      /* Mur coefficients */
+  double hd[3], cd[3];
+  int i_src;
+  int64_t ncell_tot, nfield;
+  uint32_t key0, key1;
+  /* fields: E (current), En (next), B; J in 2^-40 fixed point */
+  double *E[3], *En[3], *B[3];
+  int64_t* J[3];
+  double *ni;        /* ion density per cell */
+  double *srcA, *srcC, *srcS; /* transverse source profile (ny_s*nz_s) */
+  int nsrc_y, nsrc_z;
+  /* electrons (id order, never reordered) */
+  int64_t N;
+  double *x, *p, *tau, *w;
+  uint32_t* id;
+  uint8_t* alive;
+  /* photons */
+  int64_t pcap, pcount;
+  double *ph_x, *ph_k, *ph_e, *ph_w;
+  uint32_t *ph_step, *ph_parent, *ph_proc;
+  or_stats st;
+  uint64_t step;
+  int nthreads;
+};
+
+static int64_t fidx(const or_sim* s, int i, int j, int k) {
+  return (int64_t)(i + s->gg[0]) +
+         (int64_t)s->sz[0] * ((int64_t)(j + s->gg[1]) + (int64_t)s->sz[1] * (int64_t)(k + s->gg[2]));
+}
+
+/* ------------------------ table interpolation ----------------------------- */
+/* Inverse of one NCS cumulative row at uniform u; returns ln(xi).  Below the
+ * first grid point F/xi ~ xi^(-2/3), so the CDF ~ xi^(1/3) (READING). */
+static double ncs_inv_row(const or_sim* s, int row, double u) {
+  const double* C = s->ncs_cdf + (int64_t)row * s->n_xi;
+  if (u < C[0]) return s->ln_xi[0] + 3.0 * log(u / C[0]);
+  int lo = 0, hi = s->n_xi - 1;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) / 2;
+    if (C[mid] <= u) lo = mid; else hi = mid;
+  }
+  double t = (u - C[lo]) / (C[lo + 1] - C[lo]);
+  return s->ln_xi[lo] + t * (s->ln_xi[lo + 1] - s->ln_xi[lo]);
+}
+
+/* Inverse of one bremsstrahlung cumulative row; returns the scaled coordinate
+ * in [0,1] between ln k_cut and ln T (READING of the R2 draw, Sec. II.B). */
+static double br_inv_row(const or_sim* s, int row, double u) {
+  const double* S = s->br_cdf + (int64_t)row * s->n_y;
+  int lo = 0, hi = s->n_y - 1;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) / 2;
+    if (S[mid] <= u) lo = mid; else hi = mid;
+  }
+  double t = (u - S[lo]) / (S[lo + 1] - S[lo]);
+  return ((double)lo + t) * s->iny1;
+}
+
+/* ----------------------------- set-up ------------------------------------- */
+static double* dalloc(int64_t n) { return (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double)); }
+
+or_sim* or_create(const or_config* c, const or_tables* t, int nthreads) {
+  or_sim* s = (or_sim*)calloc(1, sizeof(or_sim));
+  s->c = *c;
+  s->nthreads = nthreads > 0 ? nthreads : 1;
+  s->dims = c->dims;
+  const double twopi = 2.0 * M_PI;
+  for (int a = 0; a < 3; ++a) {
+    s->act[a] = a < c->dims;
+    s->n[a] = s->act[a] ? c->n[a] : 1;
+    s->gg[a] = s->act[a] ? G : 0;
+    s->sz[a] = s->act[a] ? s->n[a] + 1 + 2 * G : 1;
+    s->dx[a] = s->act[a] ? c->dx_lambda[a] * twopi : 1.0;
+    s->idx[a] = 1.0 / s->dx[a];
+    s->L[a] = (double)s->n[a] * s->dx[a];
+  }
+  double q = 0.0;
+  for (int a = 0; a < c->dims; ++a) q = q + 1.0 / (s->dx[a] * s->dx[a]);
+  s->dt = c->cfl / sqrt(q);
+  double V = 1.0;
+  for (int a = 0; a < c->dims; ++a) V = V * s->dx[a];
+  s->invV = 1.0 / V;
+  for (int a = 0; a < 3; ++a) {
+    s->hd[a] = (0.5 * s->dt) / s->dx[a];
+    s->cd[a] = s->dt / s->dx[a];
+    s->cm[a] = (s->dt - s->dx[a]) / (s->dt + s->dx[a]);
+  }
+  /* physical constants (CODATA 2018) */
+  const double alpha = 7.2973525693e-3, re = 2.8179403262e-15, lC = 3.8615926796e-13;
+  const double eps0 = 8.8541878128e-12, me = 9.1093837015e-31, qe = 1.602176634e-19, cl = 299792458.0;
+  double lam = c->lambda_m;
+  double w0 = twopi * cl / lam;
+  s->n_c = eps0 * me * w0 * w0 / (qe * qe);
+  s->E_S = lam / (twopi * lC);                    /* m c^2 / (hbar w0) */
+  s->iES = 1.0 / s->E_S;
+  s->K_N = sqrt(3.0) / twopi * alpha * s->E_S;    /* NCS rate prefactor, per 1/w0 */
+  s->K_BR = s->n_c * (lam / twopi) * alpha * re * re; /* n[n_c] sigma[alpha re^2] v dt[1/w0] */
+  s->key0 = (uint32_t)c->seed;
+  s->key1 = (uint32_t)(c->seed >> 32) ^ (uint32_t)c->job_id;
+
+  /* tables */
+  s->n_eta = t->n_eta; s->n_xi = t->n_xi; s->n_T = t->n_T; s->n_y = t->n_y;
+  s->ln_eta0 = t->ln_eta0; s->dln_eta = t->dln_eta; s->idln_eta = 1.0 / t->dln_eta;
+  s->ln_T0 = t->ln_T0; s->dln_T = t->dln_T; s->idln_T = 1.0 / t->dln_T;
+  s->k_cut = t->k_cut; s->iny1 = 1.0 / (double)(t->n_y - 1);
+  s->h = dalloc(s->n_eta); memcpy(s->h, t->h, sizeof(double) * s->n_eta);
+  s->ln_xi = dalloc(s->n_xi); memcpy(s->ln_xi, t->ln_xi, sizeof(double) * s->n_xi);
+  s->ncs_cdf = dalloc((int64_t)s->n_eta * s->n_xi);
+  memcpy(s->ncs_cdf, t->ncs_cdf, sizeof(double) * (size_t)s->n_eta * s->n_xi);
+  s->sigma = dalloc(s->n_T); memcpy(s->sigma, t->sigma, sizeof(double) * s->n_T);
+  s->br_cdf = dalloc((int64_t)s->n_T * s->n_y);
+  memcpy(s->br_cdf, t->br_cdf, sizeof(double) * (size_t)s->n_T * s->n_y);
+
+  /* fields */
+  s->nfield = (int64_t)s->sz[0] * s->sz[1] * s->sz[2];
+  for (int a = 0; a < 3; ++a) {
+    s->E[a] = dalloc(s->nfield); s->En[a] = dalloc(s->nfield);
+    s->B[a] = dalloc(s->nfield);
+    s->J[a] = (int64_t*)calloc((size_t)s->nfield, sizeof(int64_t));
+  }
+  /* ions: static, n_i = n_e / q in the slab cells (Sec. III, fully or
+   * partially ionised target; READING: charge enters only through n_i) */
+  s->ncell_tot = (int64_t)s->n[0] * s->n[1] * s->n[2];
+  s->ni = dalloc(s->ncell_tot);
+  int i0 = (int)llround(c->x0_lambda / c->dx_lambda[0]);
+  int i1 = i0 + (int)llround(c->thickness_lambda / c->dx_lambda[0]);
+  if (i0 < 0) i0 = 0;
+  if (i1 > s->n[0]) i1 = s->n[0];
+  if (i1 < i0) i1 = i0;
+  double nion = c->ne_over_nc / (double)c->charge_state;
+  for (int k = 0; k < s->n[2]; ++k)
+    for (int j = 0; j < s->n[1]; ++j)
+      for (int i = i0; i < i1; ++i)
+        s->ni[i + (int64_t)s->n[0] * (j + (int64_t)s->n[1] * k)] = nion;
+
+  /* laser source plane: a current sheet at x = i_src*dx radiating a0 (READING) */
+  s->i_src = 4;
+  s->nsrc_y = s->act[1] ? s->n[1] : 1;
+  s->nsrc_z = s->act[2] ? s->n[2] + 1 : 1;
+  int64_t ns = (int64_t)s->nsrc_y * s->nsrc_z;
+  s->srcA = dalloc(ns); s->srcC = dalloc(ns); s->srcS = dalloc(ns);
+  {
+    double w0n = c->w0_lambda * twopi;
+    double xs = (double)s->i_src * s->dx[0];
+    double xf = c->focus_x_lambda * twopi;
+    double zz = xs - xf;
+    double zR = 0.5 * w0n * w0n;
+    double wz = w0n * sqrt(1.0 + (zz / zR) * (zz / zR));
+    double Rinv = zz / (zz * zz + zR * zR);
+    double psi = atan(zz / zR);
+    for (int k = 0; k < s->nsrc_z; ++k)
+      for (int j = 0; j < s->nsrc_y; ++j) {
+        int64_t m = j + (int64_t)s->nsrc_y * k;
+        if (c->dims == 1 || !(c->w0_lambda > 0.0)) {
+          s->srcA[m] = 1.0; s->srcC[m] = 1.0; s->srcS[m] = 0.0;
+          continue;
+        }
+        double yr = ((double)j + 0.5) * s->dx[1] - 0.5 * s->L[1];
+        double r2 = yr * yr;
+        double A, ph;
+        if (c->dims == 3) {
+          double zr = (double)k * s->dx[2] - 0.5 * s->L[2];
+          r2 = r2 + zr * zr;
+          A = (w0n / wz) * exp(-r2 / (wz * wz));
+          ph = 0.5 * r2 * Rinv - psi;
+        } else {
+          A = sqrt(w0n / wz) * exp(-r2 / (wz * wz));
+          ph = 0.5 * r2 * Rinv - 0.5 * psi;
+        }
+        s->srcA[m] = A; s->srcC[m] = cos(ph); s->srcS[m] = -sin(ph);
+      }
+  }
+
+  /* electrons: ppc per slab cell, uniform-random in-cell, cold, tau0 = -ln u */
+  int nslab = i1 - i0;
+  s->N = (int64_t)nslab * s->n[1] * s->n[2] * c->ppc;
+  s->x = dalloc(3 * s->N); s->p = dalloc(3 * s->N);
+  s->tau = dalloc(s->N); s->w = dalloc(s->N);
+  s->id = (uint32_t*)calloc((size_t)(s->N > 0 ? s->N : 1), 4);
+  s->alive = (uint8_t*)calloc((size_t)(s->N > 0 ? s->N : 1), 1);
+  double wgt = c->ne_over_nc * V / (double)c->ppc;
+  for (int k = 0; k < s->n[2]; ++k)
+    for (int j = 0; j < s->n[1]; ++j)
+      for (int i = i0; i < i1; ++i) {
+        int64_t rank = ((int64_t)k * s->n[1] + j) * nslab + (i - i0);
+        for (int m = 0; m < c->ppc; ++m) {
+          int64_t e = rank * c->ppc + m;
+          uint32_t r[4];
+          or_philox((uint32_t)e, 0xFFFFFFFFu, 0u, 0u, s->key0, s->key1, r);
+          s->x[3 * e + 0] = ((double)i + u32(r[0])) * s->dx[0];
+          s->x[3 * e + 1] = s->act[1] ? ((double)j + u32(r[1])) * s->dx[1] : 0.0;
+          s->x[3 * e + 2] = s->act[2] ? ((double)k + u32(r[2])) * s->dx[2] : 0.0;
+          s->tau[e] = -log(u32(r[3]));
+          s->w[e] = wgt;
+          s->id[e] = (uint32_t)e;
+          s->alive[e] = 1;
+        }
+      }
+  s->st.live = (uint64_t)s->N;
+
+  s->pcap = (int64_t)c->photon_capacity;
+  s->ph_x = dalloc(3 * s->pcap); s->ph_k = dalloc(3 * s->pcap);
+  s->ph_e = dalloc(s->pcap); s->ph_w = dalloc(s->pcap);
+  s->ph_step = (uint32_t*)calloc((size_t)(s->pcap > 0 ? s->pcap : 1), 4);
+  s->ph_parent = (uint32_t*)calloc((size_t)(s->pcap > 0 ? s->pcap : 1), 4);
+  s->ph_proc = (uint32_t*)calloc((size_t)(s->pcap > 0 ? s->pcap : 1), 4);
+  return s;
+}
+
+void or_destroy(or_sim* s) {
+  if (!s) return;
+  for (int a = 0; a < 3; ++a) { free(s->E[a]); free(s->En[a]); free(s->B[a]); free(s->J[a]); }
+  free(s->ni); free(s->srcA); free(s->srcC); free(s->srcS);
+  free(s->h); free(s->ln_xi); free(s->ncs_cdf); free(s->sigma); free(s->br_cdf);
+  free(s->x); free(s->p); free(s->tau); free(s->w); free(s->id); free(s->alive);
+  free(s->ph_x); free(s->ph_k); free(s->ph_e); free(s->ph_w);
+  free(s->ph_step); free(s->ph_parent); free(s->ph_proc);
+  free(s);
+}
+
+/* ----------------------------- fields ------------------------------------- */
+/* Yee staggering: E_a is half-integer along a; B_a is half-integer along the
+ * two other axes.  stag[c][a] = 1 when component c is half-integer along a. */
+static const int ESTAG[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+static const int BSTAG[3][3] = {{0, 1, 1}, {1, 0, 1}, {1, 1, 0}};
+
+/* B <- B - (dt/2) curl E  (half step, on every valid B node) */
+static void b_half(or_sim* s) {
+  double* Ex = s->E[0]; double* Ey = s->E[1]; double* Ez = s->E[2];
+  for (int c = 0; c < 3; ++c) {
+    int lim[3];
+    for (int a = 0; a < 3; ++a) lim[a] = s->act[a] ? (BSTAG[c][a] ? s->n[a] : s->n[a] + 1) : 1;
+    double* Bc = s->B[c];
+    for (int k = 0; k < lim[2]; ++k)
+      for (int j = 0; j < lim[1]; ++j)
+        for (int i = 0; i < lim[0]; ++i) {
+          int64_t m = fidx(s, i, j, k);
+          double b = Bc[m];
+          if (c == 0) {        /* dBx/dt = -dEz/dy + dEy/dz */
+            if (s->act[1]) b = b - s->hd[1] * (Ez[fidx(s, i, j + 1, k)] - Ez[m]);
+            if (s->act[2]) b = b + s->hd[2] * (Ey[fidx(s, i, j, k + 1)] - Ey[m]);
+          } else if (c == 1) { /* dBy/dt = -dEx/dz + dEz/dx */
+            if (s->act[2]) b = b - s->hd[2] * (Ex[fidx(s, i, j, k + 1)] - Ex[m]);
+            b = b + s->hd[0] * (Ez[fidx(s, i + 1, j, k)] - Ez[m]);
+          } else {             /* dBz/dt = -dEy/dx + dEx/dy */
+            b = b - s->hd[0] * (Ey[fidx(s, i + 1, j, k)] - Ey[m]);
+            if (s->act[1]) b = b + s->hd[1] * (Ex[fidx(s, i, j + 1, k)] - Ex[m]);
+          }
+          Bc[m] = b;
+        }
+  }
+}
+
+/* Laser source current added to J_y on the source plane: a sheet current
+ * -2a/dx radiates E_y = a on both sides. */
+static double src_val(const or_sim* s, int j, int k, double lsin, double lcos) {
+  int64_t m = j + (int64_t)s->nsrc_y * k;
+  double v = lsin * s->srcC[m] + lcos * s->srcS[m];
+  return (-2.0 / s->dx[0]) * (s->srcA[m] * v);
+}
+
+/* interior Ampere update of E_c at node (i,j,k) from E (old), B, J */
+static double e_interior(const or_sim* s, int c, int i, int j, int k, double lsin, double lcos) {
+  int64_t m = fidx(s, i, j, k);
+  const double* Bx = s->B[0]; const double* By = s->B[1]; const double* Bz = s->B[2];
+  double e = s->E[c][m];
+  double jj = (double)s->J[c][m] * 0x1p-40;
+  if (c == 0) {        /* dEx/dt = dBz/dy - dBy/dz - Jx */
+    if (s->act[1]) e = e + s->cd[1] * (Bz[m] - Bz[fidx(s, i, j - 1, k)]);
+    if (s->act[2]) e = e - s->cd[2] * (By[m] - By[fidx(s, i, j, k - 1)]);
+  } else if (c == 1) { /* dEy/dt = dBx/dz - dBz/dx - Jy */
+    if (s->act[2]) e = e + s->cd[2] * (Bx[m] - Bx[fidx(s, i, j, k - 1)]);
+    e = e - s->cd[0] * (Bz[m] - Bz[fidx(s, i - 1, j, k)]);
+    if (i == s->i_src) jj = jj + src_val(s, j, k, lsin, lcos);
+  } else {             /* dEz/dt = dBy/dx - dBx/dy - Jz */
+    e = e + s->cd[0] * (By[m] - By[fidx(s, i - 1, j, k)]);
+    if (s->act[1]) e = e - s->cd[1] * (Bx[m] - Bx[fidx(s, i, j - 1, k)]);
+  }
+  return e - s->dt * jj;
+}
+
+/* E^{n+1} into En: interior Yee update; first-order Mur on the faces for the
+ * tangential components; nodes on two boundary faces are held at zero
+ * (READING: the paper states absorbing boundaries, Sec. III). */
+static void e_full(or_sim* s, double lsin, double lcos) {
+  for (int c = 0; c < 3; ++c) {
+    double* Fn = s->En[c];
+    memset(Fn, 0, sizeof(double) * (size_t)s->nfield);
+    int lim[3];
+    for (int a = 0; a < 3; ++a) lim[a] = s->act[a] ? (ESTAG[c][a] ? s->n[a] : s->n[a] + 1) : 1;
+    /* interior */
+    for (int k = 0; k < lim[2]; ++k)
+      for (int j = 0; j < lim[1]; ++j)
+        for (int i = 0; i < lim[0]; ++i) {
+          int ijk[3] = {i, j, k}, nb = 0;
+          for (int a = 0; a < 3; ++a)
+            if (s->act[a] && !ESTAG[c][a] && (ijk[a] == 0 || ijk[a] == s->n[a])) ++nb;
+          if (nb == 0) Fn[fidx(s, i, j, k)] = e_interior(s, c, i, j, k, lsin, lcos);
+        }
+    /* faces (Mur), using the already computed interior neighbour */
+    for (int k = 0; k < lim[2]; ++k)
+      for (int j = 0; j < lim[1]; ++j)
+        for (int i = 0; i < lim[0]; ++i) {
+          int ijk[3] = {i, j, k}, nb = 0, ax = -1;
+          for (int a = 0; a < 3; ++a)
+            if (s->act[a] && !ESTAG[c][a] && (ijk[a] == 0 || ijk[a] == s->n[a])) { ++nb; ax = a; }
+          if (nb != 1) continue;
+          int in[3] = {i, j, k};
+          in[ax] += (ijk[ax] == 0) ? 1 : -1;
+          int64_t mb = fidx(s, i, j, k), mi = fidx(s, in[0], in[1], in[2]);
+          Fn[mb] = s->E[c][mi] + s->cm[ax] * (Fn[mi] - s->E[c][mb]);
+        }
+  }
+  for (int c = 0; c < 3; ++c) { double* t = s->E[c]; s->E[c] = s->En[c]; s->En[c] = t; }
+}
+
+/* linear (CIC) interpolation of one staggered component at grid coords g */
+static double gather1(const or_sim* s, const double* F, const int* st, const double* g) {
+  int i[3] = {0, 0, 0};
+  double f[3] = {0.0, 0.0, 0.0};
+  for (int a = 0; a < s->dims; ++a) {
+    double ga = g[a] - 0.5 * (double)st[a];
+    double fl = floor(ga);
+    i[a] = (int)fl;
+    f[a] = ga - fl;
+  }
+  if (s->dims == 1)
+    return (1.0 - f[0]) * F[fidx(s, i[0], 0, 0)] + f[0] * F[fidx(s, i[0] + 1, 0, 0)];
+  double v0 = (1.0 - f[0]) * F[fidx(s, i[0], i[1], i[2])] + f[0] * F[fidx(s, i[0] + 1, i[1], i[2])];
+  double v1 = (1.0 - f[0]) * F[fidx(s, i[0], i[1] + 1, i[2])] + f[0] * F[fidx(s, i[0] + 1, i[1] + 1, i[2])];
+  double a2 = (1.0 - f[1]) * v0 + f[1] * v1;
+  if (s->dims == 2) return a2;
+  double w0 = (1.0 - f[0]) * F[fidx(s, i[0], i[1], i[2] + 1)] + f[0] * F[fidx(s, i[0] + 1, i[1], i[2] + 1)];
+  double w1 = (1.0 - f[0]) * F[fidx(s, i[0], i[1] + 1, i[2] + 1)] + f[0] * F[fidx(s, i[0] + 1, i[1] + 1, i[2] + 1)];
+  double b2 = (1.0 - f[1]) * w0 + f[1] * w1;
+  return (1.0 - f[2]) * a2 + f[2] * b2;
+}
+
+/* ------------------------ per-electron step ------------------------------- */
+typedef struct {
+  double x1[3], v[3];
+  int nph;
+  double px[2][3], pk[2][3], pe[2];
+  int pproc[2], pkeep[2];
+  int clamped;
+} eres;
+
+/* Steps in the order of the method: RNG, gather, Boris push, eta, NCS
+ * (optical depth + inverse-CDF draw), bremsstrahlung (Eq. (4) test + R2 draw),
+ * recoil, move.  Deposit, append and sums happen afterwards in id order. */
+static void electron_one(or_sim* s, int64_t e, double tn, eres* out) {
+  const or_config* c = &s->c;
+  const uint32_t n = (uint32_t)s->step;
+  double* x = s->x + 3 * e;
+  double* p = s->p + 3 * e;
+  out->nph = 0; out->clamped = 0;
+  uint32_t r[4];
+  or_philox(s->id[e], n, 0u, 0u, s->key0, s->key1, r);
+
+  /* gather E^n, B^n at x^n (or prescribed fields in particle-only mode) */
+  double E[3] = {0, 0, 0}, B[3] = {0, 0, 0};
+  if (c->flags & OR_FROZEN) {
+    if (c->frozen_kind == OR_FROZEN_UNIFORM) {
+      for (int a = 0; a < 3; ++a) { E[a] = c->frozen_E[a]; B[a] = c->frozen_B[a]; }
+    } else {
+      double phi = tn - x[0];
+      if (phi > 0.0) { double v = c->frozen_a * sin(phi); E[1] = v; B[2] = v; }
+    }
+  } else {
+    double g[3];
+    for (int a = 0; a < 3; ++a) g[a] = x[a] * s->idx[a];
+    for (int a = 0; a < 3; ++a) {
+      E[a] = gather1(s, s->E[a], ESTAG[a], g);
+      B[a] = gather1(s, s->B[a], BSTAG[a], g);
+    }
+  }
+
+  /* relativistic Boris push, q = -1, m = 1 */
+  double hq = -0.5 * s->dt;
+  double umx = p[0] + hq * E[0], umy = p[1] + hq * E[1], umz = p[2] + hq * E[2];
+  double gm = sqrt(1.0 + (umx * umx + umy * umy + umz * umz));
+  double fq = hq / gm;
+  double tx = fq * B[0], ty = fq * B[1], tz = fq * B[2];
+  double sf = 2.0 / (1.0 + (tx * tx + ty * ty + tz * tz));
+  double sx = sf * tx, sy = sf * ty, sz = sf * tz;
+  double upx = umx + (umy * tz - umz * ty);
+  double upy = umy + (umz * tx - umx * tz);
+  double upz = umz + (umx * ty - umy * tx);
+  double uqx = umx + (upy * sz - upz * sy);
+  double uqy = umy + (upz * sx - upx * sz);
+  double uqz = umz + (upx * sy - upy * sx);
+  double px = uqx + hq * E[0], py = uqy + hq * E[1], pz = uqz + hq * E[2];
+  double gamma = sqrt(1.0 + (px * px + py * py + pz * pz));
+
+  /* quantum parameter: eta = |gamma E + p x B|_perp-invariant / E_S (Sec. II.A,
+   * READING of the printed form as the Lorentz invariant) */
+  double cx = gamma * E[0] + (py * B[2] - pz * B[1]);
+  double cy = gamma * E[1] + (pz * B[0] - px * B[2]);
+  double cz = gamma * E[2] + (px * B[1] - py * B[0]);
+  double pe = px * E[0] + py * E[1] + pz * E[2];
+  double q2 = (cx * cx + cy * cy + cz * cz) - pe * pe;
+  if (q2 < 0.0) q2 = 0.0;
+  double eta = sqrt(q2) * s->iES;
+
+  /* nonlinear Compton scattering: optical-depth decrement, one emission at
+   * most per step, photon fraction from the inverse cumulative spectrum */
+  if (c->flags & OR_NCS) {
+    double le = log(eta);
+    double sl = (le - s->ln_eta0) * s->idln_eta;
+    if (sl >= 0.0) {
+      int i; double f;
+      if (sl >= (double)(s->n_eta - 1)) { i = s->n_eta - 2; f = 1.0; }
+      else { i = (int)sl; f = sl - (double)i; }
+      double h = s->h[i] + f * (s->h[i + 1] - s->h[i]);
+      double dtau = s->K_N * eta / gamma * h * s->dt;
+      s->tau[e] = s->tau[e] - dtau;
+      if (s->tau[e] <= 0.0) {
+        double u2 = u32(r[2]);
+        double la = ncs_inv_row(s, i, u2);
+        double lb = ncs_inv_row(s, i + 1, u2);
+        double lx = la + f * (lb - la);
+        double xi = exp(lx);
+        double eps = xi * gamma;
+        if (eps > gamma - 1.0) eps = gamma - 1.0;
+        double pm = sqrt(px * px + py * py + pz * pz);
+        int k = out->nph++;
+        out->px[k][0] = x[0]; out->px[k][1] = x[1]; out->px[k][2] = x[2];
+        out->pk[k][0] = px / pm; out->pk[k][1] = py / pm; out->pk[k][2] = pz / pm;
+        out->pe[k] = eps; out->pproc[k] = 0;
+        out->pkeep[k] = eps >= c->photon_cut_mc2;
+        if (!(c->flags & OR_NO_RECOIL)) {
+          double gn = gamma - eps;
+          double pn = sqrt((gn - 1.0) * (gn + 1.0));
+          double sc = pn / pm;
+          px = px * sc; py = py * sc; pz = pz * sc; gamma = gn;
+        }
+        s->tau[e] = -log(u32(r[3]));
+      }
+    }
+  }
+
+  /* bremsstrahlung: Eq. (4) with n the ion density of the electron's cell,
+   * sigma(E) integrated from the cut, event iff R1 < P_br (Sec. II.B) */
+  if (c->flags & OR_BREM) {
+    double T = gamma - 1.0;
+    if (T >= s->k_cut) {
+      int ci[3] = {0, 0, 0};
+      for (int a = 0; a < s->dims; ++a) {
+        int q = (int)floor(x[a] * s->idx[a]);
+        if (q < 0) q = 0;
+        if (q > s->n[a] - 1) q = s->n[a] - 1;
+        ci[a] = q;
+      }
+      double ni = s->ni[ci[0] + (int64_t)s->n[0] * (ci[1] + (int64_t)s->n[1] * ci[2])];
+      if (ni > 0.0) {
+        double lt = log(T);
+        double sl = (lt - s->ln_T0) * s->idln_T;
+        if (sl >= 0.0) {
+          int i; double f;
+          if (sl >= (double)(s->n_T - 1)) { i = s->n_T - 2; f = 1.0; out->clamped = 1; }
+          else { i = (int)sl; f = sl - (double)i; }
+          double sig = s->sigma[i] + f * (s->sigma[i + 1] - s->sigma[i]);
+          if (sig > 0.0) {
+            double pm = sqrt(px * px + py * py + pz * pz);
+            double v = pm / gamma;
+            double X = s->K_BR * ni * sig * v * s->dt;
+            double P = -expm1(-X);
+            if (u52(r[0], r[1]) < P) {
+              uint32_t r2[4];
+              or_philox(s->id[e], n, 1u, 0u, s->key0, s->key1, r2);
+              double u = u32(r2[0]);
+              double sa = br_inv_row(s, i, u);
+              double sb = br_inv_row(s, i + 1, u);
+              double sv = sa + f * (sb - sa);
+              double lk = log(s->k_cut);
+              double eps = exp(lk + sv * (lt - lk));
+              if (eps > T) eps = T;
+              int k = out->nph++;
+              out->px[k][0] = x[0]; out->px[k][1] = x[1]; out->px[k][2] = x[2];
+              out->pk[k][0] = px / pm; out->pk[k][1] = py / pm; out->pk[k][2] = pz / pm;
+              out->pe[k] = eps; out->pproc[k] = 1; out->pkeep[k] = 1;
+              if (!(c->flags & OR_NO_RECOIL)) {
+                double gn = gamma - eps;
+                double pn = sqrt((gn - 1.0) * (gn + 1.0));
+                double sc = pn / pm;
+                px = px * sc; py = py * sc; pz = pz * sc; gamma = gn;
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+
+  p[0] = px; p[1] = py; p[2] = pz;
+  double ig = 1.0 / gamma;
+  out->v[0] = px * ig; out->v[1] = py * ig; out->v[2] = pz * ig;
+  for (int a = 0; a < 3; ++a)
+    out->x1[a] = s->act[a] ? x[a] + out->v[a] * s->dt : x[a];
+}
+
+/* node-based linear weights of a point on a 4-node window starting at base */
+static void shape4(double g, int base, double S[4]) {
+  double fl = floor(g);
+  int i = (int)fl;
+  double f = g - fl;
+  S[0] = S[1] = S[2] = S[3] = 0.0;
+  S[i - base] = 1.0 - f;
+  S[i - base + 1] = f;
+}
+
+/* Current accumulation in 2^-40 fixed point: every contribution is rounded to
+ * the nearest multiple of 2^-40 and summed as an integer, so the total does
+ * not depend on the order in which electrons are visited (READING: the paper
+ * leaves the weighting procedure unspecified). */
+static void jadd(int64_t* J, int64_t m, double v) { J[m] += (int64_t)llrint(v * 0x1p40); }
+
+/* charge-conserving current of one electron moving x0 -> x1 (Esirkepov form;
+ * in 1D the exact 1D continuity solution) */
+static void deposit(or_sim* s, const double* x0, const double* x1, const double* v, double w) {
+  double c0 = -w * s->invV;
+  double S0[3][4], S1[3][4];
+  int b[3] = {0, 0, 0};
+  for (int a = 0; a < s->dims; ++a) {
+    double g0 = x0[a] * s->idx[a], g1 = x1[a] * s->idx[a];
+    b[a] = (int)floor(g0) - 1;
+    shape4(g0, b[a], S0[a]);
+    shape4(g1, b[a], S1[a]);
+  }
+  int64_t* Jx = s->J[0]; int64_t* Jy = s->J[1]; int64_t* Jz = s->J[2];
+  if (s->dims == 1) {
+    double qx = c0 * (s->dx[0] / s->dt);
+    double acc = 0.0;
+    for (int i = 0; i < 3; ++i) {
+      acc = acc - qx * (S1[0][i] - S0[0][i]);
+      jadd(Jx, fidx(s, b[0] + i, 0, 0), acc);
+    }
+    double cy = c0 * v[1], cz = c0 * v[2];
+    for (int i = 0; i < 4; ++i) {
+      double sa = 0.5 * (S0[0][i] + S1[0][i]);
+      jadd(Jy, fidx(s, b[0] + i, 0, 0), cy * sa);
+      jadd(Jz, fidx(s, b[0] + i, 0, 0), cz * sa);
+    }
+    return;
+  }
+  if (s->dims == 2) {
+    double qx = c0 * (s->dx[0] / s->dt), qy = c0 * (s->dx[1] / s->dt), cz = c0 * v[2];
+    for (int j = 0; j < 4; ++j) {
+      double acc = 0.0;
+      for (int i = 0; i < 3; ++i) {
+        double W = 0.5 * (S1[0][i] - S0[0][i]) * (S0[1][j] + S1[1][j]);
+        acc = acc - qx * W;
+        jadd(Jx, fidx(s, b[0] + i, b[1] + j, 0), acc);
+      }
+    }
+    for (int i = 0; i < 4; ++i) {
+      double acc = 0.0;
+      for (int j = 0; j < 3; ++j) {
+        double W = 0.5 * (S0[0][i] + S1[0][i]) * (S1[1][j] - S0[1][j]);
+        acc = acc - qy * W;
+        jadd(Jy, fidx(s, b[0] + i, b[1] + j, 0), acc);
+      }
+    }
+    for (int j = 0; j < 4; ++j)
+      for (int i = 0; i < 4; ++i) {
+        double W = (S0[0][i] * S0[1][j] + S1[0][i] * S1[1][j]) * (1.0 / 3.0) +
+                   (S0[0][i] * S1[1][j] + S1[0][i] * S0[1][j]) * (1.0 / 6.0);
+        jadd(Jz, fidx(s, b[0] + i, b[1] + j, 0), cz * W);
+      }
+    return;
+  }
+  /* 3D */
+  double qx = c0 * (s->dx[0] / s->dt), qy = c0 * (s->dx[1] / s->dt), qz = c0 * (s->dx[2] / s->dt);
+  for (int k = 0; k < 4; ++k)
+    for (int j = 0; j < 4; ++j) {
+      double acc = 0.0;
+      for (int i = 0; i < 3; ++i) {
+        double T = (S0[1][j] * S0[2][k] + S1[1][j] * S1[2][k]) * (1.0 / 3.0) +
+                   (S1[1][j] * S0[2][k] + S0[1][j] * S1[2][k]) * (1.0 / 6.0);
+        acc = acc - qx * ((S1[0][i] - S0[0][i]) * T);
+        jadd(Jx, fidx(s, b[0] + i, b[1] + j, b[2] + k), acc);
+      }
+    }
+  for (int k = 0; k < 4; ++k)
+    for (int i = 0; i < 4; ++i) {
+      double acc = 0.0;
+      for (int j = 0; j < 3; ++j) {
+        double T = (S0[0][i] * S0[2][k] + S1[0][i] * S1[2][k]) * (1.0 / 3.0) +
+                   (S1[0][i] * S0[2][k] + S0[0][i] * S1[2][k]) * (1.0 / 6.0);
+        acc = acc - qy * ((S1[1][j] - S0[1][j]) * T);
+        jadd(Jy, fidx(s, b[0] + i, b[1] + j, b[2] + k), acc);
+      }
+    }
+  for (int j = 0; j < 4; ++j)
+    for (int i = 0; i < 4; ++i) {
+      double acc = 0.0;
+      for (int k = 0; k < 3; ++k) {
+        double T = (S0[0][i] * S0[1][j] + S1[0][i] * S1[1][j]) * (1.0 / 3.0) +
+                   (S1[0][i] * S0[1][j] + S0[0][i] * S1[1][j]) * (1.0 / 6.0);
+        acc = acc - qz * ((S1[2][k] - S0[2][k]) * T);
+        jadd(Jz, fidx(s, b[0] + i, b[1] + j, b[2] + k), acc);
+      }
+    }
+}
+
+static void laser_scalars(const or_sim* s, uint64_t step, double* lsin, double* lcos) {
+  double t = ((double)step + 0.5) * s->dt;
+  double TL = s->c.duration_cycles * (2.0 * M_PI);
+  double env = 0.0;
+  if (t >= 0.0 && t <= TL) { env = sin(M_PI * t / TL); env = env * env; }
+  *lsin = s->c.a0 * env * sin(t);
+  *lcos = s->c.a0 * env * cos(t);
+}
+
+void or_step(or_sim* s, int nsteps) {
+  eres* res = (eres*)malloc(sizeof(eres) * (size_t)(s->N > 0 ? s->N : 1));
+  const int frozen = (s->c.flags & OR_FROZEN) != 0;
+  for (int it = 0; it < nsteps; ++it) {
+    double tn = (double)s->step * s->dt;
+    if (!frozen) {
+      for (int a = 0; a < 3; ++a) memset(s->J[a], 0, sizeof(int64_t) * (size_t)s->nfield);
+      b_half(s);                                  /* B^{n-1/2} -> B^n */
+    }
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) num_threads(s->nthreads)
+#endif
+    for (int64_t e = 0; e < s->N; ++e)
+      if (s->alive[e]) electron_one(s, e, tn, &res[e]);
+    /* id-ordered pass: deposit, photon append, sums, absorbing walls */
+    uint64_t live = 0;
+    for (int64_t e = 0; e < s->N; ++e) {
+      if (!s->alive[e]) continue;
+      eres* r = &res[e];
+      if (!frozen) deposit(s, s->x + 3 * e, r->x1, r->v, s->w[e]);
+      for (int k = 0; k < r->nph; ++k) {
+        int pr = r->pproc[k];
+        double we = s->w[e] * r->pe[k];
+        s->st.events[pr]++;
+        if (!r->pkeep[k]) { s->st.dropped_ncs++; s->st.e_rad_dropped += we; continue; }
+        s->st.kept[pr]++;
+        s->st.e_rad_kept[pr] += we;
+        if (s->pcount < s->pcap) {
+          int64_t q = s->pcount;
+          for (int a = 0; a < 3; ++a) { s->ph_x[3 * q + a] = r->px[k][a]; s->ph_k[3 * q + a] = r->pk[k][a]; }
+          s->ph_e[q] = r->pe[k]; s->ph_w[q] = s->w[e];
+          s->ph_step[q] = (uint32_t)s->step; s->ph_parent[q] = s->id[e]; s->ph_proc[q] = (uint32_t)pr;
+        } else {
+          s->st.overflow++;
+        }
+        s->pcount++;
+      }
+      s->st.brem_clamped += (uint64_t)r->clamped;
+      int out = 0;
+      for (int a = 0; a < s->dims; ++a) {
+        s->x[3 * e + a] = r->x1[a];
+        if (r->x1[a] < 0.0 || r->x1[a] >= s->L[a]) out = 1;
+      }
+      if (out) s->alive[e] = 0; else ++live;
+    }
+    s->st.live = live;
+    if (!frozen) {
+      double ls, lc;
+      laser_scalars(s, s->step, &ls, &lc);
+      b_half(s);                                  /* B^n -> B^{n+1/2} */
+      e_full(s, ls, lc);                          /* E^n -> E^{n+1}   */
+    }
+    s->step++;
+    s->st.steps = s->step;
+  }
+  free(res);
+}
+
+/* ----------------------------- accessors ---------------------------------- */
+int64_t or_num_electrons(const or_sim* s) { return s->N; }
+int64_t or_num_photons(const or_sim* s) { return s->pcount; }
+
+void or_get_electrons(const or_sim* s, double* x, double* p, double* tau,
+                      double* w, uint32_t* id, uint8_t* alive) {
+  memcpy(x, s->x, sizeof(double) * 3 * (size_t)s->N);
+  memcpy(p, s->p, sizeof(double) * 3 * (size_t)s->N);
+  memcpy(tau, s->tau, sizeof(double) * (size_t)s->N);
+  memcpy(w, s->w, sizeof(double) * (size_t)s->N);
+  memcpy(id, s->id, sizeof(uint32_t) * (size_t)s->N);
+  memcpy(alive, s->alive, (size_t)s->N);
+}
+
+void or_set_electrons(or_sim* s, const double* x, const double* p, const double* tau) {
+  memcpy(s->x, x, sizeof(double) * 3 * (size_t)s->N);
+  memcpy(s->p, p, sizeof(double) * 3 * (size_t)s->N);
+  memcpy(s->tau, tau, sizeof(double) * (size_t)s->N);
+}
+
+void or_get_photons(const or_sim* s, double* x, double* k, double* eps, double* w,
+                    uint32_t* step, uint32_t* parent, uint32_t* proc) {
+  int64_t n = s->pcount < s->pcap ? s->pcount : s->pcap;
+  memcpy(x, s->ph_x, sizeof(double) * 3 * (size_t)n);
+  memcpy(k, s->ph_k, sizeof(double) * 3 * (size_t)n);
+  memcpy(eps, s->ph_e, sizeof(double) * (size_t)n);
+  memcpy(w, s->ph_w, sizeof(double) * (size_t)n);
+  memcpy(step, s->ph_step, 4 * (size_t)n);
+  memcpy(parent, s->ph_parent, 4 * (size_t)n);
+  memcpy(proc, s->ph_proc, 4 * (size_t)n);
+}
+
+void or_get_stats(const or_sim* s, or_stats* out) { *out = s->st; }
+
+double or_kinetic_energy(const or_sim* s) {
+  double sum = 0.0;
+  for (int64_t e = 0; e < s->N; ++e) {
+    if (!s->alive[e]) continue;
+    const double* p = s->p + 3 * e;
+    double g = sqrt(1.0 + (p[0] * p[0] + p[1] * p[1] + p[2] * p[2]));
+    sum += s->w[e] * (g - 1.0);
+  }
+  return sum;
+}
+
+double or_field_energy(const or_sim* s) {
+  double sum = 0.0;
+  for (int c = 0; c < 3; ++c)
+    for (int64_t m = 0; m < s->nfield; ++m)
+      sum += s->E[c][m] * s->E[c][m] + s->B[c][m] * s->B[c][m];
+  double V = 1.0 / s->invV;
+  return 0.5 * sum * V;
+}
+
+int64_t or_field_size(const or_sim* s) { return s->nfield; }
+
+void or_get_fields(const or_sim* s, double* out) {
+  for (int c = 0; c < 3; ++c) memcpy(out + (int64_t)c * s->nfield, s->E[c], sizeof(double) * (size_t)s->nfield);
+  for (int c = 0; c < 3; ++c) memcpy(out + (int64_t)(3 + c) * s->nfield, s->B[c], sizeof(double) * (size_t)s->nfield);
+}
+
+void or_get_current(const or_sim* s, int64_t* out) {
+  for (int c = 0; c < 3; ++c) memcpy(out + (int64_t)c * s->nfield, s->J[c], sizeof(int64_t) * (size_t)s->nfield);
+}
+
+void or_get_derived(const or_sim* s, double* o) {
+  o[0] = s->dx[0]; o[1] = s->dx[1]; o[2] = s->dx[2]; o[3] = s->dt;
+  o[4] = s->E_S; o[5] = s->K_N; o[6] = s->K_BR; o[7] = s->n_c;
+}

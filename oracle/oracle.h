@@ -1,0 +1,75 @@
+/*
+ * FP64 CPU oracle for the per-electron PIC step with Monte-Carlo photon
+ * emission (Wan et al., "Photon emission by bremsstrahlung and nonlinear
+ * Compton scattering in the interaction of ultraintense laser and plasmas").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the package smoke check and
+ * the CPU-baseline leg of the benchmark may build, load or call this code.
+ * It shares no code, header or helper with the HIP library; the two agree only
+ * through the written method (the paper's equations plus the readings listed
+ * in the design notes) and through the caller-supplied tables and configs.
+ *
+ * Units are normalised to the laser: length c/w0, time 1/w0, momentum mc,
+ * energy mc^2, field m c w0 / e, density n_c.  Charge of the electron is -1.
+ */
+#ifndef PIC_ORACLE_H
+#define PIC_ORACLE_H
+#include <stdint.h>
+
+enum { OR_NCS = 1, OR_BREM = 2, OR_FROZEN = 4, OR_NO_RECOIL = 16 };
+enum { OR_FROZEN_UNIFORM = 0, OR_FROZEN_PLANE_WAVE = 1 };
+
+typedef struct {
+  int32_t dims, flags, frozen_kind, ppc;
+  int32_t n[3];
+  int32_t Z, charge_state;
+  double dx_lambda[3];
+  double cfl, lambda_m;
+  double a0, w0_lambda, duration_cycles, focus_x_lambda;
+  double ne_over_nc, x0_lambda, thickness_lambda;
+  double photon_cut_mc2;
+  double frozen_E[3], frozen_B[3], frozen_a;
+  uint64_t seed, job_id, photon_capacity;
+} or_config;
+
+typedef struct {
+  int32_t n_eta, n_xi;
+  double ln_eta0, dln_eta;
+  const double *h, *ln_xi, *ncs_cdf;   /* n_eta, n_xi, n_eta*n_xi */
+  int32_t n_T, n_y;
+  double ln_T0, dln_T, k_cut;
+  const double *sigma, *br_cdf;        /* n_T, n_T*n_y */
+} or_tables;
+
+typedef struct {
+  uint64_t steps, live, events[2], kept[2], dropped_ncs, overflow, brem_clamped;
+  double e_rad_kept[2], e_rad_dropped;
+} or_stats;
+
+typedef struct or_sim or_sim;
+
+or_sim*  or_create(const or_config* c, const or_tables* t, int nthreads);
+void     or_destroy(or_sim* s);
+void     or_step(or_sim* s, int nsteps);
+int64_t  or_num_electrons(const or_sim* s);
+int64_t  or_num_photons(const or_sim* s);          /* may exceed capacity */
+void     or_get_electrons(const or_sim* s, double* x, double* p, double* tau,
+                          double* w, uint32_t* id, uint8_t* alive);
+void     or_set_electrons(or_sim* s, const double* x, const double* p,
+                          const double* tau);
+void     or_get_photons(const or_sim* s, double* x, double* k, double* eps,
+                        double* w, uint32_t* step, uint32_t* parent,
+                        uint32_t* proc);
+void     or_get_stats(const or_sim* s, or_stats* out);
+double   or_kinetic_energy(const or_sim* s);
+double   or_field_energy(const or_sim* s);
+/* full field arrays incl. guard cells, component order Ex,Ey,Ez,Bx,By,Bz */
+int64_t  or_field_size(const or_sim* s);
+void     or_get_fields(const or_sim* s, double* out);
+/* J^{n+1/2} of the last step in 2^-40 fixed point, 3*size values */
+void     or_get_current(const or_sim* s, int64_t* out);
+void     or_get_derived(const or_sim* s, double* out8);  /* dx[3], dt, E_S, K_N, K_BR, n_c */
+void     or_philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                   uint32_t k0, uint32_t k1, uint32_t out[4]);
+
+#endif
