@@ -1,0 +1,178 @@
+#!/usr/bin/env python3
+"""Throughput of the per-electron PIC step with MC photon emission on one
+MI355X, in electron-steps/s.
+
+Default workload: the 2D3V gold-slab configuration (2048x1024 cells at
+lambda/64, Au q=69 slab 2 um thick at n_e = 200 n_c, 16 electrons/cell =
+2,097,152 electrons, a0 = 270 Gaussian w0 = 3 um, 2000 steps), FP32 bulk with
+FP64 optical depth, weights and energy sums; the same run in FP64 is timed
+beside it.  A "step" is one full step of every electron (gather, push, eta,
+NCS, bremsstrahlung, recoil, append, move + deposit) plus the field solve.
+
+    python bench.py [--gpus 1] [--steps 2000] [--warmup 20]
+
+Prints one JSON line.  The timed region starts from a freshly created
+context (all state already resident in HBM) and covers exactly --steps
+steps, bracketed by torch.cuda.synchronize().
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per electron-step of the step kernel: the electron state
+# read once (positions, momenta, tau, weight, id) and written once (positions,
+# momenta, tau); fields and tables are amortised over the electrons of a cell
+STATE_BYTES = {("fp32", 1): 60, ("fp32", 2): 68, ("fp32", 3): 76,
+               ("fp64", 1): 92, ("fp64", 2): 108, ("fp64", 3): 124}
+
+
+def _workload(name, precision, steps):
+    from paper_1612_07592_amd import workloads as W
+    if name == "c2":
+        w = W.c2(steps=steps, precision=precision)
+    elif name == "c1":
+        w = W.c1(steps)
+        w["precision"] = precision
+    elif name == "c5":
+        w = W.c5(steps)
+        w["precision"] = precision
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return w
+
+
+def _num_electrons(w):
+    from paper_1612_07592_amd import workloads as W
+    return W.num_electrons(w)
+
+
+def run_gpu(w, tables, steps, warmup, torch):
+    from paper_1612_07592_amd import binding
+    if warmup > 0:
+        s = binding.Sim(w, tables)
+        s.pic_step(warmup)
+        s.pic_emission_stats()
+        s.pic_destroy()
+    s = binding.Sim(w, tables)
+    s.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.pic_step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = s.pic_emission_stats()
+    ms, n = s.profile_read()
+    s.pic_destroy()
+    return dict(wall_s=t1 - t0, stats=st, step_kernel_ms=float(ms[0]), field_ms=float(ms[1]),
+                step_launches=int(n[0]))
+
+
+def cpu_baseline(w, budget_s=15.0):
+    """The FP64 oracle, as is, on the host cores: a bounded number of steps of
+    the same workload from t = 0."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import conftest
+    import oracle
+    oracle.build(force=False)
+    tables = conftest.oracle_tables(int(w["Z"]))
+    ww = dict(w)
+    ww["precision"] = "fp64"
+    ww["photon_capacity"] = 1 << 22
+    nt = min(16, os.cpu_count() or 1)
+    o = oracle.OracleSim(ww, tables, nthreads=nt)
+    t0 = time.perf_counter()
+    o.step(1)
+    one = time.perf_counter() - t0
+    k = max(1, min(200, int(budget_s / max(one, 1e-6))))
+    t0 = time.perf_counter()
+    o.step(k)
+    dt = time.perf_counter() - t0
+    live = o.stats()["live"]
+    o.close()
+    return dict(value=live * k / dt, unit="electron-steps/s", cores=nt, kind="oracle",
+                sample=f"FP64 oracle, steps 1..{k + 1} of the same workload from t=0 "
+                       f"({live} electrons, {dt:.1f} s on {nt} threads)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a "
+                                   "design note, not implemented", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "no GPU visible"
+    from paper_1612_07592_amd import binding
+    binding.load()
+    w = _workload(args.workload, args.precision, args.steps)
+    t0 = time.perf_counter()
+    tables = binding.pic_build_tables(int(w["Z"]), 1.0, 16)
+    t_tables = time.perf_counter() - t0
+    print(f"[bench] tables built in {t_tables:.1f} s; {args.workload} {args.precision} "
+          f"{args.steps} steps", file=sys.stderr, flush=True)
+    r = run_gpu(w, tables, args.steps, args.warmup, torch)
+    st = r["stats"]
+    esteps = int(st["electron_steps"])
+    value = esteps / r["wall_s"]
+    dims = int(w["dims"])
+    bpe = STATE_BYTES[(args.precision, dims)]
+    achieved = bpe * esteps / (r["step_kernel_ms"] * 1e-3) / 1e9
+    out = {
+        "metric": "electron-steps/s",
+        "value": value,
+        "unit": "electron-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["wall_s"] * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": w["name"], "dims": dims, "cells": list(w["n"]),
+                   "electrons": _num_electrons(w),
+                   "precision": args.precision, "a0": w["a0"], "Z": w["Z"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": f"k_electron_step<{'float' if args.precision == 'fp32' else 'double'},{dims}>",
+                     "bytes_per_electron_step": bpe,
+                     "kernel_avg_us": r["step_kernel_ms"] * 1e3 / max(1, r["step_launches"])},
+        "step_kernel_share": r["step_kernel_ms"] / (r["wall_s"] * 1e3),
+        "emission": {"events": st["events"], "kept": st["kept"], "dropped_ncs": st["dropped_ncs"],
+                     "overflow": st["overflow"], "e_rad_kept": st["e_rad_kept"]},
+    }
+    print(f"[bench] {args.precision}: {value:.3e} e-steps/s, step kernel "
+          f"{out['roofline']['kernel_avg_us']:.1f} us, {achieved:.0f} GB/s", file=sys.stderr, flush=True)
+    if not args.no_fp64 and args.precision == "fp32":
+        w64 = _workload(args.workload, "fp64", args.steps)
+        r64 = run_gpu(w64, tables, args.steps, 0, torch)
+        v64 = r64["stats"]["electron_steps"] / r64["wall_s"]
+        out["fp64"] = {"value": v64, "ms_per_step": r64["wall_s"] * 1e3 / args.steps,
+                       "kernel_avg_us": r64["step_kernel_ms"] * 1e3 / max(1, r64["step_launches"]),
+                       "events": r64["stats"]["events"], "kept": r64["stats"]["kept"]}
+        out["fp32_over_fp64"] = value / v64
+        print(f"[bench] fp64: {v64:.3e} e-steps/s", file=sys.stderr, flush=True)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(_workload(args.workload, "fp64", args.steps))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

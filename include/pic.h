@@ -1,0 +1,253 @@
+/*
+ * libpic - C ABI of the MI355X (gfx950) per-electron PIC step with Monte-Carlo
+ * photon emission by nonlinear Compton scattering (NCS) and bremsstrahlung,
+ * after Wan et al., arXiv:1612.07592.
+ *
+ * Method (one step of every live electron, in this order):
+ *   field gather at x^n (Yee-staggered, linear weights)
+ *   relativistic Boris push p^{n-1/2} -> p^{n+1/2}            (Sec. II.B: "particle pusher")
+ *   quantum parameter eta (Lorentz invariant of Sec. II.A)
+ *   NCS: optical depth tau -= dt * K_N (eta/gamma) h(eta); an emission when
+ *        tau <= 0, photon fraction drawn from the tabulated inverse CDF
+ *        (Sec. II.A/II.B: NCS module "the same with EPOCH")
+ *   bremsstrahlung: P = 1 - exp(-n sigma(E) v dt) with n the ion density of
+ *        the electron's cell; an event when R1 < P; photon energy from
+ *        sigma(y,E) = R2 sigma(E)                              (Sec. II.B, Eqs. (1), (4))
+ *   electron recoil along p (energy conserving), photon direction v/|v|
+ *   photon-macroparticle append (NCS photons below the record cut are
+ *        counted, not stored: Sec. III keeps photons >= m_e c^2)
+ *   move x^{n+1} = x^n + dt p/gamma and charge-conserving current deposit
+ * plus the supporting Yee field solve (B half steps around the push, E full
+ * step, first-order Mur absorbing faces) and a current-sheet laser source.
+ *
+ * Units: lengths c/w0, time 1/w0, momentum mc, energy mc^2, field m c w0/e,
+ * density n_c, with w0 = 2 pi c / lambda.  Electron charge -1.
+ *
+ * Conventions for every entry point:
+ *   - Every call returns pic_status (PIC_OK = 0).  No C++ exception crosses
+ *     the ABI.  A failed call leaves its outputs untouched.
+ *   - Host pointers are read during the call only; configs and tables are
+ *     copied, so the caller may free them on return.
+ *   - The context owns all device memory it allocates (hipMalloc at
+ *     pic_create); pic_destroy frees it.  Device pointers are never exposed.
+ *   - A context is not thread-safe; distinct contexts are independent and may
+ *     be driven from different threads.
+ *   - Work is enqueued on cfg->stream (a hipStream_t, NULL = the default
+ *     stream).  Errors raised asynchronously by a kernel surface at the next
+ *     call that synchronises (pic_emission_stats, pic_copy_*).  After a device
+ *     error the context is "broken": every call except pic_destroy and
+ *     pic_last_error returns PIC_ERR_DEVICE.
+ */
+#ifndef LIBPIC_PIC_H
+#define LIBPIC_PIC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PIC_ABI_VERSION 1u
+#define PIC_TABLES_VERSION 1u
+
+typedef struct pic_ctx pic_ctx; /* opaque; owned by the library */
+
+typedef enum {
+  PIC_OK = 0,
+  PIC_ERR_INVALID = 1,  /* bad argument or config (message in pic_last_error) */
+  PIC_ERR_NOMEM = 2,    /* device allocation failed */
+  PIC_ERR_DEVICE = 3,   /* HIP runtime / kernel error; context is broken */
+  PIC_ERR_STATE = 4,    /* call out of order (e.g. step before tables) */
+  PIC_ERR_OVERFLOW = 5, /* photon buffer full: stats valid, excess photons counted not stored */
+  PIC_ERR_TABLES = 6    /* tables rejected (version, sizes, non-finite, non-monotone CDF) */
+} pic_status;
+
+enum { PIC_FP64 = 0, PIC_FP32_MIXED = 1 };
+
+/* flags */
+enum {
+  PIC_NCS = 1u << 0,           /* nonlinear Compton emission on */
+  PIC_BREM = 1u << 1,          /* bremsstrahlung on */
+  PIC_FIELDS_FROZEN = 1u << 2, /* particle-only mode: prescribed fields, no field
+                                  solve, no deposit (the benchmark mode of Sec. II.B) */
+  PIC_NO_RECOIL = 1u << 4      /* emit without changing the electron (tests only) */
+};
+enum { PIC_FROZEN_UNIFORM = 0, PIC_FROZEN_PLANE_WAVE = 1 };
+
+/* Run configuration.  Lengths in laser wavelengths unless stated.
+ * Electrons are loaded cold (p = 0), ppc per cell at uniform-random in-cell
+ * positions from the run's Philox stream, in the slab cells
+ * [round(x0/dx), round(x0/dx) + round(thickness/dx)) x all transverse cells;
+ * static ions fill the same cells at n_i = ne_over_nc / charge_state. */
+typedef struct {
+  uint32_t abi_version;     /* must be PIC_ABI_VERSION */
+  uint32_t dims;            /* 1, 2 or 3 (x, then y, then z) */
+  uint32_t precision;       /* PIC_FP64 or PIC_FP32_MIXED (FP32 push/gather/tables,
+                               FP64 optical depth, weights and energy sums) */
+  uint32_t flags;           /* PIC_* flags */
+  int32_t n[3];             /* cells per axis; unused axes ignored */
+  int32_t ppc;              /* electrons per slab cell, >= 1 */
+  uint32_t Z;               /* nuclear charge (bremsstrahlung screening) */
+  uint32_t charge_state;    /* ion charge q: n_i = n_e / q */
+  uint32_t frozen_kind;     /* PIC_FROZEN_* when PIC_FIELDS_FROZEN */
+  double dx_lambda[3];      /* cell size per axis */
+  double cfl;               /* dt = cfl / sqrt(sum 1/dx^2), in (0, 1) */
+  double lambda_m;          /* laser wavelength in metres (sets n_c, E_S, K_BR) */
+  double a0;                /* peak normalised laser amplitude, linear pol. along y */
+  double w0_lambda;         /* Gaussian waist (2D/3D); <= 0 means plane wave */
+  double duration_cycles;   /* full length of the sin^2 envelope in laser periods */
+  double focus_x_lambda;    /* focal plane */
+  double ne_over_nc;        /* electron density in the slab */
+  double x0_lambda;         /* slab front */
+  double thickness_lambda;  /* slab thickness */
+  double photon_cut_mc2;    /* NCS photons below this energy are counted, not stored */
+  double frozen_E[3];       /* PIC_FROZEN_UNIFORM fields */
+  double frozen_B[3];
+  double frozen_a;          /* PIC_FROZEN_PLANE_WAVE: E_y = B_z = a sin(t - x) for t > x */
+  uint64_t photon_capacity; /* photon records the buffer holds */
+  uint64_t seed;            /* Philox key = (seed_lo, seed_hi ^ job_id_lo) */
+  uint64_t job_id;
+  void* stream;             /* hipStream_t or NULL */
+} pic_config;
+
+/* Emission tables (host arrays, copied by pic_load_tables).
+ * NCS: eta_i = exp(ln_eta0 + i dln_eta), i < n_eta; h(eta_i) is the
+ *   dimensionless total rate, dN/dt = K_N (eta/gamma) h(eta) with
+ *   K_N = sqrt(3)/(2 pi) alpha m c^2/(hbar w0); ncs_cdf[i*n_xi + j] is the
+ *   probability that the photon fraction xi = hbar w/(gamma m c^2) is below
+ *   exp(ln_xi[j]); ln_xi ascending, last value 0; rows non-decreasing,
+ *   first entry > 0 (mass below the grid), last entry 1.
+ * Bremsstrahlung: T_i = exp(ln_T0 + i dln_T) kinetic energy in mc^2;
+ *   sigma[i] = integral of Tsai's Eq. (1) from k_cut to T_i in alpha r_e^2;
+ *   br_cdf[i*n_y + j] = fraction of sigma[i] below photon energy
+ *   k_cut (T_i/k_cut)^(j/(n_y-1)); rows start at 0, end at 1, non-decreasing.
+ */
+typedef struct {
+  uint32_t version;   /* PIC_TABLES_VERSION */
+  uint32_t Z;         /* must equal the config's Z */
+  double k_cut_mc2;   /* bremsstrahlung photon cut (> 0) */
+  int32_t n_eta, n_xi;
+  double ln_eta0, dln_eta;
+  const double* h;       /* n_eta */
+  const double* ln_xi;   /* n_xi */
+  const double* ncs_cdf; /* n_eta * n_xi */
+  int32_t n_T, n_y;
+  double ln_T0, dln_T;
+  const double* sigma;   /* n_T */
+  const double* br_cdf;  /* n_T * n_y */
+} pic_tables;
+
+/* Emission statistics.  Energies in mc^2 times the macro-particle weight
+ * unit (n_c (c/w0)^dims).  Counts are exact; sums are FP64 with Neumaier
+ * compensation per wave slot, reduced in a fixed order. */
+typedef struct {
+  uint64_t steps;            /* steps taken so far */
+  uint64_t electrons_live;   /* electrons inside the box */
+  uint64_t electron_steps;   /* sum over steps of live electrons pushed */
+  uint64_t events[2];        /* [0] NCS, [1] bremsstrahlung emissions */
+  uint64_t kept[2];          /* photons recorded (or counted as overflow) */
+  uint64_t dropped_ncs;      /* NCS photons below the record cut */
+  uint64_t overflow;         /* kept photons that did not fit the buffer */
+  uint64_t brem_clamped;     /* sigma evaluated above the table's last energy */
+  uint64_t photons_stored;   /* records in the photon buffer */
+  double e_rad_kept[2];      /* sum w*eps of kept photons per process */
+  double e_rad_dropped;      /* sum w*eps of dropped NCS photons */
+  double e_kin_e;            /* sum w*(gamma-1) over live electrons (snapshot) */
+  double e_field;            /* (1/2) sum (E^2 + B^2) dV (snapshot) */
+} pic_stats;
+
+/* ---- the five calls of the hot path ------------------------------------- */
+
+/* Validate cfg, allocate the context's device memory and load the electrons
+ * and ions on the device.  On success *out owns everything.
+ * Errors: PIC_ERR_INVALID (bad cfg), PIC_ERR_NOMEM, PIC_ERR_DEVICE. */
+pic_status pic_create(const pic_config* cfg, pic_ctx** out);
+
+/* Copy and check the emission tables (NCS tables of the quantum-synchrotron
+ * spectrum; bremsstrahlung tables of Eq. (1) integrated as in Eq. (4)'s
+ * sigma(E)).  Required before pic_step when PIC_NCS or PIC_BREM is set.
+ * Errors: PIC_ERR_TABLES, PIC_ERR_INVALID, PIC_ERR_DEVICE. */
+pic_status pic_load_tables(pic_ctx* ctx, const pic_tables* t);
+
+/* Enqueue nsteps >= 0 full steps on the context's stream; returns without
+ * waiting for the device.  Errors: PIC_ERR_STATE (no tables while emission
+ * is on), PIC_ERR_INVALID, PIC_ERR_DEVICE. */
+pic_status pic_step(pic_ctx* ctx, int32_t nsteps);
+
+/* Wait for the context's stream and return the statistics.  Returns
+ * PIC_ERR_OVERFLOW (with *out filled) when photons did not fit. */
+pic_status pic_emission_stats(pic_ctx* ctx, pic_stats* out);
+
+/* Release everything the context owns.  NULL is a no-op. */
+void pic_destroy(pic_ctx* ctx);
+
+/* ---- helpers (tests, tools, serving) ------------------------------------ */
+
+/* Last error message of ctx (or of the last failed pic_create when ctx is
+ * NULL, per thread).  Never NULL. */
+const char* pic_last_error(const pic_ctx* ctx);
+
+/* Device bytes pic_create would allocate for cfg (tables included). */
+pic_status pic_memory_required(const pic_config* cfg, uint64_t* bytes);
+
+/* Number of macro-electrons loaded (live or not) and photon records the
+ * buffer holds / photons kept so far (may exceed the capacity). */
+pic_status pic_counts(pic_ctx* ctx, uint64_t* electrons, uint64_t* photons_stored,
+                      uint64_t* photons_kept);
+
+/* Copy all electrons to host arrays of pic_counts' electron count, ordered by
+ * id and widened to double: x[3n] (unused axes 0), p[3n], tau[n], w[n],
+ * id[n], alive[n] (0/1).  Any pointer may be NULL.  Synchronises. */
+pic_status pic_copy_electrons(pic_ctx* ctx, double* x, double* p, double* tau,
+                              double* w, uint32_t* id, uint8_t* alive);
+
+/* Overwrite positions, momenta and optical depths (host arrays ordered by
+ * id, layout as pic_copy_electrons).  For tests that set up beams. */
+pic_status pic_set_electrons(pic_ctx* ctx, const double* x, const double* p,
+                             const double* tau);
+
+/* Copy photon records [off, off+n) of the buffer (n <= stored - off):
+ * x[3n] emission point, k[3n] unit direction, eps[n] energy (mc^2), w[n]
+ * weight, step[n], parent[n] electron id, proc[n] (0 NCS, 1 brem).
+ * Record order is the device append order (not deterministic). */
+pic_status pic_copy_photons(pic_ctx* ctx, uint64_t off, uint64_t n, double* x,
+                            double* k, double* eps, double* w, uint32_t* step,
+                            uint32_t* parent, uint32_t* proc);
+
+/* Size (elements per component, guard cells included) of the field arrays
+ * and a copy of Ex,Ey,Ez,Bx,By,Bz (6*size doubles) in the library layout:
+ * index (i+g) + sx*((j+g) + sy*(k+g)), g = 2 on active axes. */
+pic_status pic_field_size(pic_ctx* ctx, uint64_t* size);
+pic_status pic_copy_fields(pic_ctx* ctx, double* out);
+
+/* Copy the current density of the last step, J^{n+1/2}, as the library keeps
+ * it: 3*size int64 values (Jx, Jy, Jz) in units of 2^-40 (n_c e c), same
+ * layout as pic_copy_fields.  Zero before the first step. */
+pic_status pic_copy_current(pic_ctx* ctx, int64_t* out);
+
+/* Build the emission tables with the library's own quadrature (host, FP64).
+ * Caller provides arrays of the standard sizes: h[256], ln_xi[256],
+ * ncs_cdf[256*256], sigma[128], br_cdf[128*64]; *out is filled to point at
+ * them.  nthreads <= 0 uses all host cores. */
+pic_status pic_build_tables(uint32_t Z, double k_cut_mc2, int32_t nthreads,
+                            double* h, double* ln_xi, double* ncs_cdf,
+                            double* sigma, double* br_cdf, pic_tables* out);
+
+/* Device Philox4x32-10 of n counters (ctr[4n]) under one key (key[2]) into
+ * out[4n]; host buffers.  Exposes the generator the step kernels use. */
+pic_status pic_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, uint64_t n);
+
+/* Kernel timing with HIP events recorded on the context's stream around
+ * every electron-step launch and every field-solve group (enable != 0 starts
+ * a fresh accumulation).  pic_profile_read synchronises and returns the summed
+ * milliseconds and launch counts: ms[0] electron step, ms[1] field solve. */
+pic_status pic_profile(pic_ctx* ctx, int32_t enable);
+pic_status pic_profile_read(pic_ctx* ctx, double* ms2, uint64_t* launches2);
+
+/* Derived constants of ctx: dx[3], dt, E_S, K_N, K_BR, n_c (8 doubles). */
+pic_status pic_derived(pic_ctx* ctx, double* out8);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LIBPIC_PIC_H */

@@ -1,0 +1,337 @@
+"""ctypes binding of libpic (include/pic.h): the same entry points by name,
+argument marshalling only.  Every step of the method runs in the HIP kernels of
+libpic.so; there is no Python or CPU fallback, and loading fails loudly when
+the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpic.so")
+
+PIC_ABI_VERSION = 1
+PIC_TABLES_VERSION = 1
+PIC_FP64, PIC_FP32_MIXED = 0, 1
+PIC_NCS, PIC_BREM, PIC_FIELDS_FROZEN, PIC_NO_RECOIL = 1, 2, 4, 16
+PIC_FROZEN_UNIFORM, PIC_FROZEN_PLANE_WAVE = 0, 1
+STATUS = {0: "PIC_OK", 1: "PIC_ERR_INVALID", 2: "PIC_ERR_NOMEM", 3: "PIC_ERR_DEVICE",
+          4: "PIC_ERR_STATE", 5: "PIC_ERR_OVERFLOW", 6: "PIC_ERR_TABLES"}
+
+EXPORTS = ["pic_create", "pic_load_tables", "pic_step", "pic_emission_stats", "pic_destroy",
+           "pic_last_error", "pic_memory_required", "pic_counts", "pic_copy_electrons",
+           "pic_set_electrons", "pic_copy_photons", "pic_field_size", "pic_copy_fields",
+           "pic_build_tables", "pic_philox", "pic_derived", "pic_profile", "pic_profile_read",
+           "pic_copy_current"]
+
+
+class pic_config(C.Structure):
+    _fields_ = [("abi_version", C.c_uint32), ("dims", C.c_uint32), ("precision", C.c_uint32),
+                ("flags", C.c_uint32), ("n", C.c_int32 * 3), ("ppc", C.c_int32),
+                ("Z", C.c_uint32), ("charge_state", C.c_uint32), ("frozen_kind", C.c_uint32),
+                ("dx_lambda", C.c_double * 3), ("cfl", C.c_double), ("lambda_m", C.c_double),
+                ("a0", C.c_double), ("w0_lambda", C.c_double), ("duration_cycles", C.c_double),
+                ("focus_x_lambda", C.c_double), ("ne_over_nc", C.c_double),
+                ("x0_lambda", C.c_double), ("thickness_lambda", C.c_double),
+                ("photon_cut_mc2", C.c_double), ("frozen_E", C.c_double * 3),
+                ("frozen_B", C.c_double * 3), ("frozen_a", C.c_double),
+                ("photon_capacity", C.c_uint64), ("seed", C.c_uint64), ("job_id", C.c_uint64),
+                ("stream", C.c_void_p)]
+
+
+class pic_tables(C.Structure):
+    _fields_ = [("version", C.c_uint32), ("Z", C.c_uint32), ("k_cut_mc2", C.c_double),
+                ("n_eta", C.c_int32), ("n_xi", C.c_int32), ("ln_eta0", C.c_double),
+                ("dln_eta", C.c_double), ("h", C.POINTER(C.c_double)),
+                ("ln_xi", C.POINTER(C.c_double)), ("ncs_cdf", C.POINTER(C.c_double)),
+                ("n_T", C.c_int32), ("n_y", C.c_int32), ("ln_T0", C.c_double),
+                ("dln_T", C.c_double), ("sigma", C.POINTER(C.c_double)),
+                ("br_cdf", C.POINTER(C.c_double))]
+
+
+class pic_stats(C.Structure):
+    _fields_ = [("steps", C.c_uint64), ("electrons_live", C.c_uint64),
+                ("electron_steps", C.c_uint64), ("events", C.c_uint64 * 2),
+                ("kept", C.c_uint64 * 2), ("dropped_ncs", C.c_uint64), ("overflow", C.c_uint64),
+                ("brem_clamped", C.c_uint64), ("photons_stored", C.c_uint64),
+                ("e_rad_kept", C.c_double * 2), ("e_rad_dropped", C.c_double),
+                ("e_kin_e", C.c_double), ("e_field", C.c_double)]
+
+
+class PicError(RuntimeError):
+    def __init__(self, fn, code, msg):
+        super().__init__(f"{fn} -> {STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load libpic.so (built by ``paper_1612_07592_amd.build``); no fallback."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libpic.so not built ({LIB_PATH}); run python -m paper_1612_07592_amd.build")
+    src = os.path.join(HERE, "csrc")
+    newest = max(os.path.getmtime(os.path.join(src, f)) for f in os.listdir(src))
+    if newest > os.path.getmtime(LIB_PATH) + 1.0:
+        import warnings
+        warnings.warn("libpic.so is older than its sources; rebuild with "
+                      "python -m paper_1612_07592_amd.build", RuntimeWarning)
+    L = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    i32, u32, u64, dbl = C.c_int32, C.c_uint32, C.c_uint64, C.c_double
+    L.pic_create.argtypes = [C.POINTER(pic_config), C.POINTER(P)]
+    L.pic_load_tables.argtypes = [P, C.POINTER(pic_tables)]
+    L.pic_step.argtypes = [P, i32]
+    L.pic_emission_stats.argtypes = [P, C.POINTER(pic_stats)]
+    L.pic_destroy.argtypes = [P]
+    L.pic_destroy.restype = None
+    L.pic_last_error.argtypes = [P]
+    L.pic_last_error.restype = C.c_char_p
+    L.pic_memory_required.argtypes = [C.POINTER(pic_config), C.POINTER(u64)]
+    L.pic_counts.argtypes = [P, C.POINTER(u64), C.POINTER(u64), C.POINTER(u64)]
+    L.pic_copy_electrons.argtypes = [P] + [C.c_void_p] * 6
+    L.pic_set_electrons.argtypes = [P] + [C.c_void_p] * 3
+    L.pic_copy_photons.argtypes = [P, u64, u64] + [C.c_void_p] * 7
+    L.pic_field_size.argtypes = [P, C.POINTER(u64)]
+    L.pic_copy_fields.argtypes = [P, C.c_void_p]
+    L.pic_build_tables.argtypes = [u32, dbl, i32] + [C.c_void_p] * 5 + [C.POINTER(pic_tables)]
+    L.pic_philox.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, u64]
+    L.pic_derived.argtypes = [P, C.c_void_p]
+    L.pic_copy_current.argtypes = [P, C.c_void_p]
+    L.pic_profile.argtypes = [P, i32]
+    L.pic_profile_read.argtypes = [P, C.c_void_p, C.c_void_p]
+    for name in EXPORTS:
+        fn = getattr(L, name)
+        if name not in ("pic_destroy", "pic_last_error"):
+            fn.restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(fn, code, ctx=None, ok=(0,)):
+    if code not in ok:
+        msg = load().pic_last_error(ctx)
+        raise PicError(fn, code, msg.decode() if msg else "")
+    return code
+
+
+def config_from(w: dict, stream=None) -> pic_config:
+    """pic_config from a workload recipe dict (``workloads.py`` keys)."""
+    c = pic_config()
+    c.abi_version = PIC_ABI_VERSION
+    c.dims = int(w["dims"])
+    c.precision = PIC_FP32_MIXED if w.get("precision", "fp64") == "fp32" else PIC_FP64
+    f = 0
+    f |= PIC_NCS if w.get("ncs", True) else 0
+    f |= PIC_BREM if w.get("brem", True) else 0
+    f |= PIC_FIELDS_FROZEN if w.get("frozen", False) else 0
+    f |= PIC_NO_RECOIL if w.get("no_recoil", False) else 0
+    c.flags = f
+    n = list(w["n"]) + [1] * (3 - len(w["n"]))
+    dx = list(w["dx_lambda"]) + [1.0] * (3 - len(w["dx_lambda"]))
+    for a in range(3):
+        c.n[a] = int(n[a])
+        c.dx_lambda[a] = float(dx[a])
+    c.ppc = int(w["ppc"])
+    c.Z = int(w["Z"])
+    c.charge_state = int(w["charge_state"])
+    c.frozen_kind = int(w.get("frozen_kind", PIC_FROZEN_UNIFORM))
+    c.cfl = float(w.get("cfl", 0.95))
+    c.lambda_m = float(w.get("lambda_m", 1e-6))
+    c.a0 = float(w.get("a0", 0.0))
+    c.w0_lambda = float(w.get("w0_lambda", 0.0))
+    c.duration_cycles = float(w.get("duration_cycles", 10.0))
+    c.focus_x_lambda = float(w.get("focus_x_lambda", 0.0))
+    c.ne_over_nc = float(w["ne_over_nc"])
+    c.x0_lambda = float(w["x0_lambda"])
+    c.thickness_lambda = float(w["thickness_lambda"])
+    c.photon_cut_mc2 = float(w.get("photon_cut_mc2", 1.0))
+    fe = list(w.get("frozen_E", [0.0] * 3))
+    fb = list(w.get("frozen_B", [0.0] * 3))
+    for a in range(3):
+        c.frozen_E[a] = float(fe[a])
+        c.frozen_B[a] = float(fb[a])
+    c.frozen_a = float(w.get("frozen_a", 0.0))
+    c.photon_capacity = int(w.get("photon_capacity", 1 << 20))
+    c.seed = int(w.get("seed", 1))
+    c.job_id = int(w.get("job_id", 0))
+    c.stream = stream
+    return c
+
+
+def tables_struct(t: dict):
+    """pic_tables pointing at the arrays of a table dict; returns (struct, keepalive)."""
+    s = pic_tables()
+    s.version = PIC_TABLES_VERSION
+    s.Z = int(t["Z"])
+    s.k_cut_mc2 = float(t["k_cut"])
+    s.n_eta, s.n_xi = int(t["n_eta"]), int(t["n_xi"])
+    s.ln_eta0, s.dln_eta = float(t["ln_eta0"]), float(t["dln_eta"])
+    s.n_T, s.n_y = int(t["n_T"]), int(t["n_y"])
+    s.ln_T0, s.dln_T = float(t["ln_T0"]), float(t["dln_T"])
+    keep = []
+    for name in ("h", "ln_xi", "ncs_cdf", "sigma", "br_cdf"):
+        a = np.ascontiguousarray(t[name], dtype=np.float64)
+        keep.append(a)
+        setattr(s, name, a.ctypes.data_as(C.POINTER(C.c_double)))
+    return s, keep
+
+
+def pic_build_tables(Z: int, k_cut_mc2: float = 1.0, nthreads: int = 0) -> dict:
+    """The library's own emission tables as a dict of numpy arrays."""
+    L = load()
+    h = np.zeros(256); lx = np.zeros(256); ncs = np.zeros(256 * 256)
+    sig = np.zeros(128); br = np.zeros(128 * 64)
+    out = pic_tables()
+    _check("pic_build_tables", L.pic_build_tables(int(Z), float(k_cut_mc2), int(nthreads),
+                                                  h.ctypes.data, lx.ctypes.data, ncs.ctypes.data,
+                                                  sig.ctypes.data, br.ctypes.data, C.byref(out)))
+    return dict(Z=int(Z), k_cut=float(k_cut_mc2), n_eta=out.n_eta, n_xi=out.n_xi,
+                ln_eta0=out.ln_eta0, dln_eta=out.dln_eta, h=h, ln_xi=lx,
+                ncs_cdf=ncs.reshape(256, 256), n_T=out.n_T, n_y=out.n_y, ln_T0=out.ln_T0,
+                dln_T=out.dln_T, sigma=sig, br_cdf=br.reshape(128, 64))
+
+
+def pic_philox(ctr, key) -> np.ndarray:
+    """Device Philox4x32-10 of counters ctr[n,4] under key[2]."""
+    L = load()
+    ctr = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
+    key = np.ascontiguousarray(key, dtype=np.uint32).reshape(2)
+    out = np.zeros_like(ctr)
+    _check("pic_philox", L.pic_philox(ctr.ctypes.data, key.ctypes.data, out.ctypes.data, ctr.shape[0]))
+    return out
+
+
+def pic_memory_required(w: dict) -> int:
+    L = load()
+    c = config_from(w)
+    b = C.c_uint64(0)
+    _check("pic_memory_required", L.pic_memory_required(C.byref(c), C.byref(b)))
+    return int(b.value)
+
+
+class Sim:
+    """One libpic context: pic_create / pic_load_tables / pic_step /
+    pic_emission_stats / pic_destroy plus the copy helpers."""
+
+    def __init__(self, w: dict, tables: dict | None = None, stream=None):
+        L = load()
+        self._L = L
+        self.workload = dict(w)
+        cfg = config_from(w, stream)
+        h = C.c_void_p()
+        _check("pic_create", L.pic_create(C.byref(cfg), C.byref(h)))
+        self._h = h
+        n = C.c_uint64()
+        _check("pic_counts", L.pic_counts(self._h, C.byref(n), None, None), self._h)
+        self.N = int(n.value)
+        if tables is not None:
+            self.pic_load_tables(tables)
+
+    # --- the five calls ---------------------------------------------------
+    def pic_load_tables(self, tables: dict):
+        s, keep = tables_struct(tables)
+        _check("pic_load_tables", self._L.pic_load_tables(self._h, C.byref(s)), self._h)
+
+    def pic_step(self, n: int = 1):
+        _check("pic_step", self._L.pic_step(self._h, int(n)), self._h)
+
+    def pic_emission_stats(self) -> dict:
+        s = pic_stats()
+        code = self._L.pic_emission_stats(self._h, C.byref(s))
+        _check("pic_emission_stats", code, self._h, ok=(0, 5))
+        return dict(steps=s.steps, live=s.electrons_live, electron_steps=s.electron_steps,
+                    events=[s.events[0], s.events[1]], kept=[s.kept[0], s.kept[1]],
+                    dropped_ncs=s.dropped_ncs, overflow=s.overflow,
+                    brem_clamped=s.brem_clamped, photons_stored=s.photons_stored,
+                    e_rad_kept=[s.e_rad_kept[0], s.e_rad_kept[1]],
+                    e_rad_dropped=s.e_rad_dropped, e_kin_e=s.e_kin_e, e_field=s.e_field,
+                    status=STATUS[code])
+
+    def pic_destroy(self):
+        if getattr(self, "_h", None):
+            self._L.pic_destroy(self._h)
+            self._h = None
+
+    close = pic_destroy
+
+    def __del__(self):
+        try:
+            self.pic_destroy()
+        except Exception:
+            pass
+
+    # --- helpers ----------------------------------------------------------
+    step = pic_step
+    stats = pic_emission_stats
+
+    def counts(self):
+        e, s, k = C.c_uint64(), C.c_uint64(), C.c_uint64()
+        _check("pic_counts", self._L.pic_counts(self._h, C.byref(e), C.byref(s), C.byref(k)), self._h)
+        return int(e.value), int(s.value), int(k.value)
+
+    def electrons(self) -> dict:
+        N = self.N
+        x = np.zeros((N, 3)); p = np.zeros((N, 3)); tau = np.zeros(N); w = np.zeros(N)
+        i = np.zeros(N, dtype=np.uint32); al = np.zeros(N, dtype=np.uint8)
+        _check("pic_copy_electrons",
+               self._L.pic_copy_electrons(self._h, x.ctypes.data, p.ctypes.data, tau.ctypes.data,
+                                          w.ctypes.data, i.ctypes.data, al.ctypes.data), self._h)
+        return dict(x=x, p=p, tau=tau, w=w, id=i, alive=al.astype(bool))
+
+    def set_electrons(self, x, p, tau):
+        x = np.ascontiguousarray(x, dtype=np.float64).reshape(self.N, 3)
+        p = np.ascontiguousarray(p, dtype=np.float64).reshape(self.N, 3)
+        tau = np.ascontiguousarray(tau, dtype=np.float64).reshape(self.N)
+        _check("pic_set_electrons", self._L.pic_set_electrons(self._h, x.ctypes.data, p.ctypes.data,
+                                                              tau.ctypes.data), self._h)
+
+    def photons(self, off: int = 0, n: int | None = None) -> dict:
+        _, stored, _ = self.counts()
+        if n is None:
+            n = stored - off
+        x = np.zeros((n, 3)); k = np.zeros((n, 3)); e = np.zeros(n); w = np.zeros(n)
+        st = np.zeros(n, dtype=np.uint32); par = np.zeros(n, dtype=np.uint32)
+        pr = np.zeros(n, dtype=np.uint32)
+        _check("pic_copy_photons",
+               self._L.pic_copy_photons(self._h, int(off), int(n), x.ctypes.data, k.ctypes.data,
+                                        e.ctypes.data, w.ctypes.data, st.ctypes.data,
+                                        par.ctypes.data, pr.ctypes.data), self._h)
+        return dict(x=x, k=k, energy=e, w=w, step=st, parent=par, proc=pr)
+
+    def fields(self) -> np.ndarray:
+        m = C.c_uint64()
+        _check("pic_field_size", self._L.pic_field_size(self._h, C.byref(m)), self._h)
+        out = np.zeros(6 * int(m.value))
+        _check("pic_copy_fields", self._L.pic_copy_fields(self._h, out.ctypes.data), self._h)
+        return out.reshape(6, int(m.value))
+
+    def profile(self, enable: bool = True):
+        _check("pic_profile", self._L.pic_profile(self._h, 1 if enable else 0), self._h)
+
+    def profile_read(self):
+        """(ms electron step, ms field solve), (launches, launch groups)."""
+        ms = np.zeros(2)
+        n = np.zeros(2, dtype=np.uint64)
+        _check("pic_profile_read", self._L.pic_profile_read(self._h, ms.ctypes.data, n.ctypes.data), self._h)
+        return ms, n
+
+    def current(self) -> np.ndarray:
+        """J^{n+1/2} of the last step, int64 in units of 2^-40, shape (3, size)."""
+        m = C.c_uint64()
+        _check("pic_field_size", self._L.pic_field_size(self._h, C.byref(m)), self._h)
+        out = np.zeros(3 * int(m.value), dtype=np.int64)
+        _check("pic_copy_current", self._L.pic_copy_current(self._h, out.ctypes.data), self._h)
+        return out.reshape(3, int(m.value))
+
+    def derived(self) -> dict:
+        o = np.zeros(8)
+        _check("pic_derived", self._L.pic_derived(self._h, o.ctypes.data), self._h)
+        return dict(dx=o[0:3].copy(), dt=o[3], E_S=o[4], K_N=o[5], K_BR=o[6], n_c=o[7])

@@ -1,0 +1,798 @@
+// libpic host runtime: the C ABI of include/pic.h.
+// Validation, device allocation, per-step kernel sequencing on the context's
+// stream, statistics read-back and the test/tool helpers.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+#include "pic_internal.hpp"
+#include "philox.hpp"
+
+namespace pic {
+void launch_b_half_zero(const Ctx& c, hipStream_t s);
+int reduce_scratch_cnt();
+int reduce_scratch_sum();
+
+Ctx::~Ctx() {
+  for (void* p : allocs) { hipError_t e = hipFree(p); (void)e; }
+  for (hipEvent_t ev : ev_pool) { hipError_t e = hipEventDestroy(ev); (void)e; }
+}
+
+hipEvent_t Ctx::prof_event() {
+  if (ev_used == ev_pool.size()) {
+    hipEvent_t ev = nullptr;
+    if (hipEventCreate(&ev) != hipSuccess) return nullptr;
+    ev_pool.push_back(ev);
+  }
+  return ev_pool[ev_used++];
+}
+}  // namespace pic
+
+using namespace pic;
+
+struct pic_ctx {
+  Ctx c;
+};
+
+static thread_local std::string g_create_err;
+
+#define FAIL(ctx, code, ...)                                   \
+  do {                                                         \
+    char _b[512];                                              \
+    snprintf(_b, sizeof(_b), __VA_ARGS__);                     \
+    (ctx).err = _b;                                            \
+    return code;                                               \
+  } while (0)
+
+#define HIPCHK(ctx, expr)                                                          \
+  do {                                                                             \
+    hipError_t _e = (expr);                                                        \
+    if (_e != hipSuccess) {                                                        \
+      (ctx).err = std::string(#expr) + ": " + hipGetErrorString(_e);               \
+      (ctx).broken = true;                                                         \
+      return PIC_ERR_DEVICE;                                                       \
+    }                                                                              \
+  } while (0)
+
+namespace {
+
+size_t real_size(const pic_config& c) { return c.precision == PIC_FP32_MIXED ? 4 : 8; }
+
+bool is_fin(double v) { return std::isfinite(v); }
+
+// Fills grid geometry and derived constants; returns an error message or "".
+std::string derive(const pic_config& cfg, Ctx& c) {
+  if (cfg.abi_version != PIC_ABI_VERSION) return "abi_version mismatch";
+  if (cfg.dims < 1 || cfg.dims > 3) return "dims must be 1, 2 or 3";
+  if (cfg.precision != PIC_FP64 && cfg.precision != PIC_FP32_MIXED) return "unknown precision";
+  if (cfg.flags & ~(uint32_t)(PIC_NCS | PIC_BREM | PIC_FIELDS_FROZEN | PIC_NO_RECOIL)) return "unknown flag bits";
+  if (cfg.ppc < 1) return "ppc must be >= 1";
+  if (cfg.Z < 1 || cfg.Z > 120) return "Z out of range";
+  if (cfg.charge_state < 1 || cfg.charge_state > cfg.Z) return "charge_state must be in [1, Z]";
+  if (!(cfg.cfl > 0.0 && cfg.cfl < 1.0)) return "cfl must be in (0, 1)";
+  if (!(cfg.lambda_m > 0.0) || !is_fin(cfg.lambda_m)) return "lambda_m must be > 0";
+  if (!is_fin(cfg.a0) || !is_fin(cfg.w0_lambda) || !is_fin(cfg.duration_cycles) ||
+      !is_fin(cfg.focus_x_lambda) || !is_fin(cfg.frozen_a))
+    return "non-finite laser parameter";
+  if (!(cfg.ne_over_nc >= 0.0) || !is_fin(cfg.ne_over_nc)) return "ne_over_nc must be finite and >= 0";
+  if (!is_fin(cfg.x0_lambda) || !(cfg.thickness_lambda >= 0.0) || !is_fin(cfg.thickness_lambda))
+    return "bad slab geometry";
+  if (!(cfg.photon_cut_mc2 >= 0.0) || !is_fin(cfg.photon_cut_mc2)) return "photon_cut_mc2 must be >= 0";
+  for (int a = 0; a < 3; ++a)
+    if (!is_fin(cfg.frozen_E[a]) || !is_fin(cfg.frozen_B[a])) return "non-finite frozen field";
+  if (cfg.frozen_kind > PIC_FROZEN_PLANE_WAVE) return "unknown frozen_kind";
+  if (cfg.photon_capacity > (1ull << 40)) return "photon_capacity too large";
+  Grid& g = c.g;
+  g.dims = (int)cfg.dims;
+  const double twopi = 2.0 * M_PI;
+  for (int a = 0; a < 3; ++a) {
+    g.act[a] = a < g.dims;
+    if (g.act[a]) {
+      if (cfg.n[a] < 8 || cfg.n[a] > (1 << 24)) return "cells per axis must be in [8, 2^24]";
+      if (!(cfg.dx_lambda[a] > 0.0) || !is_fin(cfg.dx_lambda[a])) return "dx must be > 0";
+    }
+    g.n[a] = g.act[a] ? cfg.n[a] : 1;
+    g.gg[a] = g.act[a] ? kGuard : 0;
+    g.sz[a] = g.act[a] ? g.n[a] + 1 + 2 * kGuard : 1;
+    g.dx[a] = g.act[a] ? cfg.dx_lambda[a] * twopi : 1.0;
+    g.idx[a] = 1.0 / g.dx[a];
+    g.L[a] = (double)g.n[a] * g.dx[a];
+  }
+  double q = 0.0;
+  for (int a = 0; a < g.dims; ++a) q = q + 1.0 / (g.dx[a] * g.dx[a]);
+  g.dt = cfg.cfl / sqrt(q);
+  double V = 1.0;
+  for (int a = 0; a < g.dims; ++a) V = V * g.dx[a];
+  g.invV = 1.0 / V;
+  for (int a = 0; a < 3; ++a) {
+    g.hd[a] = (0.5 * g.dt) / g.dx[a];
+    g.cd[a] = g.dt / g.dx[a];
+    g.cm[a] = (g.dt - g.dx[a]) / (g.dt + g.dx[a]);
+  }
+  g.i_src = 4;
+  g.nsrc_y = g.act[1] ? g.n[1] : 1;
+  g.nsrc_z = g.act[2] ? g.n[2] + 1 : 1;
+  g.nfield = (int64_t)g.sz[0] * g.sz[1] * g.sz[2];
+  // CODATA 2018
+  const double alpha = 7.2973525693e-3, re = 2.8179403262e-15, lC = 3.8615926796e-13;
+  const double eps0 = 8.8541878128e-12, me = 9.1093837015e-31, qe = 1.602176634e-19, cl = 299792458.0;
+  const double lam = cfg.lambda_m;
+  const double w0 = twopi * cl / lam;
+  c.n_c = eps0 * me * w0 * w0 / (qe * qe);
+  c.E_S = lam / (twopi * lC);
+  c.iES = 1.0 / c.E_S;
+  c.K_N = sqrt(3.0) / twopi * alpha * c.E_S;
+  c.K_BR = c.n_c * (lam / twopi) * alpha * re * re;
+  c.key0 = (uint32_t)cfg.seed;
+  c.key1 = (uint32_t)(cfg.seed >> 32) ^ (uint32_t)cfg.job_id;
+  int i0 = (int)llround(cfg.x0_lambda / cfg.dx_lambda[0]);
+  int i1 = i0 + (int)llround(cfg.thickness_lambda / cfg.dx_lambda[0]);
+  if (i0 < 0) i0 = 0;
+  if (i1 > g.n[0]) i1 = g.n[0];
+  if (i1 < i0) i1 = i0;
+  c.i0 = i0;
+  c.i1 = i1;
+  const int64_t N = (int64_t)(i1 - i0) * g.n[1] * g.n[2] * cfg.ppc;
+  if (N >= (int64_t)kDead) return "too many electrons (ids are 31-bit)";
+  if (g.i_src + 2 >= g.n[0]) return "grid too short for the laser source plane";
+  c.N = N;
+  c.wgt = cfg.ne_over_nc * V / (double)cfg.ppc;
+  c.fp32 = cfg.precision == PIC_FP32_MIXED;
+  c.pcap = cfg.photon_capacity;
+  c.nslots = ((N + kBlock - 1) / kBlock) * (kBlock / 64);
+  return "";
+}
+
+// Every device buffer of a context, in allocation order.
+struct Plan {
+  struct Item { void** dst; size_t bytes; };
+  std::vector<Item> items;
+  uint64_t total = 0;
+  void add(void** dst, size_t bytes) {
+    bytes = (bytes + 255) & ~(size_t)255;
+    items.push_back({dst, bytes});
+    total += bytes;
+  }
+};
+
+Plan make_plan(Ctx& c) {
+  Plan P;
+  const size_t rs = c.fp32 ? 4 : 8;
+  const Grid& g = c.g;
+  const size_t nf = (size_t)g.nfield;
+  for (int a = 0; a < 3; ++a) {
+    P.add(&c.E[a], nf * rs);
+    P.add(&c.En[a], nf * rs);
+    P.add(&c.B[a], nf * rs);
+    P.add((void**)&c.J[a], nf * 8);
+  }
+  const size_t ncell = (size_t)g.n[0] * g.n[1] * g.n[2];
+  P.add((void**)&c.ni, ncell * 8);
+  const size_t ns = (size_t)g.nsrc_y * g.nsrc_z;
+  P.add((void**)&c.srcA, ns * 8);
+  P.add((void**)&c.srcC, ns * 8);
+  P.add((void**)&c.srcS, ns * 8);
+  const size_t N = (size_t)(c.N > 0 ? c.N : 1);
+  for (int a = 0; a < 3; ++a) {
+    if (a < g.dims) P.add(&c.x[a], N * rs);
+    P.add(&c.p[a], N * rs);
+  }
+  P.add((void**)&c.tau, N * 8);
+  P.add((void**)&c.w, N * 8);
+  P.add((void**)&c.id, N * 4);
+  const size_t pc = (size_t)(c.pcap > 0 ? c.pcap : 1);
+  for (int a = 0; a < 3; ++a) {
+    P.add(&c.px[a], pc * rs);
+    P.add(&c.pk[a], pc * rs);
+  }
+  P.add(&c.pe, pc * rs);
+  P.add((void**)&c.pw, pc * 8);
+  P.add((void**)&c.pstep, pc * 4);
+  P.add((void**)&c.ppar, pc * 4);
+  P.add((void**)&c.pproc, pc * 4);
+  P.add((void**)&c.pcount, 8);
+  const size_t nsl = (size_t)(c.nslots > 0 ? c.nslots : 1);
+  P.add((void**)&c.slot_cnt, nsl * kSlotCnt * 8);
+  P.add((void**)&c.slot_sum, nsl * kSlotSum * 8);
+  P.add((void**)&c.red_cnt, (size_t)reduce_scratch_cnt() * 8);
+  P.add((void**)&c.red_sum, (size_t)reduce_scratch_sum() * 8);
+  // tables: FP64 and FP32 copies of the standard-size tables
+  const size_t tb = (256 + 256 + 256 * 256 + 128 + 128 * 64);
+  P.total += tb * 12 + 10 * 256;
+  return P;
+}
+
+// Transverse profile of the laser source (host, once): amplitude, cos and
+// -sin of the focusing phase of a Gaussian beam at the source plane.
+void source_profile(const pic_config& cfg, const Grid& g, std::vector<double>& A,
+                    std::vector<double>& C, std::vector<double>& S) {
+  const int ny = g.nsrc_y, nz = g.nsrc_z;
+  A.assign((size_t)ny * nz, 1.0);
+  C.assign((size_t)ny * nz, 1.0);
+  S.assign((size_t)ny * nz, 0.0);
+  if (g.dims == 1 || !(cfg.w0_lambda > 0.0)) return;
+  const double twopi = 2.0 * M_PI;
+  const double w0n = cfg.w0_lambda * twopi;
+  const double xs = (double)g.i_src * g.dx[0];
+  const double xf = cfg.focus_x_lambda * twopi;
+  const double zz = xs - xf;
+  const double zR = 0.5 * w0n * w0n;
+  const double wz = w0n * sqrt(1.0 + (zz / zR) * (zz / zR));
+  const double Rinv = zz / (zz * zz + zR * zR);
+  const double psi = atan(zz / zR);
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j) {
+      const size_t m = (size_t)j + (size_t)ny * k;
+      const double yr = ((double)j + 0.5) * g.dx[1] - 0.5 * g.L[1];
+      double r2 = yr * yr;
+      double amp, ph;
+      if (g.dims == 3) {
+        const double zr = (double)k * g.dx[2] - 0.5 * g.L[2];
+        r2 = r2 + zr * zr;
+        amp = (w0n / wz) * exp(-r2 / (wz * wz));
+        ph = 0.5 * r2 * Rinv - psi;
+      } else {
+        amp = sqrt(w0n / wz) * exp(-r2 / (wz * wz));
+        ph = 0.5 * r2 * Rinv - 0.5 * psi;
+      }
+      A[m] = amp;
+      C[m] = cos(ph);
+      S[m] = -sin(ph);
+    }
+}
+
+// a0 env(t) sin t and a0 env(t) cos t at the source time of step n, (n+1/2) dt.
+void laser_scalars(const Ctx& c, uint64_t step, double* ls, double* lc) {
+  const double t = ((double)step + 0.5) * c.g.dt;
+  const double TL = c.cfg.duration_cycles * (2.0 * M_PI);
+  double env = 0.0;
+  if (t >= 0.0 && t <= TL) {
+    env = sin(M_PI * t / TL);
+    env = env * env;
+  }
+  *ls = c.cfg.a0 * env * sin(t);
+  *lc = c.cfg.a0 * env * cos(t);
+}
+
+template <class R>
+void fill_step_params(Ctx& c, StepParams<R>& P) {
+  const Grid& g = c.g;
+  P.N = c.N;
+  P.step = (uint32_t)c.step;
+  P.key0 = c.key0;
+  P.key1 = c.key1;
+  P.flags = c.cfg.flags;
+  P.frozen_kind = c.cfg.frozen_kind;
+  P.dt = g.dt;
+  P.tn = (double)c.step * g.dt;
+  for (int a = 0; a < 3; ++a) {
+    P.x[a] = (R*)c.x[a];
+    P.p[a] = (R*)c.p[a];
+    P.E[a] = (const R*)c.E[a];
+    P.B[a] = (const R*)c.B[a];
+    P.J[a] = c.J[a];
+    P.n[a] = g.n[a];
+    P.gg[a] = g.gg[a];
+    P.sz[a] = g.sz[a];
+    P.idx[a] = g.idx[a];
+    P.L[a] = g.L[a];
+    P.dxdt[a] = g.dx[a] / g.dt;
+    P.fE[a] = c.cfg.frozen_E[a];
+    P.fB[a] = c.cfg.frozen_B[a];
+    P.px[a] = (R*)c.px[a];
+    P.pk[a] = (R*)c.pk[a];
+  }
+  P.tau = c.tau;
+  P.w = c.w;
+  P.id = c.id;
+  P.invV = g.invV;
+  P.ni = c.ni;
+  P.iES = c.iES;
+  P.K_N = c.K_N;
+  P.K_BR = c.K_BR;
+  P.photon_cut = c.cfg.photon_cut_mc2;
+  P.fa = c.cfg.frozen_a;
+  const DevTables& t = c.t;
+  P.n_eta = t.n_eta; P.n_xi = t.n_xi; P.n_T = t.n_T; P.n_y = t.n_y;
+  P.ln_eta0 = t.ln_eta0; P.idln_eta = t.idln_eta; P.ln_T0 = t.ln_T0; P.idln_T = t.idln_T;
+  P.k_cut = t.k_cut; P.lnk = t.lnk; P.iny1 = t.iny1;
+  if (sizeof(R) == 8) {
+    P.h = (const R*)t.h; P.lnxi = (const R*)t.lnxi; P.ncs = (const R*)t.ncs;
+    P.sig = (const R*)t.sig; P.br = (const R*)t.br;
+  } else {
+    P.h = (const R*)t.hf; P.lnxi = (const R*)t.lnxif; P.ncs = (const R*)t.ncsf;
+    P.sig = (const R*)t.sigf; P.br = (const R*)t.brf;
+  }
+  P.pcap = c.pcap;
+  P.pe = (R*)c.pe;
+  P.pw = c.pw;
+  P.pstep = c.pstep;
+  P.ppar = c.ppar;
+  P.pproc = c.pproc;
+  P.pcount = c.pcount;
+  P.slot_cnt = c.slot_cnt;
+  P.slot_sum = c.slot_sum;
+}
+
+pic_status check_ctx(pic_ctx* ctx) {
+  if (!ctx) return PIC_ERR_INVALID;
+  if (ctx->c.broken) return PIC_ERR_DEVICE;
+  return PIC_OK;
+}
+
+}  // namespace
+
+namespace {
+template <class R>
+pic_status copy_real(Ctx& c, const void* dev, size_t n, std::vector<double>& out) {
+  std::vector<R> tmp(n);
+  HIPCHK(c, hipMemcpyAsync(tmp.data(), dev, n * sizeof(R), hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(c, hipStreamSynchronize(c.stream));
+  out.resize(n);
+  for (size_t i = 0; i < n; ++i) out[i] = (double)tmp[i];
+  return PIC_OK;
+}
+pic_status copy_any(Ctx& c, const void* dev, size_t n, std::vector<double>& out) {
+  return c.fp32 ? copy_real<float>(c, dev, n, out) : copy_real<double>(c, dev, n, out);
+}
+}  // namespace
+
+extern "C" {
+
+const char* pic_last_error(const pic_ctx* ctx) {
+  if (!ctx) return g_create_err.c_str();
+  return ctx->c.err.c_str();
+}
+
+pic_status pic_memory_required(const pic_config* cfg, uint64_t* bytes) {
+  if (!cfg || !bytes) return PIC_ERR_INVALID;
+  Ctx tmp;
+  const std::string e = derive(*cfg, tmp);
+  if (!e.empty()) {
+    g_create_err = e;
+    return PIC_ERR_INVALID;
+  }
+  *bytes = make_plan(tmp).total;
+  return PIC_OK;
+}
+
+pic_status pic_create(const pic_config* cfg, pic_ctx** out) {
+  if (!cfg || !out) {
+    g_create_err = "null argument";
+    return PIC_ERR_INVALID;
+  }
+  pic_ctx* ctx = new (std::nothrow) pic_ctx;
+  if (!ctx) {
+    g_create_err = "host allocation failed";
+    return PIC_ERR_NOMEM;
+  }
+  Ctx& c = ctx->c;
+  c.cfg = *cfg;
+  const std::string e = derive(*cfg, c);
+  if (!e.empty()) {
+    g_create_err = e;
+    delete ctx;
+    return PIC_ERR_INVALID;
+  }
+  c.stream = (hipStream_t)cfg->stream;
+  Plan P = make_plan(c);
+  for (auto& it : P.items) {
+    void* p = nullptr;
+    const hipError_t he = hipMalloc(&p, it.bytes);
+    if (he != hipSuccess) {
+      g_create_err = std::string("hipMalloc failed: ") + hipGetErrorString(he);
+      (void)hipGetLastError();
+      delete ctx;
+      return he == hipErrorOutOfMemory ? PIC_ERR_NOMEM : PIC_ERR_DEVICE;
+    }
+    c.allocs.push_back(p);
+    *it.dst = p;
+  }
+  // zero fields, J, counters, slots (plain stream-ordered memsets at set-up)
+  for (auto& it : P.items) {
+    const hipError_t he = hipMemsetAsync(*it.dst, 0, it.bytes, c.stream);
+    if (he != hipSuccess) {
+      g_create_err = std::string("hipMemsetAsync: ") + hipGetErrorString(he);
+      delete ctx;
+      return PIC_ERR_DEVICE;
+    }
+  }
+  std::vector<double> A, C, S;
+  source_profile(c.cfg, c.g, A, C, S);
+  const size_t ns = A.size() * sizeof(double);
+  hipError_t he = hipMemcpyAsync(c.srcA, A.data(), ns, hipMemcpyHostToDevice, c.stream);
+  if (he == hipSuccess) he = hipMemcpyAsync(c.srcC, C.data(), ns, hipMemcpyHostToDevice, c.stream);
+  if (he == hipSuccess) he = hipMemcpyAsync(c.srcS, S.data(), ns, hipMemcpyHostToDevice, c.stream);
+  if (he == hipSuccess) {
+    launch_init_electrons(c, c.stream);
+    he = hipGetLastError();
+  }
+  if (he == hipSuccess) he = hipStreamSynchronize(c.stream);
+  if (he != hipSuccess) {
+    g_create_err = std::string("initialisation: ") + hipGetErrorString(he);
+    delete ctx;
+    return PIC_ERR_DEVICE;
+  }
+  *out = ctx;
+  return PIC_OK;
+}
+
+void pic_destroy(pic_ctx* ctx) {
+  if (!ctx) return;
+  if (!ctx->c.broken) (void)hipStreamSynchronize(ctx->c.stream);
+  delete ctx;
+}
+
+pic_status pic_load_tables(pic_ctx* ctx, const pic_tables* t) {
+  pic_status st = check_ctx(ctx);
+  if (st) return st;
+  Ctx& c = ctx->c;
+  if (!t) FAIL(c, PIC_ERR_INVALID, "null tables");
+  if (t->version != PIC_TABLES_VERSION) FAIL(c, PIC_ERR_TABLES, "tables version %u != %u", t->version, PIC_TABLES_VERSION);
+  if (t->Z != c.cfg.Z) FAIL(c, PIC_ERR_TABLES, "tables built for Z=%u, config has Z=%u", t->Z, c.cfg.Z);
+  if (t->n_eta != 256 || t->n_xi != 256 || t->n_T != 128 || t->n_y != 64)
+    FAIL(c, PIC_ERR_TABLES, "table sizes must be 256x256 (NCS) and 128x64 (brem)");
+  if (!t->h || !t->ln_xi || !t->ncs_cdf || !t->sigma || !t->br_cdf) FAIL(c, PIC_ERR_TABLES, "null table array");
+  if (!(t->k_cut_mc2 > 0.0) || !is_fin(t->k_cut_mc2)) FAIL(c, PIC_ERR_TABLES, "k_cut must be > 0");
+  if (!(t->dln_eta > 0.0) || !(t->dln_T > 0.0) || !is_fin(t->ln_eta0) || !is_fin(t->ln_T0))
+    FAIL(c, PIC_ERR_TABLES, "bad table grid");
+  for (int i = 0; i < t->n_eta; ++i)
+    if (!(t->h[i] >= 0.0) || !is_fin(t->h[i])) FAIL(c, PIC_ERR_TABLES, "h[%d] invalid", i);
+  for (int j = 0; j < t->n_xi; ++j) {
+    if (!is_fin(t->ln_xi[j]) || (j > 0 && !(t->ln_xi[j] > t->ln_xi[j - 1])))
+      FAIL(c, PIC_ERR_TABLES, "ln_xi must be finite and increasing");
+  }
+  for (int i = 0; i < t->n_eta; ++i) {
+    const double* r = t->ncs_cdf + (size_t)i * t->n_xi;
+    if (!(r[0] > 0.0) || r[t->n_xi - 1] != 1.0) FAIL(c, PIC_ERR_TABLES, "NCS CDF row %d must start > 0 and end at 1", i);
+    for (int j = 1; j < t->n_xi; ++j)
+      if (!(r[j] >= r[j - 1]) || !is_fin(r[j])) FAIL(c, PIC_ERR_TABLES, "NCS CDF row %d not monotone", i);
+  }
+  for (int i = 0; i < t->n_T; ++i) {
+    if (!(t->sigma[i] >= 0.0) || !is_fin(t->sigma[i])) FAIL(c, PIC_ERR_TABLES, "sigma[%d] invalid", i);
+    const double* r = t->br_cdf + (size_t)i * t->n_y;
+    if (r[0] != 0.0 || r[t->n_y - 1] != 1.0) FAIL(c, PIC_ERR_TABLES, "brem CDF row %d must run 0..1", i);
+    for (int j = 1; j < t->n_y; ++j)
+      if (!(r[j] >= r[j - 1]) || !is_fin(r[j])) FAIL(c, PIC_ERR_TABLES, "brem CDF row %d not monotone", i);
+  }
+  DevTables& d = c.t;
+  auto upload = [&](double** dd, float** df, const double* src, size_t n) -> hipError_t {
+    if (!*dd) {
+      hipError_t e = hipMalloc((void**)dd, n * 8);
+      if (e != hipSuccess) return e;
+      c.allocs.push_back(*dd);
+      e = hipMalloc((void**)df, n * 4);
+      if (e != hipSuccess) return e;
+      c.allocs.push_back(*df);
+    }
+    std::vector<float> f(n);
+    for (size_t i = 0; i < n; ++i) f[i] = (float)src[i];
+    hipError_t e = hipMemcpy(*dd, src, n * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(*df, f.data(), n * 4, hipMemcpyHostToDevice);
+    return e;
+  };
+  HIPCHK(c, hipStreamSynchronize(c.stream));
+  HIPCHK(c, upload(&d.h, &d.hf, t->h, t->n_eta));
+  HIPCHK(c, upload(&d.lnxi, &d.lnxif, t->ln_xi, t->n_xi));
+  HIPCHK(c, upload(&d.ncs, &d.ncsf, t->ncs_cdf, (size_t)t->n_eta * t->n_xi));
+  HIPCHK(c, upload(&d.sig, &d.sigf, t->sigma, t->n_T));
+  HIPCHK(c, upload(&d.br, &d.brf, t->br_cdf, (size_t)t->n_T * t->n_y));
+  d.n_eta = t->n_eta; d.n_xi = t->n_xi; d.n_T = t->n_T; d.n_y = t->n_y;
+  d.ln_eta0 = t->ln_eta0; d.idln_eta = 1.0 / t->dln_eta;
+  d.ln_T0 = t->ln_T0; d.idln_T = 1.0 / t->dln_T;
+  d.k_cut = t->k_cut_mc2; d.lnk = log(t->k_cut_mc2); d.iny1 = 1.0 / (double)(t->n_y - 1);
+  c.tables_loaded = true;
+  return PIC_OK;
+}
+
+pic_status pic_step(pic_ctx* ctx, int32_t nsteps) {
+  pic_status st = check_ctx(ctx);
+  if (st) return st;
+  Ctx& c = ctx->c;
+  if (nsteps < 0) FAIL(c, PIC_ERR_INVALID, "nsteps < 0");
+  if ((c.cfg.flags & (PIC_NCS | PIC_BREM)) && !c.tables_loaded)
+    FAIL(c, PIC_ERR_STATE, "emission enabled but no tables loaded");
+  if (c.step + (uint64_t)nsteps >= 0xFFFFFFFFull) FAIL(c, PIC_ERR_INVALID, "step counter exhausted");
+  const bool frozen = (c.cfg.flags & PIC_FIELDS_FROZEN) != 0;
+  auto mark = [&](int kind) {
+    if (!c.prof) return;
+    hipEvent_t ev = c.prof_event();
+    if (ev) {
+      c.ev_kind.push_back(kind);
+      (void)hipEventRecord(ev, c.stream);
+    }
+  };
+  for (int32_t it = 0; it < nsteps; ++it) {
+    mark(1);
+    if (!frozen) launch_b_half_zero(c, c.stream);  // B^{n-1/2} -> B^n, J <- 0
+    mark(1);
+    mark(0);
+    if (c.fp32) {
+      StepParams<float> P{};
+      fill_step_params(c, P);
+      launch_step(c.g.dims, true, &P, c.stream);
+    } else {
+      StepParams<double> P{};
+      fill_step_params(c, P);
+      launch_step(c.g.dims, false, &P, c.stream);
+    }
+    mark(0);
+    mark(1);
+    if (!frozen) {
+      double ls, lc;
+      laser_scalars(c, c.step, &ls, &lc);
+      launch_b_half(c, c.stream);                  // B^n -> B^{n+1/2}
+      launch_e_full(c, ls, lc, c.stream);          // E^n -> E^{n+1}
+    }
+    mark(1);
+    c.step++;
+  }
+  HIPCHK(c, hipGetLastError());
+  return PIC_OK;
+}
+
+pic_status pic_emission_stats(pic_ctx* ctx, pic_stats* out) {
+  pic_status st = check_ctx(ctx);
+  if (st) return st;
+  Ctx& c = ctx->c;
+  if (!out) FAIL(c, PIC_ERR_INVALID, "null output");
+  unsigned long long cnt[kSlotCnt + 1];
+  double sum[5];
+  unsigned long long pcount = 0;
+  launch_stats_reduce(c, cnt, sum, nullptr, nullptr, nullptr, c.stream);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipMemcpyAsync(&pcount, c.pcount, 8, hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(c, hipStreamSynchronize(c.stream));
+  pic_stats s{};
+  s.steps = c.step;
+  s.electrons_live = cnt[kSlotCnt];
+  s.electron_steps = cnt[SC_ESTEPS];
+  s.events[0] = cnt[SC_EV_NCS];
+  s.events[1] = cnt[SC_EV_BR];
+  s.kept[0] = cnt[SC_KEPT_NCS];
+  s.kept[1] = cnt[SC_KEPT_BR];
+  s.dropped_ncs = cnt[SC_DROPPED];
+  s.brem_clamped = cnt[SC_CLAMPED];
+  s.photons_stored = pcount < c.pcap ? pcount : c.pcap;
+  s.overflow = pcount > c.pcap ? pcount - c.pcap : 0;
+  s.e_rad_kept[0] = sum[0];
+  s.e_rad_kept[1] = sum[1];
+  s.e_rad_dropped = sum[2];
+  s.e_kin_e = sum[3];
+  s.e_field = 0.5 * sum[4] * (1.0 / c.g.invV);
+  *out = s;
+  return s.overflow ? PIC_ERR_OVERFLOW : PIC_OK;
+}
+
+pic_status pic_counts(pic_ctx* ctx, uint64_t* electrons, uint64_t* stored, uint64_t* kept) {
+  pic_status st = check_ctx(ctx);
+  if (st) return st;
+  Ctx& c = ctx->c;
+  unsigned long long pc = 0;
+  HIPCHK(c, hipMemcpyAsync(&pc, c.pcount, 8, hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(c, hipStreamSynchronize(c.stream));
+  if (electrons) *electrons = (uint64_t)c.N;
+  if (stored) *stored = pc < c.pcap ? pc : c.pcap;
+  if (kept) *kept = pc;
+  return PIC_OK;
+}
+
+
+pic_status pic_copy_electrons(pic_ctx* ctx, double* x, double* p, double* tau, double* w,
+                              uint32_t* id, uint8_t* alive) {
+  pic_status st = check_ctx(ctx);
+  if (st) return st;
+  Ctx& c = ctx->c;
+  const size_t N = (size_t)c.N;
+  std::vector<uint32_t> ids(N);
+  if (N) {
+    HIPCHK(c, hipMemcpyAsync(ids.data(), c.id, N * 4, hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(c, hipStreamSynchronize(c.stream));
+  }
+  std::vector<double> v, t8(N), w8(N);
+  for (int a = 0; a < 3; ++a) {
+    if (x) {
+      if (a < c.g.dims) {
+        if ((st = copy_any(c, c.x[a], N, v))) return st;
+      } else {
+        v.assign(N, 0.0);
+      }
+      for (size_t e = 0; e < N; ++e) x[3 * (ids[e] & ~kDead) + a] = v[e];
+    }
+    if (p) {
+      if ((st = copy_any(c, c.p[a], N, v))) return st;
+      for (size_t e = 0; e < N; ++e) p[3 * (ids[e] & ~kDead) + a] = v[e];
+    }
+  }
+  if (N) {
+    HIPCHK(c, hipMemcpyAsync(t8.data(), c.tau, N * 8, hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(c, hipMemcpyAsync(w8.data(), c.w, N * 8, hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(c, hipStreamSynchronize(c.stream));
+  }
+  for (size_t e = 0; e < N; ++e) {
+    const uint32_t i = ids[e] & ~kDead;
+    if (tau) tau[i] = t8[e];
+    if (w) w[i] = w8[e];
+    if (id) id[i] = i;
+    if (alive) alive[i] = (ids[e] & kDead) ? 0 : 1;
+  }
+  return PIC_OK;
+}
+
+pic_status pic_set_electrons(pic_ctx* ctx, const double* x, const double* p, const double* tau) {
+  pic_status st = check_ctx(ctx);
+  if (st) return st;
+  Ctx& c = ctx->c;
+  if (!x || !p || !tau) FAIL(c, PIC_ERR_INVALID, "null argument");
+  const size_t N = (size_t)c.N;
+  if (!N) return PIC_OK;
+  std::vector<uint32_t> ids(N);
+  HIPCHK(c, hipMemcpyAsync(ids.data(), c.id, N * 4, hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(c, hipStreamSynchronize(c.stream));
+  for (size_t e = 0; e < N; ++e) {
+    for (int a = 0; a < 3; ++a)
+      if (!is_fin(x[3 * e + a]) || !is_fin(p[3 * e + a])) FAIL(c, PIC_ERR_INVALID, "non-finite electron state");
+    if (!is_fin(tau[e])) FAIL(c, PIC_ERR_INVALID, "non-finite optical depth");
+    // the gather and deposit stencils assume every live electron is inside the box
+    for (int a = 0; a < c.g.dims; ++a)
+      if (!(x[3 * e + a] >= 0.0 && x[3 * e + a] < c.g.L[a]))
+        FAIL(c, PIC_ERR_INVALID, "electron %zu outside the box on axis %d", e, a);
+  }
+  auto put = [&](void* dev, const double* src, int stride, int a) -> pic_status {
+    if (c.fp32) {
+      std::vector<float> f(N);
+      for (size_t e = 0; e < N; ++e) f[e] = (float)src[(size_t)stride * (ids[e] & ~kDead) + a];
+      HIPCHK(c, hipMemcpyAsync(dev, f.data(), N * 4, hipMemcpyHostToDevice, c.stream));
+      HIPCHK(c, hipStreamSynchronize(c.stream));
+    } else {
+      std::vector<double> d(N);
+      for (size_t e = 0; e < N; ++e) d[e] = src[(size_t)stride * (ids[e] & ~kDead) + a];
+      HIPCHK(c, hipMemcpyAsync(dev, d.data(), N * 8, hipMemcpyHostToDevice, c.stream));
+      HIPCHK(c, hipStreamSynchronize(c.stream));
+    }
+    return PIC_OK;
+  };
+  for (int a = 0; a < 3; ++a) {
+    if (a < c.g.dims && (st = put(c.x[a], x, 3, a))) return st;
+    if ((st = put(c.p[a], p, 3, a))) return st;
+  }
+  std::vector<double> t8(N);
+  for (size_t e = 0; e < N; ++e) t8[e] = tau[ids[e] & ~kDead];
+  HIPCHK(c, hipMemcpyAsync(c.tau, t8.data(), N * 8, hipMemcpyHostToDevice, c.stream));
+  HIPCHK(c, hipStreamSynchronize(c.stream));
+  return PIC_OK;
+}
+
+pic_status pic_copy_photons(pic_ctx* ctx, uint64_t off, uint64_t n, double* x, double* k,
+                            double* eps, double* w, uint32_t* step, uint32_t* parent,
+                            uint32_t* proc) {
+  pic_status st = check_ctx(ctx);
+  if (st) return st;
+  Ctx& c = ctx->c;
+  uint64_t stored = 0;
+  if ((st = pic_counts(ctx, nullptr, &stored, nullptr))) return st;
+  if (off > stored || n > stored - off) FAIL(c, PIC_ERR_INVALID, "photon range [%llu, +%llu) beyond %llu stored",
+                                             (unsigned long long)off, (unsigned long long)n, (unsigned long long)stored);
+  if (n == 0) return PIC_OK;
+  const size_t rs = c.fp32 ? 4 : 8;
+  std::vector<double> v;
+  for (int a = 0; a < 3; ++a) {
+    if (x) {
+      if ((st = copy_any(c, (const char*)c.px[a] + off * rs, n, v))) return st;
+      for (uint64_t i = 0; i < n; ++i) x[3 * i + a] = v[i];
+    }
+    if (k) {
+      if ((st = copy_any(c, (const char*)c.pk[a] + off * rs, n, v))) return st;
+      for (uint64_t i = 0; i < n; ++i) k[3 * i + a] = v[i];
+    }
+  }
+  if (eps) {
+    if ((st = copy_any(c, (const char*)c.pe + off * rs, n, v))) return st;
+    memcpy(eps, v.data(), n * 8);
+  }
+  if (w) HIPCHK(c, hipMemcpyAsync(w, c.pw + off, n * 8, hipMemcpyDeviceToHost, c.stream));
+  if (step) HIPCHK(c, hipMemcpyAsync(step, c.pstep + off, n * 4, hipMemcpyDeviceToHost, c.stream));
+  if (parent) HIPCHK(c, hipMemcpyAsync(parent, c.ppar + off, n * 4, hipMemcpyDeviceToHost, c.stream));
+  if (proc) HIPCHK(c, hipMemcpyAsync(proc, c.pproc + off, n * 4, hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(c, hipStreamSynchronize(c.stream));
+  return PIC_OK;
+}
+
+pic_status pic_field_size(pic_ctx* ctx, uint64_t* size) {
+  pic_status st = check_ctx(ctx);
+  if (st) return st;
+  if (!size) return PIC_ERR_INVALID;
+  *size = (uint64_t)ctx->c.g.nfield;
+  return PIC_OK;
+}
+
+pic_status pic_copy_fields(pic_ctx* ctx, double* out) {
+  pic_status st = check_ctx(ctx);
+  if (st) return st;
+  Ctx& c = ctx->c;
+  if (!out) FAIL(c, PIC_ERR_INVALID, "null output");
+  const size_t nf = (size_t)c.g.nfield;
+  std::vector<double> v;
+  for (int a = 0; a < 3; ++a) {
+    if ((st = copy_any(c, c.E[a], nf, v))) return st;
+    memcpy(out + (size_t)a * nf, v.data(), nf * 8);
+    if ((st = copy_any(c, c.B[a], nf, v))) return st;
+    memcpy(out + (size_t)(3 + a) * nf, v.data(), nf * 8);
+  }
+  return PIC_OK;
+}
+
+pic_status pic_profile(pic_ctx* ctx, int32_t enable) {
+  pic_status st = check_ctx(ctx);
+  if (st) return st;
+  Ctx& c = ctx->c;
+  HIPCHK(c, hipStreamSynchronize(c.stream));
+  c.prof = enable != 0;
+  c.ev_used = 0;
+  c.ev_kind.clear();
+  return PIC_OK;
+}
+
+pic_status pic_profile_read(pic_ctx* ctx, double* ms2, uint64_t* n2) {
+  pic_status st = check_ctx(ctx);
+  if (st) return st;
+  Ctx& c = ctx->c;
+  if (!ms2 || !n2) FAIL(c, PIC_ERR_INVALID, "null output");
+  HIPCHK(c, hipStreamSynchronize(c.stream));
+  ms2[0] = ms2[1] = 0.0;
+  n2[0] = n2[1] = 0;
+  for (size_t i = 0; i + 1 < c.ev_used; i += 2) {
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, c.ev_pool[i], c.ev_pool[i + 1]));
+    const int k = c.ev_kind[i];
+    ms2[k] += ms;
+    n2[k] += 1;
+  }
+  return PIC_OK;
+}
+
+pic_status pic_copy_current(pic_ctx* ctx, int64_t* out) {
+  pic_status st = check_ctx(ctx);
+  if (st) return st;
+  Ctx& c = ctx->c;
+  if (!out) FAIL(c, PIC_ERR_INVALID, "null output");
+  const size_t nf = (size_t)c.g.nfield;
+  for (int a = 0; a < 3; ++a)
+    HIPCHK(c, hipMemcpyAsync(out + (size_t)a * nf, c.J[a], nf * 8, hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(c, hipStreamSynchronize(c.stream));
+  return PIC_OK;
+}
+
+pic_status pic_derived(pic_ctx* ctx, double* o) {
+  pic_status st = check_ctx(ctx);
+  if (st) return st;
+  if (!o) return PIC_ERR_INVALID;
+  const Ctx& c = ctx->c;
+  o[0] = c.g.dx[0]; o[1] = c.g.dx[1]; o[2] = c.g.dx[2]; o[3] = c.g.dt;
+  o[4] = c.E_S; o[5] = c.K_N; o[6] = c.K_BR; o[7] = c.n_c;
+  return PIC_OK;
+}
+
+pic_status pic_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, uint64_t n) {
+  if (!ctr || !key || !out) return PIC_ERR_INVALID;
+  if (n == 0) return PIC_OK;
+  if (n > (1ull << 28)) return PIC_ERR_INVALID;
+  uint32_t *dc = nullptr, *doo = nullptr;
+  if (hipMalloc(&dc, n * 16) != hipSuccess) return PIC_ERR_NOMEM;
+  if (hipMalloc(&doo, n * 16) != hipSuccess) {
+    (void)!hipFree(dc);
+    return PIC_ERR_NOMEM;
+  }
+  hipError_t e = hipMemcpy(dc, ctr, n * 16, hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    launch_philox(dc, key[0], key[1], doo, n, nullptr);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpy(out, doo, n * 16, hipMemcpyDeviceToHost);
+  (void)!hipFree(dc);
+  (void)!hipFree(doo);
+  return e == hipSuccess ? PIC_OK : PIC_ERR_DEVICE;
+}
+
+}  // extern "C"

@@ -1,0 +1,415 @@
+// Supporting kernels: Yee field solve (B half step, E full step with
+// first-order Mur faces), the current-sheet laser source, electron and ion
+// loading, and the fixed-order reductions behind pic_emission_stats.
+#include "pic_internal.hpp"
+#include "philox.hpp"
+
+namespace pic {
+
+struct FieldArgs {
+  int n[3], act[3], gg[3], sz[3];
+  double hd[3], cd[3], cm[3], dt, srcfac;
+  int i_src, nsrc_y;
+  int64_t nfield;
+};
+
+static FieldArgs field_args(const Grid& g) {
+  FieldArgs a{};
+  for (int d = 0; d < 3; ++d) {
+    a.n[d] = g.n[d]; a.act[d] = g.act[d]; a.gg[d] = g.gg[d]; a.sz[d] = g.sz[d];
+    a.hd[d] = g.hd[d]; a.cd[d] = g.cd[d]; a.cm[d] = g.cm[d];
+  }
+  a.dt = g.dt;
+  a.srcfac = -2.0 / g.dx[0];
+  a.i_src = g.i_src;
+  a.nsrc_y = g.nsrc_y;
+  a.nfield = g.nfield;
+  return a;
+}
+
+__device__ inline int64_t fidx(const FieldArgs& A, int i, int j, int k) {
+  return (int64_t)(i + A.gg[0]) + (int64_t)A.sz[0] * ((int64_t)(j + A.gg[1]) + (int64_t)A.sz[1] * (int64_t)(k + A.gg[2]));
+}
+
+__device__ inline void decode(const FieldArgs& A, int64_t m, int& i, int& j, int& k) {
+  i = (int)(m % A.sz[0]) - A.gg[0];
+  const int64_t r = m / A.sz[0];
+  j = (int)(r % A.sz[1]) - A.gg[1];
+  k = (int)(r / A.sz[1]) - A.gg[2];
+}
+
+// half-integer stagger of E_c / B_c along axis a
+__device__ inline int estag(int c, int a) { return c == a; }
+__device__ inline int bstag(int c, int a) { return c != a; }
+
+// valid node of component c (isB: magnetic) on the Yee lattice
+__device__ inline bool in_range(const FieldArgs& A, bool isB, int c, int i, int j, int k) {
+  const int ijk[3] = {i, j, k};
+  for (int a = 0; a < 3; ++a) {
+    if (!A.act[a]) { if (ijk[a] != 0) return false; continue; }
+    const bool half = isB ? bstag(c, a) : estag(c, a);
+    const int hi = half ? A.n[a] : A.n[a] + 1;
+    if (ijk[a] < 0 || ijk[a] >= hi) return false;
+  }
+  return true;
+}
+
+// B <- B - (dt/2) curl E on every valid B node; optionally clears J.
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_b_half(FieldArgs A, const R* __restrict__ Ex,
+                                                   const R* __restrict__ Ey, const R* __restrict__ Ez,
+                                                   R* Bx, R* By, R* Bz, unsigned long long* Jx,
+                                                   unsigned long long* Jy, unsigned long long* Jz,
+                                                   int zeroJ) {
+  const int64_t m = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (m >= A.nfield) return;
+  if (zeroJ) { Jx[m] = 0ull; Jy[m] = 0ull; Jz[m] = 0ull; }
+  int i, j, k;
+  decode(A, m, i, j, k);
+  if (in_range(A, true, 0, i, j, k)) {  // dBx/dt = -dEz/dy + dEy/dz
+    R b = Bx[m];
+    if (A.act[1]) b = b - R(A.hd[1]) * (Ez[fidx(A, i, j + 1, k)] - Ez[m]);
+    if (A.act[2]) b = b + R(A.hd[2]) * (Ey[fidx(A, i, j, k + 1)] - Ey[m]);
+    Bx[m] = b;
+  }
+  if (in_range(A, true, 1, i, j, k)) {  // dBy/dt = -dEx/dz + dEz/dx
+    R b = By[m];
+    if (A.act[2]) b = b - R(A.hd[2]) * (Ex[fidx(A, i, j, k + 1)] - Ex[m]);
+    b = b + R(A.hd[0]) * (Ez[fidx(A, i + 1, j, k)] - Ez[m]);
+    By[m] = b;
+  }
+  if (in_range(A, true, 2, i, j, k)) {  // dBz/dt = -dEy/dx + dEx/dy
+    R b = Bz[m];
+    b = b - R(A.hd[0]) * (Ey[fidx(A, i + 1, j, k)] - Ey[m]);
+    if (A.act[1]) b = b + R(A.hd[1]) * (Ex[fidx(A, i, j + 1, k)] - Ex[m]);
+    Bz[m] = b;
+  }
+}
+
+struct EPtrs {
+  const void* E[3];
+  void* En[3];
+  const void* B[3];
+  const unsigned long long* J[3];
+  const double *srcA, *srcC, *srcS;
+};
+
+// Ampere update of E_c at an interior node (old E, B^{n+1/2}, J^{n+1/2}).
+template <class R>
+__device__ inline R e_interior(const FieldArgs& A, const EPtrs& P, int c, int i, int j, int k,
+                               double lsin, double lcos) {
+  const int64_t m = fidx(A, i, j, k);
+  const R* Bx = (const R*)P.B[0];
+  const R* By = (const R*)P.B[1];
+  const R* Bz = (const R*)P.B[2];
+  R e = ((const R*)P.E[c])[m];
+  double jj = (double)(long long)P.J[c][m] * kJInv;
+  if (c == 0) {        // dEx/dt = dBz/dy - dBy/dz - Jx
+    if (A.act[1]) e = e + R(A.cd[1]) * (Bz[m] - Bz[fidx(A, i, j - 1, k)]);
+    if (A.act[2]) e = e - R(A.cd[2]) * (By[m] - By[fidx(A, i, j, k - 1)]);
+  } else if (c == 1) { // dEy/dt = dBx/dz - dBz/dx - Jy
+    if (A.act[2]) e = e + R(A.cd[2]) * (Bx[m] - Bx[fidx(A, i, j, k - 1)]);
+    e = e - R(A.cd[0]) * (Bz[m] - Bz[fidx(A, i - 1, j, k)]);
+    if (i == A.i_src) {
+      const int64_t s = j + (int64_t)A.nsrc_y * k;
+      const double v = lsin * P.srcC[s] + lcos * P.srcS[s];
+      jj = jj + A.srcfac * (P.srcA[s] * v);
+    }
+  } else {             // dEz/dt = dBy/dx - dBx/dy - Jz
+    e = e + R(A.cd[0]) * (By[m] - By[fidx(A, i - 1, j, k)]);
+    if (A.act[1]) e = e - R(A.cd[1]) * (Bx[m] - Bx[fidx(A, i, j - 1, k)]);
+  }
+  return e - R(A.dt * jj);
+}
+
+// E^{n+1} into En: interior nodes by Ampere, tangential face nodes by Mur
+// (the interior neighbour's new value is recomputed here, bit-identically),
+// edge/corner nodes and guards 0.
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_e_full(FieldArgs A, EPtrs P, double lsin, double lcos) {
+  const int64_t m = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int c = blockIdx.y;
+  if (m >= A.nfield) return;
+  int i, j, k;
+  decode(A, m, i, j, k);
+  R* Fn = (R*)P.En[c];
+  const R* Fo = (const R*)P.E[c];
+  if (!in_range(A, false, c, i, j, k)) { Fn[m] = R(0); return; }
+  const int ijk[3] = {i, j, k};
+  int nb = 0, ax = -1;
+  for (int a = 0; a < 3; ++a)
+    if (A.act[a] && !estag(c, a) && (ijk[a] == 0 || ijk[a] == A.n[a])) { ++nb; ax = a; }
+  if (nb == 0) { Fn[m] = e_interior<R>(A, P, c, i, j, k, lsin, lcos); return; }
+  if (nb > 1) { Fn[m] = R(0); return; }
+  int in[3] = {i, j, k};
+  in[ax] += (ijk[ax] == 0) ? 1 : -1;
+  const int64_t mi = fidx(A, in[0], in[1], in[2]);
+  const R fin = e_interior<R>(A, P, c, in[0], in[1], in[2], lsin, lcos);
+  Fn[m] = Fo[mi] + R(A.cm[ax]) * (fin - Fo[m]);
+}
+
+void launch_b_half_impl(const Ctx& c, int zeroJ, hipStream_t s) {
+  const FieldArgs A = field_args(c.g);
+  const unsigned blocks = (unsigned)((A.nfield + kBlock - 1) / kBlock);
+  if (c.fp32)
+    hipLaunchKernelGGL(k_b_half<float>, dim3(blocks), dim3(kBlock), 0, s, A, (const float*)c.E[0],
+                       (const float*)c.E[1], (const float*)c.E[2], (float*)c.B[0], (float*)c.B[1],
+                       (float*)c.B[2], c.J[0], c.J[1], c.J[2], zeroJ);
+  else
+    hipLaunchKernelGGL(k_b_half<double>, dim3(blocks), dim3(kBlock), 0, s, A, (const double*)c.E[0],
+                       (const double*)c.E[1], (const double*)c.E[2], (double*)c.B[0], (double*)c.B[1],
+                       (double*)c.B[2], c.J[0], c.J[1], c.J[2], zeroJ);
+}
+
+void launch_b_half(const Ctx& c, hipStream_t s) { launch_b_half_impl(c, 0, s); }
+void launch_b_half_zero(const Ctx& c, hipStream_t s) { launch_b_half_impl(c, 1, s); }
+
+void launch_e_full(Ctx& c, double lsin, double lcos, hipStream_t s) {
+  const FieldArgs A = field_args(c.g);
+  EPtrs P{};
+  for (int d = 0; d < 3; ++d) {
+    P.E[d] = c.E[d]; P.En[d] = c.En[d]; P.B[d] = c.B[d]; P.J[d] = c.J[d];
+  }
+  P.srcA = c.srcA; P.srcC = c.srcC; P.srcS = c.srcS;
+  const unsigned blocks = (unsigned)((A.nfield + kBlock - 1) / kBlock);
+  if (c.fp32)
+    hipLaunchKernelGGL(k_e_full<float>, dim3(blocks, 3), dim3(kBlock), 0, s, A, P, lsin, lcos);
+  else
+    hipLaunchKernelGGL(k_e_full<double>, dim3(blocks, 3), dim3(kBlock), 0, s, A, P, lsin, lcos);
+  for (int d = 0; d < 3; ++d) { void* t = c.E[d]; c.E[d] = c.En[d]; c.En[d] = t; }
+}
+
+// ---- loading ----------------------------------------------------------------
+struct InitArgs {
+  int64_t N;
+  int dims, ppc, nslab, i0, ny;
+  double dx[3], wgt;
+  uint32_t key0, key1;
+  void* x[3];
+  void* p[3];
+  double* tau;
+  double* w;
+  uint32_t* id;
+  double* ni;
+  int64_t ncell;
+  int nx, nyc;
+  double nion;
+  int i1;
+};
+
+// Electron e of the slab cell with rank e/ppc; cold, uniform in the cell;
+// tau_0 = -ln u (Philox counter (id, 0xFFFFFFFF, 0, 0)).
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_init_electrons(InitArgs A) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= A.N) return;
+  const int64_t rank = e / A.ppc;
+  const int ii = (int)(rank % A.nslab) + A.i0;
+  const int64_t r2 = rank / A.nslab;
+  const int jj = A.dims >= 2 ? (int)(r2 % A.ny) : 0;
+  const int kk = A.dims >= 3 ? (int)(r2 / A.ny) : 0;
+  const U4 r = philox4x32_10((uint32_t)e, 0xFFFFFFFFu, 0u, 0u, A.key0, A.key1);
+  ((R*)A.x[0])[e] = (R)(((double)ii + unif32(r.v[0])) * A.dx[0]);
+  if (A.dims >= 2) ((R*)A.x[1])[e] = (R)(((double)jj + unif32(r.v[1])) * A.dx[1]);
+  if (A.dims >= 3) ((R*)A.x[2])[e] = (R)(((double)kk + unif32(r.v[2])) * A.dx[2]);
+  for (int a = 0; a < 3; ++a) ((R*)A.p[a])[e] = R(0);
+  A.tau[e] = -log(unif32(r.v[3]));
+  A.w[e] = A.wgt;
+  A.id[e] = (uint32_t)e;
+}
+
+__global__ __launch_bounds__(kBlock) void k_init_ions(InitArgs A) {
+  const int64_t m = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (m >= A.ncell) return;
+  const int i = (int)(m % A.nx);
+  A.ni[m] = (i >= A.i0 && i < A.i1) ? A.nion : 0.0;
+}
+
+void launch_init_electrons(const Ctx& c, hipStream_t s) {
+  InitArgs A{};
+  A.N = c.N;
+  A.dims = c.g.dims;
+  A.ppc = c.cfg.ppc;
+  A.nslab = c.i1 - c.i0;
+  A.i0 = c.i0;
+  A.i1 = c.i1;
+  A.ny = c.g.n[1];
+  for (int d = 0; d < 3; ++d) { A.dx[d] = c.g.dx[d]; A.x[d] = c.x[d]; A.p[d] = c.p[d]; }
+  A.wgt = c.wgt;
+  A.key0 = c.key0; A.key1 = c.key1;
+  A.tau = c.tau; A.w = c.w; A.id = c.id; A.ni = c.ni;
+  A.ncell = (int64_t)c.g.n[0] * c.g.n[1] * c.g.n[2];
+  A.nx = c.g.n[0];
+  A.nion = c.cfg.ne_over_nc / (double)c.cfg.charge_state;
+  if (A.N > 0) {
+    const unsigned blocks = (unsigned)((A.N + kBlock - 1) / kBlock);
+    if (c.fp32) hipLaunchKernelGGL(k_init_electrons<float>, dim3(blocks), dim3(kBlock), 0, s, A);
+    else hipLaunchKernelGGL(k_init_electrons<double>, dim3(blocks), dim3(kBlock), 0, s, A);
+  }
+  const unsigned cb = (unsigned)((A.ncell + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_init_ions, dim3(cb), dim3(kBlock), 0, s, A);
+}
+
+// ---- reductions -------------------------------------------------------------
+constexpr int kRedBlocks = 1024;
+constexpr int kRedThreads = 256;
+
+__device__ inline void neu_add(double& s, double& c, double v) {
+  const double t = s + v;
+  if (fabs(s) >= fabs(v)) c += (s - t) + v;
+  else c += (v - t) + s;
+  s = t;
+}
+
+// fixed-order tree over a block: (s, c) pairs and u64 counters
+template <int NS, int NC>
+__device__ inline void block_reduce(double (&s)[NS], double (&c)[NS], unsigned long long (&n)[NC]) {
+  __shared__ double ss[NS][kRedThreads], sc[NS][kRedThreads];
+  __shared__ unsigned long long sn[NC][kRedThreads];
+  const int t = threadIdx.x;
+  for (int q = 0; q < NS; ++q) { ss[q][t] = s[q]; sc[q][t] = c[q]; }
+  for (int q = 0; q < NC; ++q) sn[q][t] = n[q];
+  __syncthreads();
+  for (int h = kRedThreads / 2; h >= 1; h >>= 1) {
+    if (t < h) {
+      for (int q = 0; q < NS; ++q) {
+        double a = ss[q][t], b = sc[q][t];
+        neu_add(a, b, ss[q][t + h]);
+        b += sc[q][t + h];
+        ss[q][t] = a; sc[q][t] = b;
+      }
+      for (int q = 0; q < NC; ++q) sn[q][t] += sn[q][t + h];
+    }
+    __syncthreads();
+  }
+  for (int q = 0; q < NS; ++q) { s[q] = ss[q][0]; c[q] = sc[q][0]; }
+  for (int q = 0; q < NC; ++q) n[q] = sn[q][0];
+}
+
+// Pass 1: per-block partial sums of the wave slots, the electrons' kinetic
+// energy and live count, and the field energy.  Contiguous chunks per block.
+template <class R>
+__global__ __launch_bounds__(kRedThreads) void k_reduce_partial(
+    const unsigned long long* __restrict__ scnt, const double* __restrict__ ssum, int64_t nslots,
+    const R* px, const R* py, const R* pz, const double* __restrict__ w, const uint32_t* __restrict__ id,
+    int64_t N, const R* E0, const R* E1, const R* E2, const R* B0, const R* B1, const R* B2,
+    int64_t nfield, unsigned long long* out_cnt, double* out_sum) {
+  constexpr int NS = 5;   // kept0, kept1, dropped, e_kin, field
+  constexpr int NC = kSlotCnt + 1;
+  double s[NS] = {0, 0, 0, 0, 0}, c[NS] = {0, 0, 0, 0, 0};
+  unsigned long long n[NC];
+  for (int q = 0; q < NC; ++q) n[q] = 0ull;
+  const int b = blockIdx.x, t = threadIdx.x;
+  // slots
+  {
+    const int64_t per = (nslots + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = (int64_t)b * per, hi = min(nslots, lo + per);
+    for (int64_t q = lo + t; q < hi; q += kRedThreads) {
+      for (int z = 0; z < kSlotCnt; ++z) n[z] += scnt[q * kSlotCnt + z];
+      for (int z = 0; z < 3; ++z) {
+        neu_add(s[z], c[z], ssum[q * kSlotSum + 2 * z]);
+        c[z] += ssum[q * kSlotSum + 2 * z + 1];
+      }
+    }
+  }
+  // electrons
+  {
+    const int64_t per = (N + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = (int64_t)b * per, hi = min(N, lo + per);
+    for (int64_t e = lo + t; e < hi; e += kRedThreads) {
+      if (id[e] & kDead) continue;
+      const double a = (double)px[e], bb = (double)py[e], cc = (double)pz[e];
+      const double g = sqrt(1.0 + (a * a + bb * bb + cc * cc));
+      neu_add(s[3], c[3], w[e] * (g - 1.0));
+      n[kSlotCnt] += 1ull;
+    }
+  }
+  // fields
+  {
+    const int64_t per = (nfield + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = (int64_t)b * per, hi = min(nfield, lo + per);
+    for (int64_t m = lo + t; m < hi; m += kRedThreads) {
+      const double v = (double)E0[m] * (double)E0[m] + (double)E1[m] * (double)E1[m] +
+                       (double)E2[m] * (double)E2[m] + (double)B0[m] * (double)B0[m] +
+                       (double)B1[m] * (double)B1[m] + (double)B2[m] * (double)B2[m];
+      neu_add(s[4], c[4], v);
+    }
+  }
+  block_reduce<NS, NC>(s, c, n);
+  if (t == 0) {
+    for (int q = 0; q < NC; ++q) out_cnt[(int64_t)b * NC + q] = n[q];
+    for (int q = 0; q < NS; ++q) { out_sum[(int64_t)b * 2 * NS + 2 * q] = s[q]; out_sum[(int64_t)b * 2 * NS + 2 * q + 1] = c[q]; }
+  }
+}
+
+// Pass 2: one block folds the partials in block order.
+__global__ __launch_bounds__(kRedThreads) void k_reduce_final(const unsigned long long* in_cnt,
+                                                              const double* in_sum, int nblk,
+                                                              unsigned long long* out_cnt,
+                                                              double* out_sum) {
+  constexpr int NS = 5;
+  constexpr int NC = kSlotCnt + 1;
+  double s[NS] = {0, 0, 0, 0, 0}, c[NS] = {0, 0, 0, 0, 0};
+  unsigned long long n[NC];
+  for (int q = 0; q < NC; ++q) n[q] = 0ull;
+  const int t = threadIdx.x;
+  const int per = (nblk + kRedThreads - 1) / kRedThreads;
+  for (int b = t * per; b < min(nblk, (t + 1) * per); ++b) {
+    for (int q = 0; q < NC; ++q) n[q] += in_cnt[(int64_t)b * NC + q];
+    for (int q = 0; q < NS; ++q) {
+      neu_add(s[q], c[q], in_sum[(int64_t)b * 2 * NS + 2 * q]);
+      c[q] += in_sum[(int64_t)b * 2 * NS + 2 * q + 1];
+    }
+  }
+  block_reduce<NS, NC>(s, c, n);
+  if (t == 0) {
+    for (int q = 0; q < NC; ++q) out_cnt[q] = n[q];
+    for (int q = 0; q < NS; ++q) out_sum[q] = s[q] + c[q];
+  }
+}
+
+int reduce_scratch_cnt() { return kRedBlocks * (kSlotCnt + 1) + (kSlotCnt + 1); }
+int reduce_scratch_sum() { return kRedBlocks * 10 + 5; }
+
+// out_cnt[0..kSlotCnt) slot counters, out_cnt[kSlotCnt] live electrons;
+// out_sum: kept0, kept1, dropped, e_kin, sum(E^2+B^2).
+void launch_stats_reduce(const Ctx& c, unsigned long long* cnt_out, double* sum_out, double*,
+                         double*, unsigned long long*, hipStream_t s) {
+  unsigned long long* pc = c.red_cnt;
+  double* ps = c.red_sum;
+  unsigned long long* fc = pc + kRedBlocks * (kSlotCnt + 1);
+  double* fs = ps + kRedBlocks * 10;
+  if (c.fp32)
+    hipLaunchKernelGGL(k_reduce_partial<float>, dim3(kRedBlocks), dim3(kRedThreads), 0, s,
+                       c.slot_cnt, c.slot_sum, c.nslots, (const float*)c.p[0], (const float*)c.p[1],
+                       (const float*)c.p[2], c.w, c.id, c.N, (const float*)c.E[0],
+                       (const float*)c.E[1], (const float*)c.E[2], (const float*)c.B[0],
+                       (const float*)c.B[1], (const float*)c.B[2], c.g.nfield, pc, ps);
+  else
+    hipLaunchKernelGGL(k_reduce_partial<double>, dim3(kRedBlocks), dim3(kRedThreads), 0, s,
+                       c.slot_cnt, c.slot_sum, c.nslots, (const double*)c.p[0], (const double*)c.p[1],
+                       (const double*)c.p[2], c.w, c.id, c.N, (const double*)c.E[0],
+                       (const double*)c.E[1], (const double*)c.E[2], (const double*)c.B[0],
+                       (const double*)c.B[1], (const double*)c.B[2], c.g.nfield, pc, ps);
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kRedThreads), 0, s, pc, ps, kRedBlocks, fc, fs);
+  hipMemcpyAsync(cnt_out, fc, sizeof(unsigned long long) * (kSlotCnt + 1), hipMemcpyDeviceToHost, s);
+  hipMemcpyAsync(sum_out, fs, sizeof(double) * 5, hipMemcpyDeviceToHost, s);
+}
+
+// ---- Philox exposure -------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_philox(const uint32_t* ctr, uint32_t k0, uint32_t k1,
+                                                   uint32_t* out, uint64_t n) {
+  const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const U4 r = philox4x32_10(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3], k0, k1);
+  for (int q = 0; q < 4; ++q) out[4 * i + q] = r.v[q];
+}
+
+void launch_philox(const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out, uint64_t n,
+                   hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_philox, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, ctr,
+                     k0, k1, out, n);
+}
+
+}  // namespace pic

@@ -1,0 +1,153 @@
+// Internal declarations of libpic: context layout, kernel parameter blocks,
+// launcher prototypes.  gfx950 (CDNA4) only: wave64, 160 KB LDS per CU.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+#include <vector>
+#include "../../include/pic.h"
+
+namespace pic {
+
+constexpr uint32_t kDead = 0x80000000u;   // id bit marking an absorbed electron
+constexpr int kGuard = 2;                 // guard cells per side on active axes
+constexpr int kBlock = 256;               // threads per block (4 waves)
+constexpr int kSlotCnt = 8;               // u64 counters per wave slot
+constexpr int kSlotSum = 6;               // doubles per wave slot (3 Neumaier pairs)
+constexpr double kJScale = 0x1p40;        // current fixed point: units of 2^-40
+constexpr double kJInv = 0x1p-40;
+
+// counter slots
+enum { SC_ESTEPS = 0, SC_EV_NCS, SC_EV_BR, SC_KEPT_NCS, SC_KEPT_BR, SC_DROPPED, SC_CLAMPED, SC_SPARE };
+
+// Geometry shared by the field kernels (grid layout identical in every mode).
+struct Grid {
+  int dims;
+  int n[3], act[3], gg[3], sz[3];
+  double dx[3], idx[3], L[3];
+  double dt, invV;
+  double hd[3], cd[3], cm[3];   // (dt/2)/dx, dt/dx, Mur coefficients
+  int i_src, nsrc_y, nsrc_z;
+  int64_t nfield;               // elements per component
+};
+
+// Emission tables resident on the device (FP64 copy, FP32 copy).
+struct DevTables {
+  int n_eta = 0, n_xi = 0, n_T = 0, n_y = 0;
+  double ln_eta0 = 0, idln_eta = 0, ln_T0 = 0, idln_T = 0, k_cut = 0, lnk = 0, iny1 = 0;
+  double *h = nullptr, *lnxi = nullptr, *ncs = nullptr, *sig = nullptr, *br = nullptr;
+  float *hf = nullptr, *lnxif = nullptr, *ncsf = nullptr, *sigf = nullptr, *brf = nullptr;
+};
+
+// Parameter block of the electron-step kernel (passed by value).
+template <class R>
+struct StepParams {
+  int64_t N;
+  uint32_t step, key0, key1;
+  uint32_t flags, frozen_kind;
+  double dt, tn;
+  // electrons
+  R* x[3];
+  R* p[3];
+  double* tau;
+  const double* w;
+  uint32_t* id;
+  // fields
+  const R* E[3];
+  const R* B[3];
+  unsigned long long* J[3];
+  int n[3], gg[3], sz[3];
+  double idx[3], L[3], dxdt[3], invV;
+  const double* ni;
+  // physics constants
+  double iES, K_N, K_BR, photon_cut;
+  double fE[3], fB[3], fa;
+  // tables
+  int n_eta, n_xi, n_T, n_y;
+  double ln_eta0, idln_eta, ln_T0, idln_T, k_cut, lnk, iny1;
+  const R* h;
+  const R* lnxi;
+  const R* ncs;
+  const R* sig;
+  const R* br;
+  // photons
+  uint64_t pcap;
+  R* px[3];
+  R* pk[3];
+  R* pe;
+  double* pw;
+  uint32_t* pstep;
+  uint32_t* ppar;
+  uint32_t* pproc;
+  unsigned long long* pcount;
+  // stats slots
+  unsigned long long* slot_cnt;
+  double* slot_sum;
+};
+
+void launch_step(int dims, bool fp32, const void* params, hipStream_t s);
+void launch_init_electrons(const struct Ctx& c, hipStream_t s);
+void launch_b_half(const struct Ctx& c, hipStream_t s);
+void launch_e_full(struct Ctx& c, double lsin, double lcos, hipStream_t s);
+void launch_stats_reduce(const struct Ctx& c, unsigned long long* cnt_out, double* sum_out,
+                         double* ekin_out, double* efield_out, unsigned long long* live_out,
+                         hipStream_t s);
+void launch_philox(const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out, uint64_t n,
+                   hipStream_t s);
+
+// Context: everything one run owns.
+struct Ctx {
+  pic_config cfg{};
+  std::string err;
+  bool broken = false;
+  bool fp32 = false;
+  hipStream_t stream = nullptr;
+  Grid g{};
+  double E_S = 0, iES = 0, K_N = 0, K_BR = 0, n_c = 0;
+  uint32_t key0 = 0, key1 = 0;
+  uint64_t step = 0;
+  int64_t N = 0;            // electrons loaded
+  int i0 = 0, i1 = 0;       // slab cells [i0, i1)
+  double wgt = 0;           // electron weight
+  // device memory (one arena of allocations, freed in ~Ctx)
+  void* E[3] = {};
+  void* En[3] = {};
+  void* B[3] = {};
+  unsigned long long* J[3] = {};
+  double* ni = nullptr;
+  double* srcA = nullptr;
+  double* srcC = nullptr;
+  double* srcS = nullptr;
+  void* x[3] = {};
+  void* p[3] = {};
+  double* tau = nullptr;
+  double* w = nullptr;
+  uint32_t* id = nullptr;
+  uint64_t pcap = 0;
+  void* px[3] = {};
+  void* pk[3] = {};
+  void* pe = nullptr;
+  double* pw = nullptr;
+  uint32_t* pstep = nullptr;
+  uint32_t* ppar = nullptr;
+  uint32_t* pproc = nullptr;
+  unsigned long long* pcount = nullptr;
+  int64_t nslots = 0;
+  unsigned long long* slot_cnt = nullptr;
+  double* slot_sum = nullptr;
+  // reduction scratch
+  unsigned long long* red_cnt = nullptr;
+  double* red_sum = nullptr;
+  bool tables_loaded = false;
+  // optional kernel timing (pairs of events per launch group)
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<int> ev_kind;   // 0 electron step, 1 field solve
+  size_t ev_used = 0;
+  DevTables t{};
+  std::vector<void*> allocs;
+  ~Ctx();
+  hipEvent_t prof_event();
+};
+
+}  // namespace pic

@@ -1,0 +1,509 @@
+// The per-electron step on gfx950: one thread per electron, wave64.
+//
+// Per electron, in the order of the method (Wan et al., Sec. II):
+//   Philox draw keyed by (id, step) -> gather E^n, B^n -> Boris push ->
+//   eta -> NCS optical-depth decrement and inverse-CDF photon draw ->
+//   bremsstrahlung test of Eq. (4) against the cell's ion density and the
+//   R2 photon-energy draw -> recoil -> photon append -> move -> current deposit.
+// Photon append: one ballot per process and wave, one atomic per wave on the
+// photon counter, lane offsets from mbcnt (no per-lane atomics).
+// Statistics: per-wave slots (exact u64 counts, FP64 Neumaier pairs), reduced
+// in a fixed order on demand.
+// Current: each contribution rounded to 2^-40 and added as a 64-bit integer,
+// so the sum is independent of the order electrons are visited in.
+//
+// The FP64 instantiation evaluates every expression in the same order as the
+// written method (no contraction: built with -ffp-contract=off).  The FP32
+// instantiation keeps the optical depth, weights, the 52-bit brem draw
+// comparison and the energy sums in FP64.
+#include "pic_internal.hpp"
+#include "philox.hpp"
+
+namespace pic {
+
+__device__ inline double m_sqrt(double v) { return sqrt(v); }
+__device__ inline float m_sqrt(float v) { return sqrtf(v); }
+__device__ inline double m_log(double v) { return log(v); }
+__device__ inline float m_log(float v) { return logf(v); }
+__device__ inline double m_exp(double v) { return exp(v); }
+__device__ inline float m_exp(float v) { return expf(v); }
+__device__ inline double m_expm1(double v) { return expm1(v); }
+__device__ inline float m_expm1(float v) { return expm1f(v); }
+__device__ inline double m_floor(double v) { return floor(v); }
+__device__ inline float m_floor(float v) { return floorf(v); }
+__device__ inline double m_sin(double v) { return sin(v); }
+__device__ inline float m_sin(float v) { return sinf(v); }
+
+template <class R>
+__device__ inline R unif(uint32_t r);
+template <>
+__device__ inline double unif<double>(uint32_t r) { return unif32(r); }
+template <>
+__device__ inline float unif<float>(uint32_t r) { return unif24f(r); }
+
+template <class R>
+struct Idx {
+  int gg0, gg1, gg2, sz0, sz1;
+  __device__ inline int64_t operator()(int i, int j, int k) const {
+    return (int64_t)(i + gg0) + (int64_t)sz0 * ((int64_t)(j + gg1) + (int64_t)sz1 * (int64_t)(k + gg2));
+  }
+};
+
+// Linear interpolation of one Yee component (stagger S* = 1: half-integer).
+template <class R, int D, int SX, int SY, int SZ>
+__device__ inline R gather(const R* __restrict__ F, const R* g, const Idx<R>& I) {
+  int i0 = 0, i1 = 0, i2 = 0;
+  R f0 = R(0), f1 = R(0), f2 = R(0);
+  {
+    const R ga = g[0] - R(0.5) * R(SX);
+    const R fl = m_floor(ga);
+    i0 = (int)fl;
+    f0 = ga - fl;
+  }
+  if (D == 1) return (R(1) - f0) * F[I(i0, 0, 0)] + f0 * F[I(i0 + 1, 0, 0)];
+  {
+    const R ga = g[1] - R(0.5) * R(SY);
+    const R fl = m_floor(ga);
+    i1 = (int)fl;
+    f1 = ga - fl;
+  }
+  if (D == 3) {
+    const R ga = g[2] - R(0.5) * R(SZ);
+    const R fl = m_floor(ga);
+    i2 = (int)fl;
+    f2 = ga - fl;
+  }
+  const R v0 = (R(1) - f0) * F[I(i0, i1, i2)] + f0 * F[I(i0 + 1, i1, i2)];
+  const R v1 = (R(1) - f0) * F[I(i0, i1 + 1, i2)] + f0 * F[I(i0 + 1, i1 + 1, i2)];
+  const R a2 = (R(1) - f1) * v0 + f1 * v1;
+  if (D == 2) return a2;
+  const R w0 = (R(1) - f0) * F[I(i0, i1, i2 + 1)] + f0 * F[I(i0 + 1, i1, i2 + 1)];
+  const R w1 = (R(1) - f0) * F[I(i0, i1 + 1, i2 + 1)] + f0 * F[I(i0 + 1, i1 + 1, i2 + 1)];
+  const R b2 = (R(1) - f1) * w0 + f1 * w1;
+  return (R(1) - f2) * a2 + f2 * b2;
+}
+
+// Inverse of one NCS cumulative row: ln(xi) at uniform u.
+template <class R>
+__device__ inline R ncs_inverse(const R* __restrict__ C, const R* __restrict__ lnxi, int n, R u) {
+  if (u < C[0]) return lnxi[0] + R(3) * m_log(u / C[0]);
+  int lo = 0, hi = n - 1;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (C[mid] <= u) lo = mid; else hi = mid;
+  }
+  const R t = (u - C[lo]) / (C[lo + 1] - C[lo]);
+  return lnxi[lo] + t * (lnxi[lo + 1] - lnxi[lo]);
+}
+
+// Inverse of one bremsstrahlung cumulative row: scaled coordinate in [0,1].
+template <class R>
+__device__ inline R brem_inverse(const R* __restrict__ S, int n, R u, R iny1) {
+  int lo = 0, hi = n - 1;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (S[mid] <= u) lo = mid; else hi = mid;
+  }
+  const R t = (u - S[lo]) / (S[lo + 1] - S[lo]);
+  return (R(lo) + t) * iny1;
+}
+
+__device__ inline void jadd(unsigned long long* J, int64_t m, double v) {
+  const long long q = __double2ll_rn(v * kJScale);
+  if (q != 0) atomicAdd(J + m, (unsigned long long)q);
+}
+
+// node weights of a point on a 4-node window starting at base
+template <class R>
+__device__ inline void shape4(R g, int base, R S[4]) {
+  const R fl = m_floor(g);
+  const int i = (int)fl;
+  const R f = g - fl;
+  S[0] = R(0); S[1] = R(0); S[2] = R(0); S[3] = R(0);
+  const int o = i - base;  // 0, 1 or 2 (|move| < one cell)
+  if (o == 0) { S[0] = R(1) - f; S[1] = f; }
+  else if (o == 1) { S[1] = R(1) - f; S[2] = f; }
+  else { S[2] = R(1) - f; S[3] = f; }
+}
+
+template <class R, int D>
+__device__ inline void deposit(const StepParams<R>& P, const Idx<R>& I, const R* x0, const R* x1,
+                               const R* v, double w) {
+  const R c0 = R(-w * P.invV);
+  R S0[3][4], S1[3][4];
+  int b[3] = {0, 0, 0};
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const R g0 = x0[a] * R(P.idx[a]);
+    const R g1 = x1[a] * R(P.idx[a]);
+    b[a] = (int)m_floor(g0) - 1;
+    shape4<R>(g0, b[a], S0[a]);
+    shape4<R>(g1, b[a], S1[a]);
+  }
+  unsigned long long* Jx = P.J[0];
+  unsigned long long* Jy = P.J[1];
+  unsigned long long* Jz = P.J[2];
+  if (D == 1) {
+    const R qx = c0 * R(P.dxdt[0]);
+    R acc = R(0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      acc = acc - qx * (S1[0][i] - S0[0][i]);
+      jadd(Jx, I(b[0] + i, 0, 0), (double)acc);
+    }
+    const R cy = c0 * v[1], cz = c0 * v[2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const R sa = R(0.5) * (S0[0][i] + S1[0][i]);
+      jadd(Jy, I(b[0] + i, 0, 0), (double)(cy * sa));
+      jadd(Jz, I(b[0] + i, 0, 0), (double)(cz * sa));
+    }
+  } else if (D == 2) {
+    const R qx = c0 * R(P.dxdt[0]), qy = c0 * R(P.dxdt[1]), cz = c0 * v[2];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      R acc = R(0);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const R W = R(0.5) * (S1[0][i] - S0[0][i]) * (S0[1][j] + S1[1][j]);
+        acc = acc - qx * W;
+        jadd(Jx, I(b[0] + i, b[1] + j, 0), (double)acc);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      R acc = R(0);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const R W = R(0.5) * (S0[0][i] + S1[0][i]) * (S1[1][j] - S0[1][j]);
+        acc = acc - qy * W;
+        jadd(Jy, I(b[0] + i, b[1] + j, 0), (double)acc);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const R W = (S0[0][i] * S0[1][j] + S1[0][i] * S1[1][j]) * R(1.0 / 3.0) +
+                    (S0[0][i] * S1[1][j] + S1[0][i] * S0[1][j]) * R(1.0 / 6.0);
+        jadd(Jz, I(b[0] + i, b[1] + j, 0), (double)(cz * W));
+      }
+  } else {
+    const R qx = c0 * R(P.dxdt[0]), qy = c0 * R(P.dxdt[1]), qz = c0 * R(P.dxdt[2]);
+    for (int k = 0; k < 4; ++k)
+      for (int j = 0; j < 4; ++j) {
+        R acc = R(0);
+        for (int i = 0; i < 3; ++i) {
+          const R T = (S0[1][j] * S0[2][k] + S1[1][j] * S1[2][k]) * R(1.0 / 3.0) +
+                      (S1[1][j] * S0[2][k] + S0[1][j] * S1[2][k]) * R(1.0 / 6.0);
+          acc = acc - qx * ((S1[0][i] - S0[0][i]) * T);
+          jadd(Jx, I(b[0] + i, b[1] + j, b[2] + k), (double)acc);
+        }
+      }
+    for (int k = 0; k < 4; ++k)
+      for (int i = 0; i < 4; ++i) {
+        R acc = R(0);
+        for (int j = 0; j < 3; ++j) {
+          const R T = (S0[0][i] * S0[2][k] + S1[0][i] * S1[2][k]) * R(1.0 / 3.0) +
+                      (S1[0][i] * S0[2][k] + S0[0][i] * S1[2][k]) * R(1.0 / 6.0);
+          acc = acc - qy * ((S1[1][j] - S0[1][j]) * T);
+          jadd(Jy, I(b[0] + i, b[1] + j, b[2] + k), (double)acc);
+        }
+      }
+    for (int j = 0; j < 4; ++j)
+      for (int i = 0; i < 4; ++i) {
+        R acc = R(0);
+        for (int k = 0; k < 3; ++k) {
+          const R T = (S0[0][i] * S0[1][j] + S1[0][i] * S1[1][j]) * R(1.0 / 3.0) +
+                      (S1[0][i] * S0[1][j] + S0[0][i] * S1[1][j]) * R(1.0 / 6.0);
+          acc = acc - qz * ((S1[2][k] - S0[2][k]) * T);
+          jadd(Jz, I(b[0] + i, b[1] + j, b[2] + k), (double)acc);
+        }
+      }
+  }
+}
+
+__device__ inline void neumaier(double* s, double* c, double v) {
+  const double t = *s + v;
+  if (fabs(*s) >= fabs(v)) *c += (*s - t) + v;
+  else *c += (v - t) + *s;
+  *s = t;
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ inline uint32_t lane_offset(unsigned long long mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+template <class R, int D>
+__global__ __launch_bounds__(kBlock) void k_electron_step(const StepParams<R> P) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const Idx<R> I{P.gg[0], P.gg[1], P.gg[2], P.sz[0], P.sz[1]};
+  bool live = false;
+  uint32_t idv = 0;
+  if (e < P.N) {
+    idv = P.id[e];
+    live = (idv & kDead) == 0;
+  }
+  // per-lane emission results
+  bool ev_ncs = false, ev_br = false, keep_ncs = false, clamped = false;
+  R ph_e[2] = {R(0), R(0)};
+  R ph_k[2][3] = {{R(0), R(0), R(0)}, {R(0), R(0), R(0)}};
+  R xo[3] = {R(0), R(0), R(0)};
+  double wgt = 0.0;
+
+  if (live) {
+    const uint32_t n = P.step;
+    const U4 r = philox4x32_10(idv, n, 0u, 0u, P.key0, P.key1);
+    R x[3] = {R(0), R(0), R(0)};
+#pragma unroll
+    for (int a = 0; a < D; ++a) x[a] = P.x[a][e];
+    xo[0] = x[0]; xo[1] = x[1]; xo[2] = x[2];
+    R px = P.p[0][e], py = P.p[1][e], pz = P.p[2][e];
+    wgt = P.w[e];
+
+    // ---- gather E^n, B^n at x^n --------------------------------------------
+    R E0, E1, E2, B0, B1, B2;
+    if (P.flags & PIC_FIELDS_FROZEN) {
+      if (P.frozen_kind == PIC_FROZEN_UNIFORM) {
+        E0 = R(P.fE[0]); E1 = R(P.fE[1]); E2 = R(P.fE[2]);
+        B0 = R(P.fB[0]); B1 = R(P.fB[1]); B2 = R(P.fB[2]);
+      } else {
+        E0 = R(0); E1 = R(0); E2 = R(0); B0 = R(0); B1 = R(0); B2 = R(0);
+        const R phi = R(P.tn) - x[0];
+        if (phi > R(0)) {
+          const R v = R(P.fa) * m_sin(phi);
+          E1 = v;
+          B2 = v;
+        }
+      }
+    } else {
+      R g[3] = {R(0), R(0), R(0)};
+#pragma unroll
+      for (int a = 0; a < D; ++a) g[a] = x[a] * R(P.idx[a]);
+      E0 = gather<R, D, 1, 0, 0>(P.E[0], g, I);
+      E1 = gather<R, D, 0, 1, 0>(P.E[1], g, I);
+      E2 = gather<R, D, 0, 0, 1>(P.E[2], g, I);
+      B0 = gather<R, D, 0, 1, 1>(P.B[0], g, I);
+      B1 = gather<R, D, 1, 0, 1>(P.B[1], g, I);
+      B2 = gather<R, D, 1, 1, 0>(P.B[2], g, I);
+    }
+
+    // ---- relativistic Boris push (q = -1, m = 1) ----------------------------
+    const R hq = R(-0.5 * P.dt);
+    const R umx = px + hq * E0, umy = py + hq * E1, umz = pz + hq * E2;
+    const R gm = m_sqrt(R(1) + (umx * umx + umy * umy + umz * umz));
+    const R fq = hq / gm;
+    const R tx = fq * B0, ty = fq * B1, tz = fq * B2;
+    const R sf = R(2) / (R(1) + (tx * tx + ty * ty + tz * tz));
+    const R sx = sf * tx, sy = sf * ty, sz = sf * tz;
+    const R upx = umx + (umy * tz - umz * ty);
+    const R upy = umy + (umz * tx - umx * tz);
+    const R upz = umz + (umx * ty - umy * tx);
+    const R uqx = umx + (upy * sz - upz * sy);
+    const R uqy = umy + (upz * sx - upx * sz);
+    const R uqz = umz + (upx * sy - upy * sx);
+    px = uqx + hq * E0;
+    py = uqy + hq * E1;
+    pz = uqz + hq * E2;
+    R gamma = m_sqrt(R(1) + (px * px + py * py + pz * pz));
+
+    // ---- quantum parameter eta (Lorentz invariant, Sec. II.A) ---------------
+    const R cx = gamma * E0 + (py * B2 - pz * B1);
+    const R cy = gamma * E1 + (pz * B0 - px * B2);
+    const R cz = gamma * E2 + (px * B1 - py * B0);
+    const R pe = px * E0 + py * E1 + pz * E2;
+    R q2 = (cx * cx + cy * cy + cz * cz) - pe * pe;
+    if (q2 < R(0)) q2 = R(0);
+    const R eta = m_sqrt(q2) * R(P.iES);
+
+    // ---- nonlinear Compton: optical depth + inverse-CDF draw ----------------
+    if (P.flags & PIC_NCS) {
+      const R sl = (m_log(eta) - R(P.ln_eta0)) * R(P.idln_eta);
+      if (sl >= R(0)) {
+        int i;
+        R f;
+        if (sl >= R(P.n_eta - 1)) { i = P.n_eta - 2; f = R(1); }
+        else { i = (int)sl; f = sl - R(i); }
+        const R h = P.h[i] + f * (P.h[i + 1] - P.h[i]);
+        const R dtau = R(P.K_N) * eta / gamma * h * R(P.dt);
+        double tau = P.tau[e] - (double)dtau;
+        if (tau <= 0.0) {
+          const R u2 = unif<R>(r.v[2]);
+          const R la = ncs_inverse<R>(P.ncs + (int64_t)i * P.n_xi, P.lnxi, P.n_xi, u2);
+          const R lb = ncs_inverse<R>(P.ncs + (int64_t)(i + 1) * P.n_xi, P.lnxi, P.n_xi, u2);
+          const R lx = la + f * (lb - la);
+          const R xi = m_exp(lx);
+          R eps = xi * gamma;
+          if (eps > gamma - R(1)) eps = gamma - R(1);
+          const R pm = m_sqrt(px * px + py * py + pz * pz);
+          ev_ncs = true;
+          ph_e[0] = eps;
+          ph_k[0][0] = px / pm; ph_k[0][1] = py / pm; ph_k[0][2] = pz / pm;
+          keep_ncs = (double)eps >= P.photon_cut;
+          if (!(P.flags & PIC_NO_RECOIL)) {
+            const R gn = gamma - eps;
+            const R pn = m_sqrt((gn - R(1)) * (gn + R(1)));
+            const R sc = pn / pm;
+            px = px * sc; py = py * sc; pz = pz * sc;
+            gamma = gn;
+          }
+          tau = -log(unif32(r.v[3]));
+        }
+        P.tau[e] = tau;
+      }
+    }
+
+    // ---- bremsstrahlung: Eq. (4) test, R2 energy draw (Sec. II.B) -----------
+    if (P.flags & PIC_BREM) {
+      const R T = gamma - R(1);
+      if ((double)T >= P.k_cut) {
+        int ci[3] = {0, 0, 0};
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          int q = (int)m_floor(x[a] * R(P.idx[a]));
+          q = q < 0 ? 0 : (q > P.n[a] - 1 ? P.n[a] - 1 : q);
+          ci[a] = q;
+        }
+        const double ni = P.ni[ci[0] + (int64_t)P.n[0] * (ci[1] + (int64_t)P.n[1] * ci[2])];
+        if (ni > 0.0) {
+          const R lt = m_log(T);
+          const R sl = (lt - R(P.ln_T0)) * R(P.idln_T);
+          if (sl >= R(0)) {
+            int i;
+            R f;
+            if (sl >= R(P.n_T - 1)) { i = P.n_T - 2; f = R(1); clamped = true; }
+            else { i = (int)sl; f = sl - R(i); }
+            const R sig = P.sig[i] + f * (P.sig[i + 1] - P.sig[i]);
+            if (sig > R(0)) {
+              const R pm = m_sqrt(px * px + py * py + pz * pz);
+              const R v = pm / gamma;
+              const R X = R(P.K_BR) * R(ni) * sig * v * R(P.dt);
+              const R Pb = -m_expm1(-X);
+              if (unif52(r.v[0], r.v[1]) < (double)Pb) {
+                const U4 r2 = philox4x32_10(idv, n, 1u, 0u, P.key0, P.key1);
+                const R u = unif<R>(r2.v[0]);
+                const R sa = brem_inverse<R>(P.br + (int64_t)i * P.n_y, P.n_y, u, R(P.iny1));
+                const R sb = brem_inverse<R>(P.br + (int64_t)(i + 1) * P.n_y, P.n_y, u, R(P.iny1));
+                const R sv = sa + f * (sb - sa);
+                const R lk = R(P.lnk);
+                R eps = m_exp(lk + sv * (lt - lk));
+                if (eps > T) eps = T;
+                ev_br = true;
+                ph_e[1] = eps;
+                ph_k[1][0] = px / pm; ph_k[1][1] = py / pm; ph_k[1][2] = pz / pm;
+                if (!(P.flags & PIC_NO_RECOIL)) {
+                  const R gn = gamma - eps;
+                  const R pn = m_sqrt((gn - R(1)) * (gn + R(1)));
+                  const R sc = pn / pm;
+                  px = px * sc; py = py * sc; pz = pz * sc;
+                  gamma = gn;
+                }
+              }
+            }
+          }
+        }
+      }
+    }
+
+    // ---- move, deposit, absorbing walls -----------------------------------
+    P.p[0][e] = px; P.p[1][e] = py; P.p[2][e] = pz;
+    const R ig = R(1) / gamma;
+    const R v[3] = {px * ig, py * ig, pz * ig};
+    R x1[3] = {x[0], x[1], x[2]};
+    bool out = false;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      x1[a] = x[a] + v[a] * R(P.dt);
+      if (x1[a] < R(0) || x1[a] >= R(P.L[a])) out = true;
+    }
+    if (!(P.flags & PIC_FIELDS_FROZEN)) deposit<R, D>(P, I, x, x1, v, wgt);
+#pragma unroll
+    for (int a = 0; a < D; ++a) P.x[a][e] = x1[a];
+    if (out) P.id[e] = idv | kDead;
+  }
+
+  // ---- photon append: one atomic per wave and process ---------------------
+  const uint32_t lane = __lane_id();
+  const bool rec0 = ev_ncs && keep_ncs;
+  const bool rec1 = ev_br;
+#pragma unroll
+  for (int proc = 0; proc < 2; ++proc) {
+    const bool rec = proc == 0 ? rec0 : rec1;
+    const unsigned long long mask = __ballot(rec);
+    if (mask == 0ull) continue;  // wave-uniform
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(P.pcount, (unsigned long long)__popcll(mask));
+    base = __shfl(base, 0, 64);
+    if (rec) {
+      const unsigned long long slot = base + lane_offset(mask);
+      if (slot < P.pcap) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          P.px[a][slot] = xo[a];
+          P.pk[a][slot] = ph_k[proc][a];
+        }
+        P.pe[slot] = ph_e[proc];
+        P.pw[slot] = wgt;
+        P.pstep[slot] = P.step;
+        P.ppar[slot] = idv;
+        P.pproc[slot] = (uint32_t)proc;
+      }
+    }
+  }
+
+  // ---- per-wave statistics slot --------------------------------------------
+  const unsigned long long m_live = __ballot(live);
+  if (m_live == 0ull) return;  // wave-uniform
+  const int64_t slot = e >> 6;
+  const unsigned long long m_ncs = __ballot(ev_ncs);
+  const unsigned long long m_br = __ballot(ev_br);
+  const unsigned long long m_cl = __ballot(clamped);
+  unsigned long long* C = P.slot_cnt + slot * kSlotCnt;
+  if (lane == 0) C[SC_ESTEPS] += (unsigned long long)__popcll(m_live);
+  if ((m_ncs | m_br | m_cl) == 0ull) return;  // wave-uniform
+  const unsigned long long m_keep = __ballot(ev_ncs && keep_ncs);
+  const double e_keep0 = (ev_ncs && keep_ncs) ? wgt * (double)ph_e[0] : 0.0;
+  const double e_drop = (ev_ncs && !keep_ncs) ? wgt * (double)ph_e[0] : 0.0;
+  const double e_keep1 = ev_br ? wgt * (double)ph_e[1] : 0.0;
+  const double s0 = wave_sum(e_keep0), s1 = wave_sum(e_keep1), s2 = wave_sum(e_drop);
+  if (lane == 0) {
+    C[SC_EV_NCS] += (unsigned long long)__popcll(m_ncs);
+    C[SC_EV_BR] += (unsigned long long)__popcll(m_br);
+    C[SC_KEPT_NCS] += (unsigned long long)__popcll(m_keep);
+    C[SC_KEPT_BR] += (unsigned long long)__popcll(m_br);
+    C[SC_DROPPED] += (unsigned long long)__popcll(m_ncs & ~m_keep);
+    C[SC_CLAMPED] += (unsigned long long)__popcll(m_cl);
+    double* S = P.slot_sum + slot * kSlotSum;
+    if (m_keep) neumaier(S + 0, S + 1, s0);
+    if (m_br) neumaier(S + 2, S + 3, s1);
+    if (m_ncs & ~m_keep) neumaier(S + 4, S + 5, s2);
+  }
+}
+
+template <class R, int D>
+static void launch_one(const void* params, hipStream_t s) {
+  const StepParams<R>& P = *static_cast<const StepParams<R>*>(params);
+  if (P.N <= 0) return;
+  const int64_t blocks = (P.N + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL((k_electron_step<R, D>), dim3((unsigned)blocks), dim3(kBlock), 0, s, P);
+}
+
+void launch_step(int dims, bool fp32, const void* params, hipStream_t s) {
+  if (fp32) {
+    if (dims == 1) launch_one<float, 1>(params, s);
+    else if (dims == 2) launch_one<float, 2>(params, s);
+    else launch_one<float, 3>(params, s);
+  } else {
+    if (dims == 1) launch_one<double, 1>(params, s);
+    else if (dims == 2) launch_one<double, 2>(params, s);
+    else launch_one<double, 3>(params, s);
+  }
+}
+
+}  // namespace pic

@@ -1,0 +1,145 @@
+"""GPU parity: the HIP path (through the C-ABI) against the FP64 oracle.
+
+Every case prints its name before touching the GPU.  FP64 bar: identical
+emission events, momenta/positions/optical depths within 1e-12 relative
+(absolute below 1), photon energies within 1e-12, exact counts."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import scenarios as S
+from parity import compare
+
+pytestmark = pytest.mark.gpu
+
+
+def _announce(name):
+    print(f"\n[gpu-case] {name}", flush=True)
+
+
+def _pair(oracle_lib, gpu_lib, w, tables, beam=None):
+    o = oracle_lib.OracleSim(w, tables)
+    g = gpu_lib.Sim(w, tables)
+    assert g.N == o.N
+    if beam is not None:
+        x, p, tau = beam(o)
+        o.set_electrons(x, p, tau)
+        g.set_electrons(x, p, tau)
+    return o, g
+
+
+def test_philox_device_matches_oracle(oracle_lib, gpu_lib):
+    _announce("philox")
+    rng = np.random.default_rng(11)
+    ctr = rng.integers(0, 2**32, size=(4096, 4), dtype=np.uint64).astype(np.uint32)
+    key = np.array([0xDEADBEEF, 0x12345678], dtype=np.uint32)
+    dev = gpu_lib.pic_philox(ctr, key)
+    for i in range(0, 4096, 97):
+        assert np.array_equal(dev[i], oracle_lib.philox(ctr[i], key)), i
+
+
+def test_initial_state_identical(oracle_lib, gpu_lib, tables_al):
+    _announce("init C1")
+    w = S.c1_parity()
+    o, g = _pair(oracle_lib, gpu_lib, w, tables_al)
+    eo, eg = o.electrons(), g.electrons()
+    assert np.array_equal(eo["x"], eg["x"])
+    assert np.array_equal(eo["w"], eg["w"])
+    assert np.allclose(eo["tau"], eg["tau"], rtol=1e-15, atol=0)
+
+
+def _beam_B(seed, pmin=50.0, pmax=2000.0):
+    def f(o):
+        e = o.electrons()
+        p = S.beam_momenta(o.N, pmin, pmax, seed)
+        return e["x"], p, e["tau"]
+    return f
+
+
+def test_frozen_uniform_B_ncs(oracle_lib, gpu_lib, tables_al):
+    """Particle-only mode (fields prescribed): many NCS events, recoil on."""
+    _announce("frozen uniform B, NCS")
+    w = S.frozen_B_beam(B=400.0)
+    w["brem"] = False
+    o, g = _pair(oracle_lib, gpu_lib, w, tables_al, _beam_B(21))
+    o.step(200)
+    g.step(200)
+    rep = compare(o, g, label="frozen-B-ncs")
+    print(rep, flush=True)
+    assert rep["events"][0] > 1000
+
+
+def test_frozen_uniform_B_brem_dense(oracle_lib, gpu_lib, tables_au):
+    """Particle-only mode at a very high ion density: many bremsstrahlung
+    events, plus NCS, recoil on."""
+    _announce("frozen uniform B, dense brem")
+    w = S.frozen_B_beam(B=50.0, ne=5e7, Z=79, charge_state=79)
+    o, g = _pair(oracle_lib, gpu_lib, w, tables_au, _beam_B(22, 5.0, 2000.0))
+    o.step(150)
+    g.step(150)
+    rep = compare(o, g, label="frozen-B-brem")
+    print(rep, flush=True)
+    assert rep["events"][1] > 100
+
+
+def test_frozen_plane_wave_orbit(oracle_lib, gpu_lib, tables_al):
+    _announce("frozen plane wave")
+    w = S.frozen_plane_wave(a=50.0)
+    o, g = _pair(oracle_lib, gpu_lib, w, tables_al)
+    o.step(300)
+    g.step(300)
+    rep = compare(o, g, label="frozen-pw")
+    print(rep, flush=True)
+
+
+def test_c1_full_pic(oracle_lib, gpu_lib, tables_al):
+    """The 1D3V FP64 configuration, 256 steps, full PIC (fields + deposit)."""
+    _announce("C1 full PIC 256 steps")
+    w = S.c1_parity(256)
+    o, g = _pair(oracle_lib, gpu_lib, w, tables_al)
+    o.step(256)
+    g.step(256)
+    rep = compare(o, g, label="C1")
+    fo, fg = o.fields(), g.fields()
+    rep["max_dfield"] = float(np.abs(fo - fg).max())
+    print(rep, flush=True)
+    assert rep["max_dfield"] <= 1e-12 * max(1.0, np.abs(fo).max())
+
+
+def test_c1_extended_with_events(oracle_lib, gpu_lib, tables_al):
+    """C1 run to 512 steps, where the first NCS events occur."""
+    _announce("C1 extended 512 steps")
+    w = S.c1_parity(512)
+    o, g = _pair(oracle_lib, gpu_lib, w, tables_al)
+    o.step(512)
+    g.step(512)
+    rep = compare(o, g, label="C1-512")
+    print(rep, flush=True)
+    assert rep["events"][0] > 0
+
+
+def test_small_2d_full_pic(oracle_lib, gpu_lib, tables_au):
+    _announce("2D small full PIC")
+    w = S.small_2d()
+    o, g = _pair(oracle_lib, gpu_lib, w, tables_au)
+    o.step(w["steps"])
+    g.step(w["steps"])
+    rep = compare(o, g, label="2D")
+    fo, fg = o.fields(), g.fields()
+    rep["max_dfield"] = float(np.abs(fo - fg).max())
+    print(rep, flush=True)
+    assert rep["max_dfield"] <= 1e-12 * max(1.0, np.abs(fo).max())
+
+
+def test_small_3d_full_pic(oracle_lib, gpu_lib, tables_au):
+    _announce("3D small full PIC")
+    w = S.small_3d()
+    o, g = _pair(oracle_lib, gpu_lib, w, tables_au)
+    o.step(w["steps"])
+    g.step(w["steps"])
+    rep = compare(o, g, label="3D")
+    fo, fg = o.fields(), g.fields()
+    rep["max_dfield"] = float(np.abs(fo - fg).max())
+    print(rep, flush=True)
+    assert rep["max_dfield"] <= 1e-12 * max(1.0, np.abs(fo).max())
