@@ -1,0 +1,143 @@
+"""The C-ABI library on the host: it loads, exports every entry point the
+header declares, validates configs and builds tables (no GPU calls)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1612_07592_amd import binding as B
+from paper_1612_07592_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pic.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pic_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_five_calls():
+    names = declared_symbols()
+    for n in ("pic_create", "pic_load_tables", "pic_step", "pic_emission_stats", "pic_destroy"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = B.load()
+    out = subprocess.run(["nm", "-D", "--defined-only", B.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (pic_\w+)", out))
+    missing = [n for n in declared_symbols() if n not in exported]
+    assert not missing, missing
+    for n in declared_symbols():
+        assert getattr(L, n) is not None
+    assert set(B.EXPORTS) == set(declared_symbols())
+
+
+def test_binding_struct_layouts_match_header():
+    """The ctypes mirrors have the sizes a C compiler gives the header structs."""
+    src = r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "pic.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu\n", sizeof(pic_config), sizeof(pic_tables), sizeof(pic_stats),
+         offsetof(pic_config, stream), offsetof(pic_tables, br_cdf));
+  return 0;
+}'''
+    d = os.path.join(ROOT, "_build")
+    os.makedirs(d, exist_ok=True)
+    c = os.path.join(d, "layout.c")
+    exe = os.path.join(d, "layout")
+    open(c, "w").write(src)
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
+    got = [int(v) for v in subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()]
+    want = [C.sizeof(B.pic_config), C.sizeof(B.pic_tables), C.sizeof(B.pic_stats),
+            B.pic_config.stream.offset, B.pic_tables.br_cdf.offset]
+    assert got == want
+
+
+def _mem(w):
+    L = B.load()
+    c = B.config_from(w)
+    n = C.c_uint64()
+    return L.pic_memory_required(C.byref(c), C.byref(n)), n.value
+
+
+def test_memory_required_counts_buffers():
+    code, n1 = _mem(W.c1())
+    assert code == 0 and n1 > 0
+    code, n2 = _mem(W.c2())
+    assert code == 0
+    # C2 holds 2M electrons, a 2048x1024 grid and a 4e8-photon buffer
+    assert n2 > 400_000_000 * 40
+
+
+@pytest.mark.parametrize("field,value", [
+    ("dims", 4), ("ppc", 0), ("cfl", 1.2), ("cfl", 0.0), ("Z", 0), ("charge_state", 100),
+    ("lambda_m", -1.0), ("ne_over_nc", float("nan")), ("a0", float("inf")),
+    ("photon_cut_mc2", -1.0), ("thickness_lambda", -0.5)])
+def test_invalid_configs_rejected(field, value):
+    w = W.c1()
+    w[field] = value
+    code, _ = _mem(w)
+    assert code == 1  # PIC_ERR_INVALID
+    msg = B.load().pic_last_error(None)
+    assert msg and len(msg) > 3
+
+
+def test_invalid_grid_rejected():
+    w = W.c1()
+    w["n"] = [4]
+    assert _mem(w)[0] == 1
+    w = W.c1()
+    w["dx_lambda"] = [0.0]
+    assert _mem(w)[0] == 1
+
+
+def test_abi_version_checked():
+    L = B.load()
+    c = B.config_from(W.c1())
+    c.abi_version = 99
+    n = C.c_uint64()
+    assert L.pic_memory_required(C.byref(c), C.byref(n)) == 1
+
+
+def test_null_arguments():
+    L = B.load()
+    h = C.c_void_p()
+    assert L.pic_create(None, C.byref(h)) == 1
+    assert L.pic_step(None, 1) == 1
+    L.pic_destroy(None)  # NULL is a no-op
+
+
+@pytest.mark.slow
+def test_library_tables_match_oracle_tables(tables_au):
+    """Two independent quadratures of the same formulas agree (library:
+    trapezoid Bessel sums + adaptive Simpson; oracle: scipy K, adaptive GL)."""
+    t = B.pic_build_tables(79, 1.0, 0)
+    assert abs(t["ln_eta0"] - tables_au["ln_eta0"]) < 1e-15
+    assert np.allclose(t["ln_xi"], tables_au["ln_xi"], rtol=0, atol=1e-13)
+    assert np.max(np.abs(t["h"] / tables_au["h"] - 1)) < 1e-9
+    assert np.max(np.abs(t["ncs_cdf"] - tables_au["ncs_cdf"])) < 1e-9
+    pos = tables_au["sigma"] > 0
+    assert np.array_equal(t["sigma"] > 0, pos)
+    assert np.max(np.abs(t["sigma"][pos] / tables_au["sigma"][pos] - 1)) < 1e-9
+    assert np.max(np.abs(t["br_cdf"] - tables_au["br_cdf"])) < 1e-9
+
+
+def test_build_tables_rejects_bad_args():
+    L = B.load()
+    out = B.pic_tables()
+    z = np.zeros(256 * 256)
+    assert L.pic_build_tables(0, 1.0, 1, z.ctypes.data, z.ctypes.data, z.ctypes.data,
+                              z.ctypes.data, z.ctypes.data, C.byref(out)) == 1
+    assert L.pic_build_tables(13, 0.0, 1, z.ctypes.data, z.ctypes.data, z.ctypes.data,
+                              z.ctypes.data, z.ctypes.data, C.byref(out)) == 1
