@@ -72,7 +72,7 @@ def run_gpu(w, tables, steps, warmup, torch):
     ms, n = s.profile_read()
     s.pic_destroy()
     return dict(wall_s=t1 - t0, stats=st, step_kernel_ms=float(ms[0]), field_ms=float(ms[1]),
-                step_launches=int(n[0]))
+                sort_ms=float(ms[2]), step_launches=int(n[0]))
 
 
 def cpu_baseline(w, budget_s=15.0):
@@ -111,6 +111,8 @@ def main():
     ap.add_argument("--precision", default="fp32")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sort-every", type=int, default=0,
+                    help="tile-sort interval in steps (0 = library default, -1 = never)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a "
@@ -121,6 +123,7 @@ def main():
     from paper_1612_07592_amd import binding
     binding.load()
     w = _workload(args.workload, args.precision, args.steps)
+    w["sort_every"] = args.sort_every
     t0 = time.perf_counter()
     tables = binding.pic_build_tables(int(w["Z"]), 1.0, 16)
     t_tables = time.perf_counter() - t0
@@ -154,7 +157,10 @@ def main():
                      "kernel": f"k_electron_step<{'float' if args.precision == 'fp32' else 'double'},{dims}>",
                      "bytes_per_electron_step": bpe,
                      "kernel_avg_us": r["step_kernel_ms"] * 1e3 / max(1, r["step_launches"])},
-        "step_kernel_share": r["step_kernel_ms"] / (r["wall_s"] * 1e3),
+        "time_share": {"electron_step": r["step_kernel_ms"] / (r["wall_s"] * 1e3),
+                       "field_solve": r["field_ms"] / (r["wall_s"] * 1e3),
+                       "sort": r["sort_ms"] / (r["wall_s"] * 1e3)},
+        "untiled_fraction": st["untiled_steps"] / max(1, esteps),
         "emission": {"events": st["events"], "kept": st["kept"], "dropped_ncs": st["dropped_ncs"],
                      "overflow": st["overflow"], "e_rad_kept": st["e_rad_kept"]},
     }
@@ -162,6 +168,7 @@ def main():
           f"{out['roofline']['kernel_avg_us']:.1f} us, {achieved:.0f} GB/s", file=sys.stderr, flush=True)
     if not args.no_fp64 and args.precision == "fp32":
         w64 = _workload(args.workload, "fp64", args.steps)
+        w64["sort_every"] = args.sort_every
         r64 = run_gpu(w64, tables, args.steps, 0, torch)
         v64 = r64["stats"]["electron_steps"] / r64["wall_s"]
         out["fp64"] = {"value": v64, "ms_per_step": r64["wall_s"] * 1e3 / args.steps,

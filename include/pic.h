@@ -107,6 +107,10 @@ typedef struct {
   uint64_t photon_capacity; /* photon records the buffer holds */
   uint64_t seed;            /* Philox key = (seed_lo, seed_hi ^ job_id_lo) */
   uint64_t job_id;
+  int32_t sort_every;       /* re-sort electrons by cell tile every this many steps;
+                               0 = default for dims, < 0 = never (results do not
+                               depend on it) */
+  uint32_t reserved0;       /* must be 0 */
   void* stream;             /* hipStream_t or NULL */
 } pic_config;
 
@@ -150,6 +154,8 @@ typedef struct {
   uint64_t overflow;         /* kept photons that did not fit the buffer */
   uint64_t brem_clamped;     /* sigma evaluated above the table's last energy */
   uint64_t photons_stored;   /* records in the photon buffer */
+  uint64_t untiled_steps;    /* electron-steps whose workgroup box did not fit LDS
+                                (deposit and gather went to global memory) */
   double e_rad_kept[2];      /* sum w*eps of kept photons per process */
   double e_rad_dropped;      /* sum w*eps of dropped NCS photons */
   double e_kin_e;            /* sum w*(gamma-1) over live electrons (snapshot) */
@@ -238,11 +244,12 @@ pic_status pic_build_tables(uint32_t Z, double k_cut_mc2, int32_t nthreads,
 pic_status pic_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, uint64_t n);
 
 /* Kernel timing with HIP events recorded on the context's stream around
- * every electron-step launch and every field-solve group (enable != 0 starts
- * a fresh accumulation).  pic_profile_read synchronises and returns the summed
- * milliseconds and launch counts: ms[0] electron step, ms[1] field solve. */
+ * every electron-step launch, every field-solve group and every tile sort
+ * (enable != 0 starts a fresh accumulation).  pic_profile_read synchronises
+ * and returns the summed milliseconds and launch counts in ms3/launches3:
+ * [0] electron step, [1] field solve, [2] sort. */
 pic_status pic_profile(pic_ctx* ctx, int32_t enable);
-pic_status pic_profile_read(pic_ctx* ctx, double* ms2, uint64_t* launches2);
+pic_status pic_profile_read(pic_ctx* ctx, double* ms3, uint64_t* launches3);
 
 /* Derived constants of ctx: dx[3], dt, E_S, K_N, K_BR, n_c (8 doubles). */
 pic_status pic_derived(pic_ctx* ctx, double* out8);

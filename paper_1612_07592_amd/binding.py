@@ -39,7 +39,7 @@ class pic_config(C.Structure):
                 ("photon_cut_mc2", C.c_double), ("frozen_E", C.c_double * 3),
                 ("frozen_B", C.c_double * 3), ("frozen_a", C.c_double),
                 ("photon_capacity", C.c_uint64), ("seed", C.c_uint64), ("job_id", C.c_uint64),
-                ("stream", C.c_void_p)]
+                ("sort_every", C.c_int32), ("reserved0", C.c_uint32), ("stream", C.c_void_p)]
 
 
 class pic_tables(C.Structure):
@@ -57,6 +57,7 @@ class pic_stats(C.Structure):
                 ("electron_steps", C.c_uint64), ("events", C.c_uint64 * 2),
                 ("kept", C.c_uint64 * 2), ("dropped_ncs", C.c_uint64), ("overflow", C.c_uint64),
                 ("brem_clamped", C.c_uint64), ("photons_stored", C.c_uint64),
+                ("untiled_steps", C.c_uint64),
                 ("e_rad_kept", C.c_double * 2), ("e_rad_dropped", C.c_double),
                 ("e_kin_e", C.c_double), ("e_field", C.c_double)]
 
@@ -162,6 +163,7 @@ def config_from(w: dict, stream=None) -> pic_config:
     c.photon_capacity = int(w.get("photon_capacity", 1 << 20))
     c.seed = int(w.get("seed", 1))
     c.job_id = int(w.get("job_id", 0))
+    c.sort_every = int(w.get("sort_every", 0))
     c.stream = stream
     return c
 
@@ -251,6 +253,7 @@ class Sim:
                     events=[s.events[0], s.events[1]], kept=[s.kept[0], s.kept[1]],
                     dropped_ncs=s.dropped_ncs, overflow=s.overflow,
                     brem_clamped=s.brem_clamped, photons_stored=s.photons_stored,
+                    untiled_steps=s.untiled_steps,
                     e_rad_kept=[s.e_rad_kept[0], s.e_rad_kept[1]],
                     e_rad_dropped=s.e_rad_dropped, e_kin_e=s.e_kin_e, e_field=s.e_field,
                     status=STATUS[code])
@@ -317,9 +320,9 @@ class Sim:
         _check("pic_profile", self._L.pic_profile(self._h, 1 if enable else 0), self._h)
 
     def profile_read(self):
-        """(ms electron step, ms field solve), (launches, launch groups)."""
-        ms = np.zeros(2)
-        n = np.zeros(2, dtype=np.uint64)
+        """ms and launch counts: [electron step, field solve, sort]."""
+        ms = np.zeros(3)
+        n = np.zeros(3, dtype=np.uint64)
         _check("pic_profile_read", self._L.pic_profile_read(self._h, ms.ctypes.data, n.ctypes.data), self._h)
         return ms, n
 

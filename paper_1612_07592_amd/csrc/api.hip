@@ -3,14 +3,18 @@
 // stream, statistics read-back and the test/tool helpers.
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <new>
+#include <utility>
 #include <vector>
 #include "pic_internal.hpp"
 #include "philox.hpp"
 
 namespace pic {
 void launch_b_half_zero(const Ctx& c, hipStream_t s);
+int sort_scratch_words(uint32_t nkeys);
 int reduce_scratch_cnt();
 int reduce_scratch_sum();
 
@@ -140,7 +144,39 @@ std::string derive(const pic_config& cfg, Ctx& c) {
   c.wgt = cfg.ne_over_nc * V / (double)cfg.ppc;
   c.fp32 = cfg.precision == PIC_FP32_MIXED;
   c.pcap = cfg.photon_capacity;
-  c.nslots = ((N + kBlock - 1) / kBlock) * (kBlock / 64);
+  c.nblocks_step = ((N + kBlock - 1) / kBlock + 7) / 8 * 8;
+  c.nslots = c.nblocks_step * (kBlock / 64);
+  // cell tiles for the sort and the LDS box of the step kernel
+  if (cfg.reserved0 != 0) return "reserved0 must be 0";
+  const int dflt_every[4] = {0, 16, 8, 4};
+  const int tiles[4] = {0, 16, 4, 2};
+  const int ldsn[4] = {0, 64, 576, 512};
+  c.sort_every = cfg.sort_every == 0 ? dflt_every[g.dims] : (cfg.sort_every < 0 ? 0 : cfg.sort_every);
+  c.lds_nodes = ldsn[g.dims];
+  // FP32 current quantum: the largest 2^-jbits (jbits <= 40) with which the
+  // sum of one chunk's contributions to a node stays below 2^30 in int32
+  {
+    double vmax = cfg.ne_over_nc / (double)cfg.ppc;   // |c0| = w / V
+    double dxdt = 1.0;
+    for (int a = 0; a < g.dims; ++a) dxdt = std::max(dxdt, g.dx[a] / g.dt);
+    vmax = vmax * dxdt * 1.5 + 1e-30;                 // |W| <= 1, |acc| <= 1.5, |v| < 1
+    c.jbits = 40;
+    while (c.jbits > 0 && (double)kBlock * vmax * ldexp(1.0, c.jbits) >= ldexp(1.0, 30)) --c.jbits;
+    if (c.fp32 && c.jbits < 8) return "electron weight too large for the FP32 current quantum";
+  }
+  // tuning overrides (layout only; results do not depend on them)
+  if (const char* v = getenv("PIC_TUNE_LDS_NODES")) c.lds_nodes = atoi(v) & ~1;
+  int tile_edge = tiles[g.dims];
+  if (const char* v = getenv("PIC_TUNE_TILE")) tile_edge = atoi(v) > 0 ? atoi(v) : tile_edge;
+  int ntl[3] = {1, 1, 1}, bits = 0;
+  for (int a = 0; a < g.dims; ++a) {
+    c.tile[a] = tile_edge;
+    ntl[a] = (g.n[a] + c.tile[a] - 1) / c.tile[a];
+    while ((1 << bits) < ntl[a]) ++bits;
+  }
+  if (g.dims == 1) c.nkeys = (uint32_t)ntl[0] + 1;
+  else if (g.dims == 2) { if (bits > 15) return "grid too large for the tile sort"; c.nkeys = (1u << (2 * bits)) + 1; }
+  else { if (bits > 9) return "grid too large for the tile sort"; c.nkeys = (1u << (3 * bits)) + 1; }
   return "";
 }
 
@@ -181,6 +217,20 @@ Plan make_plan(Ctx& c) {
   P.add((void**)&c.tau, N * 8);
   P.add((void**)&c.w, N * 8);
   P.add((void**)&c.id, N * 4);
+  if (c.sort_every > 0) {  // second SoA buffer and sort scratch
+    for (int a = 0; a < 3; ++a) {
+      if (a < g.dims) P.add(&c.x2[a], N * rs);
+      P.add(&c.p2[a], N * rs);
+    }
+    P.add((void**)&c.tau2, N * 8);
+    P.add((void**)&c.w2, N * 8);
+    P.add((void**)&c.id2, N * 4);
+    P.add((void**)&c.skey, N * 4);
+    P.add((void**)&c.scount, (size_t)c.nkeys * 4);
+    P.add((void**)&c.soffset, (size_t)c.nkeys * 4);
+    P.add((void**)&c.scursor, ((size_t)c.nkeys + sort_scratch_words(c.nkeys)) * 4);
+  }
+  P.add((void**)&c.n_active, 8);
   const size_t pc = (size_t)(c.pcap > 0 ? c.pcap : 1);
   for (int a = 0; a < 3; ++a) {
     P.add(&c.px[a], pc * rs);
@@ -269,8 +319,8 @@ void fill_step_params(Ctx& c, StepParams<R>& P) {
   for (int a = 0; a < 3; ++a) {
     P.x[a] = (R*)c.x[a];
     P.p[a] = (R*)c.p[a];
-    P.E[a] = (const R*)c.E[a];
-    P.B[a] = (const R*)c.B[a];
+    P.F[a] = (const R*)c.E[a];
+    P.F[3 + a] = (const R*)c.B[a];
     P.J[a] = c.J[a];
     P.n[a] = g.n[a];
     P.gg[a] = g.gg[a];
@@ -297,6 +347,7 @@ void fill_step_params(Ctx& c, StepParams<R>& P) {
   P.n_eta = t.n_eta; P.n_xi = t.n_xi; P.n_T = t.n_T; P.n_y = t.n_y;
   P.ln_eta0 = t.ln_eta0; P.idln_eta = t.idln_eta; P.ln_T0 = t.ln_T0; P.idln_T = t.idln_T;
   P.k_cut = t.k_cut; P.lnk = t.lnk; P.iny1 = t.iny1;
+  P.eta_skip = t.n_eta > 0 ? exp(t.ln_eta0) * (1.0 - 1e-6) : 0.0;
   if (sizeof(R) == 8) {
     P.h = (const R*)t.h; P.lnxi = (const R*)t.lnxi; P.ncs = (const R*)t.ncs;
     P.sig = (const R*)t.sig; P.br = (const R*)t.br;
@@ -313,6 +364,9 @@ void fill_step_params(Ctx& c, StepParams<R>& P) {
   P.pcount = c.pcount;
   P.slot_cnt = c.slot_cnt;
   P.slot_sum = c.slot_sum;
+  P.n_active = c.n_active;
+  P.lds_nodes = c.lds_nodes;
+  P.jbits = c.jbits;
 }
 
 pic_status check_ctx(pic_ctx* ctx) {
@@ -404,6 +458,8 @@ pic_status pic_create(const pic_config* cfg, pic_ctx** out) {
   hipError_t he = hipMemcpyAsync(c.srcA, A.data(), ns, hipMemcpyHostToDevice, c.stream);
   if (he == hipSuccess) he = hipMemcpyAsync(c.srcC, C.data(), ns, hipMemcpyHostToDevice, c.stream);
   if (he == hipSuccess) he = hipMemcpyAsync(c.srcS, S.data(), ns, hipMemcpyHostToDevice, c.stream);
+  const uint32_t n_act = (uint32_t)c.N;
+  if (he == hipSuccess) he = hipMemcpyAsync(c.n_active, &n_act, 4, hipMemcpyHostToDevice, c.stream);
   if (he == hipSuccess) {
     launch_init_electrons(c, c.stream);
     he = hipGetLastError();
@@ -504,6 +560,27 @@ pic_status pic_step(pic_ctx* ctx, int32_t nsteps) {
     }
   };
   for (int32_t it = 0; it < nsteps; ++it) {
+    if (c.sort_every > 0 && c.step % (uint64_t)c.sort_every == 0) {
+      mark(2);
+      SortArgs A{};
+      A.N = c.N;
+      A.dims = c.g.dims;
+      for (int a = 0; a < 3; ++a) {
+        A.n[a] = c.g.n[a];
+        A.tile[a] = c.tile[a];
+        A.idx[a] = c.g.idx[a];
+        A.x[a] = c.x[a]; A.p[a] = c.p[a]; A.x2[a] = c.x2[a]; A.p2[a] = c.p2[a];
+      }
+      A.nkeys = c.nkeys;
+      A.tau = c.tau; A.w = c.w; A.id = c.id;
+      A.tau2 = c.tau2; A.w2 = c.w2; A.id2 = c.id2;
+      A.key = c.skey; A.count = c.scount; A.offset = c.soffset; A.cursor = c.scursor;
+      A.n_active = c.n_active;
+      launch_sort(A, c.fp32, c.stream);
+      for (int a = 0; a < 3; ++a) { std::swap(c.x[a], c.x2[a]); std::swap(c.p[a], c.p2[a]); }
+      std::swap(c.tau, c.tau2); std::swap(c.w, c.w2); std::swap(c.id, c.id2);
+      mark(2);
+    }
     mark(1);
     if (!frozen) launch_b_half_zero(c, c.stream);  // B^{n-1/2} -> B^n, J <- 0
     mark(1);
@@ -554,6 +631,7 @@ pic_status pic_emission_stats(pic_ctx* ctx, pic_stats* out) {
   s.kept[1] = cnt[SC_KEPT_BR];
   s.dropped_ncs = cnt[SC_DROPPED];
   s.brem_clamped = cnt[SC_CLAMPED];
+  s.untiled_steps = cnt[SC_UNTILED];
   s.photons_stored = pcount < c.pcap ? pcount : c.pcap;
   s.overflow = pcount > c.pcap ? pcount - c.pcap : 0;
   s.e_rad_kept[0] = sum[0];
@@ -740,8 +818,8 @@ pic_status pic_profile_read(pic_ctx* ctx, double* ms2, uint64_t* n2) {
   Ctx& c = ctx->c;
   if (!ms2 || !n2) FAIL(c, PIC_ERR_INVALID, "null output");
   HIPCHK(c, hipStreamSynchronize(c.stream));
-  ms2[0] = ms2[1] = 0.0;
-  n2[0] = n2[1] = 0;
+  ms2[0] = ms2[1] = ms2[2] = 0.0;
+  n2[0] = n2[1] = n2[2] = 0;
   for (size_t i = 0; i + 1 < c.ev_used; i += 2) {
     float ms = 0.f;
     HIPCHK(c, hipEventElapsedTime(&ms, c.ev_pool[i], c.ev_pool[i + 1]));

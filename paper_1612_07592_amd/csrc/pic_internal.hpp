@@ -18,7 +18,7 @@ constexpr double kJScale = 0x1p40;        // current fixed point: units of 2^-40
 constexpr double kJInv = 0x1p-40;
 
 // counter slots
-enum { SC_ESTEPS = 0, SC_EV_NCS, SC_EV_BR, SC_KEPT_NCS, SC_KEPT_BR, SC_DROPPED, SC_CLAMPED, SC_SPARE };
+enum { SC_ESTEPS = 0, SC_EV_NCS, SC_EV_BR, SC_KEPT_NCS, SC_KEPT_BR, SC_DROPPED, SC_CLAMPED, SC_UNTILED };
 
 // Geometry shared by the field kernels (grid layout identical in every mode).
 struct Grid {
@@ -52,9 +52,8 @@ struct StepParams {
   double* tau;
   const double* w;
   uint32_t* id;
-  // fields
-  const R* E[3];
-  const R* B[3];
+  // fields: Ex, Ey, Ez, Bx, By, Bz
+  const R* F[6];
   unsigned long long* J[3];
   int n[3], gg[3], sz[3];
   double idx[3], L[3], dxdt[3], invV;
@@ -65,6 +64,7 @@ struct StepParams {
   // tables
   int n_eta, n_xi, n_T, n_y;
   double ln_eta0, idln_eta, ln_T0, idln_T, k_cut, lnk, iny1;
+  double eta_skip;  // slightly below the first eta of the table
   const R* h;
   const R* lnxi;
   const R* ncs;
@@ -83,7 +83,38 @@ struct StepParams {
   // stats slots
   unsigned long long* slot_cnt;
   double* slot_sum;
+  // cell-sorted layout: live electrons are [0, *n_active); LDS tile capacity
+  const uint32_t* n_active;
+  int lds_nodes;
+  // FP32 path: current contributions rounded to 2^-jbits (int32 in LDS), widened
+  // to the 2^-40 grid when flushed; jbits is chosen so a chunk sum fits int32
+  int jbits;
 };
+
+// Arguments of the tile sort (sort.hip).
+struct SortArgs {
+  int64_t N;
+  int dims;
+  int n[3], tile[3];
+  double idx[3];
+  uint32_t nkeys;           // Morton keys of the tiles + 1 bucket for absorbed electrons
+  const void* x[3];
+  const void* p[3];
+  const double* tau;
+  const double* w;
+  const uint32_t* id;
+  void* x2[3];
+  void* p2[3];
+  double* tau2;
+  double* w2;
+  uint32_t* id2;
+  uint32_t* key;
+  uint32_t* count;
+  uint32_t* offset;
+  uint32_t* cursor;
+  uint32_t* n_active;
+};
+void launch_sort(const SortArgs& A, bool fp32, hipStream_t s);
 
 void launch_step(int dims, bool fp32, const void* params, hipStream_t s);
 void launch_init_electrons(const struct Ctx& c, hipStream_t s);
@@ -133,6 +164,23 @@ struct Ctx {
   uint32_t* pproc = nullptr;
   unsigned long long* pcount = nullptr;
   int64_t nslots = 0;
+  int64_t nblocks_step = 0;   // step-kernel grid (multiple of 8 for the XCD mapping)
+  // cell-tile sort
+  int sort_every = 0;
+  int tile[3] = {1, 1, 1};
+  uint32_t nkeys = 0;
+  void* x2[3] = {};
+  void* p2[3] = {};
+  double* tau2 = nullptr;
+  double* w2 = nullptr;
+  uint32_t* id2 = nullptr;
+  uint32_t* skey = nullptr;
+  uint32_t* scount = nullptr;
+  uint32_t* soffset = nullptr;
+  uint32_t* scursor = nullptr;
+  uint32_t* n_active = nullptr;
+  int lds_nodes = 0;
+  int jbits = 40;
   unsigned long long* slot_cnt = nullptr;
   double* slot_sum = nullptr;
   // reduction scratch
@@ -142,7 +190,7 @@ struct Ctx {
   // optional kernel timing (pairs of events per launch group)
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
-  std::vector<int> ev_kind;   // 0 electron step, 1 field solve
+  std::vector<int> ev_kind;   // 0 electron step, 1 field solve, 2 sort
   size_t ev_used = 0;
   DevTables t{};
   std::vector<void*> allocs;

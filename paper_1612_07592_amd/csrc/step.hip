@@ -18,6 +18,7 @@
 // comparison and the energy sums in FP64.
 #include "pic_internal.hpp"
 #include "philox.hpp"
+#include <type_traits>
 
 namespace pic {
 
@@ -33,6 +34,11 @@ __device__ inline double m_floor(double v) { return floor(v); }
 __device__ inline float m_floor(float v) { return floorf(v); }
 __device__ inline double m_sin(double v) { return sin(v); }
 __device__ inline float m_sin(float v) { return sinf(v); }
+// divisions and square roots: IEEE in FP64 (bit parity), hardware rate in FP32
+__device__ inline double m_div(double a, double b) { return a / b; }
+__device__ inline float m_div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ inline double m_fsqrt(double v) { return sqrt(v); }
+__device__ inline float m_fsqrt(float v) { return __builtin_amdgcn_sqrtf(v); }
 
 template <class R>
 __device__ inline R unif(uint32_t r);
@@ -49,9 +55,70 @@ struct Idx {
   }
 };
 
-// Linear interpolation of one Yee component (stagger S* = 1: half-integer).
-template <class R, int D, int SX, int SY, int SZ>
-__device__ inline R gather(const R* __restrict__ F, const R* g, const Idx<R>& I) {
+// FP32 path: contribution -> multiple of 2^-jbits in float arithmetic.
+__device__ inline int q32(float v, float scale) { return (int)rintf(v * scale); }
+
+struct GlobalCurrent32 {
+  unsigned long long* J[3];
+  Idx<float> I;
+  float scale;
+  int shift;  // 40 - jbits
+  __device__ inline void operator()(int c, int i, int j, int k, float v) const {
+    const int q = q32(v, scale);
+    if (q != 0) atomicAdd(J[c] + I(i, j, k), (unsigned long long)((long long)q << shift));
+  }
+};
+
+struct LdsCurrent32 {
+  int* T;
+  int lo0, lo1, lo2, e0, e1, nodes;
+  float scale;
+  __device__ inline void operator()(int c, int i, int j, int k, float v) const {
+    // unconditional: adding 0 is harmless and keeps the wave convergent
+    atomicAdd(T + c * nodes + (i - lo0) + e0 * ((j - lo1) + e1 * (k - lo2)), q32(v, scale));
+  }
+};
+
+// Field access: straight from the Yee arrays, or from the block's LDS box.
+template <class R>
+struct GlobalField {
+  const R* const* F;
+  Idx<R> I;
+  __device__ inline R operator()(int c, int i, int j, int k) const { return F[c][I(i, j, k)]; }
+};
+
+template <class R>
+struct LdsField {
+  const R* T;
+  int lo0, lo1, lo2, e0, e1, nodes;
+  __device__ inline R operator()(int c, int i, int j, int k) const {
+    return T[c * nodes + (i - lo0) + e0 * ((j - lo1) + e1 * (k - lo2))];
+  }
+};
+
+// Current accumulation in 2^-40 fixed point: global atomics, or LDS atomics
+// (ds_add_u64) on the block's box, flushed once per node afterwards.
+struct GlobalCurrent {
+  unsigned long long* J[3];
+  Idx<double> I;
+  __device__ inline void operator()(int c, int i, int j, int k, double v) const {
+    const long long q = __double2ll_rn(v * kJScale);
+    if (q != 0) atomicAdd(J[c] + I(i, j, k), (unsigned long long)q);
+  }
+};
+
+struct LdsCurrent {
+  unsigned long long* T;
+  int lo0, lo1, lo2, e0, e1, nodes;
+  __device__ inline void operator()(int c, int i, int j, int k, double v) const {
+    const long long q = __double2ll_rn(v * kJScale);
+    if (q != 0) atomicAdd(T + c * nodes + (i - lo0) + e0 * ((j - lo1) + e1 * (k - lo2)), (unsigned long long)q);
+  }
+};
+
+// Linear interpolation of Yee component c (stagger S* = 1: half-integer).
+template <class R, int D, int SX, int SY, int SZ, class F>
+__device__ inline R gather(const F& f, int c, const R* g) {
   int i0 = 0, i1 = 0, i2 = 0;
   R f0 = R(0), f1 = R(0), f2 = R(0);
   {
@@ -60,7 +127,7 @@ __device__ inline R gather(const R* __restrict__ F, const R* g, const Idx<R>& I)
     i0 = (int)fl;
     f0 = ga - fl;
   }
-  if (D == 1) return (R(1) - f0) * F[I(i0, 0, 0)] + f0 * F[I(i0 + 1, 0, 0)];
+  if (D == 1) return (R(1) - f0) * f(c, i0, 0, 0) + f0 * f(c, i0 + 1, 0, 0);
   {
     const R ga = g[1] - R(0.5) * R(SY);
     const R fl = m_floor(ga);
@@ -73,12 +140,12 @@ __device__ inline R gather(const R* __restrict__ F, const R* g, const Idx<R>& I)
     i2 = (int)fl;
     f2 = ga - fl;
   }
-  const R v0 = (R(1) - f0) * F[I(i0, i1, i2)] + f0 * F[I(i0 + 1, i1, i2)];
-  const R v1 = (R(1) - f0) * F[I(i0, i1 + 1, i2)] + f0 * F[I(i0 + 1, i1 + 1, i2)];
+  const R v0 = (R(1) - f0) * f(c, i0, i1, i2) + f0 * f(c, i0 + 1, i1, i2);
+  const R v1 = (R(1) - f0) * f(c, i0, i1 + 1, i2) + f0 * f(c, i0 + 1, i1 + 1, i2);
   const R a2 = (R(1) - f1) * v0 + f1 * v1;
   if (D == 2) return a2;
-  const R w0 = (R(1) - f0) * F[I(i0, i1, i2 + 1)] + f0 * F[I(i0 + 1, i1, i2 + 1)];
-  const R w1 = (R(1) - f0) * F[I(i0, i1 + 1, i2 + 1)] + f0 * F[I(i0 + 1, i1 + 1, i2 + 1)];
+  const R w0 = (R(1) - f0) * f(c, i0, i1, i2 + 1) + f0 * f(c, i0 + 1, i1, i2 + 1);
+  const R w1 = (R(1) - f0) * f(c, i0, i1 + 1, i2 + 1) + f0 * f(c, i0 + 1, i1 + 1, i2 + 1);
   const R b2 = (R(1) - f1) * w0 + f1 * w1;
   return (R(1) - f2) * a2 + f2 * b2;
 }
@@ -86,13 +153,13 @@ __device__ inline R gather(const R* __restrict__ F, const R* g, const Idx<R>& I)
 // Inverse of one NCS cumulative row: ln(xi) at uniform u.
 template <class R>
 __device__ inline R ncs_inverse(const R* __restrict__ C, const R* __restrict__ lnxi, int n, R u) {
-  if (u < C[0]) return lnxi[0] + R(3) * m_log(u / C[0]);
+  if (u < C[0]) return lnxi[0] + R(3) * m_log(m_div(u, C[0]));
   int lo = 0, hi = n - 1;
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
     if (C[mid] <= u) lo = mid; else hi = mid;
   }
-  const R t = (u - C[lo]) / (C[lo + 1] - C[lo]);
+  const R t = m_div(u - C[lo], C[lo + 1] - C[lo]);
   return lnxi[lo] + t * (lnxi[lo + 1] - lnxi[lo]);
 }
 
@@ -104,13 +171,8 @@ __device__ inline R brem_inverse(const R* __restrict__ S, int n, R u, R iny1) {
     const int mid = (lo + hi) >> 1;
     if (S[mid] <= u) lo = mid; else hi = mid;
   }
-  const R t = (u - S[lo]) / (S[lo + 1] - S[lo]);
+  const R t = m_div(u - S[lo], S[lo + 1] - S[lo]);
   return (R(lo) + t) * iny1;
-}
-
-__device__ inline void jadd(unsigned long long* J, int64_t m, double v) {
-  const long long q = __double2ll_rn(v * kJScale);
-  if (q != 0) atomicAdd(J + m, (unsigned long long)q);
 }
 
 // node weights of a point on a 4-node window starting at base
@@ -126,8 +188,124 @@ __device__ inline void shape4(R g, int base, R S[4]) {
   else { S[2] = R(1) - f; S[3] = f; }
 }
 
-template <class R, int D>
-__device__ inline void deposit(const StepParams<R>& P, const Idx<R>& I, const R* x0, const R* x1,
+// node weights of a point on a 3-node window starting at m (m = lower of the
+// two cells of the move, so the window holds both supports)
+template <class R>
+__device__ inline void shape3(R g, int m, R S[3]) {
+  const R fl = m_floor(g);
+  const int o = (int)fl - m;  // 0 or 1
+  const R f = g - fl;
+  S[0] = o == 0 ? R(1) - f : R(0);
+  S[1] = o == 0 ? f : R(1) - f;
+  S[2] = o == 0 ? R(0) : f;
+}
+
+// FP32 form of the charge-conserving deposit on the 3-node windows that the
+// move actually touches (the fourth node of the general window carries zero).
+template <int D, class Acc>
+__device__ inline void deposit3(const StepParams<float>& P, const Acc& J, const float* x0,
+                                const float* x1, const float* v, double w) {
+  const float c0 = (float)(-w * P.invV);
+  float S0[3][3], S1[3][3];
+  int m[3] = {0, 0, 0};
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const float g0 = x0[a] * (float)P.idx[a];
+    const float g1 = x1[a] * (float)P.idx[a];
+    m[a] = min((int)floorf(g0), (int)floorf(g1));
+    shape3<float>(g0, m[a], S0[a]);
+    shape3<float>(g1, m[a], S1[a]);
+  }
+  if (D == 1) {
+    const float qx = c0 * (float)P.dxdt[0];
+    float acc = 0.f;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      acc = acc - qx * (S1[0][i] - S0[0][i]);
+      J(0, m[0] + i, 0, 0, acc);
+    }
+    const float cy = c0 * v[1], cz = c0 * v[2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const float sa = 0.5f * (S0[0][i] + S1[0][i]);
+      J(1, m[0] + i, 0, 0, cy * sa);
+      J(2, m[0] + i, 0, 0, cz * sa);
+    }
+  } else if (D == 2) {
+    const float qx = c0 * (float)P.dxdt[0], qy = c0 * (float)P.dxdt[1], cz = c0 * v[2];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      float acc = 0.f;
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        acc = acc - qx * (0.5f * (S1[0][i] - S0[0][i]) * (S0[1][j] + S1[1][j]));
+        J(0, m[0] + i, m[1] + j, 0, acc);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      float acc = 0.f;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        acc = acc - qy * (0.5f * (S0[0][i] + S1[0][i]) * (S1[1][j] - S0[1][j]));
+        J(1, m[0] + i, m[1] + j, 0, acc);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const float W = (S0[0][i] * S0[1][j] + S1[0][i] * S1[1][j]) * (1.f / 3.f) +
+                        (S0[0][i] * S1[1][j] + S1[0][i] * S0[1][j]) * (1.f / 6.f);
+        J(2, m[0] + i, m[1] + j, 0, cz * W);
+      }
+  } else {
+    const float qx = c0 * (float)P.dxdt[0], qy = c0 * (float)P.dxdt[1], qz = c0 * (float)P.dxdt[2];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const float T = (S0[1][j] * S0[2][k] + S1[1][j] * S1[2][k]) * (1.f / 3.f) +
+                        (S1[1][j] * S0[2][k] + S0[1][j] * S1[2][k]) * (1.f / 6.f);
+        float acc = 0.f;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          acc = acc - qx * ((S1[0][i] - S0[0][i]) * T);
+          J(0, m[0] + i, m[1] + j, m[2] + k, acc);
+        }
+      }
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const float T = (S0[0][i] * S0[2][k] + S1[0][i] * S1[2][k]) * (1.f / 3.f) +
+                        (S1[0][i] * S0[2][k] + S0[0][i] * S1[2][k]) * (1.f / 6.f);
+        float acc = 0.f;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          acc = acc - qy * ((S1[1][j] - S0[1][j]) * T);
+          J(1, m[0] + i, m[1] + j, m[2] + k, acc);
+        }
+      }
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const float T = (S0[0][i] * S0[1][j] + S1[0][i] * S1[1][j]) * (1.f / 3.f) +
+                        (S1[0][i] * S0[1][j] + S0[0][i] * S1[1][j]) * (1.f / 6.f);
+        float acc = 0.f;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          acc = acc - qz * ((S1[2][k] - S0[2][k]) * T);
+          J(2, m[0] + i, m[1] + j, m[2] + k, acc);
+        }
+      }
+  }
+}
+
+// charge-conserving current of one electron moving x0 -> x1 (Esirkepov form)
+template <class R, int D, class Acc>
+__device__ inline void deposit(const StepParams<R>& P, const Acc& J, const R* x0, const R* x1,
                                const R* v, double w) {
   const R c0 = R(-w * P.invV);
   R S0[3][4], S1[3][4];
@@ -140,23 +318,20 @@ __device__ inline void deposit(const StepParams<R>& P, const Idx<R>& I, const R*
     shape4<R>(g0, b[a], S0[a]);
     shape4<R>(g1, b[a], S1[a]);
   }
-  unsigned long long* Jx = P.J[0];
-  unsigned long long* Jy = P.J[1];
-  unsigned long long* Jz = P.J[2];
   if (D == 1) {
     const R qx = c0 * R(P.dxdt[0]);
     R acc = R(0);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       acc = acc - qx * (S1[0][i] - S0[0][i]);
-      jadd(Jx, I(b[0] + i, 0, 0), (double)acc);
+      J(0, b[0] + i, 0, 0, acc);
     }
     const R cy = c0 * v[1], cz = c0 * v[2];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const R sa = R(0.5) * (S0[0][i] + S1[0][i]);
-      jadd(Jy, I(b[0] + i, 0, 0), (double)(cy * sa));
-      jadd(Jz, I(b[0] + i, 0, 0), (double)(cz * sa));
+      J(1, b[0] + i, 0, 0, cy * sa);
+      J(2, b[0] + i, 0, 0, cz * sa);
     }
   } else if (D == 2) {
     const R qx = c0 * R(P.dxdt[0]), qy = c0 * R(P.dxdt[1]), cz = c0 * v[2];
@@ -167,7 +342,7 @@ __device__ inline void deposit(const StepParams<R>& P, const Idx<R>& I, const R*
       for (int i = 0; i < 3; ++i) {
         const R W = R(0.5) * (S1[0][i] - S0[0][i]) * (S0[1][j] + S1[1][j]);
         acc = acc - qx * W;
-        jadd(Jx, I(b[0] + i, b[1] + j, 0), (double)acc);
+        J(0, b[0] + i, b[1] + j, 0, acc);
       }
     }
 #pragma unroll
@@ -177,7 +352,7 @@ __device__ inline void deposit(const StepParams<R>& P, const Idx<R>& I, const R*
       for (int j = 0; j < 3; ++j) {
         const R W = R(0.5) * (S0[0][i] + S1[0][i]) * (S1[1][j] - S0[1][j]);
         acc = acc - qy * W;
-        jadd(Jy, I(b[0] + i, b[1] + j, 0), (double)acc);
+        J(1, b[0] + i, b[1] + j, 0, acc);
       }
     }
 #pragma unroll
@@ -186,7 +361,7 @@ __device__ inline void deposit(const StepParams<R>& P, const Idx<R>& I, const R*
       for (int i = 0; i < 4; ++i) {
         const R W = (S0[0][i] * S0[1][j] + S1[0][i] * S1[1][j]) * R(1.0 / 3.0) +
                     (S0[0][i] * S1[1][j] + S1[0][i] * S0[1][j]) * R(1.0 / 6.0);
-        jadd(Jz, I(b[0] + i, b[1] + j, 0), (double)(cz * W));
+        J(2, b[0] + i, b[1] + j, 0, cz * W);
       }
   } else {
     const R qx = c0 * R(P.dxdt[0]), qy = c0 * R(P.dxdt[1]), qz = c0 * R(P.dxdt[2]);
@@ -197,7 +372,7 @@ __device__ inline void deposit(const StepParams<R>& P, const Idx<R>& I, const R*
           const R T = (S0[1][j] * S0[2][k] + S1[1][j] * S1[2][k]) * R(1.0 / 3.0) +
                       (S1[1][j] * S0[2][k] + S0[1][j] * S1[2][k]) * R(1.0 / 6.0);
           acc = acc - qx * ((S1[0][i] - S0[0][i]) * T);
-          jadd(Jx, I(b[0] + i, b[1] + j, b[2] + k), (double)acc);
+          J(0, b[0] + i, b[1] + j, b[2] + k, acc);
         }
       }
     for (int k = 0; k < 4; ++k)
@@ -207,7 +382,7 @@ __device__ inline void deposit(const StepParams<R>& P, const Idx<R>& I, const R*
           const R T = (S0[0][i] * S0[2][k] + S1[0][i] * S1[2][k]) * R(1.0 / 3.0) +
                       (S1[0][i] * S0[2][k] + S0[0][i] * S1[2][k]) * R(1.0 / 6.0);
           acc = acc - qy * ((S1[1][j] - S0[1][j]) * T);
-          jadd(Jy, I(b[0] + i, b[1] + j, b[2] + k), (double)acc);
+          J(1, b[0] + i, b[1] + j, b[2] + k, acc);
         }
       }
     for (int j = 0; j < 4; ++j)
@@ -217,7 +392,7 @@ __device__ inline void deposit(const StepParams<R>& P, const Idx<R>& I, const R*
           const R T = (S0[0][i] * S0[1][j] + S1[0][i] * S1[1][j]) * R(1.0 / 3.0) +
                       (S1[0][i] * S0[1][j] + S0[0][i] * S1[1][j]) * R(1.0 / 6.0);
           acc = acc - qz * ((S1[2][k] - S0[2][k]) * T);
-          jadd(Jz, I(b[0] + i, b[1] + j, b[2] + k), (double)acc);
+          J(2, b[0] + i, b[1] + j, b[2] + k, acc);
         }
       }
   }
@@ -240,198 +415,332 @@ __device__ inline uint32_t lane_offset(unsigned long long mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-template <class R, int D>
-__global__ __launch_bounds__(kBlock) void k_electron_step(const StepParams<R> P) {
-  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const Idx<R> I{P.gg[0], P.gg[1], P.gg[2], P.sz[0], P.sz[1]};
-  bool live = false;
-  uint32_t idv = 0;
-  if (e < P.N) {
-    idv = P.id[e];
-    live = (idv & kDead) == 0;
-  }
-  // per-lane emission results
+// Per-electron results the block-level stages (append, statistics) need.
+template <class R>
+struct Emit {
   bool ev_ncs = false, ev_br = false, keep_ncs = false, clamped = false;
-  R ph_e[2] = {R(0), R(0)};
-  R ph_k[2][3] = {{R(0), R(0), R(0)}, {R(0), R(0), R(0)}};
+  R e[2] = {R(0), R(0)};
+  R k[2][3] = {{R(0), R(0), R(0)}, {R(0), R(0), R(0)}};
   R xo[3] = {R(0), R(0), R(0)};
-  double wgt = 0.0;
+};
 
-  if (live) {
-    const uint32_t n = P.step;
-    const U4 r = philox4x32_10(idv, n, 0u, 0u, P.key0, P.key1);
-    R x[3] = {R(0), R(0), R(0)};
-#pragma unroll
-    for (int a = 0; a < D; ++a) x[a] = P.x[a][e];
-    xo[0] = x[0]; xo[1] = x[1]; xo[2] = x[2];
-    R px = P.p[0][e], py = P.p[1][e], pz = P.p[2][e];
-    wgt = P.w[e];
+// One electron: gather, Boris, eta, NCS, bremsstrahlung, recoil, move, deposit.
+template <class R, int D, class FA, class JA>
+__device__ inline void electron_physics(const StepParams<R>& P, int64_t e, uint32_t idv, double wgt,
+                                        const R* xin, const FA& fld, const JA& cur, Emit<R>& out) {
+  const uint32_t n = P.step;
+  // Philox words of (id, step): drawn only when a test or an event needs them
+  U4 r;
+  bool have_r = false;
+  auto draw = [&]() {
+    if (!have_r) { r = philox4x32_10(idv, n, 0u, 0u, P.key0, P.key1); have_r = true; }
+  };
+  R x[3] = {xin[0], xin[1], xin[2]};
+  out.xo[0] = x[0]; out.xo[1] = x[1]; out.xo[2] = x[2];
+  R px = P.p[0][e], py = P.p[1][e], pz = P.p[2][e];
 
-    // ---- gather E^n, B^n at x^n --------------------------------------------
-    R E0, E1, E2, B0, B1, B2;
-    if (P.flags & PIC_FIELDS_FROZEN) {
-      if (P.frozen_kind == PIC_FROZEN_UNIFORM) {
-        E0 = R(P.fE[0]); E1 = R(P.fE[1]); E2 = R(P.fE[2]);
-        B0 = R(P.fB[0]); B1 = R(P.fB[1]); B2 = R(P.fB[2]);
-      } else {
-        E0 = R(0); E1 = R(0); E2 = R(0); B0 = R(0); B1 = R(0); B2 = R(0);
-        const R phi = R(P.tn) - x[0];
-        if (phi > R(0)) {
-          const R v = R(P.fa) * m_sin(phi);
-          E1 = v;
-          B2 = v;
-        }
-      }
+  // ---- gather E^n, B^n at x^n ----------------------------------------------
+  R E0, E1, E2, B0, B1, B2;
+  if (P.flags & PIC_FIELDS_FROZEN) {
+    if (P.frozen_kind == PIC_FROZEN_UNIFORM) {
+      E0 = R(P.fE[0]); E1 = R(P.fE[1]); E2 = R(P.fE[2]);
+      B0 = R(P.fB[0]); B1 = R(P.fB[1]); B2 = R(P.fB[2]);
     } else {
-      R g[3] = {R(0), R(0), R(0)};
-#pragma unroll
-      for (int a = 0; a < D; ++a) g[a] = x[a] * R(P.idx[a]);
-      E0 = gather<R, D, 1, 0, 0>(P.E[0], g, I);
-      E1 = gather<R, D, 0, 1, 0>(P.E[1], g, I);
-      E2 = gather<R, D, 0, 0, 1>(P.E[2], g, I);
-      B0 = gather<R, D, 0, 1, 1>(P.B[0], g, I);
-      B1 = gather<R, D, 1, 0, 1>(P.B[1], g, I);
-      B2 = gather<R, D, 1, 1, 0>(P.B[2], g, I);
-    }
-
-    // ---- relativistic Boris push (q = -1, m = 1) ----------------------------
-    const R hq = R(-0.5 * P.dt);
-    const R umx = px + hq * E0, umy = py + hq * E1, umz = pz + hq * E2;
-    const R gm = m_sqrt(R(1) + (umx * umx + umy * umy + umz * umz));
-    const R fq = hq / gm;
-    const R tx = fq * B0, ty = fq * B1, tz = fq * B2;
-    const R sf = R(2) / (R(1) + (tx * tx + ty * ty + tz * tz));
-    const R sx = sf * tx, sy = sf * ty, sz = sf * tz;
-    const R upx = umx + (umy * tz - umz * ty);
-    const R upy = umy + (umz * tx - umx * tz);
-    const R upz = umz + (umx * ty - umy * tx);
-    const R uqx = umx + (upy * sz - upz * sy);
-    const R uqy = umy + (upz * sx - upx * sz);
-    const R uqz = umz + (upx * sy - upy * sx);
-    px = uqx + hq * E0;
-    py = uqy + hq * E1;
-    pz = uqz + hq * E2;
-    R gamma = m_sqrt(R(1) + (px * px + py * py + pz * pz));
-
-    // ---- quantum parameter eta (Lorentz invariant, Sec. II.A) ---------------
-    const R cx = gamma * E0 + (py * B2 - pz * B1);
-    const R cy = gamma * E1 + (pz * B0 - px * B2);
-    const R cz = gamma * E2 + (px * B1 - py * B0);
-    const R pe = px * E0 + py * E1 + pz * E2;
-    R q2 = (cx * cx + cy * cy + cz * cz) - pe * pe;
-    if (q2 < R(0)) q2 = R(0);
-    const R eta = m_sqrt(q2) * R(P.iES);
-
-    // ---- nonlinear Compton: optical depth + inverse-CDF draw ----------------
-    if (P.flags & PIC_NCS) {
-      const R sl = (m_log(eta) - R(P.ln_eta0)) * R(P.idln_eta);
-      if (sl >= R(0)) {
-        int i;
-        R f;
-        if (sl >= R(P.n_eta - 1)) { i = P.n_eta - 2; f = R(1); }
-        else { i = (int)sl; f = sl - R(i); }
-        const R h = P.h[i] + f * (P.h[i + 1] - P.h[i]);
-        const R dtau = R(P.K_N) * eta / gamma * h * R(P.dt);
-        double tau = P.tau[e] - (double)dtau;
-        if (tau <= 0.0) {
-          const R u2 = unif<R>(r.v[2]);
-          const R la = ncs_inverse<R>(P.ncs + (int64_t)i * P.n_xi, P.lnxi, P.n_xi, u2);
-          const R lb = ncs_inverse<R>(P.ncs + (int64_t)(i + 1) * P.n_xi, P.lnxi, P.n_xi, u2);
-          const R lx = la + f * (lb - la);
-          const R xi = m_exp(lx);
-          R eps = xi * gamma;
-          if (eps > gamma - R(1)) eps = gamma - R(1);
-          const R pm = m_sqrt(px * px + py * py + pz * pz);
-          ev_ncs = true;
-          ph_e[0] = eps;
-          ph_k[0][0] = px / pm; ph_k[0][1] = py / pm; ph_k[0][2] = pz / pm;
-          keep_ncs = (double)eps >= P.photon_cut;
-          if (!(P.flags & PIC_NO_RECOIL)) {
-            const R gn = gamma - eps;
-            const R pn = m_sqrt((gn - R(1)) * (gn + R(1)));
-            const R sc = pn / pm;
-            px = px * sc; py = py * sc; pz = pz * sc;
-            gamma = gn;
-          }
-          tau = -log(unif32(r.v[3]));
-        }
-        P.tau[e] = tau;
+      E0 = R(0); E1 = R(0); E2 = R(0); B0 = R(0); B1 = R(0); B2 = R(0);
+      const R phi = R(P.tn) - x[0];
+      if (phi > R(0)) {
+        const R v = R(P.fa) * m_sin(phi);
+        E1 = v;
+        B2 = v;
       }
     }
-
-    // ---- bremsstrahlung: Eq. (4) test, R2 energy draw (Sec. II.B) -----------
-    if (P.flags & PIC_BREM) {
-      const R T = gamma - R(1);
-      if ((double)T >= P.k_cut) {
-        int ci[3] = {0, 0, 0};
+  } else {
+    R g[3] = {R(0), R(0), R(0)};
 #pragma unroll
-        for (int a = 0; a < D; ++a) {
-          int q = (int)m_floor(x[a] * R(P.idx[a]));
-          q = q < 0 ? 0 : (q > P.n[a] - 1 ? P.n[a] - 1 : q);
-          ci[a] = q;
+    for (int a = 0; a < D; ++a) g[a] = x[a] * R(P.idx[a]);
+    E0 = gather<R, D, 1, 0, 0>(fld, 0, g);
+    E1 = gather<R, D, 0, 1, 0>(fld, 1, g);
+    E2 = gather<R, D, 0, 0, 1>(fld, 2, g);
+    B0 = gather<R, D, 0, 1, 1>(fld, 3, g);
+    B1 = gather<R, D, 1, 0, 1>(fld, 4, g);
+    B2 = gather<R, D, 1, 1, 0>(fld, 5, g);
+  }
+
+  // ---- relativistic Boris push (q = -1, m = 1) ------------------------------
+  const R hq = R(-0.5 * P.dt);
+  const R umx = px + hq * E0, umy = py + hq * E1, umz = pz + hq * E2;
+  const R gm = m_fsqrt(R(1) + (umx * umx + umy * umy + umz * umz));
+  const R fq = m_div(hq, gm);
+  const R tx = fq * B0, ty = fq * B1, tz = fq * B2;
+  const R sf = m_div(R(2), R(1) + (tx * tx + ty * ty + tz * tz));
+  const R sx = sf * tx, sy = sf * ty, sz = sf * tz;
+  const R upx = umx + (umy * tz - umz * ty);
+  const R upy = umy + (umz * tx - umx * tz);
+  const R upz = umz + (umx * ty - umy * tx);
+  const R uqx = umx + (upy * sz - upz * sy);
+  const R uqy = umy + (upz * sx - upx * sz);
+  const R uqz = umz + (upx * sy - upy * sx);
+  px = uqx + hq * E0;
+  py = uqy + hq * E1;
+  pz = uqz + hq * E2;
+  R gamma = m_fsqrt(R(1) + (px * px + py * py + pz * pz));
+
+  // ---- quantum parameter eta (Lorentz invariant, Sec. II.A) -----------------
+  const R cx = gamma * E0 + (py * B2 - pz * B1);
+  const R cy = gamma * E1 + (pz * B0 - px * B2);
+  const R cz = gamma * E2 + (px * B1 - py * B0);
+  const R pe = px * E0 + py * E1 + pz * E2;
+  R q2 = (cx * cx + cy * cy + cz * cz) - pe * pe;
+  if (q2 < R(0)) q2 = R(0);
+  const R eta = m_fsqrt(q2) * R(P.iES);
+
+  // ---- nonlinear Compton: optical depth + inverse-CDF draw ------------------
+  // eta clearly below the first table point: no decrement (same decision as
+  // the logarithm test below, without evaluating it)
+  if ((P.flags & PIC_NCS) && (double)eta >= P.eta_skip) {
+    const R sl = (m_log(eta) - R(P.ln_eta0)) * R(P.idln_eta);
+    if (sl >= R(0)) {
+      int i;
+      R f;
+      if (sl >= R(P.n_eta - 1)) { i = P.n_eta - 2; f = R(1); }
+      else { i = (int)sl; f = sl - R(i); }
+      const R h = P.h[i] + f * (P.h[i + 1] - P.h[i]);
+      const R dtau = m_div(R(P.K_N) * eta, gamma) * h * R(P.dt);
+      double tau = P.tau[e] - (double)dtau;
+      if (tau <= 0.0) {
+        draw();
+        const R u2 = unif<R>(r.v[2]);
+        const R la = ncs_inverse<R>(P.ncs + (int64_t)i * P.n_xi, P.lnxi, P.n_xi, u2);
+        const R lb = ncs_inverse<R>(P.ncs + (int64_t)(i + 1) * P.n_xi, P.lnxi, P.n_xi, u2);
+        const R lx = la + f * (lb - la);
+        const R xi = m_exp(lx);
+        R eps = xi * gamma;
+        if (eps > gamma - R(1)) eps = gamma - R(1);
+        const R pm = m_sqrt(px * px + py * py + pz * pz);
+        out.ev_ncs = true;
+        out.e[0] = eps;
+        out.k[0][0] = m_div(px, pm); out.k[0][1] = m_div(py, pm); out.k[0][2] = m_div(pz, pm);
+        out.keep_ncs = (double)eps >= P.photon_cut;
+        if (!(P.flags & PIC_NO_RECOIL)) {
+          const R gn = gamma - eps;
+          const R pn = m_sqrt((gn - R(1)) * (gn + R(1)));
+          const R sc = m_div(pn, pm);
+          px = px * sc; py = py * sc; pz = pz * sc;
+          gamma = gn;
         }
-        const double ni = P.ni[ci[0] + (int64_t)P.n[0] * (ci[1] + (int64_t)P.n[1] * ci[2])];
-        if (ni > 0.0) {
-          const R lt = m_log(T);
-          const R sl = (lt - R(P.ln_T0)) * R(P.idln_T);
-          if (sl >= R(0)) {
-            int i;
-            R f;
-            if (sl >= R(P.n_T - 1)) { i = P.n_T - 2; f = R(1); clamped = true; }
-            else { i = (int)sl; f = sl - R(i); }
-            const R sig = P.sig[i] + f * (P.sig[i + 1] - P.sig[i]);
-            if (sig > R(0)) {
-              const R pm = m_sqrt(px * px + py * py + pz * pz);
-              const R v = pm / gamma;
-              const R X = R(P.K_BR) * R(ni) * sig * v * R(P.dt);
-              const R Pb = -m_expm1(-X);
-              if (unif52(r.v[0], r.v[1]) < (double)Pb) {
-                const U4 r2 = philox4x32_10(idv, n, 1u, 0u, P.key0, P.key1);
-                const R u = unif<R>(r2.v[0]);
-                const R sa = brem_inverse<R>(P.br + (int64_t)i * P.n_y, P.n_y, u, R(P.iny1));
-                const R sb = brem_inverse<R>(P.br + (int64_t)(i + 1) * P.n_y, P.n_y, u, R(P.iny1));
-                const R sv = sa + f * (sb - sa);
-                const R lk = R(P.lnk);
-                R eps = m_exp(lk + sv * (lt - lk));
-                if (eps > T) eps = T;
-                ev_br = true;
-                ph_e[1] = eps;
-                ph_k[1][0] = px / pm; ph_k[1][1] = py / pm; ph_k[1][2] = pz / pm;
-                if (!(P.flags & PIC_NO_RECOIL)) {
-                  const R gn = gamma - eps;
-                  const R pn = m_sqrt((gn - R(1)) * (gn + R(1)));
-                  const R sc = pn / pm;
-                  px = px * sc; py = py * sc; pz = pz * sc;
-                  gamma = gn;
-                }
+        tau = -log(unif32(r.v[3]));
+      }
+      P.tau[e] = tau;
+    }
+  }
+
+  // ---- bremsstrahlung: Eq. (4) test, R2 energy draw (Sec. II.B) -------------
+  if (P.flags & PIC_BREM) {
+    const R T = gamma - R(1);
+    if ((double)T >= P.k_cut) {
+      int ci[3] = {0, 0, 0};
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        int q = (int)m_floor(x[a] * R(P.idx[a]));
+        q = q < 0 ? 0 : (q > P.n[a] - 1 ? P.n[a] - 1 : q);
+        ci[a] = q;
+      }
+      const double ni = P.ni[ci[0] + (int64_t)P.n[0] * (ci[1] + (int64_t)P.n[1] * ci[2])];
+      if (ni > 0.0) {
+        const R lt = m_log(T);
+        const R sl = (lt - R(P.ln_T0)) * R(P.idln_T);
+        if (sl >= R(0)) {
+          int i;
+          R f;
+          if (sl >= R(P.n_T - 1)) { i = P.n_T - 2; f = R(1); out.clamped = true; }
+          else { i = (int)sl; f = sl - R(i); }
+          const R sig = P.sig[i] + f * (P.sig[i + 1] - P.sig[i]);
+          if (sig > R(0)) {
+            const R pm = m_sqrt(px * px + py * py + pz * pz);
+            const R v = m_div(pm, gamma);
+            const R X = R(P.K_BR) * R(ni) * sig * v * R(P.dt);
+            const R Pb = -m_expm1(-X);
+            draw();
+            if (unif52(r.v[0], r.v[1]) < (double)Pb) {
+              const U4 r2 = philox4x32_10(idv, n, 1u, 0u, P.key0, P.key1);
+              const R u = unif<R>(r2.v[0]);
+              const R sa = brem_inverse<R>(P.br + (int64_t)i * P.n_y, P.n_y, u, R(P.iny1));
+              const R sb = brem_inverse<R>(P.br + (int64_t)(i + 1) * P.n_y, P.n_y, u, R(P.iny1));
+              const R sv = sa + f * (sb - sa);
+              const R lk = R(P.lnk);
+              R eps = m_exp(lk + sv * (lt - lk));
+              if (eps > T) eps = T;
+              out.ev_br = true;
+              out.e[1] = eps;
+              out.k[1][0] = m_div(px, pm); out.k[1][1] = m_div(py, pm); out.k[1][2] = m_div(pz, pm);
+              if (!(P.flags & PIC_NO_RECOIL)) {
+                const R gn = gamma - eps;
+                const R pn = m_sqrt((gn - R(1)) * (gn + R(1)));
+                const R sc = m_div(pn, pm);
+                px = px * sc; py = py * sc; pz = pz * sc;
+                gamma = gn;
               }
             }
           }
         }
       }
     }
+  }
 
-    // ---- move, deposit, absorbing walls -----------------------------------
-    P.p[0][e] = px; P.p[1][e] = py; P.p[2][e] = pz;
-    const R ig = R(1) / gamma;
-    const R v[3] = {px * ig, py * ig, pz * ig};
-    R x1[3] = {x[0], x[1], x[2]};
-    bool out = false;
+  // ---- move, deposit, absorbing walls ---------------------------------------
+  P.p[0][e] = px; P.p[1][e] = py; P.p[2][e] = pz;
+  const R ig = m_div(R(1), gamma);
+  const R v[3] = {px * ig, py * ig, pz * ig};
+  R x1[3] = {x[0], x[1], x[2]};
+  bool outside = false;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    x1[a] = x[a] + v[a] * R(P.dt);
+    if (x1[a] < R(0) || x1[a] >= R(P.L[a])) outside = true;
+  }
+  if (!(P.flags & PIC_FIELDS_FROZEN)) {
+    if constexpr (sizeof(R) == 4) deposit3<D>(P, cur, x, x1, v, wgt);
+    else deposit<R, D>(P, cur, x, x1, v, wgt);
+  }
+#pragma unroll
+  for (int a = 0; a < D; ++a) P.x[a][e] = x1[a];
+  if (outside) P.id[e] = idv | kDead;
+}
+
+// One workgroup = one chunk of 256 consecutive electrons of the (tile-sorted)
+// SoA.  Chunks are spread so that each XCD (blockIdx % 8) owns a contiguous
+// run of chunks, i.e. a compact region of the grid for its L2.  Inside a chunk
+// electrons are dealt to lanes with a stride of 16, so the 64 lanes of a wave
+// come from many cells and rarely hit the same LDS current node at once.
+// When the chunk's cells fit the LDS box, the fields of the box are staged in
+// LDS and the current is accumulated there (FP64: int64 in units of 2^-40;
+// FP32: int32 in units of 2^-jbits); otherwise both go to global memory.
+template <class R, int D>
+__global__ __launch_bounds__(kBlock) void k_electron_step(const StepParams<R> P) {
+  constexpr bool kF32 = sizeof(R) == 4;
+  using JT = typename std::conditional<kF32, int, unsigned long long>::type;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int s_lo[3], s_hi[3];
+  const uint32_t per = gridDim.x >> 3;
+  const uint32_t chunk = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
+  const uint32_t t = threadIdx.x;
+  const int64_t e = (int64_t)chunk * kBlock + (int64_t)((t & 15u) * 16u + (t >> 4));
+  const int64_t n_act = (int64_t)*P.n_active;
+  const bool frozen = (P.flags & PIC_FIELDS_FROZEN) != 0;
+  bool live = false;
+  uint32_t idv = 0;
+  if (e < n_act) {
+    idv = P.id[e];
+    live = (idv & kDead) == 0;
+  }
+  R x[3] = {R(0), R(0), R(0)};
+  int bb[3] = {0, 0, 0};
+  if (live) {
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      x1[a] = x[a] + v[a] * R(P.dt);
-      if (x1[a] < R(0) || x1[a] >= R(P.L[a])) out = true;
+      x[a] = P.x[a][e];
+      bb[a] = (int)m_floor(x[a] * R(P.idx[a])) - 1;
     }
-    if (!(P.flags & PIC_FIELDS_FROZEN)) deposit<R, D>(P, I, x, x1, v, wgt);
+  }
+  // ---- the chunk's box of nodes (deposit windows cover the gathers) --------
+  if (t < 3) { s_lo[t] = 0x7fffffff; s_hi[t] = -0x7fffffff; }
+  __syncthreads();
+  if (live && !frozen) {
 #pragma unroll
-    for (int a = 0; a < D; ++a) P.x[a][e] = x1[a];
-    if (out) P.id[e] = idv | kDead;
+    for (int a = 0; a < D; ++a) {
+      atomicMin(&s_lo[a], bb[a]);
+      atomicMax(&s_hi[a], bb[a] + 3);
+    }
+  }
+  __syncthreads();
+  int lo[3] = {0, 0, 0}, ext[3] = {1, 1, 1};
+  int nodes = 0;
+  bool tiled = false;
+  if (!frozen && P.lds_nodes > 0 && s_lo[0] <= s_hi[0]) {
+    nodes = 1;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      lo[a] = s_lo[a];
+      ext[a] = s_hi[a] - s_lo[a] + 1;
+      nodes *= ext[a];
+    }
+    tiled = nodes <= P.lds_nodes;
+  }
+  R* sF = reinterpret_cast<R*>(smem);
+  JT* sJ = reinterpret_cast<JT*>(smem + (size_t)6 * P.lds_nodes * sizeof(R));
+  const Idx<R> I{P.gg[0], P.gg[1], P.gg[2], P.sz[0], P.sz[1]};
+  // node l of the box -> (i, j, k); exact float-reciprocal division (l < 2^20)
+  const float r0 = 1.0f / (float)ext[0], r1 = 1.0f / (float)ext[1];
+  auto decode = [&](int l, int& i, int& j, int& k) {
+    const int q0 = (int)(((float)l + 0.5f) * r0);
+    i = l - q0 * ext[0] + lo[0];
+    if (D == 1) { j = 0; k = 0; return; }
+    const int q1 = (int)(((float)q0 + 0.5f) * r1);
+    j = q0 - q1 * ext[1] + lo[1];
+    k = (D == 3 ? q1 : 0) + lo[2];
+  };
+  if (tiled) {
+    for (int l = t; l < nodes; l += kBlock) {
+      int i, j, k;
+      decode(l, i, j, k);
+      const int64_t m = I(i, j, k);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        sF[c * nodes + l] = P.F[c][m];
+        sF[(3 + c) * nodes + l] = P.F[3 + c][m];
+        sJ[c * nodes + l] = JT(0);
+      }
+    }
+  }
+  __syncthreads();
+
+  Emit<R> out;
+  double wgt = 0.0;
+  if (live) {
+    wgt = P.w[e];
+    if (tiled) {
+      const LdsField<R> fa{sF, lo[0], lo[1], lo[2], ext[0], ext[1], nodes};
+      if constexpr (kF32) {
+        const LdsCurrent32 ja{reinterpret_cast<int*>(sJ), lo[0], lo[1], lo[2], ext[0], ext[1], nodes,
+                              (float)ldexp(1.0, P.jbits)};
+        electron_physics<R, D>(P, e, idv, wgt, x, fa, ja, out);
+      } else {
+        const LdsCurrent ja{reinterpret_cast<unsigned long long*>(sJ), lo[0], lo[1], lo[2], ext[0], ext[1], nodes};
+        electron_physics<R, D>(P, e, idv, wgt, x, fa, ja, out);
+      }
+    } else {
+      const GlobalField<R> fa{P.F, I};
+      if constexpr (kF32) {
+        const GlobalCurrent32 ja{{P.J[0], P.J[1], P.J[2]}, {P.gg[0], P.gg[1], P.gg[2], P.sz[0], P.sz[1]},
+                                 (float)ldexp(1.0, P.jbits), 40 - P.jbits};
+        electron_physics<R, D>(P, e, idv, wgt, x, fa, ja, out);
+      } else {
+        const GlobalCurrent ja{{P.J[0], P.J[1], P.J[2]}, {P.gg[0], P.gg[1], P.gg[2], P.sz[0], P.sz[1]}};
+        electron_physics<R, D>(P, e, idv, wgt, x, fa, ja, out);
+      }
+    }
+  }
+  __syncthreads();
+  if (tiled) {  // flush the LDS current: one global atomic per touched node
+    for (int l = t; l < nodes; l += kBlock) {
+      int i, j, k;
+      decode(l, i, j, k);
+      const int64_t m = I(i, j, k);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const JT q = sJ[c * nodes + l];
+        if (q != JT(0)) {
+          if constexpr (kF32) atomicAdd(P.J[c] + m, (unsigned long long)((long long)q << (40 - P.jbits)));
+          else atomicAdd(P.J[c] + m, q);
+        }
+      }
+    }
   }
 
   // ---- photon append: one atomic per wave and process ---------------------
   const uint32_t lane = __lane_id();
-  const bool rec0 = ev_ncs && keep_ncs;
-  const bool rec1 = ev_br;
+  const bool rec0 = out.ev_ncs && out.keep_ncs;
+  const bool rec1 = out.ev_br;
 #pragma unroll
   for (int proc = 0; proc < 2; ++proc) {
     const bool rec = proc == 0 ? rec0 : rec1;
@@ -445,10 +754,10 @@ __global__ __launch_bounds__(kBlock) void k_electron_step(const StepParams<R> P)
       if (slot < P.pcap) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          P.px[a][slot] = xo[a];
-          P.pk[a][slot] = ph_k[proc][a];
+          P.px[a][slot] = out.xo[a];
+          P.pk[a][slot] = out.k[proc][a];
         }
-        P.pe[slot] = ph_e[proc];
+        P.pe[slot] = out.e[proc];
         P.pw[slot] = wgt;
         P.pstep[slot] = P.step;
         P.ppar[slot] = idv;
@@ -460,17 +769,20 @@ __global__ __launch_bounds__(kBlock) void k_electron_step(const StepParams<R> P)
   // ---- per-wave statistics slot --------------------------------------------
   const unsigned long long m_live = __ballot(live);
   if (m_live == 0ull) return;  // wave-uniform
-  const int64_t slot = e >> 6;
-  const unsigned long long m_ncs = __ballot(ev_ncs);
-  const unsigned long long m_br = __ballot(ev_br);
-  const unsigned long long m_cl = __ballot(clamped);
+  const int64_t slot = (int64_t)chunk * (kBlock / 64) + (t >> 6);
+  const unsigned long long m_ncs = __ballot(out.ev_ncs);
+  const unsigned long long m_br = __ballot(out.ev_br);
+  const unsigned long long m_cl = __ballot(out.clamped);
   unsigned long long* C = P.slot_cnt + slot * kSlotCnt;
-  if (lane == 0) C[SC_ESTEPS] += (unsigned long long)__popcll(m_live);
+  if (lane == 0) {
+    C[SC_ESTEPS] += (unsigned long long)__popcll(m_live);
+    if (!tiled && !frozen) C[SC_UNTILED] += (unsigned long long)__popcll(m_live);
+  }
   if ((m_ncs | m_br | m_cl) == 0ull) return;  // wave-uniform
-  const unsigned long long m_keep = __ballot(ev_ncs && keep_ncs);
-  const double e_keep0 = (ev_ncs && keep_ncs) ? wgt * (double)ph_e[0] : 0.0;
-  const double e_drop = (ev_ncs && !keep_ncs) ? wgt * (double)ph_e[0] : 0.0;
-  const double e_keep1 = ev_br ? wgt * (double)ph_e[1] : 0.0;
+  const unsigned long long m_keep = __ballot(rec0);
+  const double e_keep0 = rec0 ? wgt * (double)out.e[0] : 0.0;
+  const double e_drop = (out.ev_ncs && !out.keep_ncs) ? wgt * (double)out.e[0] : 0.0;
+  const double e_keep1 = out.ev_br ? wgt * (double)out.e[1] : 0.0;
   const double s0 = wave_sum(e_keep0), s1 = wave_sum(e_keep1), s2 = wave_sum(e_drop);
   if (lane == 0) {
     C[SC_EV_NCS] += (unsigned long long)__popcll(m_ncs);
@@ -479,10 +791,10 @@ __global__ __launch_bounds__(kBlock) void k_electron_step(const StepParams<R> P)
     C[SC_KEPT_BR] += (unsigned long long)__popcll(m_br);
     C[SC_DROPPED] += (unsigned long long)__popcll(m_ncs & ~m_keep);
     C[SC_CLAMPED] += (unsigned long long)__popcll(m_cl);
-    double* S = P.slot_sum + slot * kSlotSum;
-    if (m_keep) neumaier(S + 0, S + 1, s0);
-    if (m_br) neumaier(S + 2, S + 3, s1);
-    if (m_ncs & ~m_keep) neumaier(S + 4, S + 5, s2);
+    double* Sm = P.slot_sum + slot * kSlotSum;
+    if (m_keep) neumaier(Sm + 0, Sm + 1, s0);
+    if (m_br) neumaier(Sm + 2, Sm + 3, s1);
+    if (m_ncs & ~m_keep) neumaier(Sm + 4, Sm + 5, s2);
   }
 }
 
@@ -490,8 +802,11 @@ template <class R, int D>
 static void launch_one(const void* params, hipStream_t s) {
   const StepParams<R>& P = *static_cast<const StepParams<R>*>(params);
   if (P.N <= 0) return;
-  const int64_t blocks = (P.N + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL((k_electron_step<R, D>), dim3((unsigned)blocks), dim3(kBlock), 0, s, P);
+  int64_t blocks = (P.N + kBlock - 1) / kBlock;
+  blocks = (blocks + 7) / 8 * 8;  // XCD-aware chunk mapping needs a multiple of 8
+  const size_t jsz = sizeof(R) == 4 ? sizeof(int) : sizeof(unsigned long long);
+  const size_t lds = (size_t)P.lds_nodes * (6 * sizeof(R) + 3 * jsz);
+  hipLaunchKernelGGL((k_electron_step<R, D>), dim3((unsigned)blocks), dim3(kBlock), lds, s, P);
 }
 
 void launch_step(int dims, bool fp32, const void* params, hipStream_t s) {
