@@ -54,7 +54,7 @@ def _num_electrons(w):
     return W.num_electrons(w)
 
 
-def run_gpu(w, tables, steps, warmup, torch):
+def run_gpu(w, tables, steps, warmup, torch, photons=False):
     from paper_1612_07592_amd import binding
     if warmup > 0:
         s = binding.Sim(w, tables)
@@ -63,16 +63,73 @@ def run_gpu(w, tables, steps, warmup, torch):
         s.pic_destroy()
     s = binding.Sim(w, tables)
     s.profile(True)
+    s.synchronize()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s.pic_step(steps)
+    s.synchronize()          # libpic's own HIP runtime (torch's does not see its queues)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     st = s.pic_emission_stats()
     ms, n = s.profile_read()
+    ph = s.photons() if photons else None
     s.pic_destroy()
     return dict(wall_s=t1 - t0, stats=st, step_kernel_ms=float(ms[0]), field_ms=float(ms[1]),
-                sort_ms=float(ms[2]), step_launches=int(n[0]))
+                sort_ms=float(ms[2]), step_launches=int(n[0]), photons=ph)
+
+
+def precision_check(r32, r64):
+    """FP32-mixed against FP64 on the same workload and Philox streams:
+    kept-photon count within 3 sigma (Poisson), photon-energy spectrum
+    two-sample KS p > 0.01, total radiated energy within 1%."""
+    from scipy import stats as sst
+    s32, s64 = r32["stats"], r64["stats"]
+    n32, n64 = sum(s32["kept"]), sum(s64["kept"])
+    sigma = max(n64, 1) ** 0.5
+    e32 = s32["e_rad_kept"][0] + s32["e_rad_kept"][1] + s32["e_rad_dropped"]
+    e64 = s64["e_rad_kept"][0] + s64["e_rad_kept"][1] + s64["e_rad_dropped"]
+    out = {"photon_count": {"fp32": n32, "fp64": n64, "z": (n32 - n64) / sigma,
+                            "pass": abs(n32 - n64) <= 3 * sigma},
+           "radiated_energy": {"fp32": e32, "fp64": e64, "rel": (e32 - e64) / e64 if e64 else None,
+                               "pass": bool(e64) and abs(e32 - e64) <= 0.01 * abs(e64)}}
+    p32, p64 = r32["photons"], r64["photons"]
+    if p32 is not None and p64 is not None and len(p32["energy"]) and len(p64["energy"]):
+        ks = sst.ks_2samp(p32["energy"], p64["energy"])
+        out["spectrum_ks"] = {"statistic": float(ks.statistic), "p": float(ks.pvalue),
+                              "n": [len(p32["energy"]), len(p64["energy"])],
+                              "pass": float(ks.pvalue) > 0.01}
+    else:
+        out["spectrum_ks"] = {"p": None, "pass": None, "n": [0, 0]}
+    return out
+
+
+def serving(args, torch):
+    """Scan jobs through the continuous-batching server: the 8-job
+    intensity x target batch (FP32, FP64, and FP32 one job after another),
+    then the first --c4-jobs jobs of the Poisson stream."""
+    from paper_1612_07592_amd import binding, serving as SV
+    from paper_1612_07592_amd import workloads as W
+    tb = {13: binding.pic_build_tables(13, 1.0, 16), 79: binding.pic_build_tables(79, 1.0, 16)}
+    log = lambda m: print(f"[serve] {m}", file=sys.stderr, flush=True)
+    out = {}
+    jobs = W.c3_jobs(args.c3_steps)
+    _, out["c3_fp32"] = SV.run_batch(jobs, tb)
+    log(f"c3 fp32 {out['c3_fp32']['electron_steps_per_s']:.3e} e-steps/s")
+    _, out["c3_fp64"] = SV.run_batch([dict(w, precision="fp64") for w in jobs], tb)
+    log(f"c3 fp64 {out['c3_fp64']['electron_steps_per_s']:.3e} e-steps/s")
+    out["c3_fp32_sequential"] = SV.run_sequential(jobs, tb)
+    log(f"c3 fp32 one at a time {out['c3_fp32_sequential']['electron_steps_per_s']:.3e} e-steps/s")
+    if args.c4_jobs > 0:
+        arr = W.c4_stream()[:args.c4_jobs]
+        _, c4 = SV.run_stream(arr, tb, log=log)
+        offered = sum(W.num_electrons(w) * w["steps"] for _, w in arr) / max(arr[-1][0], 1e-9)
+        c4["offered_electron_steps_per_s"] = offered
+        c4["arrival_rate_per_s"] = 4.0
+        out["c4_stream"] = c4
+        log(f"c4 {c4['jobs']} jobs: p50 {c4['latency_p50_s']:.2f} s p99 {c4['latency_p99_s']:.2f} s "
+            f"{c4['electron_steps_per_s']:.3e} e-steps/s")
+    out["scan_fp32_over_fp64"] = out["c3_fp32"]["electron_steps_per_s"] / out["c3_fp64"]["electron_steps_per_s"]
+    return out
 
 
 def cpu_baseline(w, budget_s=15.0):
@@ -113,6 +170,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sort-every", type=int, default=0,
                     help="tile-sort interval in steps (0 = library default, -1 = never)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the scan-job server runs")
+    ap.add_argument("--c3-steps", type=int, default=1000)
+    ap.add_argument("--c4-jobs", type=int, default=24,
+                    help="jobs of the Poisson stream served (0 = none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a "
@@ -129,7 +190,7 @@ def main():
     t_tables = time.perf_counter() - t0
     print(f"[bench] tables built in {t_tables:.1f} s; {args.workload} {args.precision} "
           f"{args.steps} steps", file=sys.stderr, flush=True)
-    r = run_gpu(w, tables, args.steps, args.warmup, torch)
+    r = run_gpu(w, tables, args.steps, args.warmup, torch, photons=not args.no_fp64)
     st = r["stats"]
     esteps = int(st["electron_steps"])
     value = esteps / r["wall_s"]
@@ -169,13 +230,16 @@ def main():
     if not args.no_fp64 and args.precision == "fp32":
         w64 = _workload(args.workload, "fp64", args.steps)
         w64["sort_every"] = args.sort_every
-        r64 = run_gpu(w64, tables, args.steps, 0, torch)
+        r64 = run_gpu(w64, tables, args.steps, 0, torch, photons=True)
         v64 = r64["stats"]["electron_steps"] / r64["wall_s"]
         out["fp64"] = {"value": v64, "ms_per_step": r64["wall_s"] * 1e3 / args.steps,
                        "kernel_avg_us": r64["step_kernel_ms"] * 1e3 / max(1, r64["step_launches"]),
                        "events": r64["stats"]["events"], "kept": r64["stats"]["kept"]}
         out["fp32_over_fp64"] = value / v64
-        print(f"[bench] fp64: {v64:.3e} e-steps/s", file=sys.stderr, flush=True)
+        out["fp32_vs_fp64"] = precision_check(r, r64)
+        print(f"[bench] fp64: {v64:.3e} e-steps/s; {out['fp32_vs_fp64']}", file=sys.stderr, flush=True)
+    if not args.no_serving and args.workload == "c2":
+        out["serving"] = serving(args, torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(_workload(args.workload, "fp64", args.steps))
     print(json.dumps(out), flush=True)

@@ -111,7 +111,8 @@ typedef struct {
                                0 = default for dims, < 0 = never (results do not
                                depend on it) */
   uint32_t reserved0;       /* must be 0 */
-  void* stream;             /* hipStream_t or NULL */
+  void* stream;             /* hipStream_t of the HIP runtime libpic links
+                               (/opt/rocm), or NULL for its default stream */
 } pic_config;
 
 /* Emission tables (host arrays, copied by pic_load_tables).
@@ -196,6 +197,13 @@ const char* pic_last_error(const pic_ctx* ctx);
 /* Device bytes pic_create would allocate for cfg (tables included). */
 pic_status pic_memory_required(const pic_config* cfg, uint64_t* bytes);
 
+/* Wait until the context's stream has drained (the work of every pic_step
+ * so far); surfaces asynchronous kernel errors.  libpic links the system
+ * HIP runtime, which is a separate instance from the one bundled with
+ * PyTorch: a torch synchronisation does not wait for libpic's work, this
+ * call does. */
+pic_status pic_synchronize(pic_ctx* ctx);
+
 /* Number of macro-electrons loaded (live or not) and photon records the
  * buffer holds / photons kept so far (may exceed the capacity). */
 pic_status pic_counts(pic_ctx* ctx, uint64_t* electrons, uint64_t* photons_stored,
@@ -253,6 +261,99 @@ pic_status pic_profile_read(pic_ctx* ctx, double* ms3, uint64_t* launches3);
 
 /* Derived constants of ctx: dx[3], dt, E_S, K_N, K_BR, n_c (8 doubles). */
 pic_status pic_derived(pic_ctx* ctx, double* out8);
+
+/* ---- batched stepping (several runs, one launch per kernel and step) ---- */
+
+typedef struct pic_batch pic_batch; /* opaque staging for pic_step_many */
+
+/* Staging buffers (pinned host + device) for pic_step_many on `stream`
+ * (hipStream_t or NULL).  Every context passed to pic_step_many with this
+ * batch must have been created on the same stream.
+ * Errors: PIC_ERR_INVALID (out NULL), PIC_ERR_NOMEM, PIC_ERR_DEVICE. */
+pic_status pic_batch_create(void* stream, pic_batch** out);
+void pic_batch_destroy(pic_batch* b); /* NULL is a no-op; waits for its last upload */
+const char* pic_batch_last_error(const pic_batch* b);
+
+/* Advance run j of ctxs[0..njobs) by nsteps[j] >= 0 steps, all on the batch's
+ * stream, returning without waiting for the device.  Step s of the call
+ * issues, for the runs with nsteps[j] > s: their due tile sorts, then one
+ * batched launch per kernel of the step (B half step, electron step per
+ * dims and precision, B half step, E step) whose workgroups walk a table of
+ * the runs' parameters.  Each run's electrons, fields, photons and
+ * statistics end bit-identical to pic_step(ctxs[j], nsteps[j]) (up to the
+ * order of photon records and of FP64 sums inside a wave slot, which no
+ * result depends on beyond rounding).  The runs must be distinct.  Nothing
+ * moves unless every run passes validation.
+ * Errors: PIC_ERR_INVALID (bad list, duplicate run, stream mismatch),
+ * PIC_ERR_STATE (a run without tables), PIC_ERR_DEVICE (every run of the
+ * call is then broken). */
+pic_status pic_step_many(pic_batch* b, pic_ctx* const* ctxs, const int32_t* nsteps,
+                         int32_t njobs);
+
+/* ---- serving: continuous batching of scan jobs on one device ------------ */
+
+typedef struct pic_server pic_server; /* opaque */
+
+typedef struct {
+  uint32_t abi_version;       /* PIC_ABI_VERSION */
+  int32_t max_jobs;           /* runs resident on the device at once, >= 1 */
+  int32_t quantum_steps;      /* steps each resident run advances per round, >= 1 */
+  uint32_t keep_finished;     /* 1: a finished run keeps its context (for read-back)
+                                 until pic_server_release; 0: freed at completion */
+  uint64_t hbm_reserve_bytes; /* device memory admission leaves free */
+  void* stream;               /* hipStream_t every run is created on, or NULL */
+} pic_server_config;
+
+typedef struct {
+  uint64_t job;          /* handle from pic_server_submit */
+  int32_t status;        /* PIC_OK, PIC_ERR_OVERFLOW (stats valid) or the error
+                            that ended the run (PIC_ERR_NOMEM: larger than the device) */
+  int32_t steps;         /* steps requested */
+  double t_submit;       /* arrival time, seconds on the server clock */
+  double t_admit;        /* admission (context creation) */
+  double t_finish;       /* completion observed (statistics read) */
+  uint64_t device_bytes; /* pic_memory_required of the run */
+  pic_stats stats;       /* statistics at completion */
+} pic_job_result;
+
+/* Free and total memory of the current device as the HIP runtime reports
+ * them (hipMemGetInfo): the figure admission compares against.
+ * Errors: PIC_ERR_INVALID (NULL), PIC_ERR_DEVICE. */
+pic_status pic_device_memory(uint64_t* free_bytes, uint64_t* total_bytes);
+
+/* Create a server (one pic_batch on sc->stream).  Errors: PIC_ERR_INVALID. */
+pic_status pic_server_create(const pic_server_config* sc, pic_server** out);
+/* Destroy the server and every context it still holds.  NULL is a no-op. */
+void pic_server_destroy(pic_server* s);
+/* Seconds since pic_server_create (monotonic). */
+double pic_server_clock(const pic_server* s);
+const char* pic_server_last_error(const pic_server* s);
+
+/* Queue a job: a run of cfg (cfg->stream is replaced by the server's) for
+ * nsteps steps, with tables t (deep-copied; NULL if no emission is on).
+ * t_arrival < 0 stamps the current server time, otherwise it is taken as the
+ * arrival time for latency.  Thread-safe with respect to pic_server_run.
+ * Errors: PIC_ERR_INVALID (bad cfg: nothing queued), PIC_ERR_TABLES. */
+pic_status pic_server_submit(pic_server* s, const pic_config* cfg, const pic_tables* t,
+                             int32_t nsteps, double t_arrival, uint64_t* job);
+
+/* One scheduling round: admit waiting jobs in arrival order while a slot is
+ * free and hipMemGetInfo's free memory covers the job's
+ * pic_memory_required plus the reserve; advance every resident run by up to
+ * quantum_steps steps with one pic_step_many call; wait for the device and
+ * retire the runs that are done.  Returns the resident and waiting counts
+ * after the round.  A device error ends every resident run with that
+ * status.  Call from one thread. */
+pic_status pic_server_run(pic_server* s, int32_t* resident, int32_t* queued);
+
+/* Move up to max finished jobs into out (completion order); *n = count. */
+pic_status pic_server_poll(pic_server* s, pic_job_result* out, int32_t max, int32_t* n);
+
+/* Borrow the context of a finished job (keep_finished = 1) for pic_copy_*;
+ * valid until pic_server_release or pic_server_destroy.
+ * Errors: PIC_ERR_STATE (unknown, unfinished or released job). */
+pic_status pic_server_job_ctx(pic_server* s, uint64_t job, pic_ctx** ctx);
+pic_status pic_server_release(pic_server* s, uint64_t job);
 
 #ifdef __cplusplus
 }

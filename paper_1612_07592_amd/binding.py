@@ -25,7 +25,10 @@ EXPORTS = ["pic_create", "pic_load_tables", "pic_step", "pic_emission_stats", "p
            "pic_last_error", "pic_memory_required", "pic_counts", "pic_copy_electrons",
            "pic_set_electrons", "pic_copy_photons", "pic_field_size", "pic_copy_fields",
            "pic_build_tables", "pic_philox", "pic_derived", "pic_profile", "pic_profile_read",
-           "pic_copy_current"]
+           "pic_copy_current", "pic_batch_create", "pic_batch_destroy", "pic_batch_last_error",
+           "pic_step_many", "pic_server_create", "pic_server_destroy", "pic_server_clock",
+           "pic_server_last_error", "pic_server_submit", "pic_server_run", "pic_server_poll",
+           "pic_server_job_ctx", "pic_server_release", "pic_device_memory", "pic_synchronize"]
 
 
 class pic_config(C.Structure):
@@ -60,6 +63,18 @@ class pic_stats(C.Structure):
                 ("untiled_steps", C.c_uint64),
                 ("e_rad_kept", C.c_double * 2), ("e_rad_dropped", C.c_double),
                 ("e_kin_e", C.c_double), ("e_field", C.c_double)]
+
+
+class pic_server_config(C.Structure):
+    _fields_ = [("abi_version", C.c_uint32), ("max_jobs", C.c_int32),
+                ("quantum_steps", C.c_int32), ("keep_finished", C.c_uint32),
+                ("hbm_reserve_bytes", C.c_uint64), ("stream", C.c_void_p)]
+
+
+class pic_job_result(C.Structure):
+    _fields_ = [("job", C.c_uint64), ("status", C.c_int32), ("steps", C.c_int32),
+                ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_finish", C.c_double),
+                ("device_bytes", C.c_uint64), ("stats", pic_stats)]
 
 
 class PicError(RuntimeError):
@@ -108,9 +123,32 @@ def load() -> C.CDLL:
     L.pic_copy_current.argtypes = [P, C.c_void_p]
     L.pic_profile.argtypes = [P, i32]
     L.pic_profile_read.argtypes = [P, C.c_void_p, C.c_void_p]
+    L.pic_batch_create.argtypes = [P, C.POINTER(P)]
+    L.pic_batch_destroy.argtypes = [P]
+    L.pic_batch_destroy.restype = None
+    L.pic_batch_last_error.argtypes = [P]
+    L.pic_batch_last_error.restype = C.c_char_p
+    L.pic_step_many.argtypes = [P, C.c_void_p, C.c_void_p, i32]
+    L.pic_server_create.argtypes = [C.POINTER(pic_server_config), C.POINTER(P)]
+    L.pic_server_destroy.argtypes = [P]
+    L.pic_server_destroy.restype = None
+    L.pic_server_clock.argtypes = [P]
+    L.pic_server_clock.restype = C.c_double
+    L.pic_server_last_error.argtypes = [P]
+    L.pic_server_last_error.restype = C.c_char_p
+    L.pic_server_submit.argtypes = [P, C.POINTER(pic_config), C.POINTER(pic_tables), i32, dbl,
+                                    C.POINTER(u64)]
+    L.pic_server_run.argtypes = [P, C.POINTER(i32), C.POINTER(i32)]
+    L.pic_server_poll.argtypes = [P, C.c_void_p, i32, C.POINTER(i32)]
+    L.pic_server_job_ctx.argtypes = [P, u64, C.POINTER(P)]
+    L.pic_server_release.argtypes = [P, u64]
+    L.pic_device_memory.argtypes = [C.POINTER(u64), C.POINTER(u64)]
+    L.pic_synchronize.argtypes = [P]
+    no_status = ("pic_destroy", "pic_last_error", "pic_batch_destroy", "pic_batch_last_error",
+                 "pic_server_destroy", "pic_server_clock", "pic_server_last_error")
     for name in EXPORTS:
         fn = getattr(L, name)
-        if name not in ("pic_destroy", "pic_last_error"):
+        if name not in no_status:
             fn.restype = C.c_int
     _lib = L
     return L
@@ -219,18 +257,41 @@ def pic_memory_required(w: dict) -> int:
     return int(b.value)
 
 
+def stats_dict(s: pic_stats, code: int = 0) -> dict:
+    return dict(steps=s.steps, live=s.electrons_live, electron_steps=s.electron_steps,
+                events=[s.events[0], s.events[1]], kept=[s.kept[0], s.kept[1]],
+                dropped_ncs=s.dropped_ncs, overflow=s.overflow,
+                brem_clamped=s.brem_clamped, photons_stored=s.photons_stored,
+                untiled_steps=s.untiled_steps,
+                e_rad_kept=[s.e_rad_kept[0], s.e_rad_kept[1]],
+                e_rad_dropped=s.e_rad_dropped, e_kin_e=s.e_kin_e, e_field=s.e_field,
+                status=STATUS.get(code, code))
+
+
+def pic_device_memory():
+    """(free, total) bytes of the current device, as admission sees them."""
+    L = load()
+    f, t = C.c_uint64(), C.c_uint64()
+    _check("pic_device_memory", L.pic_device_memory(C.byref(f), C.byref(t)))
+    return int(f.value), int(t.value)
+
+
 class Sim:
     """One libpic context: pic_create / pic_load_tables / pic_step /
     pic_emission_stats / pic_destroy plus the copy helpers."""
 
-    def __init__(self, w: dict, tables: dict | None = None, stream=None):
+    def __init__(self, w: dict, tables: dict | None = None, stream=None, _handle=None):
         L = load()
         self._L = L
         self.workload = dict(w)
-        cfg = config_from(w, stream)
-        h = C.c_void_p()
-        _check("pic_create", L.pic_create(C.byref(cfg), C.byref(h)))
-        self._h = h
+        self._owned = _handle is None
+        if _handle is None:
+            cfg = config_from(w, stream)
+            h = C.c_void_p()
+            _check("pic_create", L.pic_create(C.byref(cfg), C.byref(h)))
+            self._h = h
+        else:
+            self._h = _handle
         n = C.c_uint64()
         _check("pic_counts", L.pic_counts(self._h, C.byref(n), None, None), self._h)
         self.N = int(n.value)
@@ -249,18 +310,16 @@ class Sim:
         s = pic_stats()
         code = self._L.pic_emission_stats(self._h, C.byref(s))
         _check("pic_emission_stats", code, self._h, ok=(0, 5))
-        return dict(steps=s.steps, live=s.electrons_live, electron_steps=s.electron_steps,
-                    events=[s.events[0], s.events[1]], kept=[s.kept[0], s.kept[1]],
-                    dropped_ncs=s.dropped_ncs, overflow=s.overflow,
-                    brem_clamped=s.brem_clamped, photons_stored=s.photons_stored,
-                    untiled_steps=s.untiled_steps,
-                    e_rad_kept=[s.e_rad_kept[0], s.e_rad_kept[1]],
-                    e_rad_dropped=s.e_rad_dropped, e_kin_e=s.e_kin_e, e_field=s.e_field,
-                    status=STATUS[code])
+        return stats_dict(s, code)
+
+    def synchronize(self):
+        """Wait for this context's stream (pic_synchronize)."""
+        _check("pic_synchronize", self._L.pic_synchronize(self._h), self._h)
 
     def pic_destroy(self):
         if getattr(self, "_h", None):
-            self._L.pic_destroy(self._h)
+            if getattr(self, "_owned", True):
+                self._L.pic_destroy(self._h)
             self._h = None
 
     close = pic_destroy
@@ -338,3 +397,122 @@ class Sim:
         o = np.zeros(8)
         _check("pic_derived", self._L.pic_derived(self._h, o.ctypes.data), self._h)
         return dict(dx=o[0:3].copy(), dt=o[3], E_S=o[4], K_N=o[5], K_BR=o[6], n_c=o[7])
+
+
+class Batch:
+    """pic_batch_create / pic_step_many / pic_batch_destroy: several runs
+    advanced with one launch per kernel and step."""
+
+    def __init__(self, stream=None):
+        self._L = load()
+        h = C.c_void_p()
+        code = self._L.pic_batch_create(stream, C.byref(h))
+        if code:
+            raise PicError("pic_batch_create", code, "")
+        self._h = h
+
+    def step_many(self, sims, nsteps):
+        n = len(sims)
+        ctxs = (C.c_void_p * max(n, 1))(*[s._h for s in sims])
+        steps = (C.c_int32 * max(n, 1))(*[int(k) for k in nsteps])
+        code = self._L.pic_step_many(self._h, ctxs, steps, n)
+        if code:
+            raise PicError("pic_step_many", code, self._L.pic_batch_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.pic_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """The continuous-batching scan-job server of libpic (pic_server_*)."""
+
+    def __init__(self, max_jobs=64, quantum_steps=16, keep_finished=False,
+                 hbm_reserve_bytes=8 << 30, stream=None):
+        self._L = load()
+        sc = pic_server_config()
+        sc.abi_version = PIC_ABI_VERSION
+        sc.max_jobs = int(max_jobs)
+        sc.quantum_steps = int(quantum_steps)
+        sc.keep_finished = 1 if keep_finished else 0
+        sc.hbm_reserve_bytes = int(hbm_reserve_bytes)
+        sc.stream = stream
+        h = C.c_void_p()
+        code = self._L.pic_server_create(C.byref(sc), C.byref(h))
+        if code:
+            raise PicError("pic_server_create", code, "")
+        self._h = h
+        self._keep = []
+
+    def _err(self, fn, code):
+        raise PicError(fn, code, self._L.pic_server_last_error(self._h).decode())
+
+    def clock(self) -> float:
+        return float(self._L.pic_server_clock(self._h))
+
+    def submit(self, w: dict, tables: dict | None, nsteps: int, t_arrival: float = -1.0) -> int:
+        cfg = config_from(w)
+        job = C.c_uint64()
+        if tables is not None:
+            ts, keep = tables_struct(tables)
+            code = self._L.pic_server_submit(self._h, C.byref(cfg), C.byref(ts), int(nsteps),
+                                             float(t_arrival), C.byref(job))
+        else:
+            code = self._L.pic_server_submit(self._h, C.byref(cfg), None, int(nsteps),
+                                             float(t_arrival), C.byref(job))
+        if code:
+            self._err("pic_server_submit", code)
+        return int(job.value)
+
+    def run(self):
+        """One scheduling round; returns (resident, queued)."""
+        r, q = C.c_int32(), C.c_int32()
+        code = self._L.pic_server_run(self._h, C.byref(r), C.byref(q))
+        if code:
+            self._err("pic_server_run", code)
+        return int(r.value), int(q.value)
+
+    def poll(self, max_results: int = 1024) -> list:
+        out = (pic_job_result * max_results)()
+        n = C.c_int32()
+        code = self._L.pic_server_poll(self._h, out, int(max_results), C.byref(n))
+        if code:
+            self._err("pic_server_poll", code)
+        res = []
+        for k in range(n.value):
+            r = out[k]
+            res.append(dict(job=int(r.job), status=STATUS.get(r.status, r.status), steps=int(r.steps),
+                            t_submit=r.t_submit, t_admit=r.t_admit, t_finish=r.t_finish,
+                            device_bytes=int(r.device_bytes), stats=stats_dict(r.stats)))
+        return res
+
+    def job_sim(self, job: int, w: dict) -> Sim:
+        """Borrowed view of a finished job's context (keep_finished servers)."""
+        h = C.c_void_p()
+        code = self._L.pic_server_job_ctx(self._h, int(job), C.byref(h))
+        if code:
+            self._err("pic_server_job_ctx", code)
+        return Sim(w, None, _handle=h)
+
+    def release(self, job: int):
+        code = self._L.pic_server_release(self._h, int(job))
+        if code:
+            self._err("pic_server_release", code)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.pic_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <algorithm>
 #include <new>
+#include <string>
 #include <utility>
 #include <vector>
 #include "pic_internal.hpp"
@@ -146,10 +147,18 @@ std::string derive(const pic_config& cfg, Ctx& c) {
   c.pcap = cfg.photon_capacity;
   c.nblocks_step = ((N + kBlock - 1) / kBlock + 7) / 8 * 8;
   c.nslots = c.nblocks_step * (kBlock / 64);
+  // FP32 positions: int32 fixed point in cells; n << fb stays below 2^30 so a
+  // move of less than a cell past either wall cannot overflow, and fb <= 24
+  // keeps the in-cell fraction exact in a float
+  for (int a = 0; a < 3; ++a) {
+    int bits = 0;
+    while ((1 << bits) < g.n[a]) ++bits;
+    g.fb[a] = g.act[a] ? std::min(24, 30 - bits) : 0;
+  }
   // cell tiles for the sort and the LDS box of the step kernel
   if (cfg.reserved0 != 0) return "reserved0 must be 0";
   const int dflt_every[4] = {0, 16, 8, 4};
-  const int tiles[4] = {0, 16, 4, 2};
+  const int tiles[4] = {0, 16, 2, 2};
   const int ldsn[4] = {0, 64, 576, 512};
   c.sort_every = cfg.sort_every == 0 ? dflt_every[g.dims] : (cfg.sort_every < 0 ? 0 : cfg.sort_every);
   c.lds_nodes = ldsn[g.dims];
@@ -367,6 +376,48 @@ void fill_step_params(Ctx& c, StepParams<R>& P) {
   P.n_active = c.n_active;
   P.lds_nodes = c.lds_nodes;
   P.jbits = c.jbits;
+  for (int a = 0; a < 3; ++a) {
+    P.fb[a] = g.fb[a];
+    P.iqs[a] = (float)ldexp(1.0, -g.fb[a]);
+    P.iqd[a] = (float)(g.dx[a] * ldexp(1.0, -g.fb[a]));
+    P.mvq[a] = (float)(g.dt * g.idx[a] * ldexp(1.0, g.fb[a]));
+  }
+}
+
+bool sort_due(const Ctx& c) { return c.sort_every > 0 && c.step % (uint64_t)c.sort_every == 0; }
+
+// Sort of the electron SoA into the second buffer set (swap_sorted then
+// makes the sorted copy current).
+SortArgs sort_args(const Ctx& c) {
+  SortArgs A{};
+  A.N = c.N;
+  A.dims = c.g.dims;
+  for (int a = 0; a < 3; ++a) {
+    A.n[a] = c.g.n[a];
+    A.tile[a] = c.tile[a];
+    A.idx[a] = c.g.idx[a];
+    A.fb[a] = c.g.fb[a];
+    A.x[a] = c.x[a]; A.p[a] = c.p[a]; A.x2[a] = c.x2[a]; A.p2[a] = c.p2[a];
+  }
+  A.nkeys = c.nkeys;
+  A.tau = c.tau; A.w = c.w; A.id = c.id;
+  A.tau2 = c.tau2; A.w2 = c.w2; A.id2 = c.id2;
+  A.key = c.skey; A.count = c.scount; A.offset = c.soffset; A.cursor = c.scursor;
+  A.n_active = c.n_active;
+  return A;
+}
+
+void swap_sorted(Ctx& c) {
+  for (int a = 0; a < 3; ++a) { std::swap(c.x[a], c.x2[a]); std::swap(c.p[a], c.p2[a]); }
+  std::swap(c.tau, c.tau2); std::swap(c.w, c.w2); std::swap(c.id, c.id2);
+}
+
+pic_status step_ready(Ctx& c, int32_t nsteps) {
+  if (nsteps < 0) FAIL(c, PIC_ERR_INVALID, "nsteps < 0");
+  if ((c.cfg.flags & (PIC_NCS | PIC_BREM)) && !c.tables_loaded)
+    FAIL(c, PIC_ERR_STATE, "emission enabled but no tables loaded");
+  if (c.step + (uint64_t)nsteps >= 0xFFFFFFFFull) FAIL(c, PIC_ERR_INVALID, "step counter exhausted");
+  return PIC_OK;
 }
 
 pic_status check_ctx(pic_ctx* ctx) {
@@ -390,6 +441,77 @@ pic_status copy_real(Ctx& c, const void* dev, size_t n, std::vector<double>& out
 pic_status copy_any(Ctx& c, const void* dev, size_t n, std::vector<double>& out) {
   return c.fp32 ? copy_real<float>(c, dev, n, out) : copy_real<double>(c, dev, n, out);
 }
+}  // namespace
+
+// Staging of the per-run parameter tables of pic_step_many: built on the host
+// for the whole call, uploaded with one copy, read by the batched kernels.
+struct pic_batch {
+  hipStream_t stream = nullptr;
+  std::string err;
+  unsigned char* host = nullptr;   // pinned
+  size_t host_cap = 0;
+  unsigned char* dev = nullptr;
+  size_t dev_cap = 0;
+  hipEvent_t uploaded = nullptr;   // the last upload has left the pinned buffer
+  bool pending = false;
+  std::vector<unsigned char> stage;
+  ~pic_batch() {
+    (void)hipStreamSynchronize(stream);  // kernels may still read the tables
+    if (pending && uploaded) (void)hipEventSynchronize(uploaded);
+    if (uploaded) (void)hipEventDestroy(uploaded);
+    if (host) (void)hipHostFree(host);
+    if (dev) (void)hipFree(dev);
+  }
+};
+
+namespace {
+
+struct BatchLaunch {
+  int kind;          // 0 sort, 1 B half step + clear J, 2 electron step, 3 B half step, 4 E step
+  int dims = 0;
+  bool fp32 = false;
+  size_t tab = 0, first = 0;
+  int njobs = 0;
+  uint32_t total = 0;
+  int lds_nodes = 0;
+  SortArgs sort{};
+  hipStream_t stream = nullptr;
+};
+
+size_t stage_put(std::vector<unsigned char>& st, const void* src, size_t n) {
+  const size_t off = (st.size() + 255) & ~(size_t)255;
+  st.resize(off + n);
+  std::memcpy(st.data() + off, src, n);
+  return off;
+}
+
+template <class R>
+void stage_step_group(std::vector<unsigned char>& st, std::vector<BatchLaunch>& L,
+                      std::vector<Ctx*>& jobs, int dims) {
+  std::vector<StepParams<R>> tab;
+  std::vector<uint32_t> first{0u};
+  int lds = 0;
+  for (Ctx* c : jobs) {
+    if (c->g.dims != dims || c->fp32 != (sizeof(R) == 4) || c->N <= 0) continue;
+    StepParams<R> P{};
+    fill_step_params(*c, P);
+    tab.push_back(P);
+    first.push_back(first.back() + (uint32_t)((c->N + kBlock - 1) / kBlock));
+    lds = std::max(lds, c->lds_nodes);
+  }
+  if (tab.empty()) return;
+  BatchLaunch b{};
+  b.kind = 2;
+  b.dims = dims;
+  b.fp32 = sizeof(R) == 4;
+  b.tab = stage_put(st, tab.data(), tab.size() * sizeof(StepParams<R>));
+  b.first = stage_put(st, first.data(), first.size() * sizeof(uint32_t));
+  b.njobs = (int)tab.size();
+  b.total = first.back();
+  b.lds_nodes = lds;
+  L.push_back(b);
+}
+
 }  // namespace
 
 extern "C" {
@@ -546,10 +668,8 @@ pic_status pic_step(pic_ctx* ctx, int32_t nsteps) {
   pic_status st = check_ctx(ctx);
   if (st) return st;
   Ctx& c = ctx->c;
-  if (nsteps < 0) FAIL(c, PIC_ERR_INVALID, "nsteps < 0");
-  if ((c.cfg.flags & (PIC_NCS | PIC_BREM)) && !c.tables_loaded)
-    FAIL(c, PIC_ERR_STATE, "emission enabled but no tables loaded");
-  if (c.step + (uint64_t)nsteps >= 0xFFFFFFFFull) FAIL(c, PIC_ERR_INVALID, "step counter exhausted");
+  st = step_ready(c, nsteps);
+  if (st) return st;
   const bool frozen = (c.cfg.flags & PIC_FIELDS_FROZEN) != 0;
   auto mark = [&](int kind) {
     if (!c.prof) return;
@@ -560,25 +680,10 @@ pic_status pic_step(pic_ctx* ctx, int32_t nsteps) {
     }
   };
   for (int32_t it = 0; it < nsteps; ++it) {
-    if (c.sort_every > 0 && c.step % (uint64_t)c.sort_every == 0) {
+    if (sort_due(c)) {
       mark(2);
-      SortArgs A{};
-      A.N = c.N;
-      A.dims = c.g.dims;
-      for (int a = 0; a < 3; ++a) {
-        A.n[a] = c.g.n[a];
-        A.tile[a] = c.tile[a];
-        A.idx[a] = c.g.idx[a];
-        A.x[a] = c.x[a]; A.p[a] = c.p[a]; A.x2[a] = c.x2[a]; A.p2[a] = c.p2[a];
-      }
-      A.nkeys = c.nkeys;
-      A.tau = c.tau; A.w = c.w; A.id = c.id;
-      A.tau2 = c.tau2; A.w2 = c.w2; A.id2 = c.id2;
-      A.key = c.skey; A.count = c.scount; A.offset = c.soffset; A.cursor = c.scursor;
-      A.n_active = c.n_active;
-      launch_sort(A, c.fp32, c.stream);
-      for (int a = 0; a < 3; ++a) { std::swap(c.x[a], c.x2[a]); std::swap(c.p[a], c.p2[a]); }
-      std::swap(c.tau, c.tau2); std::swap(c.w, c.w2); std::swap(c.id, c.id2);
+      launch_sort(sort_args(c), c.fp32, c.stream);
+      swap_sorted(c);
       mark(2);
     }
     mark(1);
@@ -643,6 +748,188 @@ pic_status pic_emission_stats(pic_ctx* ctx, pic_stats* out) {
   return s.overflow ? PIC_ERR_OVERFLOW : PIC_OK;
 }
 
+pic_status pic_batch_create(void* stream, pic_batch** out) {
+  if (!out) return PIC_ERR_INVALID;
+  *out = nullptr;
+  pic_batch* b = new (std::nothrow) pic_batch;
+  if (!b) return PIC_ERR_NOMEM;
+  b->stream = (hipStream_t)stream;
+  if (hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming) != hipSuccess) {
+    g_create_err = "hipEventCreate failed";
+    delete b;
+    return PIC_ERR_DEVICE;
+  }
+  *out = b;
+  return PIC_OK;
+}
+
+void pic_batch_destroy(pic_batch* b) { delete b; }
+
+const char* pic_batch_last_error(const pic_batch* b) { return b ? b->err.c_str() : ""; }
+
+pic_status pic_step_many(pic_batch* b, pic_ctx* const* ctxs, const int32_t* nsteps, int32_t njobs) {
+  if (!b) return PIC_ERR_INVALID;
+  if (njobs < 0 || (njobs > 0 && (!ctxs || !nsteps))) {
+    b->err = "bad job list";
+    return PIC_ERR_INVALID;
+  }
+  // validate everything before any run's state moves
+  int32_t S = 0;
+  std::vector<Ctx*> all;
+  for (int32_t j = 0; j < njobs; ++j) {
+    pic_status st = check_ctx(ctxs[j]);
+    if (st) {
+      b->err = "job " + std::to_string(j) + ": null or broken context";
+      return st;
+    }
+    Ctx& c = ctxs[j]->c;
+    st = step_ready(c, nsteps[j]);
+    if (st) {
+      b->err = "job " + std::to_string(j) + ": " + c.err;
+      return st;
+    }
+    if (c.stream != b->stream) {
+      b->err = "job " + std::to_string(j) + ": context stream differs from the batch stream";
+      return PIC_ERR_INVALID;
+    }
+    for (Ctx* o : all)
+      if (o == &c) {
+        b->err = "job " + std::to_string(j) + ": context listed twice";
+        return PIC_ERR_INVALID;
+      }
+    all.push_back(&c);
+    S = std::max(S, nsteps[j]);
+  }
+  if (S == 0) return PIC_OK;
+
+  // host pass: the launches of every step, with the parameter tables staged
+  std::vector<unsigned char>& st = b->stage;
+  st.clear();
+  std::vector<BatchLaunch> L;
+  std::vector<Ctx*> act;
+  for (int32_t s = 0; s < S; ++s) {
+    act.clear();
+    for (int32_t j = 0; j < njobs; ++j)
+      if (nsteps[j] > s) act.push_back(all[j]);
+    for (Ctx* c : act)
+      if (sort_due(*c)) {
+        BatchLaunch l{};
+        l.kind = 0;
+        l.fp32 = c->fp32;
+        l.sort = sort_args(*c);
+        L.push_back(l);
+        swap_sorted(*c);
+      }
+    BatchLaunch fl[2];
+    bool have_f[2] = {false, false};
+    for (int f = 0; f < 2; ++f) {
+      std::vector<FieldJob> tab;
+      std::vector<uint32_t> first{0u};
+      for (Ctx* c : act) {
+        if ((c->cfg.flags & PIC_FIELDS_FROZEN) || c->fp32 != (f == 1)) continue;
+        double ls, lc;
+        laser_scalars(*c, c->step, &ls, &lc);
+        FieldJob F{};
+        fill_field_job(*c, ls, lc, F);
+        tab.push_back(F);
+        first.push_back(first.back() + field_blocks(*c));
+      }
+      if (tab.empty()) continue;
+      fl[f].fp32 = f == 1;
+      fl[f].tab = stage_put(st, tab.data(), tab.size() * sizeof(FieldJob));
+      fl[f].first = stage_put(st, first.data(), first.size() * sizeof(uint32_t));
+      fl[f].njobs = (int)tab.size();
+      fl[f].total = first.back();
+      have_f[f] = true;
+    }
+    for (int f = 0; f < 2; ++f)
+      if (have_f[f]) { BatchLaunch l = fl[f]; l.kind = 1; L.push_back(l); }
+    for (int d = 1; d <= 3; ++d) {
+      stage_step_group<float>(st, L, act, d);
+      stage_step_group<double>(st, L, act, d);
+    }
+    for (int f = 0; f < 2; ++f)
+      if (have_f[f]) { BatchLaunch l = fl[f]; l.kind = 3; L.push_back(l); }
+    for (int f = 0; f < 2; ++f)
+      if (have_f[f]) { BatchLaunch l = fl[f]; l.kind = 4; L.push_back(l); }
+    for (Ctx* c : act) {
+      if (!(c->cfg.flags & PIC_FIELDS_FROZEN))
+        for (int d = 0; d < 3; ++d) std::swap(c->E[d], c->En[d]);
+      c->step++;
+    }
+  }
+
+  // one upload of every table, then the launches in order
+  auto fail = [&](const char* what, hipError_t e) {
+    b->err = std::string(what) + ": " + hipGetErrorString(e);
+    for (Ctx* c : all) { c->broken = true; c->err = b->err; }
+    return PIC_ERR_DEVICE;
+  };
+  hipError_t e = hipSuccess;
+  if (b->pending) {
+    e = hipEventSynchronize(b->uploaded);
+    if (e != hipSuccess) return fail("hipEventSynchronize", e);
+    b->pending = false;
+  }
+  const size_t need = st.size();
+  if (need > b->host_cap) {
+    if (b->host) (void)hipHostFree(b->host);
+    b->host = nullptr;
+    b->host_cap = 0;
+    e = hipHostMalloc((void**)&b->host, need * 2, hipHostMallocDefault);
+    if (e != hipSuccess) return fail("hipHostMalloc", e);
+    b->host_cap = need * 2;
+  }
+  if (need > b->dev_cap) {
+    if (b->dev) {
+      e = hipStreamSynchronize(b->stream);  // earlier launches may still read it
+      if (e != hipSuccess) return fail("hipStreamSynchronize", e);
+      (void)hipFree(b->dev);
+    }
+    b->dev = nullptr;
+    b->dev_cap = 0;
+    e = hipMalloc((void**)&b->dev, need * 2);
+    if (e != hipSuccess) return fail("hipMalloc", e);
+    b->dev_cap = need * 2;
+  }
+  std::memcpy(b->host, st.data(), need);
+  e = hipMemcpyAsync(b->dev, b->host, need, hipMemcpyHostToDevice, b->stream);
+  if (e != hipSuccess) return fail("hipMemcpyAsync", e);
+  e = hipEventRecord(b->uploaded, b->stream);
+  if (e != hipSuccess) return fail("hipEventRecord", e);
+  b->pending = true;
+  unsigned char* D = b->dev;
+  for (const BatchLaunch& l : L) {
+    switch (l.kind) {
+      case 0: launch_sort(l.sort, l.fp32, b->stream); break;
+      case 1:
+      case 3:
+        launch_b_half_batch(l.fp32, (const FieldJob*)(D + l.tab), (const uint32_t*)(D + l.first),
+                            l.njobs, l.total, l.kind == 1, b->stream);
+        break;
+      case 2:
+        launch_step_batch(l.dims, l.fp32, D + l.tab, (const uint32_t*)(D + l.first), l.njobs, l.total,
+                          l.lds_nodes, b->stream);
+        break;
+      default:
+        launch_e_full_batch(l.fp32, (const FieldJob*)(D + l.tab), (const uint32_t*)(D + l.first),
+                            l.njobs, l.total, b->stream);
+    }
+  }
+  e = hipGetLastError();
+  if (e != hipSuccess) return fail("launch", e);
+  return PIC_OK;
+}
+
+pic_status pic_synchronize(pic_ctx* ctx) {
+  pic_status st = check_ctx(ctx);
+  if (st) return st;
+  Ctx& c = ctx->c;
+  HIPCHK(c, hipStreamSynchronize(c.stream));
+  HIPCHK(c, hipGetLastError());
+  return PIC_OK;
+}
+
 pic_status pic_counts(pic_ctx* ctx, uint64_t* electrons, uint64_t* stored, uint64_t* kept) {
   pic_status st = check_ctx(ctx);
   if (st) return st;
@@ -671,7 +958,14 @@ pic_status pic_copy_electrons(pic_ctx* ctx, double* x, double* p, double* tau, d
   std::vector<double> v, t8(N), w8(N);
   for (int a = 0; a < 3; ++a) {
     if (x) {
-      if (a < c.g.dims) {
+      if (a < c.g.dims && c.fp32) {  // fixed point -> absolute position
+        std::vector<int32_t> qv(N);
+        HIPCHK(c, hipMemcpyAsync(qv.data(), c.x[a], N * 4, hipMemcpyDeviceToHost, c.stream));
+        HIPCHK(c, hipStreamSynchronize(c.stream));
+        v.resize(N);
+        const double s = ldexp(1.0, -c.g.fb[a]) * c.g.dx[a];
+        for (size_t e = 0; e < N; ++e) v[e] = (double)qv[e] * s;
+      } else if (a < c.g.dims) {
         if ((st = copy_any(c, c.x[a], N, v))) return st;
       } else {
         v.assign(N, 0.0);
@@ -732,7 +1026,17 @@ pic_status pic_set_electrons(pic_ctx* ctx, const double* x, const double* p, con
     return PIC_OK;
   };
   for (int a = 0; a < 3; ++a) {
-    if (a < c.g.dims && (st = put(c.x[a], x, 3, a))) return st;
+    if (a < c.g.dims && c.fp32) {  // absolute position -> fixed point in cells
+      std::vector<int32_t> qv(N);
+      const double s = ldexp(1.0, c.g.fb[a]) * c.g.idx[a];
+      const double qmax = ldexp((double)c.g.n[a], c.g.fb[a]) - 1.0;
+      for (size_t e = 0; e < N; ++e)
+        qv[e] = (int32_t)std::min(qmax, (double)llrint(x[3 * (size_t)(ids[e] & ~kDead) + a] * s));
+      HIPCHK(c, hipMemcpyAsync(c.x[a], qv.data(), N * 4, hipMemcpyHostToDevice, c.stream));
+      HIPCHK(c, hipStreamSynchronize(c.stream));
+    } else if (a < c.g.dims && (st = put(c.x[a], x, 3, a))) {
+      return st;
+    }
     if ((st = put(c.p[a], p, 3, a))) return st;
   }
   std::vector<double> t8(N);

@@ -6,12 +6,6 @@
 
 namespace pic {
 
-struct FieldArgs {
-  int n[3], act[3], gg[3], sz[3];
-  double hd[3], cd[3], cm[3], dt, srcfac;
-  int i_src, nsrc_y;
-  int64_t nfield;
-};
 
 static FieldArgs field_args(const Grid& g) {
   FieldArgs a{};
@@ -56,12 +50,11 @@ __device__ inline bool in_range(const FieldArgs& A, bool isB, int c, int i, int 
 
 // B <- B - (dt/2) curl E on every valid B node; optionally clears J.
 template <class R>
-__global__ __launch_bounds__(kBlock) void k_b_half(FieldArgs A, const R* __restrict__ Ex,
-                                                   const R* __restrict__ Ey, const R* __restrict__ Ez,
-                                                   R* Bx, R* By, R* Bz, unsigned long long* Jx,
-                                                   unsigned long long* Jy, unsigned long long* Jz,
-                                                   int zeroJ) {
-  const int64_t m = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+__device__ __forceinline__ void b_half_node(const FieldArgs& A, const R* __restrict__ Ex,
+                                            const R* __restrict__ Ey, const R* __restrict__ Ez,
+                                            R* Bx, R* By, R* Bz, unsigned long long* Jx,
+                                            unsigned long long* Jy, unsigned long long* Jz,
+                                            int zeroJ, const int64_t m) {
   if (m >= A.nfield) return;
   if (zeroJ) { Jx[m] = 0ull; Jy[m] = 0ull; Jz[m] = 0ull; }
   int i, j, k;
@@ -86,13 +79,6 @@ __global__ __launch_bounds__(kBlock) void k_b_half(FieldArgs A, const R* __restr
   }
 }
 
-struct EPtrs {
-  const void* E[3];
-  void* En[3];
-  const void* B[3];
-  const unsigned long long* J[3];
-  const double *srcA, *srcC, *srcS;
-};
 
 // Ampere update of E_c at an interior node (old E, B^{n+1/2}, J^{n+1/2}).
 template <class R>
@@ -126,9 +112,8 @@ __device__ inline R e_interior(const FieldArgs& A, const EPtrs& P, int c, int i,
 // (the interior neighbour's new value is recomputed here, bit-identically),
 // edge/corner nodes and guards 0.
 template <class R>
-__global__ __launch_bounds__(kBlock) void k_e_full(FieldArgs A, EPtrs P, double lsin, double lcos) {
-  const int64_t m = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const int c = blockIdx.y;
+__device__ __forceinline__ void e_full_node(const FieldArgs& A, const EPtrs& P, double lsin,
+                                            double lcos, const int c, const int64_t m) {
   if (m >= A.nfield) return;
   int i, j, k;
   decode(A, m, i, j, k);
@@ -146,6 +131,80 @@ __global__ __launch_bounds__(kBlock) void k_e_full(FieldArgs A, EPtrs P, double 
   const int64_t mi = fidx(A, in[0], in[1], in[2]);
   const R fin = e_interior<R>(A, P, c, in[0], in[1], in[2], lsin, lcos);
   Fn[m] = Fo[mi] + R(A.cm[ax]) * (fin - Fo[m]);
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_b_half(FieldArgs A, const R* __restrict__ Ex,
+                                                   const R* __restrict__ Ey, const R* __restrict__ Ez,
+                                                   R* Bx, R* By, R* Bz, unsigned long long* Jx,
+                                                   unsigned long long* Jy, unsigned long long* Jz,
+                                                   int zeroJ) {
+  b_half_node<R>(A, Ex, Ey, Ez, Bx, By, Bz, Jx, Jy, Jz, zeroJ,
+                 (int64_t)blockIdx.x * kBlock + threadIdx.x);
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_e_full(FieldArgs A, EPtrs P, double lsin, double lcos) {
+  e_full_node<R>(A, P, lsin, lcos, (int)blockIdx.y, (int64_t)blockIdx.x * kBlock + threadIdx.x);
+}
+
+// Batched forms: the workgroups of every run laid end to end (run j owns
+// blocks [first[j], first[j+1])); each run is updated exactly as alone.
+__device__ inline int batch_job(const uint32_t* __restrict__ first, int njobs, uint32_t b) {
+  int lo = 0, hi = njobs - 1;  // largest j with first[j] <= b
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (first[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_b_half_batch(const FieldJob* __restrict__ tab,
+                                                         const uint32_t* __restrict__ first,
+                                                         int njobs, int zeroJ) {
+  const int j = batch_job(first, njobs, blockIdx.x);
+  const FieldJob& F = tab[j];
+  b_half_node<R>(F.A, (const R*)F.P.E[0], (const R*)F.P.E[1], (const R*)F.P.E[2], (R*)F.Bw[0],
+                 (R*)F.Bw[1], (R*)F.Bw[2], F.Jw[0], F.Jw[1], F.Jw[2], zeroJ,
+                 (int64_t)(blockIdx.x - first[j]) * kBlock + threadIdx.x);
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_e_full_batch(const FieldJob* __restrict__ tab,
+                                                         const uint32_t* __restrict__ first,
+                                                         int njobs) {
+  const int j = batch_job(first, njobs, blockIdx.x);
+  const FieldJob& F = tab[j];
+  e_full_node<R>(F.A, F.P, F.lsin, F.lcos, (int)blockIdx.y,
+                 (int64_t)(blockIdx.x - first[j]) * kBlock + threadIdx.x);
+}
+
+uint32_t field_blocks(const Ctx& c) { return (uint32_t)((c.g.nfield + kBlock - 1) / kBlock); }
+
+void fill_field_job(const Ctx& c, double lsin, double lcos, FieldJob& F) {
+  F.A = field_args(c.g);
+  for (int d = 0; d < 3; ++d) {
+    F.P.E[d] = c.E[d]; F.P.En[d] = c.En[d]; F.P.B[d] = c.B[d]; F.P.J[d] = c.J[d];
+    F.Bw[d] = c.B[d]; F.Jw[d] = c.J[d];
+  }
+  F.P.srcA = c.srcA; F.P.srcC = c.srcC; F.P.srcS = c.srcS;
+  F.lsin = lsin;
+  F.lcos = lcos;
+}
+
+void launch_b_half_batch(bool fp32, const FieldJob* tab, const uint32_t* first, int njobs,
+                         uint32_t total, int zeroJ, hipStream_t s) {
+  if (njobs <= 0 || total == 0) return;
+  if (fp32) hipLaunchKernelGGL(k_b_half_batch<float>, dim3(total), dim3(kBlock), 0, s, tab, first, njobs, zeroJ);
+  else hipLaunchKernelGGL(k_b_half_batch<double>, dim3(total), dim3(kBlock), 0, s, tab, first, njobs, zeroJ);
+}
+
+void launch_e_full_batch(bool fp32, const FieldJob* tab, const uint32_t* first, int njobs,
+                         uint32_t total, hipStream_t s) {
+  if (njobs <= 0 || total == 0) return;
+  if (fp32) hipLaunchKernelGGL(k_e_full_batch<float>, dim3(total, 3), dim3(kBlock), 0, s, tab, first, njobs);
+  else hipLaunchKernelGGL(k_e_full_batch<double>, dim3(total, 3), dim3(kBlock), 0, s, tab, first, njobs);
 }
 
 void launch_b_half_impl(const Ctx& c, int zeroJ, hipStream_t s) {
@@ -195,6 +254,7 @@ struct InitArgs {
   int nx, nyc;
   double nion;
   int i1;
+  int fb[3];
 };
 
 // Electron e of the slab cell with rank e/ppc; cold, uniform in the cell;
@@ -209,9 +269,15 @@ __global__ __launch_bounds__(kBlock) void k_init_electrons(InitArgs A) {
   const int jj = A.dims >= 2 ? (int)(r2 % A.ny) : 0;
   const int kk = A.dims >= 3 ? (int)(r2 / A.ny) : 0;
   const U4 r = philox4x32_10((uint32_t)e, 0xFFFFFFFFu, 0u, 0u, A.key0, A.key1);
-  ((R*)A.x[0])[e] = (R)(((double)ii + unif32(r.v[0])) * A.dx[0]);
-  if (A.dims >= 2) ((R*)A.x[1])[e] = (R)(((double)jj + unif32(r.v[1])) * A.dx[1]);
-  if (A.dims >= 3) ((R*)A.x[2])[e] = (R)(((double)kk + unif32(r.v[2])) * A.dx[2]);
+  if constexpr (sizeof(R) == 4) {  // fixed point in cells, fb fraction bits
+    const int c3[3] = {ii, jj, kk};
+    for (int a = 0; a < A.dims; ++a)
+      ((int*)A.x[a])[e] = (c3[a] << A.fb[a]) + (int)(unif32(r.v[a]) * ldexp(1.0, A.fb[a]));
+  } else {
+    ((R*)A.x[0])[e] = (R)(((double)ii + unif32(r.v[0])) * A.dx[0]);
+    if (A.dims >= 2) ((R*)A.x[1])[e] = (R)(((double)jj + unif32(r.v[1])) * A.dx[1]);
+    if (A.dims >= 3) ((R*)A.x[2])[e] = (R)(((double)kk + unif32(r.v[2])) * A.dx[2]);
+  }
   for (int a = 0; a < 3; ++a) ((R*)A.p[a])[e] = R(0);
   A.tau[e] = -log(unif32(r.v[3]));
   A.w[e] = A.wgt;
@@ -234,7 +300,9 @@ void launch_init_electrons(const Ctx& c, hipStream_t s) {
   A.i0 = c.i0;
   A.i1 = c.i1;
   A.ny = c.g.n[1];
-  for (int d = 0; d < 3; ++d) { A.dx[d] = c.g.dx[d]; A.x[d] = c.x[d]; A.p[d] = c.p[d]; }
+  for (int d = 0; d < 3; ++d) {
+    A.dx[d] = c.g.dx[d]; A.x[d] = c.x[d]; A.p[d] = c.p[d]; A.fb[d] = c.g.fb[d];
+  }
   A.wgt = c.wgt;
   A.key0 = c.key0; A.key1 = c.key1;
   A.tau = c.tau; A.w = c.w; A.id = c.id; A.ni = c.ni;

@@ -35,8 +35,10 @@ __host__ __device__ inline U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c
 
 // (r + 1/2) 2^-32: a double in (0, 1), exact.
 __host__ __device__ inline double unif32(uint32_t r) { return ((double)r + 0.5) * 0x1p-32; }
-// float in (0, 1) from the top 24 bits, exact.
-__host__ __device__ inline float unif24f(uint32_t r) { return ((float)(r >> 8) + 0.5f) * 0x1p-24f; }
+// float in (0, 1) from the top 23 bits: (k + 1/2) 2^-23 with k < 2^23 needs
+// 24 significant bits, so it is exact and never reaches 1.  (With 24 bits,
+// k + 1/2 would round to 2^24 for the largest k and the draw would be 1.0.)
+__host__ __device__ inline float unif23f(uint32_t r) { return ((float)(r >> 9) + 0.5f) * 0x1p-23f; }
 // 52-bit uniform from two words: (k + 1/2) 2^-52, k < 2^52, exact in double.
 __host__ __device__ inline double unif52(uint32_t r0, uint32_t r1) {
   const uint64_t k = ((uint64_t)r0 << 20) | (uint64_t)(r1 >> 12);

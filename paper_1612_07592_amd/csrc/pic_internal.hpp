@@ -29,6 +29,32 @@ struct Grid {
   double hd[3], cd[3], cm[3];   // (dt/2)/dx, dt/dx, Mur coefficients
   int i_src, nsrc_y, nsrc_z;
   int64_t nfield;               // elements per component
+  int fb[3];                    // FP32 path: fraction bits of the fixed-point positions
+};
+
+// Parameter block of the field kernels (one run).
+struct FieldArgs {
+  int n[3], act[3], gg[3], sz[3];
+  double hd[3], cd[3], cm[3], dt, srcfac;
+  int i_src, nsrc_y;
+  int64_t nfield;
+};
+
+struct EPtrs {
+  const void* E[3];
+  void* En[3];
+  const void* B[3];
+  const unsigned long long* J[3];
+  const double *srcA, *srcC, *srcS;
+};
+
+// One run's entry in a batched field launch.
+struct FieldJob {
+  FieldArgs A;
+  EPtrs P;
+  void* Bw[3];
+  unsigned long long* Jw[3];
+  double lsin, lcos;
 };
 
 // Emission tables resident on the device (FP64 copy, FP32 copy).
@@ -89,6 +115,12 @@ struct StepParams {
   // FP32 path: current contributions rounded to 2^-jbits (int32 in LDS), widened
   // to the 2^-40 grid when flushed; jbits is chosen so a chunk sum fits int32
   int jbits;
+  // FP32 path: positions are int32 fixed point in cell units with fb fraction
+  // bits (uniform resolution 2^-fb cell over the whole box)
+  int fb[3];
+  float iqs[3];   // 2^-fb
+  float iqd[3];   // dx 2^-fb: fixed point -> absolute position
+  float mvq[3];   // dt/dx 2^fb: velocity -> fixed-point displacement per step
 };
 
 // Arguments of the tile sort (sort.hip).
@@ -97,6 +129,7 @@ struct SortArgs {
   int dims;
   int n[3], tile[3];
   double idx[3];
+  int fb[3];                // FP32 fixed-point positions: cell = q >> fb
   uint32_t nkeys;           // Morton keys of the tiles + 1 bucket for absorbed electrons
   const void* x[3];
   const void* p[3];
@@ -117,6 +150,16 @@ struct SortArgs {
 void launch_sort(const SortArgs& A, bool fp32, hipStream_t s);
 
 void launch_step(int dims, bool fp32, const void* params, hipStream_t s);
+// batched forms (device-resident tables of per-run entries; first[] is the
+// exclusive prefix of chunks / workgroups per run, with first[njobs] = total)
+void launch_step_batch(int dims, bool fp32, const void* tab, const uint32_t* first, int njobs,
+                       uint32_t total, int lds_nodes, hipStream_t s);
+void launch_b_half_batch(bool fp32, const FieldJob* tab, const uint32_t* first, int njobs,
+                         uint32_t total, int zeroJ, hipStream_t s);
+void launch_e_full_batch(bool fp32, const FieldJob* tab, const uint32_t* first, int njobs,
+                         uint32_t total, hipStream_t s);
+uint32_t field_blocks(const struct Ctx& c);
+void fill_field_job(const struct Ctx& c, double lsin, double lcos, FieldJob& F);
 void launch_init_electrons(const struct Ctx& c, hipStream_t s);
 void launch_b_half(const struct Ctx& c, hipStream_t s);
 void launch_e_full(struct Ctx& c, double lsin, double lcos, hipStream_t s);

@@ -58,7 +58,9 @@ __global__ __launch_bounds__(kBlock) void k_sort_key(SortArgs A) {
   if (valid && !(A.id[e] & kDead)) {
     uint32_t t[3] = {0u, 0u, 0u};
     for (int a = 0; a < A.dims; ++a) {
-      int c = (int)floor((double)((const R*)A.x[a])[e] * A.idx[a]);
+      int c;
+      if constexpr (sizeof(R) == 4) c = ((const int*)A.x[a])[e] >> A.fb[a];  // fixed point
+      else c = (int)floor(((const R*)A.x[a])[e] * A.idx[a]);
       c = c < 0 ? 0 : (c >= A.n[a] ? A.n[a] - 1 : c);
       t[a] = (uint32_t)(c / A.tile[a]);
     }

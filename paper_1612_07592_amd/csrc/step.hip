@@ -18,6 +18,7 @@
 // comparison and the energy sums in FP64.
 #include "pic_internal.hpp"
 #include "philox.hpp"
+#include <algorithm>
 #include <type_traits>
 
 namespace pic {
@@ -45,7 +46,7 @@ __device__ inline R unif(uint32_t r);
 template <>
 __device__ inline double unif<double>(uint32_t r) { return unif32(r); }
 template <>
-__device__ inline float unif<float>(uint32_t r) { return unif24f(r); }
+__device__ inline float unif<float>(uint32_t r) { return unif23f(r); }
 
 template <class R>
 struct Idx {
@@ -150,6 +151,33 @@ __device__ inline R gather(const F& f, int c, const R* g) {
   return (R(1) - f2) * a2 + f2 * b2;
 }
 
+// FP32 path: the same interpolation from fixed-point positions q (cell units,
+// fb fraction bits); node index and in-cell fraction come from integer
+// arithmetic, so they are as fine far from the origin as near it.
+__device__ inline void split_q(int q, int S, int fb, float iqs, int& i, float& f) {
+  const int qs = q - (S << (fb - 1));    // half-integer stagger: shift by half a cell
+  i = qs >> fb;                          // floor (arithmetic shift)
+  f = (float)(qs & ((1 << fb) - 1)) * iqs;
+}
+
+template <int D, int SX, int SY, int SZ, class F>
+__device__ inline float gather_q(const F& f, int c, const int* q, const int* fb, const float* iqs) {
+  int i0 = 0, i1 = 0, i2 = 0;
+  float f0 = 0.f, f1 = 0.f, f2 = 0.f;
+  split_q(q[0], SX, fb[0], iqs[0], i0, f0);
+  if (D == 1) return (1.f - f0) * f(c, i0, 0, 0) + f0 * f(c, i0 + 1, 0, 0);
+  split_q(q[1], SY, fb[1], iqs[1], i1, f1);
+  if (D == 3) split_q(q[2], SZ, fb[2], iqs[2], i2, f2);
+  const float v0 = (1.f - f0) * f(c, i0, i1, i2) + f0 * f(c, i0 + 1, i1, i2);
+  const float v1 = (1.f - f0) * f(c, i0, i1 + 1, i2) + f0 * f(c, i0 + 1, i1 + 1, i2);
+  const float a2 = (1.f - f1) * v0 + f1 * v1;
+  if (D == 2) return a2;
+  const float w0 = (1.f - f0) * f(c, i0, i1, i2 + 1) + f0 * f(c, i0 + 1, i1, i2 + 1);
+  const float w1 = (1.f - f0) * f(c, i0, i1 + 1, i2 + 1) + f0 * f(c, i0 + 1, i1 + 1, i2 + 1);
+  const float b2 = (1.f - f1) * w0 + f1 * w1;
+  return (1.f - f2) * a2 + f2 * b2;
+}
+
 // Inverse of one NCS cumulative row: ln(xi) at uniform u.
 template <class R>
 __device__ inline R ncs_inverse(const R* __restrict__ C, const R* __restrict__ lnxi, int n, R u) {
@@ -190,31 +218,30 @@ __device__ inline void shape4(R g, int base, R S[4]) {
 
 // node weights of a point on a 3-node window starting at m (m = lower of the
 // two cells of the move, so the window holds both supports)
-template <class R>
-__device__ inline void shape3(R g, int m, R S[3]) {
-  const R fl = m_floor(g);
-  const int o = (int)fl - m;  // 0 or 1
-  const R f = g - fl;
-  S[0] = o == 0 ? R(1) - f : R(0);
-  S[1] = o == 0 ? f : R(1) - f;
-  S[2] = o == 0 ? R(0) : f;
+__device__ inline void shape3(int cell, float f, int m, float S[3]) {
+  const int o = cell - m;  // 0 or 1
+  S[0] = o == 0 ? 1.f - f : 0.f;
+  S[1] = o == 0 ? f : 1.f - f;
+  S[2] = o == 0 ? 0.f : f;
 }
 
 // FP32 form of the charge-conserving deposit on the 3-node windows that the
 // move actually touches (the fourth node of the general window carries zero).
 template <int D, class Acc>
-__device__ inline void deposit3(const StepParams<float>& P, const Acc& J, const float* x0,
-                                const float* x1, const float* v, double w) {
+__device__ inline void deposit3(const StepParams<float>& P, const Acc& J, const int* q0,
+                                const int* q1, const float* v, double w) {
   const float c0 = (float)(-w * P.invV);
   float S0[3][3], S1[3][3];
   int m[3] = {0, 0, 0};
 #pragma unroll
   for (int a = 0; a < D; ++a) {
-    const float g0 = x0[a] * (float)P.idx[a];
-    const float g1 = x1[a] * (float)P.idx[a];
-    m[a] = min((int)floorf(g0), (int)floorf(g1));
-    shape3<float>(g0, m[a], S0[a]);
-    shape3<float>(g1, m[a], S1[a]);
+    int i0, i1;
+    float f0, f1;
+    split_q(q0[a], 0, P.fb[a], P.iqs[a], i0, f0);
+    split_q(q1[a], 0, P.fb[a], P.iqs[a], i1, f1);
+    m[a] = min(i0, i1);
+    shape3(i0, f0, m[a], S0[a]);
+    shape3(i1, f1, m[a], S1[a]);
   }
   if (D == 1) {
     const float qx = c0 * (float)P.dxdt[0];
@@ -427,7 +454,9 @@ struct Emit {
 // One electron: gather, Boris, eta, NCS, bremsstrahlung, recoil, move, deposit.
 template <class R, int D, class FA, class JA>
 __device__ inline void electron_physics(const StepParams<R>& P, int64_t e, uint32_t idv, double wgt,
-                                        const R* xin, const FA& fld, const JA& cur, Emit<R>& out) {
+                                        const R* xin, const int* qin, const FA& fld, const JA& cur,
+                                        Emit<R>& out) {
+  constexpr bool kF32 = sizeof(R) == 4;
   const uint32_t n = P.step;
   // Philox words of (id, step): drawn only when a test or an event needs them
   U4 r;
@@ -435,7 +464,13 @@ __device__ inline void electron_physics(const StepParams<R>& P, int64_t e, uint3
   auto draw = [&]() {
     if (!have_r) { r = philox4x32_10(idv, n, 0u, 0u, P.key0, P.key1); have_r = true; }
   };
+  // absolute position (FP32 path: from the fixed point, for records and the
+  // prescribed plane wave only; gather, cells and moves use the integers)
   R x[3] = {xin[0], xin[1], xin[2]};
+  if constexpr (kF32) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) x[a] = (float)qin[a] * P.iqd[a];
+  }
   out.xo[0] = x[0]; out.xo[1] = x[1]; out.xo[2] = x[2];
   R px = P.p[0][e], py = P.p[1][e], pz = P.p[2][e];
 
@@ -454,6 +489,13 @@ __device__ inline void electron_physics(const StepParams<R>& P, int64_t e, uint3
         B2 = v;
       }
     }
+  } else if constexpr (kF32) {
+    E0 = gather_q<D, 1, 0, 0>(fld, 0, qin, P.fb, P.iqs);
+    E1 = gather_q<D, 0, 1, 0>(fld, 1, qin, P.fb, P.iqs);
+    E2 = gather_q<D, 0, 0, 1>(fld, 2, qin, P.fb, P.iqs);
+    B0 = gather_q<D, 0, 1, 1>(fld, 3, qin, P.fb, P.iqs);
+    B1 = gather_q<D, 1, 0, 1>(fld, 4, qin, P.fb, P.iqs);
+    B2 = gather_q<D, 1, 1, 0>(fld, 5, qin, P.fb, P.iqs);
   } else {
     R g[3] = {R(0), R(0), R(0)};
 #pragma unroll
@@ -541,7 +583,9 @@ __device__ inline void electron_physics(const StepParams<R>& P, int64_t e, uint3
       int ci[3] = {0, 0, 0};
 #pragma unroll
       for (int a = 0; a < D; ++a) {
-        int q = (int)m_floor(x[a] * R(P.idx[a]));
+        int q;
+        if constexpr (kF32) q = qin[a] >> P.fb[a];
+        else q = (int)m_floor(x[a] * R(P.idx[a]));
         q = q < 0 ? 0 : (q > P.n[a] - 1 ? P.n[a] - 1 : q);
         ci[a] = q;
       }
@@ -591,19 +635,30 @@ __device__ inline void electron_physics(const StepParams<R>& P, int64_t e, uint3
   P.p[0][e] = px; P.p[1][e] = py; P.p[2][e] = pz;
   const R ig = m_div(R(1), gamma);
   const R v[3] = {px * ig, py * ig, pz * ig};
-  R x1[3] = {x[0], x[1], x[2]};
   bool outside = false;
+  if constexpr (kF32) {
+    // fixed-point move: displacement rounded to 2^-fb cell; the deposit sees
+    // exactly the stored move, so charge is conserved on the stored positions
+    int q1[3] = {qin[0], qin[1], qin[2]};
 #pragma unroll
-  for (int a = 0; a < D; ++a) {
-    x1[a] = x[a] + v[a] * R(P.dt);
-    if (x1[a] < R(0) || x1[a] >= R(P.L[a])) outside = true;
-  }
-  if (!(P.flags & PIC_FIELDS_FROZEN)) {
-    if constexpr (sizeof(R) == 4) deposit3<D>(P, cur, x, x1, v, wgt);
-    else deposit<R, D>(P, cur, x, x1, v, wgt);
-  }
+    for (int a = 0; a < D; ++a) {
+      q1[a] = qin[a] + (int)rintf(v[a] * P.mvq[a]);
+      if (q1[a] < 0 || q1[a] >= (P.n[a] << P.fb[a])) outside = true;
+    }
+    if (!(P.flags & PIC_FIELDS_FROZEN)) deposit3<D>(P, cur, qin, q1, v, wgt);
 #pragma unroll
-  for (int a = 0; a < D; ++a) P.x[a][e] = x1[a];
+    for (int a = 0; a < D; ++a) reinterpret_cast<int*>(P.x[a])[e] = q1[a];
+  } else {
+    R x1[3] = {x[0], x[1], x[2]};
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      x1[a] = x[a] + v[a] * R(P.dt);
+      if (x1[a] < R(0) || x1[a] >= R(P.L[a])) outside = true;
+    }
+    if (!(P.flags & PIC_FIELDS_FROZEN)) deposit<R, D>(P, cur, x, x1, v, wgt);
+#pragma unroll
+    for (int a = 0; a < D; ++a) P.x[a][e] = x1[a];
+  }
   if (outside) P.id[e] = idv | kDead;
 }
 
@@ -616,13 +671,10 @@ __device__ inline void electron_physics(const StepParams<R>& P, int64_t e, uint3
 // LDS and the current is accumulated there (FP64: int64 in units of 2^-40;
 // FP32: int32 in units of 2^-jbits); otherwise both go to global memory.
 template <class R, int D>
-__global__ __launch_bounds__(kBlock) void k_electron_step(const StepParams<R> P) {
+__device__ __forceinline__ void step_chunk(const StepParams<R>& P, const uint32_t chunk,
+                                           unsigned char* smem, int* s_lo, int* s_hi) {
   constexpr bool kF32 = sizeof(R) == 4;
   using JT = typename std::conditional<kF32, int, unsigned long long>::type;
-  extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ int s_lo[3], s_hi[3];
-  const uint32_t per = gridDim.x >> 3;
-  const uint32_t chunk = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
   const uint32_t t = threadIdx.x;
   const int64_t e = (int64_t)chunk * kBlock + (int64_t)((t & 15u) * 16u + (t >> 4));
   const int64_t n_act = (int64_t)*P.n_active;
@@ -634,12 +686,18 @@ __global__ __launch_bounds__(kBlock) void k_electron_step(const StepParams<R> P)
     live = (idv & kDead) == 0;
   }
   R x[3] = {R(0), R(0), R(0)};
+  int q[3] = {0, 0, 0};
   int bb[3] = {0, 0, 0};
   if (live) {
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      x[a] = P.x[a][e];
-      bb[a] = (int)m_floor(x[a] * R(P.idx[a])) - 1;
+      if constexpr (kF32) {
+        q[a] = reinterpret_cast<const int*>(P.x[a])[e];
+        bb[a] = (q[a] >> P.fb[a]) - 1;
+      } else {
+        x[a] = P.x[a][e];
+        bb[a] = (int)m_floor(x[a] * R(P.idx[a])) - 1;
+      }
     }
   }
   // ---- the chunk's box of nodes (deposit windows cover the gathers) --------
@@ -703,20 +761,20 @@ __global__ __launch_bounds__(kBlock) void k_electron_step(const StepParams<R> P)
       if constexpr (kF32) {
         const LdsCurrent32 ja{reinterpret_cast<int*>(sJ), lo[0], lo[1], lo[2], ext[0], ext[1], nodes,
                               (float)ldexp(1.0, P.jbits)};
-        electron_physics<R, D>(P, e, idv, wgt, x, fa, ja, out);
+        electron_physics<R, D>(P, e, idv, wgt, x, q, fa, ja, out);
       } else {
         const LdsCurrent ja{reinterpret_cast<unsigned long long*>(sJ), lo[0], lo[1], lo[2], ext[0], ext[1], nodes};
-        electron_physics<R, D>(P, e, idv, wgt, x, fa, ja, out);
+        electron_physics<R, D>(P, e, idv, wgt, x, q, fa, ja, out);
       }
     } else {
       const GlobalField<R> fa{P.F, I};
       if constexpr (kF32) {
         const GlobalCurrent32 ja{{P.J[0], P.J[1], P.J[2]}, {P.gg[0], P.gg[1], P.gg[2], P.sz[0], P.sz[1]},
                                  (float)ldexp(1.0, P.jbits), 40 - P.jbits};
-        electron_physics<R, D>(P, e, idv, wgt, x, fa, ja, out);
+        electron_physics<R, D>(P, e, idv, wgt, x, q, fa, ja, out);
       } else {
         const GlobalCurrent ja{{P.J[0], P.J[1], P.J[2]}, {P.gg[0], P.gg[1], P.gg[2], P.sz[0], P.sz[1]}};
-        electron_physics<R, D>(P, e, idv, wgt, x, fa, ja, out);
+        electron_physics<R, D>(P, e, idv, wgt, x, q, fa, ja, out);
       }
     }
   }
@@ -799,6 +857,38 @@ __global__ __launch_bounds__(kBlock) void k_electron_step(const StepParams<R> P)
 }
 
 template <class R, int D>
+__global__ __launch_bounds__(kBlock) void k_electron_step(const StepParams<R> P) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int s_lo[3], s_hi[3];
+  const uint32_t per = gridDim.x >> 3;
+  step_chunk<R, D>(P, (blockIdx.x & 7u) * per + (blockIdx.x >> 3), smem, s_lo, s_hi);
+}
+
+// Batched form for several runs: the chunks of every run are laid end to end
+// (run j owns [first[j], first[j+1])) and one launch covers them all, with the
+// same XCD-aware spread as the single-run kernel.  A chunk is processed
+// exactly as the single-run kernel processes it, so a run's results do not
+// depend on what else is in the batch.  (One chunk per workgroup: a
+// grid-stride loop over chunks raises the kernel from 68 to 106 VGPRs and
+// drops occupancy from 7 to 4 waves per SIMD.)
+template <class R, int D>
+__global__ __launch_bounds__(kBlock) void k_electron_step_batch(const StepParams<R>* __restrict__ tab,
+                                                                const uint32_t* __restrict__ first,
+                                                                int njobs) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int s_lo[3], s_hi[3];
+  const uint32_t per = gridDim.x >> 3;
+  const uint32_t w = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
+  if (w >= first[njobs]) return;  // padding of the grid to a multiple of 8
+  int lo = 0, hi = njobs - 1;     // largest j with first[j] <= w
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (first[mid] <= w) lo = mid; else hi = mid - 1;
+  }
+  step_chunk<R, D>(tab[lo], w - first[lo], smem, s_lo, s_hi);
+}
+
+template <class R, int D>
 static void launch_one(const void* params, hipStream_t s) {
   const StepParams<R>& P = *static_cast<const StepParams<R>*>(params);
   if (P.N <= 0) return;
@@ -807,6 +897,30 @@ static void launch_one(const void* params, hipStream_t s) {
   const size_t jsz = sizeof(R) == 4 ? sizeof(int) : sizeof(unsigned long long);
   const size_t lds = (size_t)P.lds_nodes * (6 * sizeof(R) + 3 * jsz);
   hipLaunchKernelGGL((k_electron_step<R, D>), dim3((unsigned)blocks), dim3(kBlock), lds, s, P);
+}
+
+template <class R, int D>
+static void launch_batch(const void* tab, const uint32_t* first, int njobs, uint32_t total,
+                         int lds_nodes, hipStream_t s) {
+  if (njobs <= 0 || total == 0) return;
+  const size_t jsz = sizeof(R) == 4 ? sizeof(int) : sizeof(unsigned long long);
+  const size_t lds = (size_t)lds_nodes * (6 * sizeof(R) + 3 * jsz);
+  const int64_t blocks = ((int64_t)total + 7) / 8 * 8;
+  hipLaunchKernelGGL((k_electron_step_batch<R, D>), dim3((unsigned)blocks), dim3(kBlock), lds, s,
+                     static_cast<const StepParams<R>*>(tab), first, njobs);
+}
+
+void launch_step_batch(int dims, bool fp32, const void* tab, const uint32_t* first, int njobs,
+                       uint32_t total, int lds_nodes, hipStream_t s) {
+  if (fp32) {
+    if (dims == 1) launch_batch<float, 1>(tab, first, njobs, total, lds_nodes, s);
+    else if (dims == 2) launch_batch<float, 2>(tab, first, njobs, total, lds_nodes, s);
+    else launch_batch<float, 3>(tab, first, njobs, total, lds_nodes, s);
+  } else {
+    if (dims == 1) launch_batch<double, 1>(tab, first, njobs, total, lds_nodes, s);
+    else if (dims == 2) launch_batch<double, 2>(tab, first, njobs, total, lds_nodes, s);
+    else launch_batch<double, 3>(tab, first, njobs, total, lds_nodes, s);
+  }
 }
 
 void launch_step(int dims, bool fp32, const void* params, hipStream_t s) {

@@ -48,8 +48,10 @@ def test_binding_struct_layouts_match_header():
 #include <stddef.h>
 #include "pic.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu\n", sizeof(pic_config), sizeof(pic_tables), sizeof(pic_stats),
-         offsetof(pic_config, stream), offsetof(pic_tables, br_cdf));
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(pic_config), sizeof(pic_tables),
+         sizeof(pic_stats), offsetof(pic_config, stream), offsetof(pic_tables, br_cdf),
+         sizeof(pic_server_config), offsetof(pic_server_config, stream), sizeof(pic_job_result),
+         offsetof(pic_job_result, stats));
   return 0;
 }'''
     d = os.path.join(ROOT, "_build")
@@ -60,7 +62,9 @@ int main(void) {
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
     got = [int(v) for v in subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()]
     want = [C.sizeof(B.pic_config), C.sizeof(B.pic_tables), C.sizeof(B.pic_stats),
-            B.pic_config.stream.offset, B.pic_tables.br_cdf.offset]
+            B.pic_config.stream.offset, B.pic_tables.br_cdf.offset,
+            C.sizeof(B.pic_server_config), B.pic_server_config.stream.offset,
+            C.sizeof(B.pic_job_result), B.pic_job_result.stats.offset]
     assert got == want
 
 
@@ -108,6 +112,34 @@ def test_abi_version_checked():
     c.abi_version = 99
     n = C.c_uint64()
     assert L.pic_memory_required(C.byref(c), C.byref(n)) == 1
+
+
+def test_batch_and_server_argument_checks():
+    """Argument checks that fail before any device call."""
+    L = B.load()
+    h = C.c_void_p()
+    assert L.pic_batch_create(None, None) == 1
+    assert L.pic_step_many(None, None, None, 0) == 1
+    sc = B.pic_server_config()
+    sc.abi_version = B.PIC_ABI_VERSION
+    sc.max_jobs = 0
+    sc.quantum_steps = 8
+    assert L.pic_server_create(C.byref(sc), C.byref(h)) == 1
+    sc.max_jobs = 4
+    sc.quantum_steps = 0
+    assert L.pic_server_create(C.byref(sc), C.byref(h)) == 1
+    sc.quantum_steps = 8
+    sc.abi_version = 7
+    assert L.pic_server_create(C.byref(sc), C.byref(h)) == 1
+    job = C.c_uint64()
+    cfg = B.config_from(W.c1())
+    assert L.pic_server_submit(None, C.byref(cfg), None, 1, -1.0, C.byref(job)) == 1
+    n = C.c_int32()
+    assert L.pic_server_poll(None, None, 0, C.byref(n)) == 1
+    assert L.pic_server_run(None, None, None) == 1
+    L.pic_server_destroy(None)
+    L.pic_batch_destroy(None)
+    assert L.pic_server_clock(None) == 0.0
 
 
 def test_null_arguments():
