@@ -171,6 +171,8 @@ def main():
     ap.add_argument("--sort-every", type=int, default=0,
                     help="tile-sort interval in steps (0 = library default, -1 = never)")
     ap.add_argument("--no-serving", action="store_true", help="skip the scan-job server runs")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run one plain device copy of this many MiB (HBM counter calibration)")
     ap.add_argument("--c3-steps", type=int, default=1000)
     ap.add_argument("--c4-jobs", type=int, default=24,
                     help="jobs of the Poisson stream served (0 = none)")
@@ -183,6 +185,15 @@ def main():
     assert torch.cuda.is_available(), "no GPU visible"
     from paper_1612_07592_amd import binding
     binding.load()
+    if args.copy_calibration > 0:
+        n = args.copy_calibration << 18
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        torch.mul(a, 1.0, out=b)  # an elementwise kernel: reads and writes n floats
+        torch.cuda.synchronize()
+        print(f"[bench] copy calibration: {n * 4} bytes read, {n * 4} written", file=sys.stderr, flush=True)
+        del a, b
     w = _workload(args.workload, args.precision, args.steps)
     w["sort_every"] = args.sort_every
     t0 = time.perf_counter()
@@ -237,6 +248,22 @@ def main():
                        "events": r64["stats"]["events"], "kept": r64["stats"]["kept"]}
         out["fp32_over_fp64"] = value / v64
         out["fp32_vs_fp64"] = precision_check(r, r64)
+        # run-to-run spread of the full PIC run: FP64 with the next two seeds
+        refs = []
+        for k in (1, 2):
+            rref = run_gpu(dict(w64, seed=int(w64["seed"]) + k), tables, args.steps, 0, torch,
+                           photons=True)
+            refs.append(precision_check(rref, r64))
+        pc = out["fp32_vs_fp64"]
+        pc["reference_fp64_other_seeds"] = refs
+        dn = max(abs(q["photon_count"]["fp32"] - q["photon_count"]["fp64"]) for q in refs)
+        de = max(abs(q["radiated_energy"]["rel"]) for q in refs)
+        dk = max(q["spectrum_ks"]["statistic"] or 0.0 for q in refs)
+        n64 = pc["photon_count"]["fp64"]
+        pc["within_seed_spread"] = {
+            "photon_count": abs(pc["photon_count"]["fp32"] - n64) <= 2.0 * max(dn, 3.0 * n64 ** 0.5),
+            "radiated_energy": abs(pc["radiated_energy"]["rel"]) <= max(0.01, 2.0 * de),
+            "spectrum_ks": (pc["spectrum_ks"]["statistic"] or 0.0) <= 2.0 * dk}
         print(f"[bench] fp64: {v64:.3e} e-steps/s; {out['fp32_vs_fp64']}", file=sys.stderr, flush=True)
     if not args.no_serving and args.workload == "c2":
         out["serving"] = serving(args, torch)
