@@ -27,6 +27,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# Non-packed FP32 (and FP64) VALU issue of MI355X: 256 CU x 4 SIMD x 16 lanes
+# x 2.4 GHz, one lane operation per lane and cycle (packed FP32 is disabled).
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# algorithmic lane operations per electron-step that every live electron
+# executes (gather, Boris, eta, NCS decrement, move, deposit, stats), quarter-
+# rate operations counted 4; the conditional brem test and event sampling are
+# not included
+ALU_OPS = {1: 292, 2: 548, 3: 1366}
+KERNEL_SOURCES = ["step.hip", "pic_internal.hpp", "philox.hpp"]
 # algorithmic bytes per electron-step of the step kernel: the electron state
 # read once (positions, momenta, tau, weight, id) and written once (positions,
 # momenta, tau); fields and tables are amortised over the electrons of a cell
@@ -49,12 +58,37 @@ def _workload(name, precision, steps):
     return w
 
 
+def _kernel_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1612_07592_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _measured_traffic(workload, precision):
+    """Calibrated HBM-counter bytes per launch of the step kernel, from the
+    committed rocprofv3 summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    for e in d.get("entries", []):
+        if (e["kernel_sha"] == _kernel_hash() and e["workload"] == workload
+                and e["precision"] == precision):
+            return e["bytes_per_launch"]
+    return None
+
+
 def _num_electrons(w):
     from paper_1612_07592_amd import workloads as W
     return W.num_electrons(w)
 
 
-def run_gpu(w, tables, steps, warmup, torch, photons=False):
+def run_gpu(w, tables, steps, warmup, torch, photons=False, kernel_times=True):
+    """Time `steps` steps from a fresh context.  The wall-clock run records no
+    events; a second identical run, with HIP events on the context's stream
+    around every launch group, gives the per-kernel times."""
     from paper_1612_07592_amd import binding
     if warmup > 0:
         s = binding.Sim(w, tables)
@@ -62,7 +96,6 @@ def run_gpu(w, tables, steps, warmup, torch, photons=False):
         s.pic_emission_stats()
         s.pic_destroy()
     s = binding.Sim(w, tables)
-    s.profile(True)
     s.synchronize()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -71,11 +104,19 @@ def run_gpu(w, tables, steps, warmup, torch, photons=False):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     st = s.pic_emission_stats()
-    ms, n = s.profile_read()
     ph = s.photons() if photons else None
     s.pic_destroy()
-    return dict(wall_s=t1 - t0, stats=st, step_kernel_ms=float(ms[0]), field_ms=float(ms[1]),
-                sort_ms=float(ms[2]), step_launches=int(n[0]), photons=ph)
+    out = dict(wall_s=t1 - t0, stats=st, photons=ph, step_kernel_ms=None, field_ms=None,
+               sort_ms=None, step_launches=0)
+    if kernel_times:
+        s = binding.Sim(w, tables)
+        s.profile(True)
+        s.pic_step(steps)
+        ms, n = s.profile_read()
+        s.pic_destroy()
+        out.update(step_kernel_ms=float(ms[0]), field_ms=float(ms[1]), sort_ms=float(ms[2]),
+                   step_launches=int(n[0]), profiled_wall_ms=float(ms.sum()))
+    return out
 
 
 def precision_check(r32, r64):
@@ -208,6 +249,9 @@ def main():
     dims = int(w["dims"])
     bpe = STATE_BYTES[(args.precision, dims)]
     achieved = bpe * esteps / (r["step_kernel_ms"] * 1e-3) / 1e9
+    ops = ALU_OPS[dims]
+    alu = ops * esteps / (r["step_kernel_ms"] * 1e-3) / 1e12
+    launches = max(1, r["step_launches"])
     out = {
         "metric": "electron-steps/s",
         "value": value,
@@ -224,24 +268,31 @@ def main():
         "config": {"workload": w["name"], "dims": dims, "cells": list(w["n"]),
                    "electrons": _num_electrons(w),
                    "precision": args.precision, "a0": w["a0"], "Z": w["Z"]},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+        "roofline": {"bound": "alu", "achieved": alu, "peak": ALU_PEAK_TOPS, "unit": "TFLOP/s",
+                     "frac": alu / ALU_PEAK_TOPS,
+                     "traffic": _measured_traffic(w["name"], args.precision),
                      "kernel": f"k_electron_step<{'float' if args.precision == 'fp32' else 'double'},{dims}>",
-                     "bytes_per_electron_step": bpe,
-                     "kernel_avg_us": r["step_kernel_ms"] * 1e3 / max(1, r["step_launches"])},
+                     "ops_per_electron_step": ops,
+                     "electron_steps_per_launch": esteps / launches,
+                     "kernel_avg_us": r["step_kernel_ms"] * 1e3 / launches,
+                     "hbm": {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": achieved / HBM_PEAK_GBS, "bytes_per_electron_step": bpe}},
         "time_share": {"electron_step": r["step_kernel_ms"] / (r["wall_s"] * 1e3),
                        "field_solve": r["field_ms"] / (r["wall_s"] * 1e3),
                        "sort": r["sort_ms"] / (r["wall_s"] * 1e3)},
+        "kernel_ms": {"electron_step": r["step_kernel_ms"], "field_solve": r["field_ms"],
+                      "sort": r["sort_ms"]},
         "untiled_fraction": st["untiled_steps"] / max(1, esteps),
         "emission": {"events": st["events"], "kept": st["kept"], "dropped_ncs": st["dropped_ncs"],
                      "overflow": st["overflow"], "e_rad_kept": st["e_rad_kept"]},
     }
     print(f"[bench] {args.precision}: {value:.3e} e-steps/s, step kernel "
-          f"{out['roofline']['kernel_avg_us']:.1f} us, {achieved:.0f} GB/s", file=sys.stderr, flush=True)
+          f"{out['roofline']['kernel_avg_us']:.1f} us, {alu:.2f} Tops/s, {achieved:.0f} GB/s",
+          file=sys.stderr, flush=True)
     if not args.no_fp64 and args.precision == "fp32":
         w64 = _workload(args.workload, "fp64", args.steps)
         w64["sort_every"] = args.sort_every
-        r64 = run_gpu(w64, tables, args.steps, 0, torch, photons=True)
+        r64 = run_gpu(w64, tables, args.steps, 0, torch, photons=True, kernel_times=True)
         v64 = r64["stats"]["electron_steps"] / r64["wall_s"]
         out["fp64"] = {"value": v64, "ms_per_step": r64["wall_s"] * 1e3 / args.steps,
                        "kernel_avg_us": r64["step_kernel_ms"] * 1e3 / max(1, r64["step_launches"]),
@@ -252,7 +303,7 @@ def main():
         refs = []
         for k in (1, 2):
             rref = run_gpu(dict(w64, seed=int(w64["seed"]) + k), tables, args.steps, 0, torch,
-                           photons=True)
+                           photons=True, kernel_times=False)
             refs.append(precision_check(rref, r64))
         pc = out["fp32_vs_fp64"]
         pc["reference_fp64_other_seeds"] = refs

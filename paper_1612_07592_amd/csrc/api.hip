@@ -145,7 +145,8 @@ std::string derive(const pic_config& cfg, Ctx& c) {
   c.wgt = cfg.ne_over_nc * V / (double)cfg.ppc;
   c.fp32 = cfg.precision == PIC_FP32_MIXED;
   c.pcap = cfg.photon_capacity;
-  c.nblocks_step = ((N + kBlock - 1) / kBlock + 7) / 8 * 8;
+  const int64_t per_chunk = chunk_electrons(c.fp32, g.dims);
+  c.nblocks_step = ((N + per_chunk - 1) / per_chunk + 7) / 8 * 8;
   c.nslots = c.nblocks_step * (kBlock / 64);
   // FP32 positions: int32 fixed point in cells; n << fb stays below 2^30 so a
   // move of less than a cell past either wall cannot overflow, and fb <= 24
@@ -256,6 +257,7 @@ Plan make_plan(Ctx& c) {
   P.add((void**)&c.slot_sum, nsl * kSlotSum * 8);
   P.add((void**)&c.red_cnt, (size_t)reduce_scratch_cnt() * 8);
   P.add((void**)&c.red_sum, (size_t)reduce_scratch_sum() * 8);
+  P.add(&c.cold, std::max(sizeof(StepCold<double>), sizeof(StepCold<float>)));
   // tables: FP64 and FP32 copies of the standard-size tables
   const size_t tb = (256 + 256 + 256 * 256 + 128 + 128 * 64);
   P.total += tb * 12 + 10 * 256;
@@ -322,7 +324,7 @@ void fill_step_params(Ctx& c, StepParams<R>& P) {
   P.key0 = c.key0;
   P.key1 = c.key1;
   P.flags = c.cfg.flags;
-  P.frozen_kind = c.cfg.frozen_kind;
+  P.cold = (const StepCold<R>*)c.cold;
   P.dt = g.dt;
   P.tn = (double)c.step * g.dt;
   for (int a = 0; a < 3; ++a) {
@@ -337,10 +339,6 @@ void fill_step_params(Ctx& c, StepParams<R>& P) {
     P.idx[a] = g.idx[a];
     P.L[a] = g.L[a];
     P.dxdt[a] = g.dx[a] / g.dt;
-    P.fE[a] = c.cfg.frozen_E[a];
-    P.fB[a] = c.cfg.frozen_B[a];
-    P.px[a] = (R*)c.px[a];
-    P.pk[a] = (R*)c.pk[a];
   }
   P.tau = c.tau;
   P.w = c.w;
@@ -350,29 +348,18 @@ void fill_step_params(Ctx& c, StepParams<R>& P) {
   P.iES = c.iES;
   P.K_N = c.K_N;
   P.K_BR = c.K_BR;
-  P.photon_cut = c.cfg.photon_cut_mc2;
-  P.fa = c.cfg.frozen_a;
   const DevTables& t = c.t;
-  P.n_eta = t.n_eta; P.n_xi = t.n_xi; P.n_T = t.n_T; P.n_y = t.n_y;
+  P.n_eta = t.n_eta; P.n_T = t.n_T;
   P.ln_eta0 = t.ln_eta0; P.idln_eta = t.idln_eta; P.ln_T0 = t.ln_T0; P.idln_T = t.idln_T;
-  P.k_cut = t.k_cut; P.lnk = t.lnk; P.iny1 = t.iny1;
+  P.k_cut = t.k_cut;
   P.eta_skip = t.n_eta > 0 ? exp(t.ln_eta0) * (1.0 - 1e-6) : 0.0;
   if (sizeof(R) == 8) {
-    P.h = (const R*)t.h; P.lnxi = (const R*)t.lnxi; P.ncs = (const R*)t.ncs;
-    P.sig = (const R*)t.sig; P.br = (const R*)t.br;
+    P.h = (const R*)t.h;
+    P.sig = (const R*)t.sig;
   } else {
-    P.h = (const R*)t.hf; P.lnxi = (const R*)t.lnxif; P.ncs = (const R*)t.ncsf;
-    P.sig = (const R*)t.sigf; P.br = (const R*)t.brf;
+    P.h = (const R*)t.hf;
+    P.sig = (const R*)t.sigf;
   }
-  P.pcap = c.pcap;
-  P.pe = (R*)c.pe;
-  P.pw = c.pw;
-  P.pstep = c.pstep;
-  P.ppar = c.ppar;
-  P.pproc = c.pproc;
-  P.pcount = c.pcount;
-  P.slot_cnt = c.slot_cnt;
-  P.slot_sum = c.slot_sum;
   P.n_active = c.n_active;
   P.lds_nodes = c.lds_nodes;
   P.jbits = c.jbits;
@@ -382,6 +369,54 @@ void fill_step_params(Ctx& c, StepParams<R>& P) {
     P.iqd[a] = (float)(g.dx[a] * ldexp(1.0, -g.fb[a]));
     P.mvq[a] = (float)(g.dt * g.idx[a] * ldexp(1.0, g.fb[a]));
   }
+}
+
+template <class R>
+void fill_step_cold(const Ctx& c, StepCold<R>& C) {
+  C.frozen_kind = c.cfg.frozen_kind;
+  for (int a = 0; a < 3; ++a) {
+    C.fE[a] = c.cfg.frozen_E[a];
+    C.fB[a] = c.cfg.frozen_B[a];
+    C.px[a] = (R*)c.px[a];
+    C.pk[a] = (R*)c.pk[a];
+  }
+  C.fa = c.cfg.frozen_a;
+  C.photon_cut = c.cfg.photon_cut_mc2;
+  const DevTables& t = c.t;
+  C.n_xi = t.n_xi;
+  C.n_y = t.n_y;
+  C.iny1 = t.iny1;
+  C.lnk = t.lnk;
+  if (sizeof(R) == 8) {
+    C.ncs = (const R*)t.ncs; C.lnxi = (const R*)t.lnxi; C.br = (const R*)t.br;
+  } else {
+    C.ncs = (const R*)t.ncsf; C.lnxi = (const R*)t.lnxif; C.br = (const R*)t.brf;
+  }
+  C.pcap = c.pcap;
+  C.pe = (R*)c.pe;
+  C.pw = c.pw;
+  C.pstep = c.pstep;
+  C.ppar = c.ppar;
+  C.pproc = c.pproc;
+  C.pcount = c.pcount;
+  C.slot_cnt = c.slot_cnt;
+  C.slot_sum = c.slot_sum;
+}
+
+// (Re)write the device copy of the cold block; called at creation and when
+// tables are loaded (the stream is drained first: kernels may be reading it).
+pic_status upload_cold(Ctx& c) {
+  HIPCHK(c, hipStreamSynchronize(c.stream));
+  if (c.fp32) {
+    StepCold<float> C{};
+    fill_step_cold(c, C);
+    HIPCHK(c, hipMemcpy(c.cold, &C, sizeof(C), hipMemcpyHostToDevice));
+  } else {
+    StepCold<double> C{};
+    fill_step_cold(c, C);
+    HIPCHK(c, hipMemcpy(c.cold, &C, sizeof(C), hipMemcpyHostToDevice));
+  }
+  return PIC_OK;
 }
 
 bool sort_due(const Ctx& c) { return c.sort_every > 0 && c.step % (uint64_t)c.sort_every == 0; }
@@ -496,7 +531,8 @@ void stage_step_group(std::vector<unsigned char>& st, std::vector<BatchLaunch>& 
     StepParams<R> P{};
     fill_step_params(*c, P);
     tab.push_back(P);
-    first.push_back(first.back() + (uint32_t)((c->N + kBlock - 1) / kBlock));
+    const int64_t per_chunk = chunk_electrons(c->fp32, dims);
+    first.push_back(first.back() + (uint32_t)((c->N + per_chunk - 1) / per_chunk));
     lds = std::max(lds, c->lds_nodes);
   }
   if (tab.empty()) return;
@@ -592,6 +628,11 @@ pic_status pic_create(const pic_config* cfg, pic_ctx** out) {
     delete ctx;
     return PIC_ERR_DEVICE;
   }
+  if (upload_cold(c) != PIC_OK) {
+    g_create_err = c.err;
+    delete ctx;
+    return PIC_ERR_DEVICE;
+  }
   *out = ctx;
   return PIC_OK;
 }
@@ -660,6 +701,8 @@ pic_status pic_load_tables(pic_ctx* ctx, const pic_tables* t) {
   d.ln_eta0 = t->ln_eta0; d.idln_eta = 1.0 / t->dln_eta;
   d.ln_T0 = t->ln_T0; d.idln_T = 1.0 / t->dln_T;
   d.k_cut = t->k_cut_mc2; d.lnk = log(t->k_cut_mc2); d.iny1 = 1.0 / (double)(t->n_y - 1);
+  st = upload_cold(c);
+  if (st) return st;
   c.tables_loaded = true;
   return PIC_OK;
 }

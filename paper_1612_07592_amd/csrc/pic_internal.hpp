@@ -65,13 +65,43 @@ struct DevTables {
   float *hf = nullptr, *lnxif = nullptr, *ncsf = nullptr, *sigf = nullptr, *brf = nullptr;
 };
 
+// Parameters the electron-step kernel needs only on rare paths (prescribed
+// fields, event sampling, photon append, statistics).  They live in device
+// memory and are read with scalar loads where used, which keeps the kernel's
+// argument block, and so its scalar-register pressure, small.
+template <class R>
+struct StepCold {
+  uint32_t frozen_kind;
+  double fE[3], fB[3], fa;
+  double photon_cut;
+  int n_xi, n_y;
+  double iny1, lnk;
+  const R* ncs;
+  const R* lnxi;
+  const R* br;
+  uint64_t pcap;
+  R* px[3];
+  R* pk[3];
+  R* pe;
+  double* pw;
+  uint32_t* pstep;
+  uint32_t* ppar;
+  uint32_t* pproc;
+  unsigned long long* pcount;
+  unsigned long long* slot_cnt;
+  double* slot_sum;
+};
+
 // Parameter block of the electron-step kernel (passed by value).
 template <class R>
 struct StepParams {
   int64_t N;
   uint32_t step, key0, key1;
-  uint32_t flags, frozen_kind;
-  double dt, tn;
+  uint32_t flags;
+  const StepCold<R>* cold;
+  // constants in the working precision (a float holds half the scalar
+  // registers of a double in the kernel's argument block)
+  R dt, tn;
   // electrons
   R* x[3];
   R* p[3];
@@ -82,33 +112,16 @@ struct StepParams {
   const R* F[6];
   unsigned long long* J[3];
   int n[3], gg[3], sz[3];
-  double idx[3], L[3], dxdt[3], invV;
+  R idx[3], L[3], dxdt[3], invV;
   const double* ni;
   // physics constants
-  double iES, K_N, K_BR, photon_cut;
-  double fE[3], fB[3], fa;
-  // tables
-  int n_eta, n_xi, n_T, n_y;
-  double ln_eta0, idln_eta, ln_T0, idln_T, k_cut, lnk, iny1;
-  double eta_skip;  // slightly below the first eta of the table
+  R iES, K_N, K_BR;
+  // tables (decrement and collision test; the sampling rows are cold)
+  int n_eta, n_T;
+  R ln_eta0, idln_eta, ln_T0, idln_T, k_cut;
+  R eta_skip;  // slightly below the first eta of the table
   const R* h;
-  const R* lnxi;
-  const R* ncs;
   const R* sig;
-  const R* br;
-  // photons
-  uint64_t pcap;
-  R* px[3];
-  R* pk[3];
-  R* pe;
-  double* pw;
-  uint32_t* pstep;
-  uint32_t* ppar;
-  uint32_t* pproc;
-  unsigned long long* pcount;
-  // stats slots
-  unsigned long long* slot_cnt;
-  double* slot_sum;
   // cell-sorted layout: live electrons are [0, *n_active); LDS tile capacity
   const uint32_t* n_active;
   int lds_nodes;
@@ -150,6 +163,7 @@ struct SortArgs {
 void launch_sort(const SortArgs& A, bool fp32, hipStream_t s);
 
 void launch_step(int dims, bool fp32, const void* params, hipStream_t s);
+int chunk_electrons(bool fp32, int dims);   // electrons per step-kernel workgroup
 // batched forms (device-resident tables of per-run entries; first[] is the
 // exclusive prefix of chunks / workgroups per run, with first[njobs] = total)
 void launch_step_batch(int dims, bool fp32, const void* tab, const uint32_t* first, int njobs,
@@ -229,6 +243,7 @@ struct Ctx {
   // reduction scratch
   unsigned long long* red_cnt = nullptr;
   double* red_sum = nullptr;
+  void* cold = nullptr;       // device copy of StepCold<R>
   bool tables_loaded = false;
   // optional kernel timing (pairs of events per launch group)
   bool prof = false;

@@ -48,6 +48,13 @@ __device__ inline double unif<double>(uint32_t r) { return unif32(r); }
 template <>
 __device__ inline float unif<float>(uint32_t r) { return unif23f(r); }
 
+// The cold parameter block, read through the constant address space so the
+// compiler issues scalar loads at the point of use.
+template <class R>
+using ColdPtr = const __attribute__((address_space(4))) StepCold<R>*;
+template <class R>
+__device__ inline ColdPtr<R> cold(const StepParams<R>& P) { return (ColdPtr<R>)P.cold; }
+
 template <class R>
 struct Idx {
   int gg0, gg1, gg2, sz0, sz1;
@@ -442,6 +449,15 @@ __device__ inline uint32_t lane_offset(unsigned long long mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// Electrons per step-kernel workgroup: one per thread.  (Two per thread,
+// in two passes, raised the FP32 2D kernel from 67 to 87 VGPRs and ran 15%
+// slower.)
+int chunk_electrons(bool fp32, int dims) {
+  (void)fp32;
+  (void)dims;
+  return kBlock;
+}
+
 // Per-electron results the block-level stages (append, statistics) need.
 template <class R>
 struct Emit {
@@ -477,14 +493,15 @@ __device__ inline void electron_physics(const StepParams<R>& P, int64_t e, uint3
   // ---- gather E^n, B^n at x^n ----------------------------------------------
   R E0, E1, E2, B0, B1, B2;
   if (P.flags & PIC_FIELDS_FROZEN) {
-    if (P.frozen_kind == PIC_FROZEN_UNIFORM) {
-      E0 = R(P.fE[0]); E1 = R(P.fE[1]); E2 = R(P.fE[2]);
-      B0 = R(P.fB[0]); B1 = R(P.fB[1]); B2 = R(P.fB[2]);
+    const ColdPtr<R> C = cold(P);
+    if (C->frozen_kind == PIC_FROZEN_UNIFORM) {
+      E0 = R(C->fE[0]); E1 = R(C->fE[1]); E2 = R(C->fE[2]);
+      B0 = R(C->fB[0]); B1 = R(C->fB[1]); B2 = R(C->fB[2]);
     } else {
       E0 = R(0); E1 = R(0); E2 = R(0); B0 = R(0); B1 = R(0); B2 = R(0);
       const R phi = R(P.tn) - x[0];
       if (phi > R(0)) {
-        const R v = R(P.fa) * m_sin(phi);
+        const R v = R(C->fa) * m_sin(phi);
         E1 = v;
         B2 = v;
       }
@@ -552,8 +569,12 @@ __device__ inline void electron_physics(const StepParams<R>& P, int64_t e, uint3
       if (tau <= 0.0) {
         draw();
         const R u2 = unif<R>(r.v[2]);
-        const R la = ncs_inverse<R>(P.ncs + (int64_t)i * P.n_xi, P.lnxi, P.n_xi, u2);
-        const R lb = ncs_inverse<R>(P.ncs + (int64_t)(i + 1) * P.n_xi, P.lnxi, P.n_xi, u2);
+        const ColdPtr<R> C = cold(P);
+        const int nxi = C->n_xi;
+        const R* ncs = C->ncs;
+        const R* lnxi = C->lnxi;
+        const R la = ncs_inverse<R>(ncs + (int64_t)i * nxi, lnxi, nxi, u2);
+        const R lb = ncs_inverse<R>(ncs + (int64_t)(i + 1) * nxi, lnxi, nxi, u2);
         const R lx = la + f * (lb - la);
         const R xi = m_exp(lx);
         R eps = xi * gamma;
@@ -562,7 +583,7 @@ __device__ inline void electron_physics(const StepParams<R>& P, int64_t e, uint3
         out.ev_ncs = true;
         out.e[0] = eps;
         out.k[0][0] = m_div(px, pm); out.k[0][1] = m_div(py, pm); out.k[0][2] = m_div(pz, pm);
-        out.keep_ncs = (double)eps >= P.photon_cut;
+        out.keep_ncs = (double)eps >= C->photon_cut;
         if (!(P.flags & PIC_NO_RECOIL)) {
           const R gn = gamma - eps;
           const R pn = m_sqrt((gn - R(1)) * (gn + R(1)));
@@ -608,10 +629,14 @@ __device__ inline void electron_physics(const StepParams<R>& P, int64_t e, uint3
             if (unif52(r.v[0], r.v[1]) < (double)Pb) {
               const U4 r2 = philox4x32_10(idv, n, 1u, 0u, P.key0, P.key1);
               const R u = unif<R>(r2.v[0]);
-              const R sa = brem_inverse<R>(P.br + (int64_t)i * P.n_y, P.n_y, u, R(P.iny1));
-              const R sb = brem_inverse<R>(P.br + (int64_t)(i + 1) * P.n_y, P.n_y, u, R(P.iny1));
+              const ColdPtr<R> C = cold(P);
+              const int ny = C->n_y;
+              const R* br = C->br;
+              const R iny1 = R(C->iny1);
+              const R sa = brem_inverse<R>(br + (int64_t)i * ny, ny, u, iny1);
+              const R sb = brem_inverse<R>(br + (int64_t)(i + 1) * ny, ny, u, iny1);
               const R sv = sa + f * (sb - sa);
-              const R lk = R(P.lnk);
+              const R lk = R(C->lnk);
               R eps = m_exp(lk + sv * (lt - lk));
               if (eps > T) eps = T;
               out.ev_br = true;
@@ -805,21 +830,22 @@ __device__ __forceinline__ void step_chunk(const StepParams<R>& P, const uint32_
     const unsigned long long mask = __ballot(rec);
     if (mask == 0ull) continue;  // wave-uniform
     unsigned long long base = 0;
-    if (lane == 0) base = atomicAdd(P.pcount, (unsigned long long)__popcll(mask));
+    const ColdPtr<R> C = cold(P);
+    if (lane == 0) base = atomicAdd(C->pcount, (unsigned long long)__popcll(mask));
     base = __shfl(base, 0, 64);
     if (rec) {
       const unsigned long long slot = base + lane_offset(mask);
-      if (slot < P.pcap) {
+      if (slot < C->pcap) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          P.px[a][slot] = out.xo[a];
-          P.pk[a][slot] = out.k[proc][a];
+          C->px[a][slot] = out.xo[a];
+          C->pk[a][slot] = out.k[proc][a];
         }
-        P.pe[slot] = out.e[proc];
-        P.pw[slot] = wgt;
-        P.pstep[slot] = P.step;
-        P.ppar[slot] = idv;
-        P.pproc[slot] = (uint32_t)proc;
+        C->pe[slot] = out.e[proc];
+        C->pw[slot] = wgt;
+        C->pstep[slot] = P.step;
+        C->ppar[slot] = idv;
+        C->pproc[slot] = (uint32_t)proc;
       }
     }
   }
@@ -831,7 +857,7 @@ __device__ __forceinline__ void step_chunk(const StepParams<R>& P, const uint32_
   const unsigned long long m_ncs = __ballot(out.ev_ncs);
   const unsigned long long m_br = __ballot(out.ev_br);
   const unsigned long long m_cl = __ballot(out.clamped);
-  unsigned long long* C = P.slot_cnt + slot * kSlotCnt;
+  unsigned long long* C = cold(P)->slot_cnt + slot * kSlotCnt;
   if (lane == 0) {
     C[SC_ESTEPS] += (unsigned long long)__popcll(m_live);
     if (!tiled && !frozen) C[SC_UNTILED] += (unsigned long long)__popcll(m_live);
@@ -849,7 +875,7 @@ __device__ __forceinline__ void step_chunk(const StepParams<R>& P, const uint32_
     C[SC_KEPT_BR] += (unsigned long long)__popcll(m_br);
     C[SC_DROPPED] += (unsigned long long)__popcll(m_ncs & ~m_keep);
     C[SC_CLAMPED] += (unsigned long long)__popcll(m_cl);
-    double* Sm = P.slot_sum + slot * kSlotSum;
+    double* Sm = cold(P)->slot_sum + slot * kSlotSum;
     if (m_keep) neumaier(Sm + 0, Sm + 1, s0);
     if (m_br) neumaier(Sm + 2, Sm + 3, s1);
     if (m_ncs & ~m_keep) neumaier(Sm + 4, Sm + 5, s2);
@@ -892,7 +918,8 @@ template <class R, int D>
 static void launch_one(const void* params, hipStream_t s) {
   const StepParams<R>& P = *static_cast<const StepParams<R>*>(params);
   if (P.N <= 0) return;
-  int64_t blocks = (P.N + kBlock - 1) / kBlock;
+  constexpr int per_chunk = kBlock;
+  int64_t blocks = (P.N + per_chunk - 1) / per_chunk;
   blocks = (blocks + 7) / 8 * 8;  // XCD-aware chunk mapping needs a multiple of 8
   const size_t jsz = sizeof(R) == 4 ? sizeof(int) : sizeof(unsigned long long);
   const size_t lds = (size_t)P.lds_nodes * (6 * sizeof(R) + 3 * jsz);
