@@ -522,3 +522,129 @@ def test_cold_plasma_oscillation_frequency(oracle_lib, tables_al):
     wp = math.sqrt(4.0)
     w_leap = 2 / dt * math.asin(wp * dt / 2)
     assert abs(w_meas / w_leap - 1) < 5e-3, (w_meas, w_leap)
+
+
+# ----------------------------------------------- 16-particle brute force (MC)
+# An independent Philox4x32-10 (Salmon et al., SC'11) in plain Python, checked
+# against the published known answers, drives a step-by-step replay of the
+# emission decisions of 16 electrons; the oracle's event lists must equal the
+# replay exactly.
+_PH_M = (0xD2511F53, 0xCD9E8D57)
+_PH_W = (0x9E3779B9, 0xBB67AE85)
+
+
+def _philox_py(ctr, key):
+    c = [int(v) & 0xFFFFFFFF for v in ctr]
+    k = [int(v) & 0xFFFFFFFF for v in key]
+    for _ in range(10):
+        p0 = _PH_M[0] * c[0]
+        p1 = _PH_M[1] * c[2]
+        c = [((p1 >> 32) ^ c[1] ^ k[0]) & 0xFFFFFFFF, p1 & 0xFFFFFFFF,
+             ((p0 >> 32) ^ c[3] ^ k[1]) & 0xFFFFFFFF, p0 & 0xFFFFFFFF]
+        k = [(k[0] + _PH_W[0]) & 0xFFFFFFFF, (k[1] + _PH_W[1]) & 0xFFFFFFFF]
+    return c
+
+
+def _u32(r):
+    return (r + 0.5) * 2.0 ** -32
+
+
+def test_python_philox_matches_known_answers():
+    for line in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")):
+        if not line.strip() or line.startswith("#"):
+            continue
+        v = [int(t, 16) for t in line.split()]
+        assert _philox_py(v[0:4], v[4:6]) == v[6:10]
+
+
+def _E_S():
+    return 1e-6 / (2 * math.pi * 3.8615926796e-13)
+
+
+def _K_BR():
+    eps0, me, e, c = 8.8541878128e-12, 9.1093837015e-31, 1.602176634e-19, 299792458.0
+    lam = 1e-6
+    n_c = eps0 * me * (2 * math.pi * c / lam) ** 2 / e ** 2
+    return n_c * (lam / (2 * math.pi)) * ALPHA * (RE_CM * 1e-2) ** 2
+
+
+def test_ncs_events_16_electrons_brute_force(oracle_lib, tables_al):
+    """16 electrons gyrating in a uniform B (no recoil, no brem): eta and gamma
+    are constant, so each step lowers tau by K_N (eta/gamma) h(eta) dt; an
+    event when tau <= 0, then tau = -ln u(r3 of the step's counter).  Replayed
+    independently with eta at a table node."""
+    i_eta = 170
+    eta = math.exp(tables_al["ln_eta0"] + i_eta * tables_al["dln_eta"])
+    pm = 600.0
+    B = eta * _E_S() / pm
+    w = S.frozen_B_beam(n_cells=256, ppc=16, slab=(128, 129), B=B, seed=11)
+    w.update(brem=False, no_recoil=True, photon_cut_mc2=0.0)
+    o = oracle.OracleSim(w, tables_al)
+    assert o.N == 16
+    d = o.derived()
+    assert abs(d["E_S"] / _E_S() - 1) < 1e-14
+    e = o.electrons()
+    p = np.zeros((16, 3))
+    p[:, 0] = pm
+    o.set_electrons(e["x"], p, e["tau"])
+    M = 300
+    o.step(M)
+    gam = math.sqrt(1 + pm * pm)
+    K_N = math.sqrt(3) / (2 * math.pi) * ALPHA * _E_S()
+    dtau = K_N * eta / gam * tables_al["h"][i_eta] * d["dt"]
+    key = (11, 0)
+    want = []
+    for idv in range(16):
+        tau = -math.log(_u32(_philox_py((idv, 0xFFFFFFFF, 0, 0), key)[3]))
+        assert abs(tau - e["tau"][idv]) <= 1e-15 * tau
+        for n in range(M):
+            tau -= dtau
+            if tau <= 0.0:
+                want.append((idv, n))
+                tau = -math.log(_u32(_philox_py((idv, n, 0, 0), key)[3]))
+    ph = o.photons()
+    got = sorted(zip(ph["parent"].tolist(), ph["step"].tolist()))
+    assert len(want) > 100
+    assert got == sorted(want)
+
+
+def test_brem_events_16_electrons_brute_force(oracle_lib, tables_au):
+    """16 electrons at fixed energy (no recoil, zero fields, NCS off) in a
+    dense static target: Eq. (4) per step with P = -expm1(-K_BR n_i sigma v dt)
+    and the 52-bit uniform of (r0, r1).  Replayed independently at a table
+    node of sigma."""
+    i = 100
+    Tk = math.exp(tables_au["ln_T0"] + i * tables_au["dln_T"])
+    pm = math.sqrt(Tk * (Tk + 2))
+    q = 79
+    gam = math.sqrt(1 + pm * pm)
+    # ion density for X = 0.05 per step (dt = 0.95 dx, dx = 2 pi c/w0)
+    ni = 0.05 / (_K_BR() * tables_au["sigma"][i] * (pm / gam) * 0.95 * 2 * math.pi)
+    w = S.base(name="brem-16", dims=1, n=[64], dx_lambda=[1.0], ppc=1, x0_lambda=0.0,
+               thickness_lambda=16.0, frozen=True, frozen_kind=0, Z=79, charge_state=q,
+               ne_over_nc=ni * q, ncs=False, brem=True, no_recoil=True, seed=13)
+    o = oracle.OracleSim(w, tables_au)
+    assert o.N == 16
+    d = o.derived()
+    assert abs(d["K_BR"] / _K_BR() - 1) < 1e-9
+    e = o.electrons()
+    p = np.zeros((16, 3))
+    p[:, 1] = pm                     # along y: the 1D cell does not change
+    o.set_electrons(e["x"], p, e["tau"])
+    M = 300
+    o.step(M)
+    X = d["K_BR"] * ni * tables_au["sigma"][i] * (pm / gam) * d["dt"]
+    P = -math.expm1(-X)
+    assert 0.01 < P < 0.2
+    key = (13, 0)
+    want = []
+    for idv in range(16):
+        for n in range(M):
+            r = _philox_py((idv, n, 0, 0), key)
+            k = r[0] * 2 ** 20 + (r[1] >> 12)
+            if (k + 0.5) * 2.0 ** -52 < P:
+                want.append((idv, n))
+    ph = o.photons()
+    got = sorted(zip(ph["parent"].tolist(), ph["step"].tolist()))
+    assert len(want) > 100
+    assert got == sorted(want)
