@@ -158,9 +158,12 @@ std::string derive(const pic_config& cfg, Ctx& c) {
   }
   // cell tiles for the sort and the LDS box of the step kernel
   if (cfg.reserved0 != 0) return "reserved0 must be 0";
-  const int dflt_every[4] = {0, 16, 8, 4};
+  const int dflt_every[4] = {0, 16, 8, 6};
   const int tiles[4] = {0, 16, 2, 2};
-  const int ldsn[4] = {0, 64, 576, 512};
+  // LDS box capacity in nodes (2D: fields + current, 36 B/node in FP32;
+  // 3D: current only, 12 B/node); chosen by measurement on the 2D and 3D
+  // gold-slab workloads
+  const int ldsn[4] = {0, 64, 576, 2048};
   c.sort_every = cfg.sort_every == 0 ? dflt_every[g.dims] : (cfg.sort_every < 0 ? 0 : cfg.sort_every);
   c.lds_nodes = ldsn[g.dims];
   // FP32 current quantum: the largest 2^-jbits (jbits <= 40) with which the
@@ -240,7 +243,7 @@ Plan make_plan(Ctx& c) {
     P.add((void**)&c.soffset, (size_t)c.nkeys * 4);
     P.add((void**)&c.scursor, ((size_t)c.nkeys + sort_scratch_words(c.nkeys)) * 4);
   }
-  P.add((void**)&c.n_active, 8);
+  P.add((void**)&c.n_active, 16);  // live count, count being built, count before the last sort
   const size_t pc = (size_t)(c.pcap > 0 ? c.pcap : 1);
   for (int a = 0; a < 3; ++a) {
     P.add(&c.px[a], pc * rs);
@@ -616,8 +619,8 @@ pic_status pic_create(const pic_config* cfg, pic_ctx** out) {
   hipError_t he = hipMemcpyAsync(c.srcA, A.data(), ns, hipMemcpyHostToDevice, c.stream);
   if (he == hipSuccess) he = hipMemcpyAsync(c.srcC, C.data(), ns, hipMemcpyHostToDevice, c.stream);
   if (he == hipSuccess) he = hipMemcpyAsync(c.srcS, S.data(), ns, hipMemcpyHostToDevice, c.stream);
-  const uint32_t n_act = (uint32_t)c.N;
-  if (he == hipSuccess) he = hipMemcpyAsync(c.n_active, &n_act, 4, hipMemcpyHostToDevice, c.stream);
+  const uint32_t n_act[4] = {(uint32_t)c.N, (uint32_t)c.N, (uint32_t)c.N, 0u};
+  if (he == hipSuccess) he = hipMemcpyAsync(c.n_active, n_act, 16, hipMemcpyHostToDevice, c.stream);
   if (he == hipSuccess) {
     launch_init_electrons(c, c.stream);
     he = hipGetLastError();

@@ -6,10 +6,20 @@
 // contiguous chunk of electrons covers a compact box of cells, which is what
 // lets the step kernel stage fields and accumulate currents in LDS.
 //
-// Passes: key + histogram (one atomic per run of equal keys in a wave), a three-pass exclusive
+// Passes: key + histogram (one atomic per distinct key in a workgroup), a three-pass exclusive
 // scan of the tile counts, scatter into the second SoA buffer
 // (order inside a tile is arbitrary; nothing downstream depends on it: the
 // current is summed in fixed point and Philox streams follow the electron id).
+//
+// Absorbed electrons never change again, so a sort covers only the range that
+// was live after the previous sort, [0, n_old): its live electrons go to the
+// tiles and the ones absorbed since then to [n_new, n_old).  The older dead
+// tail [n_old, N) is already in place in the destination buffer except for
+// the stretch that died during the previous interval, [n_old, n_prev), which
+// is copied across.  Counter words: n[0] live count (read by the step
+// kernel), n[1] the count being built, n[2] the live count before the last
+// sort.
+#include <algorithm>
 #include "pic_internal.hpp"
 
 namespace pic {
@@ -32,46 +42,59 @@ __device__ inline uint32_t spread3(uint32_t v) {  // 10 bits -> every third bit
   return v;
 }
 
-// Runs of equal keys inside a wave (the input is mostly sorted already):
-// first lane of the run and its length, so one atomic serves the whole run.
-struct Run {
-  int start, len;
-};
-__device__ inline Run wave_run(uint32_t key, bool valid) {
-  const int lane = (int)__lane_id();
-  const uint32_t prev = __shfl_up(key, 1u, 64);
-  const bool head = valid && (lane == 0 || prev != key);
-  const unsigned long long heads = __ballot(head);
-  const unsigned long long valids = __ballot(valid);
-  const unsigned long long upto = lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1ull);
-  const int start = 63 - __clzll(heads & upto);
-  const unsigned long long after = start == 63 ? 0ull : (heads & ~((1ull << (start + 1)) - 1ull));
-  const int end = after ? __ffsll((long long)after) - 1 : __popcll(valids);
-  return Run{start, end - start};
+// Workgroup-level aggregation of equal keys: an LDS hash table (open
+// addressing, twice as many slots as threads) counts the electrons of each
+// distinct tile in the workgroup, so each tile costs one global atomic per
+// workgroup however its electrons are ordered.
+constexpr int kHash = 2 * kBlock;
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+
+__device__ inline int hash_slot(uint32_t key) { return (int)((key * 2654435761u) >> 23) & (kHash - 1); }
+
+// Insert key; returns its slot and, through rank, the electron's rank among
+// the workgroup's electrons of that key.
+__device__ inline int hash_insert(uint32_t* hkey, uint32_t* hcnt, uint32_t key, uint32_t& rank) {
+  int h = hash_slot(key);
+  for (;;) {
+    const uint32_t prev = atomicCAS(&hkey[h], kEmpty, key);
+    if (prev == kEmpty || prev == key) {
+      rank = atomicAdd(&hcnt[h], 1u);
+      return h;
+    }
+    h = (h + 1) & (kHash - 1);
+  }
 }
 
 template <class R>
 __global__ __launch_bounds__(kBlock) void k_sort_key(SortArgs A) {
-  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const bool valid = e < A.N;
-  uint32_t key = A.nkeys - 1;  // absorbed electrons: last bucket
-  if (valid && !(A.id[e] & kDead)) {
-    uint32_t t[3] = {0u, 0u, 0u};
-    for (int a = 0; a < A.dims; ++a) {
-      int c;
-      if constexpr (sizeof(R) == 4) c = ((const int*)A.x[a])[e] >> A.fb[a];  // fixed point
-      else c = (int)floor(((const R*)A.x[a])[e] * A.idx[a]);
-      c = c < 0 ? 0 : (c >= A.n[a] ? A.n[a] - 1 : c);
-      t[a] = (uint32_t)(c / A.tile[a]);
+  __shared__ uint32_t hkey[kHash], hcnt[kHash];
+  const int t = threadIdx.x;
+  for (int i = t; i < kHash; i += kBlock) { hkey[i] = kEmpty; hcnt[i] = 0u; }
+  __syncthreads();
+  const int64_t e = (int64_t)blockIdx.x * kBlock + t;
+  const bool valid = e < (int64_t)A.n_active[0];
+  if (valid) {
+    uint32_t key = A.nkeys - 1;  // absorbed electrons: last bucket
+    if (!(A.id[e] & kDead)) {
+      uint32_t tt[3] = {0u, 0u, 0u};
+      for (int a = 0; a < A.dims; ++a) {
+        int c;
+        if constexpr (sizeof(R) == 4) c = ((const int*)A.x[a])[e] >> A.fb[a];  // fixed point
+        else c = (int)floor(((const R*)A.x[a])[e] * A.idx[a]);
+        c = c < 0 ? 0 : (c >= A.n[a] ? A.n[a] - 1 : c);
+        tt[a] = (uint32_t)(c / A.tile[a]);
+      }
+      if (A.dims == 1) key = tt[0];
+      else if (A.dims == 2) key = spread2(tt[0]) | (spread2(tt[1]) << 1);
+      else key = spread3(tt[0]) | (spread3(tt[1]) << 1) | (spread3(tt[2]) << 2);
     }
-    if (A.dims == 1) key = t[0];
-    else if (A.dims == 2) key = spread2(t[0]) | (spread2(t[1]) << 1);
-    else key = spread3(t[0]) | (spread3(t[1]) << 1) | (spread3(t[2]) << 2);
+    A.key[e] = key;
+    uint32_t rank;
+    hash_insert(hkey, hcnt, key, rank);
   }
-  const Run r = wave_run(key, valid);
-  if (!valid) return;
-  A.key[e] = key;
-  if ((int)__lane_id() == r.start) atomicAdd(A.count + key, (uint32_t)r.len);
+  __syncthreads();
+  for (int i = t; i < kHash; i += kBlock)
+    if (hkey[i] != kEmpty) atomicAdd(A.count + hkey[i], hcnt[i]);
 }
 
 // Exclusive scan of count[0..nkeys) into offset and cursor, in three passes:
@@ -145,28 +168,54 @@ __global__ __launch_bounds__(kBlock) void k_scan_fixup(SortArgs A, const uint32_
       A.offset[k] = o;
       A.cursor[k] = o;
       // live electrons = everything before the absorbed bucket (the last key)
-      if (k == A.nkeys - 1) *A.n_active = o;
+      if (k == A.nkeys - 1) A.n_active[1] = o;
     }
   }
 }
 
 template <class R>
 __global__ __launch_bounds__(kBlock) void k_sort_scatter(SortArgs A) {
-  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const bool valid = e < A.N;
-  const uint32_t key = valid ? A.key[e] : 0xFFFFFFFFu;
-  const Run r = wave_run(key, valid);
-  const int lane = (int)__lane_id();
-  uint32_t base = 0;
-  if (valid && lane == r.start) base = atomicAdd(A.cursor + key, (uint32_t)r.len);
-  base = __shfl(base, r.start, 64);
+  __shared__ uint32_t hkey[kHash], hcnt[kHash];
+  const int t = threadIdx.x;
+  for (int i = t; i < kHash; i += kBlock) { hkey[i] = kEmpty; hcnt[i] = 0u; }
+  __syncthreads();
+  const int64_t e = (int64_t)blockIdx.x * kBlock + t;
+  const bool valid = e < (int64_t)A.n_active[0];
+  int h = 0;
+  uint32_t rank = 0;
+  if (valid) h = hash_insert(hkey, hcnt, A.key[e], rank);
+  __syncthreads();
+  // one cursor atomic per distinct key of the workgroup; the slot's count is
+  // replaced by the base of the workgroup's range for that key
+  for (int i = t; i < kHash; i += kBlock)
+    if (hkey[i] != kEmpty) hcnt[i] = atomicAdd(A.cursor + hkey[i], hcnt[i]);
+  __syncthreads();
   if (!valid) return;
-  const uint32_t d = base + (uint32_t)(lane - r.start);
+  const uint32_t d = hcnt[h] + rank;
   for (int a = 0; a < A.dims; ++a) ((R*)A.x2[a])[d] = ((const R*)A.x[a])[e];
   for (int a = 0; a < 3; ++a) ((R*)A.p2[a])[d] = ((const R*)A.p[a])[e];
   A.tau2[d] = A.tau[e];
   A.w2[d] = A.w[e];
   A.id2[d] = A.id[e];
+}
+
+// The dead stretch [n_old, n_prev) into the destination buffer (grid-stride).
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_sort_tail(SortArgs A) {
+  const int64_t lo = (int64_t)A.n_active[0], hi = (int64_t)A.n_active[2];
+  for (int64_t e = lo + (int64_t)blockIdx.x * kBlock + threadIdx.x; e < hi;
+       e += (int64_t)gridDim.x * kBlock) {
+    for (int a = 0; a < A.dims; ++a) ((R*)A.x2[a])[e] = ((const R*)A.x[a])[e];
+    for (int a = 0; a < 3; ++a) ((R*)A.p2[a])[e] = ((const R*)A.p[a])[e];
+    A.tau2[e] = A.tau[e];
+    A.w2[e] = A.w[e];
+    A.id2[e] = A.id[e];
+  }
+}
+
+__global__ void k_sort_commit(uint32_t* n) {
+  n[2] = n[0];
+  n[0] = n[1];
 }
 
 int sort_scratch_words(uint32_t nkeys) { return (int)(((int64_t)nkeys + kSeg - 1) / kSeg); }
@@ -183,6 +232,10 @@ void launch_sort(const SortArgs& A, bool fp32, hipStream_t s) {
   hipLaunchKernelGGL(k_scan_fixup, dim3(nseg), dim3(kBlock), 0, s, A, btot);
   if (fp32) hipLaunchKernelGGL(k_sort_scatter<float>, dim3(blocks), dim3(kBlock), 0, s, A);
   else hipLaunchKernelGGL(k_sort_scatter<double>, dim3(blocks), dim3(kBlock), 0, s, A);
+  const unsigned tail_blocks = (unsigned)std::min<int64_t>(blocks, 1024);
+  if (fp32) hipLaunchKernelGGL(k_sort_tail<float>, dim3(tail_blocks), dim3(kBlock), 0, s, A);
+  else hipLaunchKernelGGL(k_sort_tail<double>, dim3(tail_blocks), dim3(kBlock), 0, s, A);
+  hipLaunchKernelGGL(k_sort_commit, dim3(1), dim3(1), 0, s, A.n_active);
 }
 
 }  // namespace pic

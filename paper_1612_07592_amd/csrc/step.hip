@@ -449,6 +449,23 @@ __device__ inline uint32_t lane_offset(unsigned long long mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// Whether the step kernel stages the box's fields in LDS.  In 3D it does not:
+// fields are gathered from global memory through the caches and only the
+// current lives in LDS, which fits a three times larger box (2048 nodes) in
+// the same LDS.  Measured on the 3D gold slab (134M electrons): 7.2e9 vs
+// 6.6e9 electron-steps/s at the best staged-field box (1024 nodes).  In 2D
+// the staged fields win (8.9e9 vs 8.6e9 on the 2D gold slab).
+template <class R, int D>
+struct FieldsInLds {
+  static constexpr bool value = D != 3;
+};
+
+template <class R, int D>
+constexpr size_t lds_bytes_per_node() {
+  return (FieldsInLds<R, D>::value ? 6 * sizeof(R) : 0) +
+         3 * (sizeof(R) == 4 ? sizeof(int) : sizeof(unsigned long long));
+}
+
 // Electrons per step-kernel workgroup: one per thread.  (Two per thread,
 // in two passes, raised the FP32 2D kernel from 67 to 87 VGPRs and ran 15%
 // slower.)
@@ -749,8 +766,9 @@ __device__ __forceinline__ void step_chunk(const StepParams<R>& P, const uint32_
     }
     tiled = nodes <= P.lds_nodes;
   }
+  constexpr bool kFL = FieldsInLds<R, D>::value;
   R* sF = reinterpret_cast<R*>(smem);
-  JT* sJ = reinterpret_cast<JT*>(smem + (size_t)6 * P.lds_nodes * sizeof(R));
+  JT* sJ = reinterpret_cast<JT*>(smem + (kFL ? (size_t)6 * P.lds_nodes * sizeof(R) : 0));
   const Idx<R> I{P.gg[0], P.gg[1], P.gg[2], P.sz[0], P.sz[1]};
   // node l of the box -> (i, j, k); exact float-reciprocal division (l < 2^20)
   const float r0 = 1.0f / (float)ext[0], r1 = 1.0f / (float)ext[1];
@@ -769,8 +787,10 @@ __device__ __forceinline__ void step_chunk(const StepParams<R>& P, const uint32_
       const int64_t m = I(i, j, k);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        sF[c * nodes + l] = P.F[c][m];
-        sF[(3 + c) * nodes + l] = P.F[3 + c][m];
+        if constexpr (kFL) {
+          sF[c * nodes + l] = P.F[c][m];
+          sF[(3 + c) * nodes + l] = P.F[3 + c][m];
+        }
         sJ[c * nodes + l] = JT(0);
       }
     }
@@ -782,7 +802,10 @@ __device__ __forceinline__ void step_chunk(const StepParams<R>& P, const uint32_
   if (live) {
     wgt = P.w[e];
     if (tiled) {
-      const LdsField<R> fa{sF, lo[0], lo[1], lo[2], ext[0], ext[1], nodes};
+      using FA = typename std::conditional<kFL, LdsField<R>, GlobalField<R>>::type;
+      FA fa;
+      if constexpr (kFL) fa = LdsField<R>{sF, lo[0], lo[1], lo[2], ext[0], ext[1], nodes};
+      else fa = GlobalField<R>{P.F, I};
       if constexpr (kF32) {
         const LdsCurrent32 ja{reinterpret_cast<int*>(sJ), lo[0], lo[1], lo[2], ext[0], ext[1], nodes,
                               (float)ldexp(1.0, P.jbits)};
@@ -921,8 +944,7 @@ static void launch_one(const void* params, hipStream_t s) {
   constexpr int per_chunk = kBlock;
   int64_t blocks = (P.N + per_chunk - 1) / per_chunk;
   blocks = (blocks + 7) / 8 * 8;  // XCD-aware chunk mapping needs a multiple of 8
-  const size_t jsz = sizeof(R) == 4 ? sizeof(int) : sizeof(unsigned long long);
-  const size_t lds = (size_t)P.lds_nodes * (6 * sizeof(R) + 3 * jsz);
+  const size_t lds = (size_t)P.lds_nodes * lds_bytes_per_node<R, D>();
   hipLaunchKernelGGL((k_electron_step<R, D>), dim3((unsigned)blocks), dim3(kBlock), lds, s, P);
 }
 
@@ -930,8 +952,7 @@ template <class R, int D>
 static void launch_batch(const void* tab, const uint32_t* first, int njobs, uint32_t total,
                          int lds_nodes, hipStream_t s) {
   if (njobs <= 0 || total == 0) return;
-  const size_t jsz = sizeof(R) == 4 ? sizeof(int) : sizeof(unsigned long long);
-  const size_t lds = (size_t)lds_nodes * (6 * sizeof(R) + 3 * jsz);
+  const size_t lds = (size_t)lds_nodes * lds_bytes_per_node<R, D>();
   const int64_t blocks = ((int64_t)total + 7) / 8 * 8;
   hipLaunchKernelGGL((k_electron_step_batch<R, D>), dim3((unsigned)blocks), dim3(kBlock), lds, s,
                      static_cast<const StepParams<R>*>(tab), first, njobs);
