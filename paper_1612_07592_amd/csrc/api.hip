@@ -119,6 +119,7 @@ std::string derive(const pic_config& cfg, Ctx& c) {
   g.nsrc_y = g.act[1] ? g.n[1] : 1;
   g.nsrc_z = g.act[2] ? g.n[2] + 1 : 1;
   g.nfield = (int64_t)g.sz[0] * g.sz[1] * g.sz[2];
+  if (g.nfield >= (int64_t)1 << 31) return "grid too large (nodes per field component must stay below 2^31)";
   // CODATA 2018
   const double alpha = 7.2973525693e-3, re = 2.8179403262e-15, lC = 3.8615926796e-13;
   const double eps0 = 8.8541878128e-12, me = 9.1093837015e-31, qe = 1.602176634e-19, cl = 299792458.0;

@@ -66,6 +66,9 @@ struct Idx {
 // FP32 path: contribution -> multiple of 2^-jbits in float arithmetic.
 __device__ inline int q32(float v, float scale) { return (int)rintf(v * scale); }
 
+// The FP32 accessors also offer a linear form: lin(i, j, k) gives a node's
+// index once, neighbours are lin + 1, lin + s1, lin + s2 (32-bit indices; the
+// field arrays hold fewer than 2^31 nodes).
 struct GlobalCurrent32 {
   unsigned long long* J[3];
   Idx<float> I;
@@ -74,6 +77,13 @@ struct GlobalCurrent32 {
   __device__ inline void operator()(int c, int i, int j, int k, float v) const {
     const int q = q32(v, scale);
     if (q != 0) atomicAdd(J[c] + I(i, j, k), (unsigned long long)((long long)q << shift));
+  }
+  __device__ inline int lin(int i, int j, int k) const { return (int)I(i, j, k); }
+  __device__ inline int s1() const { return I.sz0; }
+  __device__ inline int s2() const { return I.sz0 * I.sz1; }
+  __device__ inline void add(int c, int l, float v) const {
+    const int q = q32(v, scale);
+    if (q != 0) atomicAdd(J[c] + l, (unsigned long long)((long long)q << shift));
   }
 };
 
@@ -85,6 +95,10 @@ struct LdsCurrent32 {
     // unconditional: adding 0 is harmless and keeps the wave convergent
     atomicAdd(T + c * nodes + (i - lo0) + e0 * ((j - lo1) + e1 * (k - lo2)), q32(v, scale));
   }
+  __device__ inline int lin(int i, int j, int k) const { return (i - lo0) + e0 * ((j - lo1) + e1 * (k - lo2)); }
+  __device__ inline int s1() const { return e0; }
+  __device__ inline int s2() const { return e0 * e1; }
+  __device__ inline void add(int c, int l, float v) const { atomicAdd(T + c * nodes + l, q32(v, scale)); }
 };
 
 // Field access: straight from the Yee arrays, or from the block's LDS box.
@@ -93,6 +107,10 @@ struct GlobalField {
   const R* const* F;
   Idx<R> I;
   __device__ inline R operator()(int c, int i, int j, int k) const { return F[c][I(i, j, k)]; }
+  __device__ inline int lin(int i, int j, int k) const { return (int)I(i, j, k); }
+  __device__ inline int s1() const { return I.sz0; }
+  __device__ inline int s2() const { return I.sz0 * I.sz1; }
+  __device__ inline R at(int c, int l) const { return F[c][l]; }
 };
 
 template <class R>
@@ -102,6 +120,10 @@ struct LdsField {
   __device__ inline R operator()(int c, int i, int j, int k) const {
     return T[c * nodes + (i - lo0) + e0 * ((j - lo1) + e1 * (k - lo2))];
   }
+  __device__ inline int lin(int i, int j, int k) const { return (i - lo0) + e0 * ((j - lo1) + e1 * (k - lo2)); }
+  __device__ inline int s1() const { return e0; }
+  __device__ inline int s2() const { return e0 * e1; }
+  __device__ inline R at(int c, int l) const { return T[c * nodes + l]; }
 };
 
 // Current accumulation in 2^-40 fixed point: global atomics, or LDS atomics
@@ -167,20 +189,38 @@ __device__ inline void split_q(int q, int S, int fb, float iqs, int& i, float& f
   f = (float)(qs & ((1 << fb) - 1)) * iqs;
 }
 
+// The node/fraction pairs of one position for both staggers of every axis.
+struct Splits {
+  int i[3][2];
+  float f[3][2];
+};
+
+template <int D>
+__device__ inline Splits make_splits(const int* q, const int* fb, const float* iqs) {
+  Splits s{};
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    split_q(q[a], 0, fb[a], iqs[a], s.i[a][0], s.f[a][0]);
+    split_q(q[a], 1, fb[a], iqs[a], s.i[a][1], s.f[a][1]);
+  }
+  return s;
+}
+
 template <int D, int SX, int SY, int SZ, class F>
-__device__ inline float gather_q(const F& f, int c, const int* q, const int* fb, const float* iqs) {
-  int i0 = 0, i1 = 0, i2 = 0;
-  float f0 = 0.f, f1 = 0.f, f2 = 0.f;
-  split_q(q[0], SX, fb[0], iqs[0], i0, f0);
-  if (D == 1) return (1.f - f0) * f(c, i0, 0, 0) + f0 * f(c, i0 + 1, 0, 0);
-  split_q(q[1], SY, fb[1], iqs[1], i1, f1);
-  if (D == 3) split_q(q[2], SZ, fb[2], iqs[2], i2, f2);
-  const float v0 = (1.f - f0) * f(c, i0, i1, i2) + f0 * f(c, i0 + 1, i1, i2);
-  const float v1 = (1.f - f0) * f(c, i0, i1 + 1, i2) + f0 * f(c, i0 + 1, i1 + 1, i2);
+__device__ inline float gather_q(const F& f, int c, const Splits& s) {
+  const float f0 = s.f[0][SX];
+  const int l = f.lin(s.i[0][SX], D >= 2 ? s.i[1][SY] : 0, D == 3 ? s.i[2][SZ] : 0);
+  if (D == 1) return (1.f - f0) * f.at(c, l) + f0 * f.at(c, l + 1);
+  const float f1 = s.f[1][SY];
+  const int s1 = f.s1();
+  const float v0 = (1.f - f0) * f.at(c, l) + f0 * f.at(c, l + 1);
+  const float v1 = (1.f - f0) * f.at(c, l + s1) + f0 * f.at(c, l + s1 + 1);
   const float a2 = (1.f - f1) * v0 + f1 * v1;
   if (D == 2) return a2;
-  const float w0 = (1.f - f0) * f(c, i0, i1, i2 + 1) + f0 * f(c, i0 + 1, i1, i2 + 1);
-  const float w1 = (1.f - f0) * f(c, i0, i1 + 1, i2 + 1) + f0 * f(c, i0 + 1, i1 + 1, i2 + 1);
+  const float f2 = s.f[2][SZ];
+  const int s2 = f.s2();
+  const float w0 = (1.f - f0) * f.at(c, l + s2) + f0 * f.at(c, l + s2 + 1);
+  const float w1 = (1.f - f0) * f.at(c, l + s2 + s1) + f0 * f.at(c, l + s2 + s1 + 1);
   const float b2 = (1.f - f1) * w0 + f1 * w1;
   return (1.f - f2) * a2 + f2 * b2;
 }
@@ -250,20 +290,23 @@ __device__ inline void deposit3(const StepParams<float>& P, const Acc& J, const 
     shape3(i0, f0, m[a], S0[a]);
     shape3(i1, f1, m[a], S1[a]);
   }
+  // node (m0 + i, m1 + j, m2 + k) is base + i + j s1 + k s2
+  const int base = J.lin(m[0], m[1], m[2]);
+  const int s1 = J.s1(), s2 = J.s2();
   if (D == 1) {
     const float qx = c0 * (float)P.dxdt[0];
     float acc = 0.f;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       acc = acc - qx * (S1[0][i] - S0[0][i]);
-      J(0, m[0] + i, 0, 0, acc);
+      J.add(0, base + i, acc);
     }
     const float cy = c0 * v[1], cz = c0 * v[2];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       const float sa = 0.5f * (S0[0][i] + S1[0][i]);
-      J(1, m[0] + i, 0, 0, cy * sa);
-      J(2, m[0] + i, 0, 0, cz * sa);
+      J.add(1, base + i, cy * sa);
+      J.add(2, base + i, cz * sa);
     }
   } else if (D == 2) {
     const float qx = c0 * (float)P.dxdt[0], qy = c0 * (float)P.dxdt[1], cz = c0 * v[2];
@@ -273,7 +316,7 @@ __device__ inline void deposit3(const StepParams<float>& P, const Acc& J, const 
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         acc = acc - qx * (0.5f * (S1[0][i] - S0[0][i]) * (S0[1][j] + S1[1][j]));
-        J(0, m[0] + i, m[1] + j, 0, acc);
+        J.add(0, base + i + j * s1, acc);
       }
     }
 #pragma unroll
@@ -282,7 +325,7 @@ __device__ inline void deposit3(const StepParams<float>& P, const Acc& J, const 
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         acc = acc - qy * (0.5f * (S0[0][i] + S1[0][i]) * (S1[1][j] - S0[1][j]));
-        J(1, m[0] + i, m[1] + j, 0, acc);
+        J.add(1, base + i + j * s1, acc);
       }
     }
 #pragma unroll
@@ -291,7 +334,7 @@ __device__ inline void deposit3(const StepParams<float>& P, const Acc& J, const 
       for (int i = 0; i < 3; ++i) {
         const float W = (S0[0][i] * S0[1][j] + S1[0][i] * S1[1][j]) * (1.f / 3.f) +
                         (S0[0][i] * S1[1][j] + S1[0][i] * S0[1][j]) * (1.f / 6.f);
-        J(2, m[0] + i, m[1] + j, 0, cz * W);
+        J.add(2, base + i + j * s1, cz * W);
       }
   } else {
     const float qx = c0 * (float)P.dxdt[0], qy = c0 * (float)P.dxdt[1], qz = c0 * (float)P.dxdt[2];
@@ -305,7 +348,7 @@ __device__ inline void deposit3(const StepParams<float>& P, const Acc& J, const 
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
           acc = acc - qx * ((S1[0][i] - S0[0][i]) * T);
-          J(0, m[0] + i, m[1] + j, m[2] + k, acc);
+          J.add(0, base + i + j * s1 + k * s2, acc);
         }
       }
 #pragma unroll
@@ -318,7 +361,7 @@ __device__ inline void deposit3(const StepParams<float>& P, const Acc& J, const 
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
           acc = acc - qy * ((S1[1][j] - S0[1][j]) * T);
-          J(1, m[0] + i, m[1] + j, m[2] + k, acc);
+          J.add(1, base + i + j * s1 + k * s2, acc);
         }
       }
 #pragma unroll
@@ -331,7 +374,7 @@ __device__ inline void deposit3(const StepParams<float>& P, const Acc& J, const 
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
           acc = acc - qz * ((S1[2][k] - S0[2][k]) * T);
-          J(2, m[0] + i, m[1] + j, m[2] + k, acc);
+          J.add(2, base + i + j * s1 + k * s2, acc);
         }
       }
   }
@@ -524,12 +567,13 @@ __device__ inline void electron_physics(const StepParams<R>& P, int64_t e, uint3
       }
     }
   } else if constexpr (kF32) {
-    E0 = gather_q<D, 1, 0, 0>(fld, 0, qin, P.fb, P.iqs);
-    E1 = gather_q<D, 0, 1, 0>(fld, 1, qin, P.fb, P.iqs);
-    E2 = gather_q<D, 0, 0, 1>(fld, 2, qin, P.fb, P.iqs);
-    B0 = gather_q<D, 0, 1, 1>(fld, 3, qin, P.fb, P.iqs);
-    B1 = gather_q<D, 1, 0, 1>(fld, 4, qin, P.fb, P.iqs);
-    B2 = gather_q<D, 1, 1, 0>(fld, 5, qin, P.fb, P.iqs);
+    const Splits sp = make_splits<D>(qin, P.fb, P.iqs);
+    E0 = gather_q<D, 1, 0, 0>(fld, 0, sp);
+    E1 = gather_q<D, 0, 1, 0>(fld, 1, sp);
+    E2 = gather_q<D, 0, 0, 1>(fld, 2, sp);
+    B0 = gather_q<D, 0, 1, 1>(fld, 3, sp);
+    B1 = gather_q<D, 1, 0, 1>(fld, 4, sp);
+    B2 = gather_q<D, 1, 1, 0>(fld, 5, sp);
   } else {
     R g[3] = {R(0), R(0), R(0)};
 #pragma unroll
