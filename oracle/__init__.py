@@ -24,7 +24,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
 
-OR_NCS, OR_BREM, OR_FROZEN, OR_NO_RECOIL = 1, 2, 4, 16
+OR_NCS, OR_BREM, OR_FROZEN, OR_NO_RECOIL, OR_BREM_FREEPATH = 1, 2, 4, 16, 32
 FROZEN_UNIFORM, FROZEN_PLANE_WAVE = 0, 1
 
 
@@ -101,6 +101,8 @@ def _load():
         L.or_num_photons.argtypes = [P]
         L.or_get_electrons.argtypes = [P] + [C.c_void_p] * 6
         L.or_set_electrons.argtypes = [P] + [C.c_void_p] * 3
+        L.or_get_tau_brem.argtypes = [P, C.c_void_p]
+        L.or_set_tau_brem.argtypes = [P, C.c_void_p]
         L.or_get_photons.argtypes = [P] + [C.c_void_p] * 7
         L.or_get_stats.argtypes = [P, C.POINTER(_Stats)]
         L.or_kinetic_energy.restype = C.c_double
@@ -139,6 +141,8 @@ def flags_from(w):
         f |= OR_FROZEN
     if w.get("no_recoil", False):
         f |= OR_NO_RECOIL
+    if w.get("brem_freepath", False):
+        f |= OR_BREM_FREEPATH
     return f
 
 
@@ -223,6 +227,16 @@ class OracleSim:
         p = np.ascontiguousarray(p, dtype=np.float64).reshape(self.N, 3)
         tau = np.ascontiguousarray(tau, dtype=np.float64).reshape(self.N)
         self._L.or_set_electrons(self._h, x.ctypes.data, p.ctypes.data, tau.ctypes.data)
+
+    def tau_brem(self):
+        """Collision optical depths of the free-path form, id order."""
+        out = np.zeros(self.N)
+        self._L.or_get_tau_brem(self._h, out.ctypes.data)
+        return out
+
+    def set_tau_brem(self, t):
+        t = np.ascontiguousarray(t, dtype=np.float64).reshape(self.N)
+        self._L.or_set_tau_brem(self._h, t.ctypes.data)
 
     def photons(self):
         n_all = int(self._L.or_num_photons(self._h))

@@ -88,6 +88,7 @@ struct or_sim {
   /* electrons (id order, never reordered) */
   int64_t N;
   double *x, *p, *tau, *w;
+  double* taub;      /* collision optical depth (free-path bremsstrahlung only) */
   uint32_t* id;
   uint8_t* alive;
   /* photons */
@@ -252,6 +253,7 @@ or_sim* or_create(const or_config* c, const or_tables* t, int nthreads) {
   s->N = (int64_t)nslab * s->n[1] * s->n[2] * c->ppc;
   s->x = dalloc(3 * s->N); s->p = dalloc(3 * s->N);
   s->tau = dalloc(s->N); s->w = dalloc(s->N);
+  s->taub = (c->flags & OR_BREM_FREEPATH) ? dalloc(s->N) : NULL;
   s->id = (uint32_t*)calloc((size_t)(s->N > 0 ? s->N : 1), 4);
   s->alive = (uint8_t*)calloc((size_t)(s->N > 0 ? s->N : 1), 1);
   double wgt = c->ne_over_nc * V / (double)c->ppc;
@@ -267,6 +269,11 @@ or_sim* or_create(const or_config* c, const or_tables* t, int nthreads) {
           s->x[3 * e + 1] = s->act[1] ? ((double)j + u32(r[1])) * s->dx[1] : 0.0;
           s->x[3 * e + 2] = s->act[2] ? ((double)k + u32(r[2])) * s->dx[2] : 0.0;
           s->tau[e] = -log(u32(r[3]));
+          if (s->taub) {  /* first free path, in mean free paths: -ln u */
+            uint32_t rb[4];
+            or_philox((uint32_t)e, 0xFFFFFFFFu, 1u, 0u, s->key0, s->key1, rb);
+            s->taub[e] = -log(u32(rb[0]));
+          }
           s->w[e] = wgt;
           s->id[e] = (uint32_t)e;
           s->alive[e] = 1;
@@ -288,7 +295,7 @@ void or_destroy(or_sim* s) {
   for (int a = 0; a < 3; ++a) { free(s->E[a]); free(s->En[a]); free(s->B[a]); free(s->J[a]); }
   free(s->ni); free(s->srcA); free(s->srcC); free(s->srcS);
   free(s->h); free(s->ln_xi); free(s->ncs_cdf); free(s->sigma); free(s->br_cdf);
-  free(s->x); free(s->p); free(s->tau); free(s->w); free(s->id); free(s->alive);
+  free(s->x); free(s->p); free(s->tau); free(s->taub); free(s->w); free(s->id); free(s->alive);
   free(s->ph_x); free(s->ph_k); free(s->ph_e); free(s->ph_w);
   free(s->ph_step); free(s->ph_parent); free(s->ph_proc);
   free(s);
@@ -516,7 +523,15 @@ static void electron_one(or_sim* s, int64_t e, double tn, eres* out) {
   }
 
   /* bremsstrahlung: Eq. (4) with n the ion density of the electron's cell,
-   * sigma(E) integrated from the cut, event iff R1 < P_br (Sec. II.B) */
+   * sigma(E) integrated from the cut, event iff R1 < P_br (Sec. II.B).
+   * Free-path form (OR_BREM_FREEPATH): the exponent X = n sigma v dt of Eq. (4)
+   * is the path of the step in mean free paths, Delta s / lambda; the electron
+   * carries the number of mean free paths left to its next collision,
+   * exponentially distributed, and collides in the step in which that number
+   * is used up.  Given no collision so far, the chance of one within a step is
+   * 1 - exp(-X): the per-step law of Eq. (4), with no draw until the collision
+   * (the random free path of Sec. II.B, the cheaper sampling suggested in
+   * Sec. IV). */
   if (c->flags & OR_BREM) {
     double T = gamma - 1.0;
     if (T >= s->k_cut) {
@@ -540,10 +555,19 @@ static void electron_one(or_sim* s, int64_t e, double tn, eres* out) {
             double pm = sqrt(px * px + py * py + pz * pz);
             double v = pm / gamma;
             double X = s->K_BR * ni * sig * v * s->dt;
-            double P = -expm1(-X);
-            if (u52(r[0], r[1]) < P) {
+            int hit;
+            if (c->flags & OR_BREM_FREEPATH) {
+              s->taub[e] = s->taub[e] - X;
+              hit = s->taub[e] <= 0.0;
+            } else {
+              double P = -expm1(-X);
+              hit = u52(r[0], r[1]) < P;
+            }
+            if (hit) {
               uint32_t r2[4];
               or_philox(s->id[e], n, 1u, 0u, s->key0, s->key1, r2);
+              /* the next free path: word 1 of the event's second draw */
+              if (c->flags & OR_BREM_FREEPATH) s->taub[e] = -log(u32(r2[1]));
               double u = u32(r2[0]);
               double sa = br_inv_row(s, i, u);
               double sb = br_inv_row(s, i + 1, u);
@@ -758,6 +782,14 @@ void or_get_electrons(const or_sim* s, double* x, double* p, double* tau,
   memcpy(w, s->w, sizeof(double) * (size_t)s->N);
   memcpy(id, s->id, sizeof(uint32_t) * (size_t)s->N);
   memcpy(alive, s->alive, (size_t)s->N);
+}
+
+void or_get_tau_brem(const or_sim* s, double* out) {
+  if (s->taub) memcpy(out, s->taub, sizeof(double) * (size_t)s->N);
+}
+
+void or_set_tau_brem(or_sim* s, const double* in) {
+  if (s->taub) memcpy(s->taub, in, sizeof(double) * (size_t)s->N);
 }
 
 void or_set_electrons(or_sim* s, const double* x, const double* p, const double* tau) {

@@ -16,7 +16,10 @@
 #define PIC_ORACLE_H
 #include <stdint.h>
 
-enum { OR_NCS = 1, OR_BREM = 2, OR_FROZEN = 4, OR_NO_RECOIL = 16 };
+/* OR_BREM_FREEPATH: bremsstrahlung by a per-electron free path (collision
+ * optical depth) instead of a fresh Eq. (4) trial every step; the same
+ * per-step event law, see electron_one. */
+enum { OR_NCS = 1, OR_BREM = 2, OR_FROZEN = 4, OR_NO_RECOIL = 16, OR_BREM_FREEPATH = 32 };
 enum { OR_FROZEN_UNIFORM = 0, OR_FROZEN_PLANE_WAVE = 1 };
 
 typedef struct {
@@ -57,6 +60,10 @@ void     or_get_electrons(const or_sim* s, double* x, double* p, double* tau,
                           double* w, uint32_t* id, uint8_t* alive);
 void     or_set_electrons(or_sim* s, const double* x, const double* p,
                           const double* tau);
+/* collision optical depths of the free-path form (id order); no-ops without
+ * OR_BREM_FREEPATH */
+void     or_get_tau_brem(const or_sim* s, double* out);
+void     or_set_tau_brem(or_sim* s, const double* in);
 void     or_get_photons(const or_sim* s, double* x, double* k, double* eps,
                         double* w, uint32_t* step, uint32_t* parent,
                         uint32_t* proc);

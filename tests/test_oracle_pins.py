@@ -648,3 +648,98 @@ def test_brem_events_16_electrons_brute_force(oracle_lib, tables_au):
     got = sorted(zip(ph["parent"].tolist(), ph["step"].tolist()))
     assert len(want) > 100
     assert got == sorted(want)
+
+
+# ------------------------------------------------ free-path bremsstrahlung
+def test_brem_freepath_16_electrons_brute_force(oracle_lib, tables_au):
+    """Free-path form of Eq. (4): each electron carries the number of mean free
+    paths to its next collision, tau_b = -ln u (word 0 of counter
+    (id, 0xFFFFFFFF, 1, 0) at load); every step uses up X = K_BR n_i sigma v dt
+    of it; a collision when tau_b <= 0, then tau_b = -ln u (word 1 of the
+    event's energy-draw counter (id, n, 1, 0)).  Replayed independently at a
+    table node of sigma with the pinned Python Philox."""
+    i = 100
+    Tk = math.exp(tables_au["ln_T0"] + i * tables_au["dln_T"])
+    pm = math.sqrt(Tk * (Tk + 2))
+    q = 79
+    gam = math.sqrt(1 + pm * pm)
+    ni = 0.05 / (_K_BR() * tables_au["sigma"][i] * (pm / gam) * 0.95 * 2 * math.pi)
+    w = S.base(name="brem-16-fp", dims=1, n=[64], dx_lambda=[1.0], ppc=1, x0_lambda=0.0,
+               thickness_lambda=16.0, frozen=True, frozen_kind=0, Z=79, charge_state=q,
+               ne_over_nc=ni * q, ncs=False, brem=True, no_recoil=True, seed=13,
+               brem_freepath=True)
+    o = oracle.OracleSim(w, tables_au)
+    assert o.N == 16
+    d = o.derived()
+    e = o.electrons()
+    key = (13, 0)
+    tb0 = o.tau_brem()
+    for idv in range(16):
+        want0 = -math.log(_u32(_philox_py((idv, 0xFFFFFFFF, 1, 0), key)[0]))
+        assert tb0[idv] == want0
+    p = np.zeros((16, 3))
+    p[:, 1] = pm
+    o.set_electrons(e["x"], p, e["tau"])
+    M = 300
+    o.step(M)
+    X = d["K_BR"] * ni * tables_au["sigma"][i] * (pm / gam) * d["dt"]
+    assert 0.01 < X < 0.2
+    want, tb_end = [], []
+    for idv in range(16):
+        tb = float(tb0[idv])
+        for n in range(M):
+            tb -= X
+            if tb <= 0.0:
+                want.append((idv, n))
+                tb = -math.log(_u32(_philox_py((idv, n, 1, 0), key)[1]))
+        tb_end.append(tb)
+    ph = o.photons()
+    got = sorted(zip(ph["parent"].tolist(), ph["step"].tolist()))
+    assert len(want) > 100
+    assert got == sorted(want)
+    np.testing.assert_allclose(o.tau_brem(), tb_end, rtol=0, atol=1e-9)
+    # mean number of steps between collisions: 1 / P with P = 1 - exp(-X)
+    P = -math.expm1(-X)
+    assert abs(len(want) / (16 * M) - P) < 4 * math.sqrt(P * (1 - P) / (16 * M))
+
+
+def test_brem_freepath_event_counts_binomial(oracle_lib, tables_au):
+    """With the energy fixed, the steps between collisions of the free-path
+    form are geometric with P = 1 - exp(-X) (the exponential free path cut into
+    steps), so the count over M steps of N electrons is Binomial(N M, P): the
+    same law as the per-step trial of Eq. (4)."""
+    i = 110
+    Tk = math.exp(tables_au["ln_T0"] + i * tables_au["dln_T"])
+    w = _brem_case(79, 79, 7900.0, Tk)
+    w.update(no_recoil=True, brem_freepath=True)
+    o = oracle.OracleSim(w, tables_au)
+    d = o.derived()
+    e = o.electrons()
+    p = np.zeros((o.N, 3))
+    pm = math.sqrt(Tk * (Tk + 2))
+    p[:, 0] = pm
+    x = e["x"].copy()
+    x[:, 0] = 0.5 * d["dx"][0] * (np.arange(o.N) % 64 + 0.5)
+    o.set_electrons(x, p, e["tau"])
+    M = 2000
+    o.step(M)
+    st = o.stats()
+    gam = math.sqrt(1 + pm * pm)
+    X = d["K_BR"] * (7900.0 / 79) * tables_au["sigma"][i] * (pm / gam) * d["dt"]
+    P = -math.expm1(-X)
+    n = o.N * M
+    mean, sd = n * P, math.sqrt(n * P * (1 - P))
+    assert abs(st["events"][1] - mean) < 4 * sd + 1e-4 * mean, (st["events"][1], mean, sd)
+    # and the first-collision step k (1-based) is geometric, truncated at M:
+    # randomised probability-integral transform of k against
+    # F(k) = (1 - (1 - P)^k) / (1 - (1 - P)^M), then KS against uniform
+    ph = o.photons()
+    first = {}
+    for par, stp in zip(ph["parent"].tolist(), ph["step"].tolist()):
+        first[par] = min(stp, first.get(par, stp))
+    k = np.array(sorted(first.values()), dtype=np.float64) + 1.0
+    assert len(k) > 0.99 * o.N
+    F = lambda t: -np.expm1(t * math.log1p(-P)) / -math.expm1(M * math.log1p(-P))
+    u = F(k - 1) + (F(k) - F(k - 1)) * np.random.default_rng(5).random(len(k))
+    ks = stats.kstest(u, "uniform")
+    assert ks.pvalue > 1e-3, ks
