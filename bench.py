@@ -53,6 +53,8 @@ def _workload(name, precision, steps):
     elif name == "c5":
         w = W.c5(steps)
         w["precision"] = precision
+    elif name == "thick":
+        w = W.thick_target(steps, precision)
     else:
         raise SystemExit(f"unknown workload {name}")
     return w
@@ -85,17 +87,38 @@ def _num_electrons(w):
     return W.num_electrons(w)
 
 
+def _pencil_beam(w):
+    """Electrons of a thick-target recipe as a pencil beam along +x at the
+    front face, kinetic energy w["beam_energy_mev"] (set before timing)."""
+    import numpy as np
+
+    def f(s):
+        e = s.electrons()
+        x = np.zeros_like(e["x"])
+        x[:, 0] = (np.arange(s.N) % 1024 + 0.5) / 1024 * 2 * np.pi * w["dx_lambda"][0]
+        T = w["beam_energy_mev"] / 0.51099895
+        p = np.zeros_like(e["p"])
+        p[:, 0] = (T * (T + 2.0)) ** 0.5
+        s.set_electrons(x, p, e["tau"])
+    return f if "beam_energy_mev" in w else None
+
+
 def run_gpu(w, tables, steps, warmup, torch, photons=False, kernel_times=True):
     """Time `steps` steps from a fresh context.  The wall-clock run records no
     events; a second identical run, with HIP events on the context's stream
     around every launch group, gives the per-kernel times."""
     from paper_1612_07592_amd import binding
+    beam = _pencil_beam(w)
     if warmup > 0:
         s = binding.Sim(w, tables)
+        if beam:
+            beam(s)
         s.pic_step(warmup)
         s.pic_emission_stats()
         s.pic_destroy()
     s = binding.Sim(w, tables)
+    if beam:
+        beam(s)
     s.synchronize()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -110,6 +133,8 @@ def run_gpu(w, tables, steps, warmup, torch, photons=False, kernel_times=True):
                sort_ms=None, step_launches=0)
     if kernel_times:
         s = binding.Sim(w, tables)
+        if beam:
+            beam(s)
         s.profile(True)
         s.pic_step(steps)
         ms, n = s.profile_read()
@@ -117,6 +142,28 @@ def run_gpu(w, tables, steps, warmup, torch, photons=False, kernel_times=True):
         out.update(step_kernel_ms=float(ms[0]), field_ms=float(ms[1]), sort_ms=float(ms[2]),
                    step_launches=int(n[0]), profiled_wall_ms=float(ms.sum()))
     return out
+
+
+def thick_target_line(args, tables, torch):
+    """Bremsstrahlung-dominated workload: 100 MeV pencil beam of 2.1M
+    electrons into 5 mm of solid gold, particle-only, FP32, 2000 steps; the
+    per-step Eq. (4) trial against the free-path form."""
+    from paper_1612_07592_amd import workloads as W
+    res = {"workload": "thick-au-5mm", "electrons": None, "steps": 2000}
+    for form, fp in (("per_step_trial", False), ("free_path", True)):
+        w = W.thick_target(2000, "fp32")
+        w["brem_freepath"] = fp
+        r = run_gpu(w, tables, 2000, 0, torch, kernel_times=True)
+        st = r["stats"]
+        res["electrons"] = _num_electrons(w)
+        res[form] = {"value": st["electron_steps"] / r["wall_s"],
+                     "kernel_avg_us": r["step_kernel_ms"] * 1e3 / max(1, r["step_launches"]),
+                     "brem_events": st["events"][1], "e_rad_brem": st["e_rad_kept"][1]}
+    res["free_path_speedup"] = res["free_path"]["value"] / res["per_step_trial"]["value"]
+    print(f"[bench] thick target: per-step {res['per_step_trial']['value']:.3e}, free path "
+          f"{res['free_path']['value']:.3e} e-steps/s ({res['free_path_speedup']:.2f}x)",
+          file=sys.stderr, flush=True)
+    return res
 
 
 def precision_check(r32, r64):
@@ -215,6 +262,10 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of this many MiB (HBM counter calibration)")
     ap.add_argument("--c3-steps", type=int, default=1000)
+    ap.add_argument("--brem-freepath", action="store_true",
+                    help="time the free-path form of the bremsstrahlung test instead of the per-step trial")
+    ap.add_argument("--no-freepath-line", action="store_true",
+                    help="skip the free-path bremsstrahlung run reported beside the main one")
     ap.add_argument("--c4-jobs", type=int, default=24,
                     help="jobs of the Poisson stream served (0 = none)")
     args = ap.parse_args()
@@ -236,7 +287,9 @@ def main():
         print(f"[bench] copy calibration: {n * 4} bytes read, {n * 4} written", file=sys.stderr, flush=True)
         del a, b
     w = _workload(args.workload, args.precision, args.steps)
-    w["sort_every"] = args.sort_every
+    if args.sort_every or "sort_every" not in w:
+        w["sort_every"] = args.sort_every
+    w["brem_freepath"] = args.brem_freepath
     t0 = time.perf_counter()
     tables = binding.pic_build_tables(int(w["Z"]), 1.0, 16)
     t_tables = time.perf_counter() - t0
@@ -267,7 +320,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": w["name"], "dims": dims, "cells": list(w["n"]),
                    "electrons": _num_electrons(w),
-                   "precision": args.precision, "a0": w["a0"], "Z": w["Z"]},
+                   "precision": args.precision, "a0": w["a0"], "Z": w["Z"],
+                   "brem": "free-path" if args.brem_freepath else "per-step trial"},
         "roofline": {"bound": "alu", "achieved": alu, "peak": ALU_PEAK_TOPS, "unit": "TFLOP/s",
                      "frac": alu / ALU_PEAK_TOPS,
                      "traffic": _measured_traffic(w["name"], args.precision),
@@ -289,9 +343,21 @@ def main():
     print(f"[bench] {args.precision}: {value:.3e} e-steps/s, step kernel "
           f"{out['roofline']['kernel_avg_us']:.1f} us, {alu:.2f} Tops/s, {achieved:.0f} GB/s",
           file=sys.stderr, flush=True)
+    if not args.no_freepath_line and not args.brem_freepath:
+        # the same workload with the free-path form of the collision test
+        rf = run_gpu(dict(w, brem_freepath=True), tables, args.steps, 0, torch, kernel_times=True)
+        vf = rf["stats"]["electron_steps"] / rf["wall_s"]
+        out["brem_free_path"] = {
+            "value": vf, "over_per_step_trial": vf / value,
+            "kernel_avg_us": rf["step_kernel_ms"] * 1e3 / max(1, rf["step_launches"]),
+            "events": rf["stats"]["events"], "kept": rf["stats"]["kept"]}
+        print(f"[bench] free-path brem: {vf:.3e} e-steps/s ({vf / value:.3f}x)", file=sys.stderr, flush=True)
+    if not args.no_freepath_line and args.workload == "c2":
+        out["thick_target"] = thick_target_line(args, tables, torch)
     if not args.no_fp64 and args.precision == "fp32":
         w64 = _workload(args.workload, "fp64", args.steps)
-        w64["sort_every"] = args.sort_every
+        w64["sort_every"] = w["sort_every"]
+        w64["brem_freepath"] = args.brem_freepath
         r64 = run_gpu(w64, tables, args.steps, 0, torch, photons=True, kernel_times=True)
         v64 = r64["stats"]["electron_steps"] / r64["wall_s"]
         out["fp64"] = {"value": v64, "ms_per_step": r64["wall_s"] * 1e3 / args.steps,

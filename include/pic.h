@@ -70,7 +70,17 @@ enum {
   PIC_BREM = 1u << 1,          /* bremsstrahlung on */
   PIC_FIELDS_FROZEN = 1u << 2, /* particle-only mode: prescribed fields, no field
                                   solve, no deposit (the benchmark mode of Sec. II.B) */
-  PIC_NO_RECOIL = 1u << 4      /* emit without changing the electron (tests only) */
+  PIC_NO_RECOIL = 1u << 4,     /* emit without changing the electron (tests only) */
+  PIC_BREM_FREEPATH = 1u << 5  /* with PIC_BREM: collision by free path.  Each electron
+                                  carries its collision optical depth (the mean free
+                                  paths left to its next collision, -ln u at load and
+                                  after each collision); a step uses up the exponent
+                                  n sigma v dt of Eq. (4) and collides when it runs
+                                  out.  Same per-step law as the Eq. (4) trial (Sec.
+                                  II.B, random free path), no draw between collisions
+                                  (Sec. IV); different random streams, so runs agree
+                                  with the per-step form in distribution, not event
+                                  by event.  8 more bytes per electron. */
 };
 enum { PIC_FROZEN_UNIFORM = 0, PIC_FROZEN_PLANE_WAVE = 1 };
 
@@ -219,6 +229,12 @@ pic_status pic_copy_electrons(pic_ctx* ctx, double* x, double* p, double* tau,
  * id, layout as pic_copy_electrons).  For tests that set up beams. */
 pic_status pic_set_electrons(pic_ctx* ctx, const double* x, const double* p,
                              const double* tau);
+
+/* Collision optical depths of PIC_BREM_FREEPATH runs, n = pic_counts'
+ * electron count doubles ordered by id (copy: synchronises; set: for tests
+ * that set up beams, finite values only).  PIC_ERR_STATE without the flag. */
+pic_status pic_copy_brem_depth(pic_ctx* ctx, double* out);
+pic_status pic_set_brem_depth(pic_ctx* ctx, const double* in);
 
 /* Copy photon records [off, off+n) of the buffer (n <= stored - off):
  * x[3n] emission point, k[3n] unit direction, eps[n] energy (mc^2), w[n]

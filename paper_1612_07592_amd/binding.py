@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libpic.so")
 PIC_ABI_VERSION = 1
 PIC_TABLES_VERSION = 1
 PIC_FP64, PIC_FP32_MIXED = 0, 1
-PIC_NCS, PIC_BREM, PIC_FIELDS_FROZEN, PIC_NO_RECOIL = 1, 2, 4, 16
+PIC_NCS, PIC_BREM, PIC_FIELDS_FROZEN, PIC_NO_RECOIL, PIC_BREM_FREEPATH = 1, 2, 4, 16, 32
 PIC_FROZEN_UNIFORM, PIC_FROZEN_PLANE_WAVE = 0, 1
 STATUS = {0: "PIC_OK", 1: "PIC_ERR_INVALID", 2: "PIC_ERR_NOMEM", 3: "PIC_ERR_DEVICE",
           4: "PIC_ERR_STATE", 5: "PIC_ERR_OVERFLOW", 6: "PIC_ERR_TABLES"}
@@ -28,7 +28,8 @@ EXPORTS = ["pic_create", "pic_load_tables", "pic_step", "pic_emission_stats", "p
            "pic_copy_current", "pic_batch_create", "pic_batch_destroy", "pic_batch_last_error",
            "pic_step_many", "pic_server_create", "pic_server_destroy", "pic_server_clock",
            "pic_server_last_error", "pic_server_submit", "pic_server_run", "pic_server_poll",
-           "pic_server_job_ctx", "pic_server_release", "pic_device_memory", "pic_synchronize"]
+           "pic_server_job_ctx", "pic_server_release", "pic_device_memory", "pic_synchronize",
+           "pic_copy_brem_depth", "pic_set_brem_depth"]
 
 
 class pic_config(C.Structure):
@@ -114,6 +115,8 @@ def load() -> C.CDLL:
     L.pic_counts.argtypes = [P, C.POINTER(u64), C.POINTER(u64), C.POINTER(u64)]
     L.pic_copy_electrons.argtypes = [P] + [C.c_void_p] * 6
     L.pic_set_electrons.argtypes = [P] + [C.c_void_p] * 3
+    L.pic_copy_brem_depth.argtypes = [P, C.c_void_p]
+    L.pic_set_brem_depth.argtypes = [P, C.c_void_p]
     L.pic_copy_photons.argtypes = [P, u64, u64] + [C.c_void_p] * 7
     L.pic_field_size.argtypes = [P, C.POINTER(u64)]
     L.pic_copy_fields.argtypes = [P, C.c_void_p]
@@ -172,6 +175,7 @@ def config_from(w: dict, stream=None) -> pic_config:
     f |= PIC_BREM if w.get("brem", True) else 0
     f |= PIC_FIELDS_FROZEN if w.get("frozen", False) else 0
     f |= PIC_NO_RECOIL if w.get("no_recoil", False) else 0
+    f |= PIC_BREM_FREEPATH if w.get("brem_freepath", False) else 0
     c.flags = f
     n = list(w["n"]) + [1] * (3 - len(w["n"]))
     dx = list(w["dx_lambda"]) + [1.0] * (3 - len(w["dx_lambda"]))
@@ -354,6 +358,16 @@ class Sim:
         tau = np.ascontiguousarray(tau, dtype=np.float64).reshape(self.N)
         _check("pic_set_electrons", self._L.pic_set_electrons(self._h, x.ctypes.data, p.ctypes.data,
                                                               tau.ctypes.data), self._h)
+
+    def brem_depth(self) -> np.ndarray:
+        """Collision optical depths of a free-path bremsstrahlung run, id order."""
+        out = np.zeros(self.N)
+        _check("pic_copy_brem_depth", self._L.pic_copy_brem_depth(self._h, out.ctypes.data), self._h)
+        return out
+
+    def set_brem_depth(self, t):
+        t = np.ascontiguousarray(t, dtype=np.float64).reshape(self.N)
+        _check("pic_set_brem_depth", self._L.pic_set_brem_depth(self._h, t.ctypes.data), self._h)
 
     def photons(self, off: int = 0, n: int | None = None) -> dict:
         _, stored, _ = self.counts()

@@ -71,7 +71,9 @@ std::string derive(const pic_config& cfg, Ctx& c) {
   if (cfg.abi_version != PIC_ABI_VERSION) return "abi_version mismatch";
   if (cfg.dims < 1 || cfg.dims > 3) return "dims must be 1, 2 or 3";
   if (cfg.precision != PIC_FP64 && cfg.precision != PIC_FP32_MIXED) return "unknown precision";
-  if (cfg.flags & ~(uint32_t)(PIC_NCS | PIC_BREM | PIC_FIELDS_FROZEN | PIC_NO_RECOIL)) return "unknown flag bits";
+  if (cfg.flags & ~(uint32_t)(PIC_NCS | PIC_BREM | PIC_FIELDS_FROZEN | PIC_NO_RECOIL | PIC_BREM_FREEPATH))
+    return "unknown flag bits";
+  if ((cfg.flags & PIC_BREM_FREEPATH) && !(cfg.flags & PIC_BREM)) return "PIC_BREM_FREEPATH needs PIC_BREM";
   if (cfg.ppc < 1) return "ppc must be >= 1";
   if (cfg.Z < 1 || cfg.Z > 120) return "Z out of range";
   if (cfg.charge_state < 1 || cfg.charge_state > cfg.Z) return "charge_state must be in [1, Z]";
@@ -176,7 +178,9 @@ std::string derive(const pic_config& cfg, Ctx& c) {
     vmax = vmax * dxdt * 1.5 + 1e-30;                 // |W| <= 1, |acc| <= 1.5, |v| < 1
     c.jbits = 40;
     while (c.jbits > 0 && (double)kBlock * vmax * ldexp(1.0, c.jbits) >= ldexp(1.0, 30)) --c.jbits;
-    if (c.fp32 && c.jbits < 8) return "electron weight too large for the FP32 current quantum";
+    // (particle-only runs deposit nothing)
+    if (c.fp32 && c.jbits < 8 && !(cfg.flags & PIC_FIELDS_FROZEN))
+      return "electron weight too large for the FP32 current quantum";
   }
   // tuning overrides (layout only; results do not depend on them)
   if (const char* v = getenv("PIC_TUNE_LDS_NODES")) c.lds_nodes = atoi(v) & ~1;
@@ -229,6 +233,8 @@ Plan make_plan(Ctx& c) {
     P.add(&c.p[a], N * rs);
   }
   P.add((void**)&c.tau, N * 8);
+  const bool fp = (c.cfg.flags & PIC_BREM_FREEPATH) != 0;
+  if (fp) P.add((void**)&c.taub, N * 8);
   P.add((void**)&c.w, N * 8);
   P.add((void**)&c.id, N * 4);
   if (c.sort_every > 0) {  // second SoA buffer and sort scratch
@@ -237,6 +243,7 @@ Plan make_plan(Ctx& c) {
       P.add(&c.p2[a], N * rs);
     }
     P.add((void**)&c.tau2, N * 8);
+    if (fp) P.add((void**)&c.taub2, N * 8);
     P.add((void**)&c.w2, N * 8);
     P.add((void**)&c.id2, N * 4);
     P.add((void**)&c.skey, N * 4);
@@ -345,6 +352,7 @@ void fill_step_params(Ctx& c, StepParams<R>& P) {
     P.dxdt[a] = g.dx[a] / g.dt;
   }
   P.tau = c.tau;
+  P.taub = c.taub;
   P.w = c.w;
   P.id = c.id;
   P.invV = g.invV;
@@ -441,6 +449,7 @@ SortArgs sort_args(const Ctx& c) {
   A.nkeys = c.nkeys;
   A.tau = c.tau; A.w = c.w; A.id = c.id;
   A.tau2 = c.tau2; A.w2 = c.w2; A.id2 = c.id2;
+  A.taub = c.taub; A.taub2 = c.taub2;
   A.key = c.skey; A.count = c.scount; A.offset = c.soffset; A.cursor = c.scursor;
   A.n_active = c.n_active;
   return A;
@@ -449,6 +458,7 @@ SortArgs sort_args(const Ctx& c) {
 void swap_sorted(Ctx& c) {
   for (int a = 0; a < 3; ++a) { std::swap(c.x[a], c.x2[a]); std::swap(c.p[a], c.p2[a]); }
   std::swap(c.tau, c.tau2); std::swap(c.w, c.w2); std::swap(c.id, c.id2);
+  std::swap(c.taub, c.taub2);
 }
 
 pic_status step_ready(Ctx& c, int32_t nsteps) {
@@ -564,6 +574,7 @@ const char* pic_last_error(const pic_ctx* ctx) {
 pic_status pic_memory_required(const pic_config* cfg, uint64_t* bytes) {
   if (!cfg || !bytes) return PIC_ERR_INVALID;
   Ctx tmp;
+  tmp.cfg = *cfg;
   const std::string e = derive(*cfg, tmp);
   if (!e.empty()) {
     g_create_err = e;
@@ -1089,6 +1100,43 @@ pic_status pic_set_electrons(pic_ctx* ctx, const double* x, const double* p, con
   std::vector<double> t8(N);
   for (size_t e = 0; e < N; ++e) t8[e] = tau[ids[e] & ~kDead];
   HIPCHK(c, hipMemcpyAsync(c.tau, t8.data(), N * 8, hipMemcpyHostToDevice, c.stream));
+  HIPCHK(c, hipStreamSynchronize(c.stream));
+  return PIC_OK;
+}
+
+pic_status pic_copy_brem_depth(pic_ctx* ctx, double* out) {
+  pic_status st = check_ctx(ctx);
+  if (st) return st;
+  Ctx& c = ctx->c;
+  if (!(c.cfg.flags & PIC_BREM_FREEPATH)) FAIL(c, PIC_ERR_STATE, "run has no free-path bremsstrahlung");
+  if (!out) FAIL(c, PIC_ERR_INVALID, "null argument");
+  const size_t N = (size_t)c.N;
+  if (!N) return PIC_OK;
+  std::vector<uint32_t> ids(N);
+  std::vector<double> t8(N);
+  HIPCHK(c, hipMemcpyAsync(ids.data(), c.id, N * 4, hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(c, hipMemcpyAsync(t8.data(), c.taub, N * 8, hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(c, hipStreamSynchronize(c.stream));
+  for (size_t e = 0; e < N; ++e) out[ids[e] & ~kDead] = t8[e];
+  return PIC_OK;
+}
+
+pic_status pic_set_brem_depth(pic_ctx* ctx, const double* in) {
+  pic_status st = check_ctx(ctx);
+  if (st) return st;
+  Ctx& c = ctx->c;
+  if (!(c.cfg.flags & PIC_BREM_FREEPATH)) FAIL(c, PIC_ERR_STATE, "run has no free-path bremsstrahlung");
+  if (!in) FAIL(c, PIC_ERR_INVALID, "null argument");
+  const size_t N = (size_t)c.N;
+  if (!N) return PIC_OK;
+  for (size_t e = 0; e < N; ++e)
+    if (!is_fin(in[e])) FAIL(c, PIC_ERR_INVALID, "non-finite optical depth");
+  std::vector<uint32_t> ids(N);
+  HIPCHK(c, hipMemcpyAsync(ids.data(), c.id, N * 4, hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(c, hipStreamSynchronize(c.stream));
+  std::vector<double> t8(N);
+  for (size_t e = 0; e < N; ++e) t8[e] = in[ids[e] & ~kDead];
+  HIPCHK(c, hipMemcpyAsync(c.taub, t8.data(), N * 8, hipMemcpyHostToDevice, c.stream));
   HIPCHK(c, hipStreamSynchronize(c.stream));
   return PIC_OK;
 }

@@ -247,6 +247,7 @@ struct InitArgs {
   void* x[3];
   void* p[3];
   double* tau;
+  double* taub;  // free-path bremsstrahlung only
   double* w;
   uint32_t* id;
   double* ni;
@@ -258,7 +259,9 @@ struct InitArgs {
 };
 
 // Electron e of the slab cell with rank e/ppc; cold, uniform in the cell;
-// tau_0 = -ln u (Philox counter (id, 0xFFFFFFFF, 0, 0)).
+// tau_0 = -ln u (Philox counter (id, 0xFFFFFFFF, 0, 0)); the first collision
+// optical depth of free-path bremsstrahlung, -ln u of word 0 of counter
+// (id, 0xFFFFFFFF, 1, 0).
 template <class R>
 __global__ __launch_bounds__(kBlock) void k_init_electrons(InitArgs A) {
   const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -280,6 +283,10 @@ __global__ __launch_bounds__(kBlock) void k_init_electrons(InitArgs A) {
   }
   for (int a = 0; a < 3; ++a) ((R*)A.p[a])[e] = R(0);
   A.tau[e] = -log(unif32(r.v[3]));
+  if (A.taub) {
+    const U4 rb = philox4x32_10((uint32_t)e, 0xFFFFFFFFu, 1u, 0u, A.key0, A.key1);
+    A.taub[e] = -log(unif32(rb.v[0]));
+  }
   A.w[e] = A.wgt;
   A.id[e] = (uint32_t)e;
 }
@@ -305,7 +312,7 @@ void launch_init_electrons(const Ctx& c, hipStream_t s) {
   }
   A.wgt = c.wgt;
   A.key0 = c.key0; A.key1 = c.key1;
-  A.tau = c.tau; A.w = c.w; A.id = c.id; A.ni = c.ni;
+  A.tau = c.tau; A.taub = c.taub; A.w = c.w; A.id = c.id; A.ni = c.ni;
   A.ncell = (int64_t)c.g.n[0] * c.g.n[1] * c.g.n[2];
   A.nx = c.g.n[0];
   A.nion = c.cfg.ne_over_nc / (double)c.cfg.charge_state;

@@ -106,6 +106,7 @@ struct StepParams {
   R* x[3];
   R* p[3];
   double* tau;
+  double* taub;  // collision optical depth (free-path bremsstrahlung), else null
   const double* w;
   uint32_t* id;
   // fields: Ex, Ey, Ez, Bx, By, Bz
@@ -147,11 +148,13 @@ struct SortArgs {
   const void* x[3];
   const void* p[3];
   const double* tau;
+  const double* taub;       // null unless free-path bremsstrahlung
   const double* w;
   const uint32_t* id;
   void* x2[3];
   void* p2[3];
   double* tau2;
+  double* taub2;
   double* w2;
   uint32_t* id2;
   uint32_t* key;
@@ -209,6 +212,7 @@ struct Ctx {
   void* x[3] = {};
   void* p[3] = {};
   double* tau = nullptr;
+  double* taub = nullptr;     // free-path bremsstrahlung only
   double* w = nullptr;
   uint32_t* id = nullptr;
   uint64_t pcap = 0;
@@ -229,6 +233,7 @@ struct Ctx {
   void* x2[3] = {};
   void* p2[3] = {};
   double* tau2 = nullptr;
+  double* taub2 = nullptr;
   double* w2 = nullptr;
   uint32_t* id2 = nullptr;
   uint32_t* skey = nullptr;

@@ -195,6 +195,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(SortArgs A) {
   for (int a = 0; a < A.dims; ++a) ((R*)A.x2[a])[d] = ((const R*)A.x[a])[e];
   for (int a = 0; a < 3; ++a) ((R*)A.p2[a])[d] = ((const R*)A.p[a])[e];
   A.tau2[d] = A.tau[e];
+  if (A.taub) A.taub2[d] = A.taub[e];
   A.w2[d] = A.w[e];
   A.id2[d] = A.id[e];
 }
@@ -208,6 +209,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_tail(SortArgs A) {
     for (int a = 0; a < A.dims; ++a) ((R*)A.x2[a])[e] = ((const R*)A.x[a])[e];
     for (int a = 0; a < 3; ++a) ((R*)A.p2[a])[e] = ((const R*)A.p[a])[e];
     A.tau2[e] = A.tau[e];
+    if (A.taub) A.taub2[e] = A.taub[e];
     A.w2[e] = A.w[e];
     A.id2[e] = A.id[e];
   }

@@ -552,6 +552,11 @@ __device__ inline void electron_physics(const StepParams<R>& P, int64_t e, uint3
   R px, py, pz;
   if constexpr (D == 3) { px = pin[0]; py = pin[1]; pz = pin[2]; }
   else { px = P.p[0][e]; py = P.p[1][e]; pz = P.p[2][e]; }
+  // free-path collision depth: loaded here so that its latency overlaps the
+  // gather and the push (measured on the 2D gold slab: a load at the test
+  // costs 7 us per launch)
+  const bool fpath = (P.flags & PIC_BREM_FREEPATH) != 0;
+  const double taub_in = fpath ? P.taub[e] : 0.0;
 
   // ---- gather E^n, B^n at x^n ----------------------------------------------
   R E0, E1, E2, B0, B1, B2;
@@ -688,10 +693,24 @@ __device__ inline void electron_physics(const StepParams<R>& P, int64_t e, uint3
             const R pm = m_sqrt(px * px + py * py + pz * pz);
             const R v = m_div(pm, gamma);
             const R X = R(P.K_BR) * R(ni) * sig * v * R(P.dt);
-            const R Pb = -m_expm1(-X);
-            draw();
-            if (unif52(r.v[0], r.v[1]) < (double)Pb) {
+            bool hit;
+            double tb = 0.0;
+            if (fpath) {
+              // free path: X is the step's path in mean free paths; collide
+              // when the electron's remaining depth runs out (no draw until then)
+              tb = taub_in - (double)X;
+              hit = tb <= 0.0;
+            } else {
+              const R Pb = -m_expm1(-X);
+              draw();
+              hit = unif52(r.v[0], r.v[1]) < (double)Pb;
+            }
+            if (!hit) {
+              if (fpath) P.taub[e] = tb;
+            } else {
               const U4 r2 = philox4x32_10(idv, n, 1u, 0u, P.key0, P.key1);
+              // next free path from word 1 of the energy draw's counter
+              if (fpath) P.taub[e] = -log(unif32(r2.v[1]));
               const R u = unif<R>(r2.v[0]);
               const ColdPtr<R> C = cold(P);
               const int ny = C->n_y;

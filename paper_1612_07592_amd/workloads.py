@@ -110,6 +110,25 @@ def c5(steps=500):
                  steps=steps, seed=5, photon_capacity=200_000_000, precision="fp32", **AU)
 
 
+def thick_target(steps=2000, precision="fp32", energy_mev=100.0, electrons=2_097_152):
+    """Particle-only thick-target run (the bremsstrahlung benchmark of Sec.
+    II.B: field solve and deposit off, an electron bunch into a 5 mm gold
+    target): solid gold fully ionised (n_e = 4177 n_c, Sec. III), 5000 um at
+    dx = 1 um, NCS off, no fields.  `beam_energy_mev` is the kinetic energy of
+    the pencil beam the caller sets along +x at the front face (all electrons
+    in the first cell); the loader's uniform fill only provides the count and
+    the ids.  No electron leaves the target within 5000 steps, so no sort."""
+    n_cells = 5120
+    thick = 5000.0
+    ppc = -(-electrons // int(thick))
+    return _base(name="thick-au-5mm", dims=1, n=[n_cells], dx_lambda=[1.0], ppc=ppc,
+                 x0_lambda=0.0, thickness_lambda=thick, Z=79, charge_state=79,
+                 ne_over_nc=4177.0, ncs=False, brem=True, frozen=True, frozen_kind=0,
+                 frozen_E=[0.0, 0.0, 0.0], frozen_B=[0.0, 0.0, 0.0], steps=steps, seed=9,
+                 photon_capacity=40_000_000, precision=precision, sort_every=-1,
+                 beam_energy_mev=energy_mev)
+
+
 def num_electrons(w):
     """Macro-electrons the recipe loads: slab cells times ppc."""
     dx = w["dx_lambda"][0]

@@ -21,13 +21,22 @@ def photon_table(ph):
     return {k: np.asarray(v)[order] for k, v in ph.items()}
 
 
-def compare(o, g, p_tol=P_TOL, label="", check_tau=True):
+def compare(o, g, p_tol=P_TOL, label="", check_tau=True, p_scale=None):
+    """p_scale: optional per-electron momentum scale (e.g. the |p| a beam
+    started with).  Recoil computes the new momentum from gamma - eps, a
+    difference of two numbers of the size of the old energy, so after an
+    emission that takes most of the energy the remaining momentum carries the
+    absolute rounding of the old one; momenta are then compared relative to
+    the larger of the two scales."""
     eo, eg = o.electrons(), g.electrons()
     rep = {}
     assert eo["x"].shape == eg["x"].shape, label
     assert np.array_equal(eo["alive"], eg["alive"]), f"{label}: alive masks differ at " \
         f"{np.nonzero(eo['alive'] != eg['alive'])[0][:10]}"
-    dpn = np.linalg.norm(eo["p"] - eg["p"], axis=1) / np.maximum(np.linalg.norm(eo["p"], axis=1), 1.0)
+    scale = np.maximum(np.linalg.norm(eo["p"], axis=1), 1.0)
+    if p_scale is not None:
+        scale = np.maximum(scale, np.asarray(p_scale))
+    dpn = np.linalg.norm(eo["p"] - eg["p"], axis=1) / scale
     dxn = np.linalg.norm(eo["x"] - eg["x"], axis=1) / np.maximum(np.linalg.norm(eo["x"], axis=1), 1.0)
     rep["max_dp"] = float(dpn.max()) if dpn.size else 0.0
     rep["max_dx"] = float(dxn.max()) if dxn.size else 0.0
