@@ -271,7 +271,7 @@ Plan make_plan(Ctx& c) {
   P.add(&c.cold, std::max(sizeof(StepCold<double>), sizeof(StepCold<float>)));
   // tables: FP64 and FP32 copies of the standard-size tables
   const size_t tb = (256 + 256 + 256 * 256 + 128 + 128 * 64);
-  P.total += tb * 12 + 10 * 256;
+  P.total += tb * 12 + 10 * 256 + 4 * (((256 + 128) * (kGuide + 1) + 255) & ~(size_t)255);
   return P;
 }
 
@@ -401,8 +401,10 @@ void fill_step_cold(const Ctx& c, StepCold<R>& C) {
   C.lnk = t.lnk;
   if (sizeof(R) == 8) {
     C.ncs = (const R*)t.ncs; C.lnxi = (const R*)t.lnxi; C.br = (const R*)t.br;
+    C.gncs = t.gncs; C.gbr = t.gbr;
   } else {
     C.ncs = (const R*)t.ncsf; C.lnxi = (const R*)t.lnxif; C.br = (const R*)t.brf;
+    C.gncs = t.gncsf; C.gbr = t.gbrf;
   }
   C.pcap = c.pcap;
   C.pe = (R*)c.pe;
@@ -712,6 +714,35 @@ pic_status pic_load_tables(pic_ctx* ctx, const pic_tables* t) {
   HIPCHK(c, upload(&d.ncs, &d.ncsf, t->ncs_cdf, (size_t)t->n_eta * t->n_xi));
   HIPCHK(c, upload(&d.sig, &d.sigf, t->sigma, t->n_T));
   HIPCHK(c, upload(&d.br, &d.brf, t->br_cdf, (size_t)t->n_T * t->n_y));
+  // row guides of the two CDF tables, from the values each precision compares
+  auto guides = [&](uint8_t** gd, uint8_t** gf, const double* rows, int nrow, int n) -> hipError_t {
+    const size_t ng = (size_t)nrow * (kGuide + 1);
+    if (!*gd) {
+      hipError_t e = hipMalloc((void**)gd, ng);
+      if (e != hipSuccess) return e;
+      c.allocs.push_back(*gd);
+      e = hipMalloc((void**)gf, ng);
+      if (e != hipSuccess) return e;
+      c.allocs.push_back(*gf);
+    }
+    std::vector<uint8_t> g8(ng), g4(ng);
+    for (int r = 0; r < nrow; ++r) {
+      const double* v = rows + (size_t)r * n;
+      int jd = 0, jf = 0;  // largest j <= n-2 with v[j] <= b/kGuide, as b grows
+      for (int b = 0; b <= kGuide; ++b) {
+        const double th = (double)b / kGuide;
+        while (jd + 1 <= n - 2 && v[jd + 1] <= th) ++jd;
+        while (jf + 1 <= n - 2 && (float)v[jf + 1] <= (float)th) ++jf;
+        g8[(size_t)r * (kGuide + 1) + b] = (uint8_t)jd;
+        g4[(size_t)r * (kGuide + 1) + b] = (uint8_t)jf;
+      }
+    }
+    hipError_t e = hipMemcpy(*gd, g8.data(), ng, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(*gf, g4.data(), ng, hipMemcpyHostToDevice);
+    return e;
+  };
+  HIPCHK(c, guides(&d.gncs, &d.gncsf, t->ncs_cdf, t->n_eta, t->n_xi));
+  HIPCHK(c, guides(&d.gbr, &d.gbrf, t->br_cdf, t->n_T, t->n_y));
   d.n_eta = t->n_eta; d.n_xi = t->n_xi; d.n_T = t->n_T; d.n_y = t->n_y;
   d.ln_eta0 = t->ln_eta0; d.idln_eta = 1.0 / t->dln_eta;
   d.ln_T0 = t->ln_T0; d.idln_T = 1.0 / t->dln_T;

@@ -58,11 +58,20 @@ struct FieldJob {
 };
 
 // Emission tables resident on the device (FP64 copy, FP32 copy).
+// Guide of an inverse-CDF row: kGuide + 1 entries, entry b is the largest
+// index j <= n - 2 with C[j] <= b / kGuide (0 if none).  A uniform u then has
+// its bracket (the largest j <= n - 2 with C[j] <= u) between entries
+// floor(u kGuide) and that + 1, plus one, so the search covers a few points
+// instead of the whole row and returns the same bracket.
+constexpr int kGuide = 64;
+
 struct DevTables {
   int n_eta = 0, n_xi = 0, n_T = 0, n_y = 0;
   double ln_eta0 = 0, idln_eta = 0, ln_T0 = 0, idln_T = 0, k_cut = 0, lnk = 0, iny1 = 0;
   double *h = nullptr, *lnxi = nullptr, *ncs = nullptr, *sig = nullptr, *br = nullptr;
   float *hf = nullptr, *lnxif = nullptr, *ncsf = nullptr, *sigf = nullptr, *brf = nullptr;
+  // guides of the CDF rows as compared in each precision (row-major, kGuide + 1 per row)
+  uint8_t *gncs = nullptr, *gncsf = nullptr, *gbr = nullptr, *gbrf = nullptr;
 };
 
 // Parameters the electron-step kernel needs only on rare paths (prescribed
@@ -79,6 +88,8 @@ struct StepCold {
   const R* ncs;
   const R* lnxi;
   const R* br;
+  const uint8_t* gncs;  // guides of the rows of ncs and br
+  const uint8_t* gbr;
   uint64_t pcap;
   R* px[3];
   R* pk[3];

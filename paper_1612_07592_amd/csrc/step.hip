@@ -227,9 +227,13 @@ __device__ inline float gather_q(const F& f, int c, const Splits& s) {
 
 // Inverse of one NCS cumulative row: ln(xi) at uniform u.
 template <class R>
-__device__ inline R ncs_inverse(const R* __restrict__ C, const R* __restrict__ lnxi, int n, R u) {
+__device__ inline R ncs_inverse(const R* __restrict__ C, const R* __restrict__ lnxi, int n, R u,
+                               const uint8_t* __restrict__ G) {
   if (u < C[0]) return lnxi[0] + R(3) * m_log(m_div(u, C[0]));
-  int lo = 0, hi = n - 1;
+  // bracket search between the row guide's entries (same bracket as a
+  // search over the whole row)
+  const int b = (int)(u * R(kGuide));
+  int lo = G[b], hi = min((int)G[b + 1] + 1, n - 1);
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
     if (C[mid] <= u) lo = mid; else hi = mid;
@@ -240,8 +244,10 @@ __device__ inline R ncs_inverse(const R* __restrict__ C, const R* __restrict__ l
 
 // Inverse of one bremsstrahlung cumulative row: scaled coordinate in [0,1].
 template <class R>
-__device__ inline R brem_inverse(const R* __restrict__ S, int n, R u, R iny1) {
-  int lo = 0, hi = n - 1;
+__device__ inline R brem_inverse(const R* __restrict__ S, int n, R u, R iny1,
+                                const uint8_t* __restrict__ G) {
+  const int b = (int)(u * R(kGuide));
+  int lo = G[b], hi = min((int)G[b + 1] + 1, n - 1);
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
     if (S[mid] <= u) lo = mid; else hi = mid;
@@ -642,8 +648,10 @@ __device__ inline void electron_physics(const StepParams<R>& P, int64_t e, uint3
         const int nxi = C->n_xi;
         const R* ncs = C->ncs;
         const R* lnxi = C->lnxi;
-        const R la = ncs_inverse<R>(ncs + (int64_t)i * nxi, lnxi, nxi, u2);
-        const R lb = ncs_inverse<R>(ncs + (int64_t)(i + 1) * nxi, lnxi, nxi, u2);
+        const uint8_t* gn = C->gncs;
+        const R la = ncs_inverse<R>(ncs + (int64_t)i * nxi, lnxi, nxi, u2, gn + i * (kGuide + 1));
+        const R lb = ncs_inverse<R>(ncs + (int64_t)(i + 1) * nxi, lnxi, nxi, u2,
+                                    gn + (i + 1) * (kGuide + 1));
         const R lx = la + f * (lb - la);
         const R xi = m_exp(lx);
         R eps = xi * gamma;
@@ -716,8 +724,10 @@ __device__ inline void electron_physics(const StepParams<R>& P, int64_t e, uint3
               const int ny = C->n_y;
               const R* br = C->br;
               const R iny1 = R(C->iny1);
-              const R sa = brem_inverse<R>(br + (int64_t)i * ny, ny, u, iny1);
-              const R sb = brem_inverse<R>(br + (int64_t)(i + 1) * ny, ny, u, iny1);
+              const uint8_t* gb = C->gbr;
+              const R sa = brem_inverse<R>(br + (int64_t)i * ny, ny, u, iny1, gb + i * (kGuide + 1));
+              const R sb = brem_inverse<R>(br + (int64_t)(i + 1) * ny, ny, u, iny1,
+                                           gb + (i + 1) * (kGuide + 1));
               const R sv = sa + f * (sb - sa);
               const R lk = R(C->lnk);
               R eps = m_exp(lk + sv * (lt - lk));
@@ -958,9 +968,12 @@ __device__ __forceinline__ void step_chunk(const StepParams<R>& P, const uint32_
   const unsigned long long m_br = __ballot(out.ev_br);
   const unsigned long long m_cl = __ballot(out.clamped);
   unsigned long long* C = cold(P)->slot_cnt + slot * kSlotCnt;
+  // the slot is this wave's alone; the counts go in as atomics whose result
+  // is not used, so the wave does not wait for a read of the old value
+  auto bump = [&](int k, unsigned long long v) { if (v) atomicAdd(C + k, v); };
   if (lane == 0) {
-    C[SC_ESTEPS] += (unsigned long long)__popcll(m_live);
-    if (!tiled && !frozen) C[SC_UNTILED] += (unsigned long long)__popcll(m_live);
+    bump(SC_ESTEPS, (unsigned long long)__popcll(m_live));
+    if (!tiled && !frozen) bump(SC_UNTILED, (unsigned long long)__popcll(m_live));
   }
   if ((m_ncs | m_br | m_cl) == 0ull) return;  // wave-uniform
   const unsigned long long m_keep = __ballot(rec0);
@@ -969,12 +982,12 @@ __device__ __forceinline__ void step_chunk(const StepParams<R>& P, const uint32_
   const double e_keep1 = out.ev_br ? wgt * (double)out.e[1] : 0.0;
   const double s0 = wave_sum(e_keep0), s1 = wave_sum(e_keep1), s2 = wave_sum(e_drop);
   if (lane == 0) {
-    C[SC_EV_NCS] += (unsigned long long)__popcll(m_ncs);
-    C[SC_EV_BR] += (unsigned long long)__popcll(m_br);
-    C[SC_KEPT_NCS] += (unsigned long long)__popcll(m_keep);
-    C[SC_KEPT_BR] += (unsigned long long)__popcll(m_br);
-    C[SC_DROPPED] += (unsigned long long)__popcll(m_ncs & ~m_keep);
-    C[SC_CLAMPED] += (unsigned long long)__popcll(m_cl);
+    bump(SC_EV_NCS, (unsigned long long)__popcll(m_ncs));
+    bump(SC_EV_BR, (unsigned long long)__popcll(m_br));
+    bump(SC_KEPT_NCS, (unsigned long long)__popcll(m_keep));
+    bump(SC_KEPT_BR, (unsigned long long)__popcll(m_br));
+    bump(SC_DROPPED, (unsigned long long)__popcll(m_ncs & ~m_keep));
+    bump(SC_CLAMPED, (unsigned long long)__popcll(m_cl));
     double* Sm = cold(P)->slot_sum + slot * kSlotSum;
     if (m_keep) neumaier(Sm + 0, Sm + 1, s0);
     if (m_br) neumaier(Sm + 2, Sm + 3, s1);
