@@ -85,6 +85,12 @@ struct GlobalCurrent32 {
     const int q = q32(v, scale);
     if (q != 0) atomicAdd(J[c] + l, (unsigned long long)((long long)q << shift));
   }
+  // v already in units of the quantum
+  __device__ inline float qscale() const { return scale; }
+  __device__ inline void addq(int c, int l, float v) const {
+    const int q = (int)rintf(v);
+    if (q != 0) atomicAdd(J[c] + l, (unsigned long long)((long long)q << shift));
+  }
 };
 
 struct LdsCurrent32 {
@@ -99,6 +105,8 @@ struct LdsCurrent32 {
   __device__ inline int s1() const { return e0; }
   __device__ inline int s2() const { return e0 * e1; }
   __device__ inline void add(int c, int l, float v) const { atomicAdd(T + c * nodes + l, q32(v, scale)); }
+  __device__ inline float qscale() const { return scale; }
+  __device__ inline void addq(int c, int l, float v) const { atomicAdd(T + c * nodes + l, (int)rintf(v)); }
 };
 
 // Field access: straight from the Yee arrays, or from the block's LDS box.
@@ -206,23 +214,27 @@ __device__ inline Splits make_splits(const int* q, const int* fb, const float* i
   return s;
 }
 
+// linear interpolation a + f (b - a) as one subtraction and one explicit fma
+// (the FP32 path only; its rounding is judged statistically)
+__device__ inline float lerp_f(float a, float b, float f) { return __builtin_fmaf(f, b - a, a); }
+
 template <int D, int SX, int SY, int SZ, class F>
 __device__ inline float gather_q(const F& f, int c, const Splits& s) {
   const float f0 = s.f[0][SX];
   const int l = f.lin(s.i[0][SX], D >= 2 ? s.i[1][SY] : 0, D == 3 ? s.i[2][SZ] : 0);
-  if (D == 1) return (1.f - f0) * f.at(c, l) + f0 * f.at(c, l + 1);
+  if (D == 1) return lerp_f(f.at(c, l), f.at(c, l + 1), f0);
   const float f1 = s.f[1][SY];
   const int s1 = f.s1();
-  const float v0 = (1.f - f0) * f.at(c, l) + f0 * f.at(c, l + 1);
-  const float v1 = (1.f - f0) * f.at(c, l + s1) + f0 * f.at(c, l + s1 + 1);
-  const float a2 = (1.f - f1) * v0 + f1 * v1;
+  const float v0 = lerp_f(f.at(c, l), f.at(c, l + 1), f0);
+  const float v1 = lerp_f(f.at(c, l + s1), f.at(c, l + s1 + 1), f0);
+  const float a2 = lerp_f(v0, v1, f1);
   if (D == 2) return a2;
   const float f2 = s.f[2][SZ];
   const int s2 = f.s2();
-  const float w0 = (1.f - f0) * f.at(c, l + s2) + f0 * f.at(c, l + s2 + 1);
-  const float w1 = (1.f - f0) * f.at(c, l + s2 + s1) + f0 * f.at(c, l + s2 + s1 + 1);
-  const float b2 = (1.f - f1) * w0 + f1 * w1;
-  return (1.f - f2) * a2 + f2 * b2;
+  const float w0 = lerp_f(f.at(c, l + s2), f.at(c, l + s2 + 1), f0);
+  const float w1 = lerp_f(f.at(c, l + s2 + s1), f.at(c, l + s2 + s1 + 1), f0);
+  const float b2 = lerp_f(w0, w1, f1);
+  return lerp_f(a2, b2, f2);
 }
 
 // Inverse of one NCS cumulative row: ln(xi) at uniform u.
@@ -283,7 +295,8 @@ __device__ inline void shape3(int cell, float f, int m, float S[3]) {
 template <int D, class Acc>
 __device__ inline void deposit3(const StepParams<float>& P, const Acc& J, const int* q0,
                                 const int* q1, const float* v, double w) {
-  const float c0 = (float)(-w * P.invV);
+  // contributions in units of the current quantum
+  const float c0 = (float)(-w * P.invV) * J.qscale();
   float S0[3][3], S1[3][3];
   int m[3] = {0, 0, 0};
 #pragma unroll
@@ -299,89 +312,88 @@ __device__ inline void deposit3(const StepParams<float>& P, const Acc& J, const 
   // node (m0 + i, m1 + j, m2 + k) is base + i + j s1 + k s2
   const int base = J.lin(m[0], m[1], m[2]);
   const int s1 = J.s1(), s2 = J.s2();
+  // Per axis a: the flux through the first two window faces, F[a][i] = -q_a
+  // (d_0 + ... + d_i) with d = S1 - S0 (the Esirkepov prefix sum), and the
+  // factors G = (2 S0 + S1) / 6, H = (S0 + 2 S1) / 6, with which the mixed
+  // weight (S0a S0b + S1a S1b) / 3 + (S0a S1b + S1a S0b) / 6 of two axes is
+  // G[a] S0[b] + H[a] S1[b].
   if (D == 1) {
     const float qx = c0 * (float)P.dxdt[0];
-    float acc = 0.f;
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      acc = acc - qx * (S1[0][i] - S0[0][i]);
-      J.add(0, base + i, acc);
-    }
-    const float cy = c0 * v[1], cz = c0 * v[2];
+    const float F0 = -qx * (S1[0][0] - S0[0][0]);
+    const float F1 = F0 - qx * (S1[0][1] - S0[0][1]);
+    J.addq(0, base, F0);
+    J.addq(0, base + 1, F1);
+    const float cy = 0.5f * c0 * v[1], cz = 0.5f * c0 * v[2];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      const float sa = 0.5f * (S0[0][i] + S1[0][i]);
-      J.add(1, base + i, cy * sa);
-      J.add(2, base + i, cz * sa);
+      const float sa = S0[0][i] + S1[0][i];
+      J.addq(1, base + i, cy * sa);
+      J.addq(2, base + i, cz * sa);
     }
   } else if (D == 2) {
-    const float qx = c0 * (float)P.dxdt[0], qy = c0 * (float)P.dxdt[1], cz = c0 * v[2];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      float acc = 0.f;
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        acc = acc - qx * (0.5f * (S1[0][i] - S0[0][i]) * (S0[1][j] + S1[1][j]));
-        J.add(0, base + i + j * s1, acc);
-      }
-    }
+    const float qx = 0.5f * c0 * (float)P.dxdt[0], qy = 0.5f * c0 * (float)P.dxdt[1];
+    const float cz = c0 * v[2] * (1.f / 6.f);
+    float Fx[2], Fy[2], sx[3], sy[3], G[3], H[3];
+    Fx[0] = -qx * (S1[0][0] - S0[0][0]);
+    Fx[1] = Fx[0] - qx * (S1[0][1] - S0[0][1]);
+    Fy[0] = -qy * (S1[1][0] - S0[1][0]);
+    Fy[1] = Fy[0] - qy * (S1[1][1] - S0[1][1]);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      float acc = 0.f;
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        acc = acc - qy * (0.5f * (S0[0][i] + S1[0][i]) * (S1[1][j] - S0[1][j]));
-        J.add(1, base + i + j * s1, acc);
-      }
+      sx[i] = S0[0][i] + S1[0][i];
+      sy[i] = S0[1][i] + S1[1][i];
+      G[i] = cz * __builtin_fmaf(2.f, S0[0][i], S1[0][i]);
+      H[i] = cz * __builtin_fmaf(2.f, S1[0][i], S0[0][i]);
     }
 #pragma unroll
     for (int j = 0; j < 3; ++j)
 #pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        const float W = (S0[0][i] * S0[1][j] + S1[0][i] * S1[1][j]) * (1.f / 3.f) +
-                        (S0[0][i] * S1[1][j] + S1[0][i] * S0[1][j]) * (1.f / 6.f);
-        J.add(2, base + i + j * s1, cz * W);
-      }
+      for (int i = 0; i < 2; ++i) J.addq(0, base + i + j * s1, Fx[i] * sy[j]);
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) J.addq(1, base + i + j * s1, Fy[j] * sx[i]);
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        J.addq(2, base + i + j * s1, __builtin_fmaf(G[i], S0[1][j], H[i] * S1[1][j]));
   } else {
-    const float qx = c0 * (float)P.dxdt[0], qy = c0 * (float)P.dxdt[1], qz = c0 * (float)P.dxdt[2];
+    float F[3][2], G[3][3], H[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float qa = c0 * (float)P.dxdt[a];
+      F[a][0] = -qa * (S1[a][0] - S0[a][0]);
+      F[a][1] = F[a][0] - qa * (S1[a][1] - S0[a][1]);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        G[a][i] = (1.f / 6.f) * __builtin_fmaf(2.f, S0[a][i], S1[a][i]);
+        H[a][i] = (1.f / 6.f) * __builtin_fmaf(2.f, S1[a][i], S0[a][i]);
+      }
+    }
 #pragma unroll
     for (int k = 0; k < 3; ++k)
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
-        const float T = (S0[1][j] * S0[2][k] + S1[1][j] * S1[2][k]) * (1.f / 3.f) +
-                        (S1[1][j] * S0[2][k] + S0[1][j] * S1[2][k]) * (1.f / 6.f);
-        float acc = 0.f;
+        const float T = __builtin_fmaf(G[1][j], S0[2][k], H[1][j] * S1[2][k]);
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          acc = acc - qx * ((S1[0][i] - S0[0][i]) * T);
-          J.add(0, base + i + j * s1 + k * s2, acc);
-        }
+        for (int i = 0; i < 2; ++i) J.addq(0, base + i + j * s1 + k * s2, F[0][i] * T);
       }
 #pragma unroll
     for (int k = 0; k < 3; ++k)
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        const float T = (S0[0][i] * S0[2][k] + S1[0][i] * S1[2][k]) * (1.f / 3.f) +
-                        (S1[0][i] * S0[2][k] + S0[0][i] * S1[2][k]) * (1.f / 6.f);
-        float acc = 0.f;
+        const float T = __builtin_fmaf(G[0][i], S0[2][k], H[0][i] * S1[2][k]);
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          acc = acc - qy * ((S1[1][j] - S0[1][j]) * T);
-          J.add(1, base + i + j * s1 + k * s2, acc);
-        }
+        for (int j = 0; j < 2; ++j) J.addq(1, base + i + j * s1 + k * s2, F[1][j] * T);
       }
 #pragma unroll
     for (int j = 0; j < 3; ++j)
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        const float T = (S0[0][i] * S0[1][j] + S1[0][i] * S1[1][j]) * (1.f / 3.f) +
-                        (S1[0][i] * S0[1][j] + S0[0][i] * S1[1][j]) * (1.f / 6.f);
-        float acc = 0.f;
+        const float T = __builtin_fmaf(G[0][i], S0[1][j], H[0][i] * S1[1][j]);
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
-          acc = acc - qz * ((S1[2][k] - S0[2][k]) * T);
-          J.add(2, base + i + j * s1 + k * s2, acc);
-        }
+        for (int k = 0; k < 2; ++k) J.addq(2, base + i + j * s1 + k * s2, F[2][k] * T);
       }
   }
 }
@@ -855,8 +867,16 @@ __device__ __forceinline__ void step_chunk(const StepParams<R>& P, const uint32_
     tiled = nodes <= P.lds_nodes;
   }
   constexpr bool kFL = FieldsInLds<R, D>::value;
+  // 1D/2D boxes too large for fields + current may still fit the current
+  // alone in the same allocation (three times the nodes): fields are then
+  // gathered from global memory, the current still accumulates in LDS
+  bool jtiled = false;
+  if constexpr (kFL) {
+    const int jcap = (int)((size_t)P.lds_nodes * lds_bytes_per_node<R, D>() / (3 * sizeof(JT)));
+    jtiled = !tiled && nodes > 0 && nodes <= jcap;
+  }
   R* sF = reinterpret_cast<R*>(smem);
-  JT* sJ = reinterpret_cast<JT*>(smem + (kFL ? (size_t)6 * P.lds_nodes * sizeof(R) : 0));
+  JT* sJ = reinterpret_cast<JT*>(smem + (kFL && tiled ? (size_t)6 * P.lds_nodes * sizeof(R) : 0));
   const Idx<R> I{P.gg[0], P.gg[1], P.gg[2], P.sz[0], P.sz[1]};
   // node l of the box -> (i, j, k); exact float-reciprocal division (l < 2^20)
   const float r0 = 1.0f / (float)ext[0], r1 = 1.0f / (float)ext[1];
@@ -882,6 +902,8 @@ __device__ __forceinline__ void step_chunk(const StepParams<R>& P, const uint32_
         sJ[c * nodes + l] = JT(0);
       }
     }
+  } else if (jtiled) {
+    for (int l = t; l < 3 * nodes; l += kBlock) sJ[l] = JT(0);
   }
   __syncthreads();
 
@@ -893,6 +915,16 @@ __device__ __forceinline__ void step_chunk(const StepParams<R>& P, const uint32_
       FA fa;
       if constexpr (kFL) fa = LdsField<R>{sF, lo[0], lo[1], lo[2], ext[0], ext[1], nodes};
       else fa = GlobalField<R>{P.F, I};
+      if constexpr (kF32) {
+        const LdsCurrent32 ja{reinterpret_cast<int*>(sJ), lo[0], lo[1], lo[2], ext[0], ext[1], nodes,
+                              (float)ldexp(1.0, P.jbits)};
+        electron_physics<R, D>(P, e, idv, wgt, x, q, pin, tau_in, fa, ja, out);
+      } else {
+        const LdsCurrent ja{reinterpret_cast<unsigned long long*>(sJ), lo[0], lo[1], lo[2], ext[0], ext[1], nodes};
+        electron_physics<R, D>(P, e, idv, wgt, x, q, pin, tau_in, fa, ja, out);
+      }
+    } else if (jtiled) {
+      const GlobalField<R> fa{P.F, I};
       if constexpr (kF32) {
         const LdsCurrent32 ja{reinterpret_cast<int*>(sJ), lo[0], lo[1], lo[2], ext[0], ext[1], nodes,
                               (float)ldexp(1.0, P.jbits)};
@@ -914,7 +946,7 @@ __device__ __forceinline__ void step_chunk(const StepParams<R>& P, const uint32_
     }
   }
   __syncthreads();
-  if (tiled) {  // flush the LDS current: one global atomic per touched node
+  if (tiled || jtiled) {  // flush the LDS current: one global atomic per touched node
     for (int l = t; l < nodes; l += kBlock) {
       int i, j, k;
       decode(l, i, j, k);
@@ -973,7 +1005,7 @@ __device__ __forceinline__ void step_chunk(const StepParams<R>& P, const uint32_
   auto bump = [&](int k, unsigned long long v) { if (v) atomicAdd(C + k, v); };
   if (lane == 0) {
     bump(SC_ESTEPS, (unsigned long long)__popcll(m_live));
-    if (!tiled && !frozen) bump(SC_UNTILED, (unsigned long long)__popcll(m_live));
+    if (!tiled && !jtiled && !frozen) bump(SC_UNTILED, (unsigned long long)__popcll(m_live));
   }
   if ((m_ncs | m_br | m_cl) == 0ull) return;  // wave-uniform
   const unsigned long long m_keep = __ballot(rec0);
