@@ -7,6 +7,18 @@
 namespace pic {
 
 
+// Multiplier and shift for division by d of any n < 2^31: s = 31 + ceil(log2
+// d), mg = floor(2^s / d) + 1 < 2^32.  With mg d = 2^s + e, 0 < e <= d,
+// n mg / 2^s = n / d + n e / (d 2^s) and n e / (d 2^s) < 2^31 / 2^s <= 1 / d,
+// which never reaches the next multiple of 1 / d above n / d, so the floor is
+// floor(n / d) (division by invariant integers, Granlund and Montgomery 1994).
+static void div_magic(uint32_t d, uint32_t& mg, int& sh) {
+  int l = 0;
+  while ((1ull << l) < d) ++l;
+  sh = 31 + l;
+  mg = (uint32_t)((1ull << sh) / d + 1);
+}
+
 static FieldArgs field_args(const Grid& g) {
   FieldArgs a{};
   for (int d = 0; d < 3; ++d) {
@@ -18,18 +30,23 @@ static FieldArgs field_args(const Grid& g) {
   a.i_src = g.i_src;
   a.nsrc_y = g.nsrc_y;
   a.nfield = g.nfield;
+  div_magic((uint32_t)g.sz[0], a.mg0, a.sh0);
+  div_magic((uint32_t)g.sz[1], a.mg1, a.sh1);
   return a;
 }
 
+// (32-bit arithmetic: the field arrays hold fewer than 2^31 nodes)
 __device__ inline int64_t fidx(const FieldArgs& A, int i, int j, int k) {
-  return (int64_t)(i + A.gg[0]) + (int64_t)A.sz[0] * ((int64_t)(j + A.gg[1]) + (int64_t)A.sz[1] * (int64_t)(k + A.gg[2]));
+  return (int64_t)((i + A.gg[0]) + A.sz[0] * ((j + A.gg[1]) + A.sz[1] * (k + A.gg[2])));
 }
 
 __device__ inline void decode(const FieldArgs& A, int64_t m, int& i, int& j, int& k) {
-  i = (int)(m % A.sz[0]) - A.gg[0];
-  const int64_t r = m / A.sz[0];
-  j = (int)(r % A.sz[1]) - A.gg[1];
-  k = (int)(r / A.sz[1]) - A.gg[2];
+  const uint32_t mm = (uint32_t)m;
+  const uint32_t r = (uint32_t)(((uint64_t)mm * A.mg0) >> A.sh0);
+  const uint32_t q = (uint32_t)(((uint64_t)r * A.mg1) >> A.sh1);
+  i = (int)(mm - r * (uint32_t)A.sz[0]) - A.gg[0];
+  j = (int)(r - q * (uint32_t)A.sz[1]) - A.gg[1];
+  k = (int)q - A.gg[2];
 }
 
 // half-integer stagger of E_c / B_c along axis a
@@ -59,22 +76,23 @@ __device__ __forceinline__ void b_half_node(const FieldArgs& A, const R* __restr
   if (zeroJ) { Jx[m] = 0ull; Jy[m] = 0ull; Jz[m] = 0ull; }
   int i, j, k;
   decode(A, m, i, j, k);
+  const int64_t s1 = A.sz[0], s2 = (int64_t)A.sz[0] * A.sz[1];  // +1 along y, z
   if (in_range(A, true, 0, i, j, k)) {  // dBx/dt = -dEz/dy + dEy/dz
     R b = Bx[m];
-    if (A.act[1]) b = b - R(A.hd[1]) * (Ez[fidx(A, i, j + 1, k)] - Ez[m]);
-    if (A.act[2]) b = b + R(A.hd[2]) * (Ey[fidx(A, i, j, k + 1)] - Ey[m]);
+    if (A.act[1]) b = b - R(A.hd[1]) * (Ez[m + s1] - Ez[m]);
+    if (A.act[2]) b = b + R(A.hd[2]) * (Ey[m + s2] - Ey[m]);
     Bx[m] = b;
   }
   if (in_range(A, true, 1, i, j, k)) {  // dBy/dt = -dEx/dz + dEz/dx
     R b = By[m];
-    if (A.act[2]) b = b - R(A.hd[2]) * (Ex[fidx(A, i, j, k + 1)] - Ex[m]);
-    b = b + R(A.hd[0]) * (Ez[fidx(A, i + 1, j, k)] - Ez[m]);
+    if (A.act[2]) b = b - R(A.hd[2]) * (Ex[m + s2] - Ex[m]);
+    b = b + R(A.hd[0]) * (Ez[m + 1] - Ez[m]);
     By[m] = b;
   }
   if (in_range(A, true, 2, i, j, k)) {  // dBz/dt = -dEy/dx + dEx/dy
     R b = Bz[m];
-    b = b - R(A.hd[0]) * (Ey[fidx(A, i + 1, j, k)] - Ey[m]);
-    if (A.act[1]) b = b + R(A.hd[1]) * (Ex[fidx(A, i, j + 1, k)] - Ex[m]);
+    b = b - R(A.hd[0]) * (Ey[m + 1] - Ey[m]);
+    if (A.act[1]) b = b + R(A.hd[1]) * (Ex[m + s1] - Ex[m]);
     Bz[m] = b;
   }
 }
@@ -85,25 +103,26 @@ template <class R>
 __device__ inline R e_interior(const FieldArgs& A, const EPtrs& P, int c, int i, int j, int k,
                                double lsin, double lcos) {
   const int64_t m = fidx(A, i, j, k);
+  const int64_t s1 = A.sz[0], s2 = (int64_t)A.sz[0] * A.sz[1];  // -1 along y, z
   const R* Bx = (const R*)P.B[0];
   const R* By = (const R*)P.B[1];
   const R* Bz = (const R*)P.B[2];
   R e = ((const R*)P.E[c])[m];
   double jj = (double)(long long)P.J[c][m] * kJInv;
   if (c == 0) {        // dEx/dt = dBz/dy - dBy/dz - Jx
-    if (A.act[1]) e = e + R(A.cd[1]) * (Bz[m] - Bz[fidx(A, i, j - 1, k)]);
-    if (A.act[2]) e = e - R(A.cd[2]) * (By[m] - By[fidx(A, i, j, k - 1)]);
+    if (A.act[1]) e = e + R(A.cd[1]) * (Bz[m] - Bz[m - s1]);
+    if (A.act[2]) e = e - R(A.cd[2]) * (By[m] - By[m - s2]);
   } else if (c == 1) { // dEy/dt = dBx/dz - dBz/dx - Jy
-    if (A.act[2]) e = e + R(A.cd[2]) * (Bx[m] - Bx[fidx(A, i, j, k - 1)]);
-    e = e - R(A.cd[0]) * (Bz[m] - Bz[fidx(A, i - 1, j, k)]);
+    if (A.act[2]) e = e + R(A.cd[2]) * (Bx[m] - Bx[m - s2]);
+    e = e - R(A.cd[0]) * (Bz[m] - Bz[m - 1]);
     if (i == A.i_src) {
       const int64_t s = j + (int64_t)A.nsrc_y * k;
       const double v = lsin * P.srcC[s] + lcos * P.srcS[s];
       jj = jj + A.srcfac * (P.srcA[s] * v);
     }
   } else {             // dEz/dt = dBy/dx - dBx/dy - Jz
-    e = e + R(A.cd[0]) * (By[m] - By[fidx(A, i - 1, j, k)]);
-    if (A.act[1]) e = e - R(A.cd[1]) * (Bx[m] - Bx[fidx(A, i, j - 1, k)]);
+    e = e + R(A.cd[0]) * (By[m] - By[m - 1]);
+    if (A.act[1]) e = e - R(A.cd[1]) * (Bx[m] - Bx[m - s1]);
   }
   return e - R(A.dt * jj);
 }

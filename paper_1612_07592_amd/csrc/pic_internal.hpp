@@ -38,6 +38,11 @@ struct FieldArgs {
   double hd[3], cd[3], cm[3], dt, srcfac;
   int i_src, nsrc_y;
   int64_t nfield;
+  // node index -> (i, j, k) by multiply-shift division (nfield < 2^31):
+  // q = (n * mg) >> sh equals n / d for every n < 2^31, d = sz[0] (mg0, sh0)
+  // and d = sz[1] (mg1, sh1)
+  uint32_t mg0, mg1;
+  int sh0, sh1;
 };
 
 struct EPtrs {
