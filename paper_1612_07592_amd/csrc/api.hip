@@ -186,15 +186,22 @@ std::string derive(const pic_config& cfg, Ctx& c) {
   if (const char* v = getenv("PIC_TUNE_LDS_NODES")) c.lds_nodes = atoi(v) & ~1;
   int tile_edge = tiles[g.dims];
   if (const char* v = getenv("PIC_TUNE_TILE")) tile_edge = atoi(v) > 0 ? atoi(v) : tile_edge;
-  int ntl[3] = {1, 1, 1}, bits = 0;
+  // tile keys: Morton order over the bits all axes share, the extra high
+  // bits of the longer axes on top, so a 2:1 grid of tiles needs 2^(bx+by)
+  // keys rather than the 2^(2 bx) of a square Morton range
+  int ntl[3] = {1, 1, 1}, bits[3] = {0, 0, 0}, bmin = 31, btot = 0;
   for (int a = 0; a < g.dims; ++a) {
     c.tile[a] = tile_edge;
     ntl[a] = (g.n[a] + c.tile[a] - 1) / c.tile[a];
-    while ((1 << bits) < ntl[a]) ++bits;
+    while ((1 << bits[a]) < ntl[a]) ++bits[a];
+    bmin = std::min(bmin, bits[a]);
+    btot += bits[a];
   }
+  c.key_mbits = g.dims == 1 ? 0 : bmin;
+  for (int a = 0; a < 3; ++a) c.key_hb[a] = a < g.dims ? bits[a] - c.key_mbits : 0;
   if (g.dims == 1) c.nkeys = (uint32_t)ntl[0] + 1;
-  else if (g.dims == 2) { if (bits > 15) return "grid too large for the tile sort"; c.nkeys = (1u << (2 * bits)) + 1; }
-  else { if (bits > 9) return "grid too large for the tile sort"; c.nkeys = (1u << (3 * bits)) + 1; }
+  else if (btot > 30 || bmin > (g.dims == 2 ? 15 : 10)) return "grid too large for the tile sort";
+  else c.nkeys = (1u << btot) + 1;
   return "";
 }
 
@@ -449,6 +456,8 @@ SortArgs sort_args(const Ctx& c) {
     A.x[a] = c.x[a]; A.p[a] = c.p[a]; A.x2[a] = c.x2[a]; A.p2[a] = c.p2[a];
   }
   A.nkeys = c.nkeys;
+  A.mbits = c.key_mbits;
+  for (int a = 0; a < 3; ++a) A.hb[a] = c.key_hb[a];
   A.tau = c.tau; A.w = c.w; A.id = c.id;
   A.tau2 = c.tau2; A.w2 = c.w2; A.id2 = c.id2;
   A.taub = c.taub; A.taub2 = c.taub2;

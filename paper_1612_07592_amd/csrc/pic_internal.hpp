@@ -160,7 +160,11 @@ struct SortArgs {
   int n[3], tile[3];
   double idx[3];
   int fb[3];                // FP32 fixed-point positions: cell = q >> fb
-  uint32_t nkeys;           // Morton keys of the tiles + 1 bucket for absorbed electrons
+  uint32_t nkeys;           // keys of the tiles + 1 bucket for absorbed electrons
+  // tile key: the low mbits bits of every axis interleaved (Morton order),
+  // the remaining hb[a] high bits of each axis above them
+  int mbits;
+  int hb[3];
   const void* x[3];
   const void* p[3];
   const double* tau;
@@ -246,6 +250,8 @@ struct Ctx {
   int sort_every = 0;
   int tile[3] = {1, 1, 1};
   uint32_t nkeys = 0;
+  int key_mbits = 0;
+  int key_hb[3] = {0, 0, 0};
   void* x2[3] = {};
   void* p2[3] = {};
   double* tau2 = nullptr;

@@ -84,9 +84,16 @@ __global__ __launch_bounds__(kBlock) void k_sort_key(SortArgs A) {
         c = c < 0 ? 0 : (c >= A.n[a] ? A.n[a] - 1 : c);
         tt[a] = (uint32_t)(c / A.tile[a]);
       }
-      if (A.dims == 1) key = tt[0];
-      else if (A.dims == 2) key = spread2(tt[0]) | (spread2(tt[1]) << 1);
-      else key = spread3(tt[0]) | (spread3(tt[1]) << 1) | (spread3(tt[2]) << 2);
+      if (A.dims == 1) {
+        key = tt[0];
+      } else {
+        const uint32_t lm = (1u << A.mbits) - 1u;
+        const uint32_t hi = (tt[0] >> A.mbits) | ((tt[1] >> A.mbits) << A.hb[0]) |
+                            ((tt[2] >> A.mbits) << (A.hb[0] + A.hb[1]));
+        if (A.dims == 2) key = (hi << (2 * A.mbits)) | spread2(tt[0] & lm) | (spread2(tt[1] & lm) << 1);
+        else key = (hi << (3 * A.mbits)) | spread3(tt[0] & lm) | (spread3(tt[1] & lm) << 1) |
+                   (spread3(tt[2] & lm) << 2);
+      }
     }
     A.key[e] = key;
     uint32_t rank;
@@ -97,8 +104,9 @@ __global__ __launch_bounds__(kBlock) void k_sort_key(SortArgs A) {
     if (hkey[i] != kEmpty) atomicAdd(A.count + hkey[i], hcnt[i]);
 }
 
-// Exclusive scan of count[0..nkeys) into offset and cursor, in three passes:
-// segments of kSeg keys per workgroup, the segment totals, then the fix-up.
+// Exclusive scan of count[0..nkeys) into offset and cursor, in two passes:
+// segments of kSeg keys per workgroup, then a fix-up in which each
+// workgroup adds the sum of the totals of the segments before its own.
 constexpr int kSeg = 4096;                 // 256 threads x 16 keys
 constexpr int kPerThread = kSeg / kBlock;
 
@@ -135,32 +143,16 @@ __global__ __launch_bounds__(kBlock) void k_scan_segments(SortArgs A, uint32_t* 
   if (t == kBlock - 1) btot[blockIdx.x] = part[t];
 }
 
-__global__ __launch_bounds__(1024) void k_scan_totals(uint32_t* btot, int nseg) {
-  __shared__ uint32_t part[1024];
-  const int t = threadIdx.x;
-  const int per = (nseg + 1023) / 1024;
-  const int lo = t * per, hi = min(nseg, lo + per);
-  uint32_t s = 0;
-  for (int k = lo; k < hi; ++k) s += btot[k];
-  part[t] = s;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    const uint32_t u = t >= o ? part[t - o] : 0u;
-    __syncthreads();
-    part[t] += u;
-    __syncthreads();
-  }
-  uint32_t run = t == 0 ? 0u : part[t - 1];
-  for (int k = lo; k < hi; ++k) {
-    const uint32_t c = btot[k];
-    btot[k] = run;
-    run += c;
-  }
-}
-
 __global__ __launch_bounds__(kBlock) void k_scan_fixup(SortArgs A, const uint32_t* btot) {
+  __shared__ uint32_t part[kBlock / 64];
   const int64_t k0 = (int64_t)blockIdx.x * kSeg;
-  const uint32_t add = btot[blockIdx.x];
+  uint32_t s = 0;
+  for (int b = threadIdx.x; b < (int)blockIdx.x; b += kBlock) s += btot[b];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+  __syncthreads();
+  uint32_t add = 0;
+  for (int w = 0; w < kBlock / 64; ++w) add += part[w];
   for (int q = threadIdx.x; q < kSeg; q += kBlock) {
     const int64_t k = k0 + q;
     if (k < A.nkeys) {
@@ -230,7 +222,6 @@ void launch_sort(const SortArgs& A, bool fp32, hipStream_t s) {
   const int nseg = (int)(((int64_t)A.nkeys + kSeg - 1) / kSeg);
   uint32_t* btot = A.cursor + A.nkeys;  // nseg scratch words after the cursors
   hipLaunchKernelGGL(k_scan_segments, dim3(nseg), dim3(kBlock), 0, s, A, btot);
-  hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, s, btot, nseg);
   hipLaunchKernelGGL(k_scan_fixup, dim3(nseg), dim3(kBlock), 0, s, A, btot);
   if (fp32) hipLaunchKernelGGL(k_sort_scatter<float>, dim3(blocks), dim3(kBlock), 0, s, A);
   else hipLaunchKernelGGL(k_sort_scatter<double>, dim3(blocks), dim3(kBlock), 0, s, A);
