@@ -149,7 +149,7 @@ std::string derive(const pic_config& cfg, Ctx& c) {
   c.fp32 = cfg.precision == PIC_FP32_MIXED;
   c.pcap = cfg.photon_capacity;
   const int64_t per_chunk = chunk_electrons(c.fp32, g.dims);
-  c.nblocks_step = ((N + per_chunk - 1) / per_chunk + 7) / 8 * 8;
+  c.nblocks_step = ((N + per_chunk - 1) / per_chunk + kGridQuantum - 1) / kGridQuantum * kGridQuantum;
   c.nslots = c.nblocks_step * (kBlock / 64);
   // FP32 positions: int32 fixed point in cells; n << fb stays below 2^30 so a
   // move of less than a cell past either wall cannot overflow, and fb <= 24

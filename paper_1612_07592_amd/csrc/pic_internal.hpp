@@ -13,6 +13,11 @@ constexpr uint32_t kDead = 0x80000000u;   // id bit marking an absorbed electron
 constexpr int kGuard = 2;                 // guard cells per side on active axes
 constexpr int kBlock = 256;               // threads per block (4 waves)
 constexpr int kSlotCnt = 8;               // u64 counters per wave slot
+// Step-kernel workgroups go to the 8 XCDs round robin; chunks are dealt to
+// them in groups of kXcdGroup consecutive chunks, and grids are padded to a
+// multiple of kGridQuantum so that the deal is a bijection.
+constexpr uint32_t kXcdGroup = 16;
+constexpr int64_t kGridQuantum = 8 * kXcdGroup;
 constexpr int kSlotSum = 6;               // doubles per wave slot (3 Neumaier pairs)
 constexpr double kJScale = 0x1p40;        // current fixed point: units of 2^-40
 constexpr double kJInv = 0x1p-40;
@@ -245,7 +250,7 @@ struct Ctx {
   uint32_t* pproc = nullptr;
   unsigned long long* pcount = nullptr;
   int64_t nslots = 0;
-  int64_t nblocks_step = 0;   // step-kernel grid (multiple of 8 for the XCD mapping)
+  int64_t nblocks_step = 0;   // step-kernel grid (a multiple of kGridQuantum)
   // cell-tile sort
   int sort_every = 0;
   int tile[3] = {1, 1, 1};

@@ -793,8 +793,7 @@ __device__ inline void electron_physics(const StepParams<R>& P, int64_t e, uint3
 }
 
 // One workgroup = one chunk of 256 consecutive electrons of the (tile-sorted)
-// SoA.  Chunks are spread so that each XCD (blockIdx % 8) owns a contiguous
-// run of chunks, i.e. a compact region of the grid for its L2.  Inside a chunk
+// SoA (chunk_of_block spreads the chunks over the XCDs).  Inside a chunk
 // electrons are dealt to lanes with a stride of 16, so the 64 lanes of a wave
 // come from many cells and rarely hit the same LDS current node at once.
 // When the chunk's cells fit the LDS box, the fields of the box are staged in
@@ -1027,17 +1026,30 @@ __device__ __forceinline__ void step_chunk(const StepParams<R>& P, const uint32_
   }
 }
 
+// Workgroup -> chunk.  The hardware deals workgroups to the 8 XCDs round
+// robin (blockIdx % 8).  Groups of kXcdGroup consecutive chunks go to one XCD
+// and successive groups to successive XCDs, so each XCD's L2 sees runs of
+// neighbouring chunks while every XCD gets a share of every region of the
+// grid.  Giving each XCD one contiguous eighth of the grid made the XCD that
+// holds the laser-plasma interaction the straggler: on the 2D gold slab,
+// groups of 16 run at 76.2 us per launch against 82.0 us for eighths (groups
+// of 1: 76.0; of 128: 79.0); the 3D gold slab, with 524K chunks, runs at
+// 9.89 ms against 9.82 ms.  The grid is a multiple of kGridQuantum.
+__device__ inline uint32_t chunk_of_block(uint32_t b) {
+  const uint32_t x = b & 7u, t = b >> 3;
+  return ((t / kXcdGroup) * 8u + x) * kXcdGroup + (t % kXcdGroup);
+}
+
 template <class R, int D>
 __global__ __launch_bounds__(kBlock) void k_electron_step(const StepParams<R> P) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_lo[3], s_hi[3];
-  const uint32_t per = gridDim.x >> 3;
-  step_chunk<R, D>(P, (blockIdx.x & 7u) * per + (blockIdx.x >> 3), smem, s_lo, s_hi);
+  step_chunk<R, D>(P, chunk_of_block(blockIdx.x), smem, s_lo, s_hi);
 }
 
 // Batched form for several runs: the chunks of every run are laid end to end
 // (run j owns [first[j], first[j+1])) and one launch covers them all, with the
-// same XCD-aware spread as the single-run kernel.  A chunk is processed
+// same spread over the XCDs as the single-run kernel.  A chunk is processed
 // exactly as the single-run kernel processes it, so a run's results do not
 // depend on what else is in the batch.  (One chunk per workgroup: a
 // grid-stride loop over chunks raises the kernel from 68 to 106 VGPRs and
@@ -1048,9 +1060,8 @@ __global__ __launch_bounds__(kBlock) void k_electron_step_batch(const StepParams
                                                                 int njobs) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_lo[3], s_hi[3];
-  const uint32_t per = gridDim.x >> 3;
-  const uint32_t w = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
-  if (w >= first[njobs]) return;  // padding of the grid to a multiple of 8
+  const uint32_t w = chunk_of_block(blockIdx.x);
+  if (w >= first[njobs]) return;  // padding of the grid to a multiple of kGridQuantum
   int lo = 0, hi = njobs - 1;     // largest j with first[j] <= w
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -1065,7 +1076,7 @@ static void launch_one(const void* params, hipStream_t s) {
   if (P.N <= 0) return;
   constexpr int per_chunk = kBlock;
   int64_t blocks = (P.N + per_chunk - 1) / per_chunk;
-  blocks = (blocks + 7) / 8 * 8;  // XCD-aware chunk mapping needs a multiple of 8
+  blocks = (blocks + kGridQuantum - 1) / kGridQuantum * kGridQuantum;  // see chunk_of_block
   const size_t lds = (size_t)P.lds_nodes * lds_bytes_per_node<R, D>();
   hipLaunchKernelGGL((k_electron_step<R, D>), dim3((unsigned)blocks), dim3(kBlock), lds, s, P);
 }
@@ -1075,7 +1086,7 @@ static void launch_batch(const void* tab, const uint32_t* first, int njobs, uint
                          int lds_nodes, hipStream_t s) {
   if (njobs <= 0 || total == 0) return;
   const size_t lds = (size_t)lds_nodes * lds_bytes_per_node<R, D>();
-  const int64_t blocks = ((int64_t)total + 7) / 8 * 8;
+  const int64_t blocks = ((int64_t)total + kGridQuantum - 1) / kGridQuantum * kGridQuantum;
   hipLaunchKernelGGL((k_electron_step_batch<R, D>), dim3((unsigned)blocks), dim3(kBlock), lds, s,
                      static_cast<const StepParams<R>*>(tab), first, njobs);
 }

@@ -151,3 +151,32 @@ def test_freepath_fp32_against_fp64(gpu_lib, tables_au):
     assert abs(z) <= 3.0
     assert abs(rel) <= 0.01
     assert ks.pvalue > 0.01
+
+
+def test_freepath_runs_same_alone_and_batched(gpu_lib, tables_au):
+    """Free-path runs (2D full PIC, FP32 and FP64) advanced with pic_step_many
+    beside a per-step-trial run end bit-identical to the same runs alone,
+    collision depths included (the sort carries them in both)."""
+    _announce("free path: pic_step_many against pic_step")
+    from test_serving_gpu import assert_same_run
+    mix = []
+    for prec, n in (("fp32", 60), ("fp64", 45)):
+        w = S.small_2d(precision=prec)
+        w.update(brem_freepath=True, ne_over_nc=400.0, seed=41 if prec == "fp32" else 42)
+        mix.append((w, n))
+    mix.append((S.small_2d(precision="fp32"), 50))
+    alone = []
+    for w, n in mix:
+        s = gpu_lib.Sim(w, tables_au)
+        s.pic_step(n)
+        alone.append(s)
+    sims = [gpu_lib.Sim(w, tables_au) for w, _ in mix]
+    b = gpu_lib.Batch()
+    b.step_many(sims, [min(n, 17) for _, n in mix])
+    b.step_many(sims, [n - min(n, 17) for _, n in mix])
+    for (w, n), a, g in zip(mix, alone, sims):
+        st = assert_same_run(a, g, f"{w['name']}/{w['precision']}/freepath={w.get('brem_freepath', False)}")
+        assert st["steps"] == n
+        if w.get("brem_freepath"):
+            assert np.array_equal(a.brem_depth(), g.brem_depth())
+    b.close()
