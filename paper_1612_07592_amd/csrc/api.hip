@@ -14,7 +14,6 @@
 #include "philox.hpp"
 
 namespace pic {
-void launch_b_half_zero(const Ctx& c, hipStream_t s);
 int sort_scratch_words(uint32_t nkeys);
 int reduce_scratch_cnt();
 int reduce_scratch_sum();
@@ -349,7 +348,8 @@ void fill_step_params(Ctx& c, StepParams<R>& P) {
     P.x[a] = (R*)c.x[a];
     P.p[a] = (R*)c.p[a];
     P.F[a] = (const R*)c.E[a];
-    P.F[3 + a] = (const R*)c.B[a];
+    // the push gathers B^n, which the B pass leaves in En (free until the E step)
+    P.F[3 + a] = (const R*)((c.cfg.flags & PIC_FIELDS_FROZEN) ? c.B[a] : c.En[a]);
     P.J[a] = c.J[a];
     P.n[a] = g.n[a];
     P.gg[a] = g.gg[a];
@@ -527,7 +527,7 @@ struct pic_batch {
 namespace {
 
 struct BatchLaunch {
-  int kind;          // 0 sort, 1 B half step + clear J, 2 electron step, 3 B half step, 4 E step
+  int kind;          // 0 sort, 1 both B half steps + clear J, 2 electron step, 4 E step
   int dims = 0;
   bool fp32 = false;
   size_t tab = 0, first = 0;
@@ -785,7 +785,7 @@ pic_status pic_step(pic_ctx* ctx, int32_t nsteps) {
       mark(2);
     }
     mark(1);
-    if (!frozen) launch_b_half_zero(c, c.stream);  // B^{n-1/2} -> B^n, J <- 0
+    if (!frozen) launch_b_both(c, c.stream);  // B^n (into En), B^{n+1/2}, J <- 0
     mark(1);
     mark(0);
     if (c.fp32) {
@@ -802,7 +802,6 @@ pic_status pic_step(pic_ctx* ctx, int32_t nsteps) {
     if (!frozen) {
       double ls, lc;
       laser_scalars(c, c.step, &ls, &lc);
-      launch_b_half(c, c.stream);                  // B^n -> B^{n+1/2}
       launch_e_full(c, ls, lc, c.stream);          // E^n -> E^{n+1}
     }
     mark(1);
@@ -947,8 +946,6 @@ pic_status pic_step_many(pic_batch* b, pic_ctx* const* ctxs, const int32_t* nste
       stage_step_group<double>(st, L, act, d);
     }
     for (int f = 0; f < 2; ++f)
-      if (have_f[f]) { BatchLaunch l = fl[f]; l.kind = 3; L.push_back(l); }
-    for (int f = 0; f < 2; ++f)
       if (have_f[f]) { BatchLaunch l = fl[f]; l.kind = 4; L.push_back(l); }
     for (Ctx* c : act) {
       if (!(c->cfg.flags & PIC_FIELDS_FROZEN))
@@ -1001,9 +998,8 @@ pic_status pic_step_many(pic_batch* b, pic_ctx* const* ctxs, const int32_t* nste
     switch (l.kind) {
       case 0: launch_sort(l.sort, l.fp32, b->stream); break;
       case 1:
-      case 3:
-        launch_b_half_batch(l.fp32, (const FieldJob*)(D + l.tab), (const uint32_t*)(D + l.first),
-                            l.njobs, l.total, l.kind == 1, b->stream);
+        launch_b_both_batch(l.fp32, (const FieldJob*)(D + l.tab), (const uint32_t*)(D + l.first),
+                            l.njobs, l.total, b->stream);
         break;
       case 2:
         launch_step_batch(l.dims, l.fp32, D + l.tab, (const uint32_t*)(D + l.first), l.njobs, l.total,

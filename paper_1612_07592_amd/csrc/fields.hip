@@ -65,35 +65,71 @@ __device__ inline bool in_range(const FieldArgs& A, bool isB, int c, int i, int 
   return true;
 }
 
-// B <- B - (dt/2) curl E on every valid B node; optionally clears J.
+// Both B half steps of a step, which use the same E^n, in one pass over the
+// nodes: B^n = B^{n-1/2} - (dt/2) curl E^n into Bn (the field the push
+// gathers) and B^{n+1/2} = B^n - (dt/2) curl E^n back into B (the field the E
+// step uses).  Each is formed exactly as a separate half step forms it.  Bn
+// gets every node (invalid B nodes copy B, which never changes there).  J is
+// cleared for the step's deposit.
 template <class R>
-__device__ __forceinline__ void b_half_node(const FieldArgs& A, const R* __restrict__ Ex,
+__device__ __forceinline__ void b_both_node(const FieldArgs& A, const R* __restrict__ Ex,
                                             const R* __restrict__ Ey, const R* __restrict__ Ez,
-                                            R* Bx, R* By, R* Bz, unsigned long long* Jx,
-                                            unsigned long long* Jy, unsigned long long* Jz,
-                                            int zeroJ, const int64_t m) {
+                                            R* Bx, R* By, R* Bz, R* Bnx, R* Bny, R* Bnz,
+                                            unsigned long long* Jx, unsigned long long* Jy,
+                                            unsigned long long* Jz, const int64_t m) {
   if (m >= A.nfield) return;
-  if (zeroJ) { Jx[m] = 0ull; Jy[m] = 0ull; Jz[m] = 0ull; }
+  Jx[m] = 0ull; Jy[m] = 0ull; Jz[m] = 0ull;
   int i, j, k;
   decode(A, m, i, j, k);
   const int64_t s1 = A.sz[0], s2 = (int64_t)A.sz[0] * A.sz[1];  // +1 along y, z
-  if (in_range(A, true, 0, i, j, k)) {  // dBx/dt = -dEz/dy + dEy/dz
-    R b = Bx[m];
-    if (A.act[1]) b = b - R(A.hd[1]) * (Ez[m + s1] - Ez[m]);
-    if (A.act[2]) b = b + R(A.hd[2]) * (Ey[m + s2] - Ey[m]);
-    Bx[m] = b;
+  {  // dBx/dt = -dEz/dy + dEy/dz
+    const R b = Bx[m];
+    if (in_range(A, true, 0, i, j, k)) {
+      const R ty = A.act[1] ? R(A.hd[1]) * (Ez[m + s1] - Ez[m]) : R(0);
+      const R tz = A.act[2] ? R(A.hd[2]) * (Ey[m + s2] - Ey[m]) : R(0);
+      R b1 = b;
+      if (A.act[1]) b1 = b1 - ty;
+      if (A.act[2]) b1 = b1 + tz;
+      R b2 = b1;
+      if (A.act[1]) b2 = b2 - ty;
+      if (A.act[2]) b2 = b2 + tz;
+      Bnx[m] = b1;
+      Bx[m] = b2;
+    } else {
+      Bnx[m] = b;
+    }
   }
-  if (in_range(A, true, 1, i, j, k)) {  // dBy/dt = -dEx/dz + dEz/dx
-    R b = By[m];
-    if (A.act[2]) b = b - R(A.hd[2]) * (Ex[m + s2] - Ex[m]);
-    b = b + R(A.hd[0]) * (Ez[m + 1] - Ez[m]);
-    By[m] = b;
+  {  // dBy/dt = -dEx/dz + dEz/dx
+    const R b = By[m];
+    if (in_range(A, true, 1, i, j, k)) {
+      const R tz = A.act[2] ? R(A.hd[2]) * (Ex[m + s2] - Ex[m]) : R(0);
+      const R tx = R(A.hd[0]) * (Ez[m + 1] - Ez[m]);
+      R b1 = b;
+      if (A.act[2]) b1 = b1 - tz;
+      b1 = b1 + tx;
+      R b2 = b1;
+      if (A.act[2]) b2 = b2 - tz;
+      b2 = b2 + tx;
+      Bny[m] = b1;
+      By[m] = b2;
+    } else {
+      Bny[m] = b;
+    }
   }
-  if (in_range(A, true, 2, i, j, k)) {  // dBz/dt = -dEy/dx + dEx/dy
-    R b = Bz[m];
-    b = b - R(A.hd[0]) * (Ey[m + 1] - Ey[m]);
-    if (A.act[1]) b = b + R(A.hd[1]) * (Ex[m + s1] - Ex[m]);
-    Bz[m] = b;
+  {  // dBz/dt = -dEy/dx + dEx/dy
+    const R b = Bz[m];
+    if (in_range(A, true, 2, i, j, k)) {
+      const R tx = R(A.hd[0]) * (Ey[m + 1] - Ey[m]);
+      const R ty = A.act[1] ? R(A.hd[1]) * (Ex[m + s1] - Ex[m]) : R(0);
+      R b1 = b - tx;
+      if (A.act[1]) b1 = b1 + ty;
+      R b2 = b1 - tx;
+      if (A.act[1]) b2 = b2 + ty;
+      Bnz[m] = b1;
+      Bz[m] = b2;
+    } else {
+      Bnz[m] = b;
+    }
   }
 }
 
@@ -153,12 +189,12 @@ __device__ __forceinline__ void e_full_node(const FieldArgs& A, const EPtrs& P, 
 }
 
 template <class R>
-__global__ __launch_bounds__(kBlock) void k_b_half(FieldArgs A, const R* __restrict__ Ex,
+__global__ __launch_bounds__(kBlock) void k_b_both(FieldArgs A, const R* __restrict__ Ex,
                                                    const R* __restrict__ Ey, const R* __restrict__ Ez,
-                                                   R* Bx, R* By, R* Bz, unsigned long long* Jx,
-                                                   unsigned long long* Jy, unsigned long long* Jz,
-                                                   int zeroJ) {
-  b_half_node<R>(A, Ex, Ey, Ez, Bx, By, Bz, Jx, Jy, Jz, zeroJ,
+                                                   R* Bx, R* By, R* Bz, R* Bnx, R* Bny, R* Bnz,
+                                                   unsigned long long* Jx, unsigned long long* Jy,
+                                                   unsigned long long* Jz) {
+  b_both_node<R>(A, Ex, Ey, Ez, Bx, By, Bz, Bnx, Bny, Bnz, Jx, Jy, Jz,
                  (int64_t)blockIdx.x * kBlock + threadIdx.x);
 }
 
@@ -179,14 +215,14 @@ __device__ inline int batch_job(const uint32_t* __restrict__ first, int njobs, u
 }
 
 template <class R>
-__global__ __launch_bounds__(kBlock) void k_b_half_batch(const FieldJob* __restrict__ tab,
+__global__ __launch_bounds__(kBlock) void k_b_both_batch(const FieldJob* __restrict__ tab,
                                                          const uint32_t* __restrict__ first,
-                                                         int njobs, int zeroJ) {
+                                                         int njobs) {
   const int j = batch_job(first, njobs, blockIdx.x);
   const FieldJob& F = tab[j];
-  b_half_node<R>(F.A, (const R*)F.P.E[0], (const R*)F.P.E[1], (const R*)F.P.E[2], (R*)F.Bw[0],
-                 (R*)F.Bw[1], (R*)F.Bw[2], F.Jw[0], F.Jw[1], F.Jw[2], zeroJ,
-                 (int64_t)(blockIdx.x - first[j]) * kBlock + threadIdx.x);
+  b_both_node<R>(F.A, (const R*)F.P.E[0], (const R*)F.P.E[1], (const R*)F.P.E[2], (R*)F.Bw[0],
+                 (R*)F.Bw[1], (R*)F.Bw[2], (R*)F.P.En[0], (R*)F.P.En[1], (R*)F.P.En[2], F.Jw[0],
+                 F.Jw[1], F.Jw[2], (int64_t)(blockIdx.x - first[j]) * kBlock + threadIdx.x);
 }
 
 template <class R>
@@ -212,11 +248,11 @@ void fill_field_job(const Ctx& c, double lsin, double lcos, FieldJob& F) {
   F.lcos = lcos;
 }
 
-void launch_b_half_batch(bool fp32, const FieldJob* tab, const uint32_t* first, int njobs,
-                         uint32_t total, int zeroJ, hipStream_t s) {
+void launch_b_both_batch(bool fp32, const FieldJob* tab, const uint32_t* first, int njobs,
+                         uint32_t total, hipStream_t s) {
   if (njobs <= 0 || total == 0) return;
-  if (fp32) hipLaunchKernelGGL(k_b_half_batch<float>, dim3(total), dim3(kBlock), 0, s, tab, first, njobs, zeroJ);
-  else hipLaunchKernelGGL(k_b_half_batch<double>, dim3(total), dim3(kBlock), 0, s, tab, first, njobs, zeroJ);
+  if (fp32) hipLaunchKernelGGL(k_b_both_batch<float>, dim3(total), dim3(kBlock), 0, s, tab, first, njobs);
+  else hipLaunchKernelGGL(k_b_both_batch<double>, dim3(total), dim3(kBlock), 0, s, tab, first, njobs);
 }
 
 void launch_e_full_batch(bool fp32, const FieldJob* tab, const uint32_t* first, int njobs,
@@ -226,21 +262,21 @@ void launch_e_full_batch(bool fp32, const FieldJob* tab, const uint32_t* first, 
   else hipLaunchKernelGGL(k_e_full_batch<double>, dim3(total, 3), dim3(kBlock), 0, s, tab, first, njobs);
 }
 
-void launch_b_half_impl(const Ctx& c, int zeroJ, hipStream_t s) {
+// B^n goes into the E step's output buffer En, which is free until the E step
+void launch_b_both(const Ctx& c, hipStream_t s) {
   const FieldArgs A = field_args(c.g);
   const unsigned blocks = (unsigned)((A.nfield + kBlock - 1) / kBlock);
   if (c.fp32)
-    hipLaunchKernelGGL(k_b_half<float>, dim3(blocks), dim3(kBlock), 0, s, A, (const float*)c.E[0],
+    hipLaunchKernelGGL(k_b_both<float>, dim3(blocks), dim3(kBlock), 0, s, A, (const float*)c.E[0],
                        (const float*)c.E[1], (const float*)c.E[2], (float*)c.B[0], (float*)c.B[1],
-                       (float*)c.B[2], c.J[0], c.J[1], c.J[2], zeroJ);
+                       (float*)c.B[2], (float*)c.En[0], (float*)c.En[1], (float*)c.En[2], c.J[0], c.J[1],
+                       c.J[2]);
   else
-    hipLaunchKernelGGL(k_b_half<double>, dim3(blocks), dim3(kBlock), 0, s, A, (const double*)c.E[0],
+    hipLaunchKernelGGL(k_b_both<double>, dim3(blocks), dim3(kBlock), 0, s, A, (const double*)c.E[0],
                        (const double*)c.E[1], (const double*)c.E[2], (double*)c.B[0], (double*)c.B[1],
-                       (double*)c.B[2], c.J[0], c.J[1], c.J[2], zeroJ);
+                       (double*)c.B[2], (double*)c.En[0], (double*)c.En[1], (double*)c.En[2], c.J[0],
+                       c.J[1], c.J[2]);
 }
-
-void launch_b_half(const Ctx& c, hipStream_t s) { launch_b_half_impl(c, 0, s); }
-void launch_b_half_zero(const Ctx& c, hipStream_t s) { launch_b_half_impl(c, 1, s); }
 
 void launch_e_full(Ctx& c, double lsin, double lcos, hipStream_t s) {
   const FieldArgs A = field_args(c.g);

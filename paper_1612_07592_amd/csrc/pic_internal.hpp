@@ -196,14 +196,14 @@ int chunk_electrons(bool fp32, int dims);   // electrons per step-kernel workgro
 // exclusive prefix of chunks / workgroups per run, with first[njobs] = total)
 void launch_step_batch(int dims, bool fp32, const void* tab, const uint32_t* first, int njobs,
                        uint32_t total, int lds_nodes, hipStream_t s);
-void launch_b_half_batch(bool fp32, const FieldJob* tab, const uint32_t* first, int njobs,
-                         uint32_t total, int zeroJ, hipStream_t s);
+void launch_b_both_batch(bool fp32, const FieldJob* tab, const uint32_t* first, int njobs,
+                         uint32_t total, hipStream_t s);
 void launch_e_full_batch(bool fp32, const FieldJob* tab, const uint32_t* first, int njobs,
                          uint32_t total, hipStream_t s);
 uint32_t field_blocks(const struct Ctx& c);
 void fill_field_job(const struct Ctx& c, double lsin, double lcos, FieldJob& F);
 void launch_init_electrons(const struct Ctx& c, hipStream_t s);
-void launch_b_half(const struct Ctx& c, hipStream_t s);
+void launch_b_both(const struct Ctx& c, hipStream_t s);
 void launch_e_full(struct Ctx& c, double lsin, double lcos, hipStream_t s);
 void launch_stats_reduce(const struct Ctx& c, unsigned long long* cnt_out, double* sum_out,
                          double* ekin_out, double* efield_out, unsigned long long* live_out,
