@@ -23,10 +23,14 @@ Ctx::~Ctx() {
   for (hipEvent_t ev : ev_pool) { hipError_t e = hipEventDestroy(ev); (void)e; }
 }
 
+// Timing events skip the system-scope fence on record: that fence writes back
+// and invalidates the caches between launches, which both adds to the measured
+// interval and slows the launch after it.  pic_profile_read synchronises the
+// stream before it reads the events.
 hipEvent_t Ctx::prof_event() {
   if (ev_used == ev_pool.size()) {
     hipEvent_t ev = nullptr;
-    if (hipEventCreate(&ev) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     ev_pool.push_back(ev);
   }
   return ev_pool[ev_used++];
