@@ -198,9 +198,13 @@ __global__ __launch_bounds__(kBlock) void k_b_both(FieldArgs A, const R* __restr
                  (int64_t)blockIdx.x * kBlock + threadIdx.x);
 }
 
+// One thread updates the three components of its node, so each B value is
+// fetched by the threads of one pass instead of two component passes.
 template <class R>
 __global__ __launch_bounds__(kBlock) void k_e_full(FieldArgs A, EPtrs P, double lsin, double lcos) {
-  e_full_node<R>(A, P, lsin, lcos, (int)blockIdx.y, (int64_t)blockIdx.x * kBlock + threadIdx.x);
+  const int64_t m = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) e_full_node<R>(A, P, lsin, lcos, c, m);
 }
 
 // Batched forms: the workgroups of every run laid end to end (run j owns
@@ -231,8 +235,9 @@ __global__ __launch_bounds__(kBlock) void k_e_full_batch(const FieldJob* __restr
                                                          int njobs) {
   const int j = batch_job(first, njobs, blockIdx.x);
   const FieldJob& F = tab[j];
-  e_full_node<R>(F.A, F.P, F.lsin, F.lcos, (int)blockIdx.y,
-                 (int64_t)(blockIdx.x - first[j]) * kBlock + threadIdx.x);
+  const int64_t m = (int64_t)(blockIdx.x - first[j]) * kBlock + threadIdx.x;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) e_full_node<R>(F.A, F.P, F.lsin, F.lcos, c, m);
 }
 
 uint32_t field_blocks(const Ctx& c) { return (uint32_t)((c.g.nfield + kBlock - 1) / kBlock); }
@@ -258,8 +263,8 @@ void launch_b_both_batch(bool fp32, const FieldJob* tab, const uint32_t* first, 
 void launch_e_full_batch(bool fp32, const FieldJob* tab, const uint32_t* first, int njobs,
                          uint32_t total, hipStream_t s) {
   if (njobs <= 0 || total == 0) return;
-  if (fp32) hipLaunchKernelGGL(k_e_full_batch<float>, dim3(total, 3), dim3(kBlock), 0, s, tab, first, njobs);
-  else hipLaunchKernelGGL(k_e_full_batch<double>, dim3(total, 3), dim3(kBlock), 0, s, tab, first, njobs);
+  if (fp32) hipLaunchKernelGGL(k_e_full_batch<float>, dim3(total), dim3(kBlock), 0, s, tab, first, njobs);
+  else hipLaunchKernelGGL(k_e_full_batch<double>, dim3(total), dim3(kBlock), 0, s, tab, first, njobs);
 }
 
 // B^n goes into the E step's output buffer En, which is free until the E step
@@ -287,9 +292,9 @@ void launch_e_full(Ctx& c, double lsin, double lcos, hipStream_t s) {
   P.srcA = c.srcA; P.srcC = c.srcC; P.srcS = c.srcS;
   const unsigned blocks = (unsigned)((A.nfield + kBlock - 1) / kBlock);
   if (c.fp32)
-    hipLaunchKernelGGL(k_e_full<float>, dim3(blocks, 3), dim3(kBlock), 0, s, A, P, lsin, lcos);
+    hipLaunchKernelGGL(k_e_full<float>, dim3(blocks), dim3(kBlock), 0, s, A, P, lsin, lcos);
   else
-    hipLaunchKernelGGL(k_e_full<double>, dim3(blocks, 3), dim3(kBlock), 0, s, A, P, lsin, lcos);
+    hipLaunchKernelGGL(k_e_full<double>, dim3(blocks), dim3(kBlock), 0, s, A, P, lsin, lcos);
   for (int d = 0; d < 3; ++d) { void* t = c.E[d]; c.E[d] = c.En[d]; c.En[d] = t; }
 }
 
