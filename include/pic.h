@@ -246,7 +246,8 @@ pic_status pic_copy_photons(pic_ctx* ctx, uint64_t off, uint64_t n, double* x,
 
 /* Size (elements per component, guard cells included) of the field arrays
  * and a copy of Ex,Ey,Ez,Bx,By,Bz (6*size doubles) in the library layout:
- * index (i+g) + sx*((j+g) + sy*(k+g)), g = 2 on active axes. */
+ * index (i+g) + sx*((j+g) + sy*(k+g)), g = 2 on active axes.  After n steps
+ * E is E^n and B is B^{n-1/2} (the leapfrog state the next step starts from). */
 pic_status pic_field_size(pic_ctx* ctx, uint64_t* size);
 pic_status pic_copy_fields(pic_ctx* ctx, double* out);
 
