@@ -1,12 +1,13 @@
 // Cell-tile sort of the electron SoA (counting sort, every few steps).
 //
-// Electrons are keyed by the Morton index of their spatial tile; absorbed
+// Electrons are keyed by the index of their spatial tile (Morton order over
+// the bits all axes share, the longer axes' extra bits above); absorbed
 // electrons get the largest key and end up behind the live ones (their last
 // state is kept for read-back, they are never pushed again).  After a sort a
 // contiguous chunk of electrons covers a compact box of cells, which is what
 // lets the step kernel stage fields and accumulate currents in LDS.
 //
-// Passes: key + histogram (one atomic per distinct key in a workgroup), a three-pass exclusive
+// Passes: key + histogram (one atomic per distinct key in a workgroup), a two-pass exclusive
 // scan of the tile counts, scatter into the second SoA buffer
 // (order inside a tile is arbitrary; nothing downstream depends on it: the
 // current is summed in fixed point and Philox streams follow the electron id).
