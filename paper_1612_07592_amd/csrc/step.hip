@@ -794,7 +794,7 @@ __device__ inline void electron_physics(const StepParams<R>& P, int64_t e, uint3
 
 // One workgroup = one chunk of 256 consecutive electrons of the (tile-sorted)
 // SoA (chunk_of_block spreads the chunks over the XCDs).  Inside a chunk
-// electrons are dealt to lanes with a stride (16 in 1D/3D, 4 in 2D), so the
+// electrons are dealt to lanes with a stride (16 in 1D, 4 in 2D, 8 in 3D), so the
 // 64 lanes of a wave come from many cells and rarely hit the same LDS current
 // node at once.
 // When the chunk's cells fit the LDS box, the fields of the box are staged in
@@ -809,8 +809,9 @@ __device__ __forceinline__ void step_chunk(const StepParams<R>& P, const uint32_
   // electrons are dealt to lanes with stride kDeal (lane t of the workgroup
   // takes local electron (t mod (256/kDeal)) kDeal + t div (256/kDeal));
   // measured: 2D gold slab 70.2 us per launch at stride 4 against 74.3 at 16,
-  // 73.7 at 2 and 83.4 unstrided; 3D gold slab 9.87 ms at 16 against 11.6 at 4
-  constexpr uint32_t kDeal = D == 2 ? 4u : 16u;
+  // 73.7 at 2 and 83.4 unstrided; 3D gold slab 9.83 ms at 8, 9.92 at 32,
+  // 9.94 at 16, 10.14 at 64 and 11.6 at 4
+  constexpr uint32_t kDeal = D == 2 ? 4u : (D == 3 ? 8u : 16u);
   constexpr uint32_t kRow = kBlock / kDeal;
   const int64_t e = (int64_t)chunk * kBlock + (int64_t)((t % kRow) * kDeal + t / kRow);
   const int64_t n_act = (int64_t)*P.n_active;
