@@ -80,7 +80,8 @@ enum {
                                   II.B, random free path), no draw between collisions
                                   (Sec. IV); different random streams, so runs agree
                                   with the per-step form in distribution, not event
-                                  by event.  8 more bytes per electron. */
+                                  by event.  8 more bytes per electron (16 when
+                                  the electrons are re-sorted: two buffers). */
 };
 enum { PIC_FROZEN_UNIFORM = 0, PIC_FROZEN_PLANE_WAVE = 1 };
 
