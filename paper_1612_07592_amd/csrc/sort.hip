@@ -73,15 +73,31 @@ __global__ __launch_bounds__(kBlock) void k_sort_key(SortArgs A) {
   for (int i = t; i < kHash; i += kBlock) { hkey[i] = kEmpty; hcnt[i] = 0u; }
   __syncthreads();
   const int64_t e = (int64_t)blockIdx.x * kBlock + t;
+  // id and position loaded together (every e < N is in bounds), before the
+  // live count is known, so their latencies overlap
+  uint32_t idv = kDead;
+  int qv[3] = {0, 0, 0};
+  R xv[3] = {R(0), R(0), R(0)};
+  if (e < A.N) {
+    idv = A.id[e];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (a >= A.dims) break;
+      if constexpr (sizeof(R) == 4) qv[a] = ((const int*)A.x[a])[e];
+      else xv[a] = ((const R*)A.x[a])[e];
+    }
+  }
   const bool valid = e < (int64_t)A.n_active[0];
   if (valid) {
     uint32_t key = A.nkeys - 1;  // absorbed electrons: last bucket
-    if (!(A.id[e] & kDead)) {
+    if (!(idv & kDead)) {
       uint32_t tt[3] = {0u, 0u, 0u};
-      for (int a = 0; a < A.dims; ++a) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        if (a >= A.dims) break;
         int c;
-        if constexpr (sizeof(R) == 4) c = ((const int*)A.x[a])[e] >> A.fb[a];  // fixed point
-        else c = (int)floor(((const R*)A.x[a])[e] * A.idx[a]);
+        if constexpr (sizeof(R) == 4) c = qv[a] >> A.fb[a];  // fixed point
+        else c = (int)floor(xv[a] * A.idx[a]);
         c = c < 0 ? 0 : (c >= A.n[a] ? A.n[a] - 1 : c);
         tt[a] = (uint32_t)(c / A.tile[a]);
       }
@@ -173,10 +189,27 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(SortArgs A) {
   for (int i = t; i < kHash; i += kBlock) { hkey[i] = kEmpty; hcnt[i] = 0u; }
   __syncthreads();
   const int64_t e = (int64_t)blockIdx.x * kBlock + t;
+  // the electron's state is loaded up front (every e < N is in bounds), so its
+  // latency overlaps the ranking and the cursor atomics
+  R xv[3] = {R(0), R(0), R(0)}, pv[3] = {R(0), R(0), R(0)};
+  double tv = 0.0, tbv = 0.0, wv = 0.0;
+  uint32_t idv = 0u, kv = 0u;
+  if (e < A.N) {
+    kv = A.key[e];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (a < A.dims) xv[a] = ((const R*)A.x[a])[e];
+      pv[a] = ((const R*)A.p[a])[e];
+    }
+    tv = A.tau[e];
+    if (A.taub) tbv = A.taub[e];
+    wv = A.w[e];
+    idv = A.id[e];
+  }
   const bool valid = e < (int64_t)A.n_active[0];
   int h = 0;
   uint32_t rank = 0;
-  if (valid) h = hash_insert(hkey, hcnt, A.key[e], rank);
+  if (valid) h = hash_insert(hkey, hcnt, kv, rank);
   __syncthreads();
   // one cursor atomic per distinct key of the workgroup; the slot's count is
   // replaced by the base of the workgroup's range for that key
@@ -185,12 +218,15 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(SortArgs A) {
   __syncthreads();
   if (!valid) return;
   const uint32_t d = hcnt[h] + rank;
-  for (int a = 0; a < A.dims; ++a) ((R*)A.x2[a])[d] = ((const R*)A.x[a])[e];
-  for (int a = 0; a < 3; ++a) ((R*)A.p2[a])[d] = ((const R*)A.p[a])[e];
-  A.tau2[d] = A.tau[e];
-  if (A.taub) A.taub2[d] = A.taub[e];
-  A.w2[d] = A.w[e];
-  A.id2[d] = A.id[e];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (a < A.dims) ((R*)A.x2[a])[d] = xv[a];
+    ((R*)A.p2[a])[d] = pv[a];
+  }
+  A.tau2[d] = tv;
+  if (A.taub) A.taub2[d] = tbv;
+  A.w2[d] = wv;
+  A.id2[d] = idv;
 }
 
 // The dead stretch [n_old, n_prev) into the destination buffer (grid-stride).
