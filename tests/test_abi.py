@@ -173,3 +173,34 @@ def test_build_tables_rejects_bad_args():
                               z.ctypes.data, z.ctypes.data, C.byref(out)) == 1
     assert L.pic_build_tables(13, 0.0, 1, z.ctypes.data, z.ctypes.data, z.ctypes.data,
                               z.ctypes.data, z.ctypes.data, C.byref(out)) == 1
+
+
+def test_free_path_flag_checked_and_counted():
+    """PIC_BREM_FREEPATH needs PIC_BREM, and its collision depths (one
+    double per electron in each of the two electron buffers) are counted by
+    pic_memory_required."""
+    w = W.c2()
+    code, n0 = _mem(w)
+    assert code == 0
+    code, n1 = _mem(dict(w, brem_freepath=True))
+    assert code == 0
+    assert n1 - n0 >= 2 * 8 * W.num_electrons(w)
+    assert _mem(dict(w, brem_freepath=True, brem=False))[0] == 1
+
+
+def test_workload_sizes():
+    """Electron counts of the recipes as the configurations state them."""
+    assert W.num_electrons(W.c1()) == 8192
+    assert W.num_electrons(W.c2()) == 2_097_152
+    assert W.num_electrons(W.c5()) == 134_217_728
+    assert W.num_electrons(W.thick_target()) == 5000 * 420
+    assert sum(W.num_electrons(j) for j in W.c3_jobs()) == 5_898_240  # 5.9e9 e-steps over 1000 steps
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py --gpus N > 1 exits with a message (one GPU only), before it
+    touches torch or the GPU."""
+    r = subprocess.run(["python3", os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stdout
