@@ -17,7 +17,7 @@
 // tiles and the ones absorbed since then to [n_new, n_old).  The older dead
 // tail [n_old, N) is already in place in the destination buffer except for
 // the stretch that died during the previous interval, [n_old, n_prev), which
-// is copied across.  Counter words: n[0] live count (read by the step
+// the scatter copies across to the same indices.  Counter words: n[0] live count (read by the step
 // kernel), n[1] the count being built, n[2] the live count before the last
 // sort.
 #include <algorithm>
@@ -216,8 +216,11 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(SortArgs A) {
   for (int i = t; i < kHash; i += kBlock)
     if (hkey[i] != kEmpty) hcnt[i] = atomicAdd(A.cursor + hkey[i], hcnt[i]);
   __syncthreads();
-  if (!valid) return;
-  const uint32_t d = hcnt[h] + rank;
+  // electrons of the dead stretch [n_old, n_prev) keep their index (they
+  // were absorbed before the last sort and are no longer in the ranked range)
+  const bool tail = !valid && e < (int64_t)A.n_active[2];
+  if (!valid && !tail) return;
+  const int64_t d = valid ? (int64_t)(hcnt[h] + rank) : e;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     if (a < A.dims) ((R*)A.x2[a])[d] = xv[a];
@@ -227,21 +230,6 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(SortArgs A) {
   if (A.taub) A.taub2[d] = tbv;
   A.w2[d] = wv;
   A.id2[d] = idv;
-}
-
-// The dead stretch [n_old, n_prev) into the destination buffer (grid-stride).
-template <class R>
-__global__ __launch_bounds__(kBlock) void k_sort_tail(SortArgs A) {
-  const int64_t lo = (int64_t)A.n_active[0], hi = (int64_t)A.n_active[2];
-  for (int64_t e = lo + (int64_t)blockIdx.x * kBlock + threadIdx.x; e < hi;
-       e += (int64_t)gridDim.x * kBlock) {
-    for (int a = 0; a < A.dims; ++a) ((R*)A.x2[a])[e] = ((const R*)A.x[a])[e];
-    for (int a = 0; a < 3; ++a) ((R*)A.p2[a])[e] = ((const R*)A.p[a])[e];
-    A.tau2[e] = A.tau[e];
-    if (A.taub) A.taub2[e] = A.taub[e];
-    A.w2[e] = A.w[e];
-    A.id2[e] = A.id[e];
-  }
 }
 
 __global__ void k_sort_commit(uint32_t* n) {
@@ -262,9 +250,6 @@ void launch_sort(const SortArgs& A, bool fp32, hipStream_t s) {
   hipLaunchKernelGGL(k_scan_fixup, dim3(nseg), dim3(kBlock), 0, s, A, btot);
   if (fp32) hipLaunchKernelGGL(k_sort_scatter<float>, dim3(blocks), dim3(kBlock), 0, s, A);
   else hipLaunchKernelGGL(k_sort_scatter<double>, dim3(blocks), dim3(kBlock), 0, s, A);
-  const unsigned tail_blocks = (unsigned)std::min<int64_t>(blocks, 1024);
-  if (fp32) hipLaunchKernelGGL(k_sort_tail<float>, dim3(tail_blocks), dim3(kBlock), 0, s, A);
-  else hipLaunchKernelGGL(k_sort_tail<double>, dim3(tail_blocks), dim3(kBlock), 0, s, A);
   hipLaunchKernelGGL(k_sort_commit, dim3(1), dim3(1), 0, s, A.n_active);
 }
 
