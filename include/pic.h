@@ -231,6 +231,39 @@ pic_status pic_copy_electrons(pic_ctx* ctx, double* x, double* p, double* tau,
 pic_status pic_set_electrons(pic_ctx* ctx, const double* x, const double* p,
                              const double* tau);
 
+/* Borrowed device pointers to the context's live buffers, for callers that
+ * read them in place (on libpic's HIP runtime).  Valid until the next
+ * pic_step, pic_step_many or pic_destroy: a step swaps the E buffers and a
+ * tile sort swaps the electron buffers.  Electrons are in the library's
+ * sorted order (id[] gives each one's id, with bit 31 set once absorbed);
+ * in PIC_FP32_MIXED runs x[] holds int32 fixed point in cells with fb[]
+ * fraction bits and p[], fields and photon x/k/eps are float, else double.
+ * The field arrays use the pic_copy_fields layout; J is int64 in units of
+ * 2^-40.  Unused axes and absent buffers (taub without PIC_BREM_FREEPATH)
+ * are NULL.  Synchronises (the photon count is read from the device). */
+typedef struct {
+  uint32_t precision, dims;
+  int32_t fb[3];
+  uint64_t electrons, photons_stored, field_size;
+  void* x[3];
+  void* p[3];
+  double* tau;
+  double* taub;
+  double* w;
+  uint32_t* id;
+  void* E[3];
+  void* B[3];
+  int64_t* J[3];
+  void* photon_x[3];
+  void* photon_k[3];
+  void* photon_eps;
+  double* photon_w;
+  uint32_t* photon_step;
+  uint32_t* photon_parent;
+  uint32_t* photon_proc;
+} pic_buffers;
+pic_status pic_get_buffers(pic_ctx* ctx, pic_buffers* out);
+
 /* Collision optical depths of PIC_BREM_FREEPATH runs, n = pic_counts'
  * electron count doubles ordered by id (copy: synchronises; set: for tests
  * that set up beams, finite values only).  PIC_ERR_STATE without the flag. */

@@ -29,7 +29,7 @@ EXPORTS = ["pic_create", "pic_load_tables", "pic_step", "pic_emission_stats", "p
            "pic_step_many", "pic_server_create", "pic_server_destroy", "pic_server_clock",
            "pic_server_last_error", "pic_server_submit", "pic_server_run", "pic_server_poll",
            "pic_server_job_ctx", "pic_server_release", "pic_device_memory", "pic_synchronize",
-           "pic_copy_brem_depth", "pic_set_brem_depth"]
+           "pic_copy_brem_depth", "pic_set_brem_depth", "pic_get_buffers"]
 
 
 class pic_config(C.Structure):
@@ -116,6 +116,7 @@ def load() -> C.CDLL:
     L.pic_copy_electrons.argtypes = [P] + [C.c_void_p] * 6
     L.pic_set_electrons.argtypes = [P] + [C.c_void_p] * 3
     L.pic_copy_brem_depth.argtypes = [P, C.c_void_p]
+    L.pic_get_buffers.argtypes = [P, C.c_void_p]
     L.pic_set_brem_depth.argtypes = [P, C.c_void_p]
     L.pic_copy_photons.argtypes = [P, u64, u64] + [C.c_void_p] * 7
     L.pic_field_size.argtypes = [P, C.POINTER(u64)]
@@ -280,6 +281,19 @@ def pic_device_memory():
     return int(f.value), int(t.value)
 
 
+class pic_buffers(C.Structure):
+    """Borrowed device pointers of a context (pic_get_buffers)."""
+    _fields_ = [("precision", C.c_uint32), ("dims", C.c_uint32), ("fb", C.c_int32 * 3),
+                ("electrons", C.c_uint64), ("photons_stored", C.c_uint64),
+                ("field_size", C.c_uint64), ("x", C.c_void_p * 3), ("p", C.c_void_p * 3),
+                ("tau", C.c_void_p), ("taub", C.c_void_p), ("w", C.c_void_p), ("id", C.c_void_p),
+                ("E", C.c_void_p * 3), ("B", C.c_void_p * 3), ("J", C.c_void_p * 3),
+                ("photon_x", C.c_void_p * 3), ("photon_k", C.c_void_p * 3),
+                ("photon_eps", C.c_void_p), ("photon_w", C.c_void_p),
+                ("photon_step", C.c_void_p), ("photon_parent", C.c_void_p),
+                ("photon_proc", C.c_void_p)]
+
+
 class Sim:
     """One libpic context: pic_create / pic_load_tables / pic_step /
     pic_emission_stats / pic_destroy plus the copy helpers."""
@@ -358,6 +372,16 @@ class Sim:
         tau = np.ascontiguousarray(tau, dtype=np.float64).reshape(self.N)
         _check("pic_set_electrons", self._L.pic_set_electrons(self._h, x.ctypes.data, p.ctypes.data,
                                                               tau.ctypes.data), self._h)
+
+    def buffers(self) -> dict:
+        """Borrowed device pointers (ints) and sizes, valid until the next step."""
+        b = pic_buffers()
+        _check("pic_get_buffers", self._L.pic_get_buffers(self._h, C.byref(b)), self._h)
+        out = {}
+        for name, _ in pic_buffers._fields_:
+            v = getattr(b, name)
+            out[name] = list(v) if isinstance(v, C.Array) else v
+        return out
 
     def brem_depth(self) -> np.ndarray:
         """Collision optical depths of a free-path bremsstrahlung run, id order."""

@@ -1042,6 +1042,42 @@ pic_status pic_counts(pic_ctx* ctx, uint64_t* electrons, uint64_t* stored, uint6
 }
 
 
+pic_status pic_get_buffers(pic_ctx* ctx, pic_buffers* out) {
+  pic_status st = check_ctx(ctx);
+  if (st) return st;
+  Ctx& c = ctx->c;
+  if (!out) FAIL(c, PIC_ERR_INVALID, "null output");
+  uint64_t stored = 0;
+  if ((st = pic_counts(ctx, nullptr, &stored, nullptr))) return st;
+  pic_buffers b{};
+  b.precision = c.cfg.precision;
+  b.dims = (uint32_t)c.g.dims;
+  b.electrons = (uint64_t)c.N;
+  b.photons_stored = stored;
+  b.field_size = (uint64_t)c.g.nfield;
+  for (int a = 0; a < 3; ++a) {
+    b.fb[a] = c.fp32 ? c.g.fb[a] : 0;
+    b.x[a] = a < c.g.dims ? c.x[a] : nullptr;
+    b.p[a] = c.p[a];
+    b.E[a] = c.E[a];
+    b.B[a] = c.B[a];
+    b.J[a] = (int64_t*)c.J[a];
+    b.photon_x[a] = c.px[a];
+    b.photon_k[a] = c.pk[a];
+  }
+  b.tau = c.tau;
+  b.taub = c.taub;
+  b.w = c.w;
+  b.id = c.id;
+  b.photon_eps = c.pe;
+  b.photon_w = c.pw;
+  b.photon_step = c.pstep;
+  b.photon_parent = c.ppar;
+  b.photon_proc = c.pproc;
+  *out = b;
+  return PIC_OK;
+}
+
 pic_status pic_copy_electrons(pic_ctx* ctx, double* x, double* p, double* tau, double* w,
                               uint32_t* id, uint8_t* alive) {
   pic_status st = check_ctx(ctx);

@@ -48,10 +48,10 @@ def test_binding_struct_layouts_match_header():
 #include <stddef.h>
 #include "pic.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(pic_config), sizeof(pic_tables),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(pic_config), sizeof(pic_tables),
          sizeof(pic_stats), offsetof(pic_config, stream), offsetof(pic_tables, br_cdf),
          sizeof(pic_server_config), offsetof(pic_server_config, stream), sizeof(pic_job_result),
-         offsetof(pic_job_result, stats));
+         offsetof(pic_job_result, stats), sizeof(pic_buffers), offsetof(pic_buffers, photon_proc));
   return 0;
 }'''
     d = os.path.join(ROOT, "_build")
@@ -64,7 +64,8 @@ int main(void) {
     want = [C.sizeof(B.pic_config), C.sizeof(B.pic_tables), C.sizeof(B.pic_stats),
             B.pic_config.stream.offset, B.pic_tables.br_cdf.offset,
             C.sizeof(B.pic_server_config), B.pic_server_config.stream.offset,
-            C.sizeof(B.pic_job_result), B.pic_job_result.stats.offset]
+            C.sizeof(B.pic_job_result), B.pic_job_result.stats.offset,
+            C.sizeof(B.pic_buffers), B.pic_buffers.photon_proc.offset]
     assert got == want
 
 

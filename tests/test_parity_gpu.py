@@ -275,3 +275,24 @@ def test_lds_box_paths_2d(oracle_lib, gpu_lib, tables_au, monkeypatch):
     assert list(sa["events"]) == list(sb["events"])
     # energy sums: per-wave partial sums follow the (arbitrary) order inside a tile
     np.testing.assert_allclose(sa["e_rad_kept"], sb["e_rad_kept"], rtol=1e-12)
+
+
+def test_get_buffers(gpu_lib, tables_al):
+    """pic_get_buffers hands out the live device buffers: non-null where the
+    run has them, NULL for unused axes and absent arrays, and the E pointers
+    change after a step (the E step swaps its two buffers)."""
+    _announce("pic_get_buffers")
+    w = S.c1_parity(8)
+    g = gpu_lib.Sim(w, tables_al)
+    b0 = g.buffers()
+    assert b0["electrons"] == g.N and b0["dims"] == 1 and b0["precision"] == 0
+    assert all(b0[k] for k in ("tau", "w", "id", "photon_eps", "photon_w", "photon_proc"))
+    assert b0["x"][0] and not b0["x"][1] and not b0["x"][2]
+    assert all(b0["p"]) and all(b0["E"]) and all(b0["B"]) and all(b0["J"])
+    assert not b0["taub"]
+    assert b0["field_size"] == g.fields().shape[1]
+    g.step(1)
+    b1 = g.buffers()
+    assert b1["E"] != b0["E"]
+    assert b1["B"] == b0["B"]
+    g.close()
