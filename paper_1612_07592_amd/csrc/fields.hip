@@ -137,8 +137,7 @@ __device__ __forceinline__ void b_both_node(const FieldArgs& A, const R* __restr
 // Ampere update of E_c at an interior node (old E, B^{n+1/2}, J^{n+1/2}).
 template <class R>
 __device__ inline R e_interior(const FieldArgs& A, const EPtrs& P, int c, int i, int j, int k,
-                               double lsin, double lcos) {
-  const int64_t m = fidx(A, i, j, k);
+                               int64_t m, double lsin, double lcos) {
   const int64_t s1 = A.sz[0], s2 = (int64_t)A.sz[0] * A.sz[1];  // -1 along y, z
   const R* Bx = (const R*)P.B[0];
   const R* By = (const R*)P.B[1];
@@ -179,12 +178,12 @@ __device__ __forceinline__ void e_full_node(const FieldArgs& A, const EPtrs& P, 
   int nb = 0, ax = -1;
   for (int a = 0; a < 3; ++a)
     if (A.act[a] && !estag(c, a) && (ijk[a] == 0 || ijk[a] == A.n[a])) { ++nb; ax = a; }
-  if (nb == 0) { Fn[m] = e_interior<R>(A, P, c, i, j, k, lsin, lcos); return; }
+  if (nb == 0) { Fn[m] = e_interior<R>(A, P, c, i, j, k, m, lsin, lcos); return; }
   if (nb > 1) { Fn[m] = R(0); return; }
   int in[3] = {i, j, k};
   in[ax] += (ijk[ax] == 0) ? 1 : -1;
   const int64_t mi = fidx(A, in[0], in[1], in[2]);
-  const R fin = e_interior<R>(A, P, c, in[0], in[1], in[2], lsin, lcos);
+  const R fin = e_interior<R>(A, P, c, in[0], in[1], in[2], mi, lsin, lcos);
   Fn[m] = Fo[mi] + R(A.cm[ax]) * (fin - Fo[m]);
 }
 
