@@ -2,26 +2,50 @@
 """Throughput of the per-electron PIC step with MC photon emission on one
 MI355X, in electron-steps/s.
 
-Default workload: the 2D3V gold-slab configuration (2048x1024 cells at
+Headline workload: the 2D3V gold-slab configuration (2048x1024 cells at
 lambda/64, Au q=69 slab 2 um thick at n_e = 200 n_c, 16 electrons/cell =
 2,097,152 electrons, a0 = 270 Gaussian w0 = 3 um, 2000 steps), FP32 bulk with
-FP64 optical depth, weights and energy sums; the same run in FP64 is timed
-beside it.  A "step" is one full step of every electron (gather, push, eta,
-NCS, bremsstrahlung, recoil, append, move + deposit) plus the field solve.
+FP64 optical depth, weights and energy sums, with the same run in FP64 beside
+it.  A "step" is one full step of every electron (gather, push, eta, NCS,
+bremsstrahlung, recoil, append, move + deposit) plus the field solve and the
+periodic tile sort.
 
-    python bench.py [--gpus 1] [--steps 2000] [--warmup 20]
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
 
-Prints one JSON line.  The timed region starts from a freshly created
-context (all state already resident in HBM) and covers exactly --steps
-steps, bracketed by torch.cuda.synchronize().
+The K timed steps are a window of the workload's own run, placed so that it is
+centred on the step at which the peak of the laser envelope reaches the slab
+front (the laser-plasma interaction, where emission happens); the steps
+before the window are an untimed lead-in on the same context ("lead_in_steps"
+in the output).  K >= the workload's length times the whole run.  W warm-up
+steps run first on a separate context.  The timed region starts with all state
+resident in HBM and is bracketed by a synchronisation of libpic's stream and
+torch.cuda.synchronize().
+
+Beside the headline, the JSON line carries (each leg's failure is recorded in
+"errors" and never suppresses the line):
+  fp64 / fp32_over_fp64  the same window in FP64;
+  full_run               the whole 2000-step run in both precisions, with the
+                         FP32-vs-FP64 criteria (photon count within 3 sigma,
+                         spectrum KS p > 0.01, radiated energy within 1%) and
+                         two more FP64 seeds as the run-to-run spread;
+  roofline               the electron-step kernel on the 3D gold slab (134M
+                         electrons, whose 10 GB of state no cache holds), HBM
+                         bound: algorithmic bytes per launch / average launch
+                         time from HIP events on the kernel's stream;
+  cpu_baseline           the FP64 oracle on the host over the same window of a
+                         transverse slice of the headline workload;
+  serving, thick_target  scan-job server runs and the bremsstrahlung benchmark.
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
+import subprocess
 import sys
 import time
+import traceback
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -29,11 +53,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # Non-packed FP32 (and FP64) VALU issue of MI355X: 256 CU x 4 SIMD x 16 lanes
 # x 2.4 GHz, one lane operation per lane and cycle (packed FP32 is disabled).
-ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+ALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # algorithmic lane operations per electron-step that every live electron
 # executes (gather, Boris, eta, NCS decrement, move, deposit, stats), quarter-
 # rate operations counted 4; the conditional brem test and event sampling are
-# not included
+# not included.  An estimate from the method, not a counter.
 ALU_OPS = {1: 292, 2: 548, 3: 1366}
 KERNEL_SOURCES = ["step.hip", "pic_internal.hpp", "philox.hpp"]
 # algorithmic bytes per electron-step of the step kernel: the electron state
@@ -43,21 +67,48 @@ STATE_BYTES = {("fp32", 1): 60, ("fp32", 2): 68, ("fp32", 3): 76,
                ("fp64", 1): 92, ("fp64", 2): 108, ("fp64", 3): 124}
 
 
-def _workload(name, precision, steps):
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _workload(name, precision, steps=None):
     from paper_1612_07592_amd import workloads as W
     if name == "c2":
-        w = W.c2(steps=steps, precision=precision)
+        w = W.c2(precision=precision)
     elif name == "c1":
-        w = W.c1(steps)
-        w["precision"] = precision
+        w = W.c1()
     elif name == "c5":
-        w = W.c5(steps)
-        w["precision"] = precision
+        w = W.c5()
     elif name == "thick":
-        w = W.thick_target(steps, precision)
+        w = W.thick_target(precision=precision)
     else:
         raise SystemExit(f"unknown workload {name}")
+    w["precision"] = precision
+    if steps is not None:
+        w["steps"] = steps
     return w
+
+
+def step_dt(w):
+    """Time step in 1/omega0 (cell sizes in c/omega0 = lambda / (2 pi))."""
+    dx = [d * 2.0 * math.pi for d in w["dx_lambda"][:w["dims"]]]
+    return w.get("cfl", 0.95) / math.sqrt(sum(1.0 / (d * d) for d in dx))
+
+
+def peak_step(w):
+    """Step at which the peak of the sin^2 envelope (emitted at the left
+    boundary at half the pulse length) reaches the slab front."""
+    t = math.pi * w.get("duration_cycles", 10.0) + 2.0 * math.pi * w["x0_lambda"]
+    return int(round(t / step_dt(w)))
+
+
+def window(w, k):
+    """(lead_in, k) of a k-step window centred on peak_step, inside the run."""
+    total = int(w["steps"])
+    if k >= total:
+        return 0, k
+    lead = peak_step(w) - k // 2
+    return max(0, min(lead, total - k)), k
 
 
 def _kernel_hash():
@@ -77,8 +128,8 @@ def _measured_traffic(workload, precision):
     d = json.load(open(path))
     for e in d.get("entries", []):
         if (e["kernel_sha"] == _kernel_hash() and e["workload"] == workload
-                and e["precision"] == precision):
-            return e["bytes_per_launch"]
+                and e["precision"] == precision and e.get("bytes_per_launch")):
+            return e
     return None
 
 
@@ -103,48 +154,205 @@ def _pencil_beam(w):
     return f if "beam_energy_mev" in w else None
 
 
-def run_gpu(w, tables, steps, warmup, torch, photons=False, kernel_times=True):
-    """Time `steps` steps from a fresh context.  The wall-clock run records no
-    events; a second identical run, with HIP events on the context's stream
-    around every launch group, gives the per-kernel times."""
+def _esteps(s):
+    return int(s.pic_emission_stats()["electron_steps"])
+
+
+def run_window(w, tables, lead, k, torch, warmup=0, photons=False, events=True, wall=True):
+    """Lead-in of `lead` untimed steps, then k steps timed on the wall clock
+    (no events recorded), on a fresh context; optionally a second identical
+    context whose k window steps carry HIP events for per-kernel times (the
+    events are recorded on libpic's stream, around every launch group)."""
     from paper_1612_07592_amd import binding
     beam = _pencil_beam(w)
+    out = dict(lead_in=lead, steps=k)
     if warmup > 0:
         s = binding.Sim(w, tables)
         if beam:
             beam(s)
         s.pic_step(warmup)
-        s.pic_emission_stats()
+        s.synchronize()
         s.pic_destroy()
-    s = binding.Sim(w, tables)
-    if beam:
-        beam(s)
-    s.synchronize()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s.pic_step(steps)
-    s.synchronize()          # libpic's own HIP runtime (torch's does not see its queues)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    st = s.pic_emission_stats()
-    ph = s.photons() if photons else None
-    s.pic_destroy()
-    out = dict(wall_s=t1 - t0, stats=st, photons=ph, step_kernel_ms=None, field_ms=None,
-               sort_ms=None, step_launches=0)
-    if kernel_times:
+    if wall:
         s = binding.Sim(w, tables)
         if beam:
             beam(s)
-        s.profile(True)
-        s.pic_step(steps)
-        ms, n = s.profile_read()
+        if lead:
+            s.pic_step(lead)
+        s.synchronize()
+        e0 = _esteps(s)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.pic_step(k)
+        s.synchronize()          # libpic's own HIP runtime (torch's does not see its queues)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st = s.pic_emission_stats()
+        out.update(wall_s=t1 - t0, window_esteps=int(st["electron_steps"]) - e0, stats=st,
+                   photons=s.photons() if photons else None)
         s.pic_destroy()
-        out.update(step_kernel_ms=float(ms[0]), field_ms=float(ms[1]), sort_ms=float(ms[2]),
-                   step_launches=int(n[0]), profiled_wall_ms=float(ms.sum()))
+    if events:
+        s = binding.Sim(w, tables)
+        if beam:
+            beam(s)
+        if lead:
+            s.pic_step(lead)
+        s.synchronize()
+        e0 = _esteps(s)
+        s.profile(True)
+        s.pic_step(k)
+        ms, n = s.profile_read()
+        st = s.pic_emission_stats()
+        if not wall:
+            out.update(stats=st, photons=s.photons() if photons else None)
+        s.pic_destroy()
+        out.update(window_esteps=int(st["electron_steps"]) - e0,
+                   step_kernel_ms=float(ms[0]), field_ms=float(ms[1]), sort_ms=float(ms[2]),
+                   step_launches=int(n[0]), profiled_ms=float(ms.sum()))
     return out
 
 
-def thick_target_line(args, tables, torch):
+def precision_check(s32, s64, p32=None, p64=None):
+    """FP32-mixed against FP64 on the same workload and Philox streams, each
+    criterion stated per result: kept-photon count within 3 sigma (Poisson),
+    photon-energy spectrum two-sample KS p > 0.01, total radiated energy
+    within 1%.  Missing data (no photons yet) gives None, never an error."""
+    n32, n64 = sum(s32["kept"]), sum(s64["kept"])
+    sigma = max(n64, 1) ** 0.5
+    e32 = s32["e_rad_kept"][0] + s32["e_rad_kept"][1] + s32["e_rad_dropped"]
+    e64 = s64["e_rad_kept"][0] + s64["e_rad_kept"][1] + s64["e_rad_dropped"]
+    out = {"photon_count": {"fp32": n32, "fp64": n64, "z": (n32 - n64) / sigma,
+                            "pass": abs(n32 - n64) <= 3 * sigma},
+           "radiated_energy": {"fp32": e32, "fp64": e64,
+                               "rel": (e32 - e64) / e64 if e64 else None,
+                               "pass": (abs(e32 - e64) <= 0.01 * abs(e64)) if e64 else None}}
+    ks = {"statistic": None, "p": None, "pass": None, "n": [0, 0]}
+    if p32 is not None and p64 is not None and len(p32["energy"]) and len(p64["energy"]):
+        from scipy import stats as sst
+        r = sst.ks_2samp(p32["energy"], p64["energy"])
+        ks = {"statistic": float(r.statistic), "p": float(r.pvalue),
+              "n": [len(p32["energy"]), len(p64["energy"])], "pass": float(r.pvalue) > 0.01}
+    out["spectrum_ks"] = ks
+    if n64 == 0 and n32 == 0:
+        out["note"] = "no photons kept in this window"
+    return out
+
+
+def _max_or_none(vals):
+    vals = [v for v in vals if v is not None]
+    return max(vals) if vals else None
+
+
+def seed_spread(pc, refs):
+    """Each FP32 difference against twice the largest difference between the
+    FP64 run and FP64 runs with other seeds (None where a figure is absent)."""
+    n64 = pc["photon_count"]["fp64"]
+    dn = _max_or_none([abs(q["photon_count"]["fp32"] - q["photon_count"]["fp64"]) for q in refs])
+    de = _max_or_none([abs(q["radiated_energy"]["rel"]) if q["radiated_energy"]["rel"] is not None
+                       else None for q in refs])
+    dk = _max_or_none([q["spectrum_ks"]["statistic"] for q in refs])
+    rel = pc["radiated_energy"]["rel"]
+    ks = pc["spectrum_ks"]["statistic"]
+    return {
+        "photon_count": abs(pc["photon_count"]["fp32"] - n64) <= 2.0 * max(dn or 0, 3.0 * n64 ** 0.5),
+        "radiated_energy": (abs(rel) <= max(0.01, 2.0 * (de or 0.0))) if rel is not None else None,
+        "spectrum_ks": (ks <= 2.0 * dk) if (ks is not None and dk) else None}
+
+
+def full_run_leg(w32, tables, torch):
+    """The whole run in FP32 and FP64 (wall clock), the FP32-vs-FP64 criteria
+    on it, and FP64 with the next two seeds as the run-to-run spread."""
+    total = int(w32["steps"])
+    r32 = run_window(w32, tables, 0, total, torch, photons=True, events=False)
+    w64 = dict(w32, precision="fp64")
+    r64 = run_window(w64, tables, 0, total, torch, photons=True, events=False)
+    v32 = r32["window_esteps"] / r32["wall_s"]
+    v64 = r64["window_esteps"] / r64["wall_s"]
+    pc = precision_check(r32["stats"], r64["stats"], r32["photons"], r64["photons"])
+    refs = []
+    for k in (1, 2):
+        rr = run_window(dict(w64, seed=int(w64["seed"]) + k), tables, 0, total, torch,
+                        photons=True, events=False)
+        refs.append(precision_check(rr["stats"], r64["stats"], rr["photons"], r64["photons"]))
+    pc["reference_fp64_other_seeds"] = refs
+    pc["within_seed_spread"] = seed_spread(pc, refs)
+    st = r32["stats"]
+    out = {"steps": total, "fp32": {"value": v32, "ms_per_step": r32["wall_s"] * 1e3 / total,
+                                    "events": st["events"], "kept": st["kept"],
+                                    "overflow": st["overflow"]},
+           "fp64": {"value": v64, "ms_per_step": r64["wall_s"] * 1e3 / total,
+                    "events": r64["stats"]["events"], "kept": r64["stats"]["kept"]},
+           "fp32_over_fp64": v32 / v64, "fp32_vs_fp64": pc}
+    log(f"full run {total} steps: fp32 {v32:.3e}, fp64 {v64:.3e} e-steps/s; count z "
+        f"{pc['photon_count']['z']:+.2f}, energy rel {pc['radiated_energy']['rel']}, "
+        f"KS p {pc['spectrum_ks']['p']}")
+    return out
+
+
+def roofline_leg(name, k, tables, torch, with_fp64=True):
+    """HBM roofline of the electron-step kernel on the 3D gold slab: the
+    window of k steps centred on the interaction, HIP events around every
+    launch from step 0 (so that the average covers the same launches as a
+    kernel trace of this process)."""
+    from paper_1612_07592_amd import binding
+    w = _workload(name, "fp32")
+    lead, k = window(w, k)
+    s = binding.Sim(w, tables)
+    s.synchronize()
+    s.profile(True)
+    if lead:
+        s.pic_step(lead)
+    ms_a, n_a = s.profile_read()
+    e_a = _esteps(s)
+    s.profile(True)
+    s.pic_step(k)
+    ms_b, n_b = s.profile_read()
+    st = s.pic_emission_stats()
+    s.pic_destroy()
+    e_b = int(st["electron_steps"]) - e_a
+    dims = int(w["dims"])
+    bpe = STATE_BYTES[("fp32", dims)]
+    launches = int(n_a[0] + n_b[0])
+    kern_ms = float(ms_a[0] + ms_b[0])
+    esteps = e_a + e_b
+    avg_us = kern_ms * 1e3 / max(1, launches)
+    achieved = bpe * esteps / (kern_ms * 1e-3) / 1e9
+    lane_ops = ALU_OPS[dims] * esteps / (kern_ms * 1e-3)
+    tr = _measured_traffic(w["name"], "fp32")
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": (tr["bytes_per_launch"] / 1e9 * launches / (kern_ms * 1e-3)) if tr else None,
+            "traffic_bytes_per_launch": tr["bytes_per_launch"] if tr else None,
+            "traffic_over_algorithmic": (tr["bytes_per_launch"] / (bpe * esteps / launches)) if tr else None,
+            "kernel": f"k_electron_step<float, {dims}>", "workload": w["name"],
+            "electrons": _num_electrons(w), "bytes_per_electron_step": bpe,
+            "electron_steps_per_launch": esteps / max(1, launches),
+            "launches": launches, "kernel_avg_us": avg_us,
+            "steps": f"0..{lead + k} (lead-in {lead} + window {k}, all launches of the context)",
+            "window_kernel_avg_us": float(ms_b[0]) * 1e3 / max(1, int(n_b[0])),
+            "window_frac": bpe * e_b / (float(ms_b[0]) * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "window_electron_steps_per_s": e_b / (float(ms_b.sum()) * 1e-3),
+            "untiled_fraction": st["untiled_steps"] / max(1, int(st["electron_steps"])),
+            "alu_lane_ops": {"estimate_per_electron_step": ALU_OPS[dims],
+                             "achieved_per_s": lane_ops, "peak_per_s": ALU_PEAK_LANE_OPS,
+                             "frac": lane_ops / ALU_PEAK_LANE_OPS,
+                             "note": "lane operations counted from the method, not counters"}}
+    log(f"roofline {w['name']}: {avg_us:.1f} us per launch, {achieved:.0f} GB/s "
+        f"(frac {roof['frac']:.3f}); window {roof['window_kernel_avg_us']:.1f} us")
+    out = {"roofline": roof}
+    if with_fp64:
+        w64 = dict(w, precision="fp64")
+        r64 = run_window(w64, tables, lead, k, torch, events=False)
+        r32 = run_window(w, tables, lead, k, torch, events=False)
+        v64 = r64["window_esteps"] / r64["wall_s"]
+        v32 = r32["window_esteps"] / r32["wall_s"]
+        out["fp32_vs_fp64_3d"] = {"workload": w["name"], "lead_in_steps": lead, "steps": k,
+                                  "fp32": v32, "fp64": v64, "fp32_over_fp64": v32 / v64}
+        log(f"3D window: fp32 {v32:.3e}, fp64 {v64:.3e} e-steps/s")
+    return out
+
+
+def thick_target_line(tables, torch):
     """Bremsstrahlung-dominated workload: 100 MeV pencil beam of 2.1M
     electrons into 5 mm of solid gold, particle-only, FP32, 2000 steps; the
     per-step Eq. (4) trial against the free-path form."""
@@ -153,126 +361,148 @@ def thick_target_line(args, tables, torch):
     for form, fp in (("per_step_trial", False), ("free_path", True)):
         w = W.thick_target(2000, "fp32")
         w["brem_freepath"] = fp
-        r = run_gpu(w, tables, 2000, 0, torch, kernel_times=True)
+        r = run_window(w, tables, 0, 2000, torch)
         st = r["stats"]
         res["electrons"] = _num_electrons(w)
-        res[form] = {"value": st["electron_steps"] / r["wall_s"],
+        res[form] = {"value": r["window_esteps"] / r["wall_s"],
                      "kernel_avg_us": r["step_kernel_ms"] * 1e3 / max(1, r["step_launches"]),
                      "brem_events": st["events"][1], "e_rad_brem": st["e_rad_kept"][1]}
     res["free_path_speedup"] = res["free_path"]["value"] / res["per_step_trial"]["value"]
-    print(f"[bench] thick target: per-step {res['per_step_trial']['value']:.3e}, free path "
-          f"{res['free_path']['value']:.3e} e-steps/s ({res['free_path_speedup']:.2f}x)",
-          file=sys.stderr, flush=True)
+    log(f"thick target: per-step {res['per_step_trial']['value']:.3e}, free path "
+        f"{res['free_path']['value']:.3e} e-steps/s ({res['free_path_speedup']:.2f}x)")
     return res
 
 
-def precision_check(r32, r64):
-    """FP32-mixed against FP64 on the same workload and Philox streams:
-    kept-photon count within 3 sigma (Poisson), photon-energy spectrum
-    two-sample KS p > 0.01, total radiated energy within 1%."""
-    from scipy import stats as sst
-    s32, s64 = r32["stats"], r64["stats"]
-    n32, n64 = sum(s32["kept"]), sum(s64["kept"])
-    sigma = max(n64, 1) ** 0.5
-    e32 = s32["e_rad_kept"][0] + s32["e_rad_kept"][1] + s32["e_rad_dropped"]
-    e64 = s64["e_rad_kept"][0] + s64["e_rad_kept"][1] + s64["e_rad_dropped"]
-    out = {"photon_count": {"fp32": n32, "fp64": n64, "z": (n32 - n64) / sigma,
-                            "pass": abs(n32 - n64) <= 3 * sigma},
-           "radiated_energy": {"fp32": e32, "fp64": e64, "rel": (e32 - e64) / e64 if e64 else None,
-                               "pass": bool(e64) and abs(e32 - e64) <= 0.01 * abs(e64)}}
-    p32, p64 = r32["photons"], r64["photons"]
-    if p32 is not None and p64 is not None and len(p32["energy"]) and len(p64["energy"]):
-        ks = sst.ks_2samp(p32["energy"], p64["energy"])
-        out["spectrum_ks"] = {"statistic": float(ks.statistic), "p": float(ks.pvalue),
-                              "n": [len(p32["energy"]), len(p64["energy"])],
-                              "pass": float(ks.pvalue) > 0.01}
-    else:
-        out["spectrum_ks"] = {"p": None, "pass": None, "n": [0, 0]}
-    return out
-
-
-def serving(args, torch):
+def serving(args):
     """Scan jobs through the continuous-batching server: the 8-job
     intensity x target batch (FP32, FP64, and FP32 one job after another),
     then the first --c4-jobs jobs of the Poisson stream."""
     from paper_1612_07592_amd import binding, serving as SV
     from paper_1612_07592_amd import workloads as W
     tb = {13: binding.pic_build_tables(13, 1.0, 16), 79: binding.pic_build_tables(79, 1.0, 16)}
-    log = lambda m: print(f"[serve] {m}", file=sys.stderr, flush=True)
+    slog = lambda m: print(f"[serve] {m}", file=sys.stderr, flush=True)
     out = {}
     jobs = W.c3_jobs(args.c3_steps)
     _, out["c3_fp32"] = SV.run_batch(jobs, tb)
-    log(f"c3 fp32 {out['c3_fp32']['electron_steps_per_s']:.3e} e-steps/s")
+    slog(f"c3 fp32 {out['c3_fp32']['electron_steps_per_s']:.3e} e-steps/s")
     _, out["c3_fp64"] = SV.run_batch([dict(w, precision="fp64") for w in jobs], tb)
-    log(f"c3 fp64 {out['c3_fp64']['electron_steps_per_s']:.3e} e-steps/s")
+    slog(f"c3 fp64 {out['c3_fp64']['electron_steps_per_s']:.3e} e-steps/s")
     out["c3_fp32_sequential"] = SV.run_sequential(jobs, tb)
-    log(f"c3 fp32 one at a time {out['c3_fp32_sequential']['electron_steps_per_s']:.3e} e-steps/s")
+    slog(f"c3 fp32 one at a time {out['c3_fp32_sequential']['electron_steps_per_s']:.3e} e-steps/s")
+    out["scan_fp32_over_fp64"] = (out["c3_fp32"]["electron_steps_per_s"]
+                                  / out["c3_fp64"]["electron_steps_per_s"])
+    out["batched_over_sequential"] = (out["c3_fp32"]["electron_steps_per_s"]
+                                      / out["c3_fp32_sequential"]["electron_steps_per_s"])
     if args.c4_jobs > 0:
         arr = W.c4_stream()[:args.c4_jobs]
-        _, c4 = SV.run_stream(arr, tb, log=log)
+        _, c4 = SV.run_stream(arr, tb, log=slog)
         offered = sum(W.num_electrons(w) * w["steps"] for _, w in arr) / max(arr[-1][0], 1e-9)
         c4["offered_electron_steps_per_s"] = offered
         c4["arrival_rate_per_s"] = 4.0
+        c4["jobs_of_stream"] = f"first {len(arr)} of 500"
         out["c4_stream"] = c4
-        log(f"c4 {c4['jobs']} jobs: p50 {c4['latency_p50_s']:.2f} s p99 {c4['latency_p99_s']:.2f} s "
-            f"{c4['electron_steps_per_s']:.3e} e-steps/s")
-    out["scan_fp32_over_fp64"] = out["c3_fp32"]["electron_steps_per_s"] / out["c3_fp64"]["electron_steps_per_s"]
+        slog(f"c4 {c4['jobs']} jobs: p50 {c4['latency_p50_s']:.2f} s p99 "
+             f"{c4['latency_p99_s']:.2f} s {c4['electron_steps_per_s']:.3e} e-steps/s")
     return out
 
 
-def cpu_baseline(w, budget_s=15.0):
-    """The FP64 oracle, as is, on the host cores: a bounded number of steps of
-    the same workload from t = 0."""
+def host_cpu():
+    """Host processor as the GPU machine reports it."""
+    info = {"nproc": None, "affinity": None, "model": None, "lscpu_cpus": None}
+    try:
+        info["nproc"] = int(subprocess.run(["nproc"], capture_output=True, text=True).stdout.strip())
+    except Exception:
+        pass
+    try:
+        info["affinity"] = len(os.sched_getaffinity(0))
+    except Exception:
+        pass
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True).stdout
+        for line in txt.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() == "Model name":
+                info["model"] = v.strip()
+            elif k.strip() == "CPU(s)":
+                info["lscpu_cpus"] = v.strip()
+    except Exception:
+        pass
+    return info
+
+
+def cpu_baseline(w_full, lead, k, ny=64, budget_s=12.0):
+    """The FP64 oracle, as it stands, on the host cores, over the same window
+    of a transverse slice of the workload (all of its x extent, ny of its
+    cells across the laser axis, so the slice holds the most intense part of
+    the interaction).  The lead-in is untimed; the window is extended past k
+    steps, if needed, to about budget_s seconds of CPU work."""
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     import conftest
     import oracle
     oracle.build(force=False)
-    tables = conftest.oracle_tables(int(w["Z"]))
-    ww = dict(w)
-    ww["precision"] = "fp64"
-    ww["photon_capacity"] = 1 << 22
-    nt = min(16, os.cpu_count() or 1)
-    o = oracle.OracleSim(ww, tables, nthreads=nt)
+    tables = conftest.oracle_tables(int(w_full["Z"]))
+    w = dict(w_full, precision="fp64", photon_capacity=1 << 22)
+    if w["dims"] >= 2:
+        w["n"] = [w["n"][0], min(ny, w["n"][1])] + list(w["n"][2:])
+    cpu = host_cpu()
+    nt = max(1, min(16, cpu["affinity"] or os.cpu_count() or 1))
+    o = oracle.OracleSim(w, tables, nthreads=nt)
+    t0 = time.perf_counter()
+    if lead:
+        o.step(lead)
+    t_lead = time.perf_counter() - t0
     t0 = time.perf_counter()
     o.step(1)
     one = time.perf_counter() - t0
-    k = max(1, min(200, int(budget_s / max(one, 1e-6))))
+    kk = max(k - 1, int(budget_s / max(one, 1e-6)))
+    kk = min(kk, max(1, int(w_full["steps"]) - lead - 1))
     t0 = time.perf_counter()
-    o.step(k)
+    o.step(kk)
     dt = time.perf_counter() - t0
     live = o.stats()["live"]
     o.close()
-    return dict(value=live * k / dt, unit="electron-steps/s", cores=nt, kind="oracle",
-                sample=f"FP64 oracle, steps 1..{k + 1} of the same workload from t=0 "
-                       f"({live} electrons, {dt:.1f} s on {nt} threads)")
+    return dict(value=live * kk / dt, unit="electron-steps/s", cores=nt, kind="oracle",
+                sample=f"FP64 oracle on {nt} threads, {w['name']} sliced to {w['n'][:w['dims']]} "
+                       f"cells ({o.N} electrons), steps {lead + 1}..{lead + 1 + kk} after an "
+                       f"untimed lead-in of {lead + 1} steps ({t_lead:.1f} s); {live} live, "
+                       f"{dt:.1f} s timed",
+                host=cpu)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=200,
+                    help="timed steps: a window of the workload's run centred on the interaction")
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--precision", default="fp32")
-    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--roofline-workload", default="c5")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison runs")
+    ap.add_argument("--no-full-run", action="store_true")
+    ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--sort-every", type=int, default=0,
-                    help="tile-sort interval in steps (0 = library default, -1 = never)")
     ap.add_argument("--no-serving", action="store_true", help="skip the scan-job server runs")
+    ap.add_argument("--no-thick", action="store_true", help="skip the thick-target runs")
+    ap.add_argument("--only", default=None,
+                    help="run only the headline and this leg (roofline, full, cpu, serving, thick)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of this many MiB (HBM counter calibration)")
     ap.add_argument("--c3-steps", type=int, default=1000)
     ap.add_argument("--brem-freepath", action="store_true",
                     help="time the free-path form of the bremsstrahlung test instead of the per-step trial")
-    ap.add_argument("--no-freepath-line", action="store_true",
-                    help="skip the free-path bremsstrahlung run reported beside the main one")
     ap.add_argument("--c4-jobs", type=int, default=24,
                     help="jobs of the Poisson stream served (0 = none)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a "
+        print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU split is a "
                                    "design note, not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
+    legs = {"roofline": not args.no_roofline, "full": not args.no_full_run and not args.no_fp64,
+            "cpu": not args.no_cpu_baseline, "serving": not args.no_serving,
+            "thick": not args.no_thick, "fp64": not args.no_fp64}
+    if args.only:
+        legs = {k: (k == args.only) for k in legs}
     import torch
     assert torch.cuda.is_available(), "no GPU visible"
     from paper_1612_07592_amd import binding
@@ -284,109 +514,96 @@ def main():
         torch.cuda.synchronize()
         torch.mul(a, 1.0, out=b)  # an elementwise kernel: reads and writes n floats
         torch.cuda.synchronize()
-        print(f"[bench] copy calibration: {n * 4} bytes read, {n * 4} written", file=sys.stderr, flush=True)
+        log(f"copy calibration: {n * 4} bytes read, {n * 4} written")
         del a, b
-    w = _workload(args.workload, args.precision, args.steps)
-    if args.sort_every or "sort_every" not in w:
-        w["sort_every"] = args.sort_every
+    w = _workload(args.workload, args.precision)
     w["brem_freepath"] = args.brem_freepath
+    lead, k = window(w, args.steps)
     t0 = time.perf_counter()
     tables = binding.pic_build_tables(int(w["Z"]), 1.0, 16)
-    t_tables = time.perf_counter() - t0
-    print(f"[bench] tables built in {t_tables:.1f} s; {args.workload} {args.precision} "
-          f"{args.steps} steps", file=sys.stderr, flush=True)
-    r = run_gpu(w, tables, args.steps, args.warmup, torch, photons=not args.no_fp64)
-    st = r["stats"]
-    esteps = int(st["electron_steps"])
-    value = esteps / r["wall_s"]
+    log(f"tables built in {time.perf_counter() - t0:.1f} s; {w['name']} {args.precision}: "
+        f"{k} timed steps after a lead-in of {lead} (run of {w['steps']}, envelope peak at the "
+        f"slab front at step {peak_step(w)})")
     dims = int(w["dims"])
-    bpe = STATE_BYTES[(args.precision, dims)]
-    achieved = bpe * esteps / (r["step_kernel_ms"] * 1e-3) / 1e9
-    ops = ALU_OPS[dims]
-    alu = ops * esteps / (r["step_kernel_ms"] * 1e-3) / 1e12
-    launches = max(1, r["step_launches"])
     out = {
-        "metric": "electron-steps/s",
-        "value": value,
-        "unit": "electron-steps/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": r["wall_s"] * 1e3 / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32" if args.precision == "fp32" else "f64",
-        "data": "synthetic",
+        "metric": "electron-steps/s", "value": None, "unit": "electron-steps/s", "n_gpus": 1,
+        "steps": k, "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f64", "data": "synthetic",
         "config": {"workload": w["name"], "dims": dims, "cells": list(w["n"]),
-                   "electrons": _num_electrons(w),
-                   "precision": args.precision, "a0": w["a0"], "Z": w["Z"],
+                   "electrons": _num_electrons(w), "precision": args.precision,
+                   "a0": w["a0"], "Z": w["Z"], "run_steps": int(w["steps"]),
+                   "lead_in_steps": lead, "window": [lead, lead + k],
                    "brem": "free-path" if args.brem_freepath else "per-step trial"},
-        "roofline": {"bound": "alu", "achieved": alu, "peak": ALU_PEAK_TOPS, "unit": "TFLOP/s",
-                     "frac": alu / ALU_PEAK_TOPS,
-                     "traffic": _measured_traffic(w["name"], args.precision),
-                     "kernel": f"k_electron_step<{'float' if args.precision == 'fp32' else 'double'},{dims}>",
-                     "ops_per_electron_step": ops,
-                     "electron_steps_per_launch": esteps / launches,
-                     "kernel_avg_us": r["step_kernel_ms"] * 1e3 / launches,
-                     "hbm": {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                             "frac": achieved / HBM_PEAK_GBS, "bytes_per_electron_step": bpe}},
-        "time_share": {"electron_step": r["step_kernel_ms"] / (r["wall_s"] * 1e3),
-                       "field_solve": r["field_ms"] / (r["wall_s"] * 1e3),
-                       "sort": r["sort_ms"] / (r["wall_s"] * 1e3)},
-        "kernel_ms": {"electron_step": r["step_kernel_ms"], "field_solve": r["field_ms"],
-                      "sort": r["sort_ms"]},
-        "untiled_fraction": st["untiled_steps"] / max(1, esteps),
-        "emission": {"events": st["events"], "kept": st["kept"], "dropped_ncs": st["dropped_ncs"],
-                     "overflow": st["overflow"], "e_rad_kept": st["e_rad_kept"]},
+        "roofline": None, "cpu_baseline": None, "errors": {},
     }
-    print(f"[bench] {args.precision}: {value:.3e} e-steps/s, step kernel "
-          f"{out['roofline']['kernel_avg_us']:.1f} us, {alu:.2f} Tops/s, {achieved:.0f} GB/s",
-          file=sys.stderr, flush=True)
-    if not args.no_freepath_line and not args.brem_freepath:
-        # the same workload with the free-path form of the collision test
-        rf = run_gpu(dict(w, brem_freepath=True), tables, args.steps, 0, torch, kernel_times=True)
-        vf = rf["stats"]["electron_steps"] / rf["wall_s"]
-        out["brem_free_path"] = {
-            "value": vf, "over_per_step_trial": vf / value,
-            "kernel_avg_us": rf["step_kernel_ms"] * 1e3 / max(1, rf["step_launches"]),
-            "events": rf["stats"]["events"], "kept": rf["stats"]["kept"]}
-        print(f"[bench] free-path brem: {vf:.3e} e-steps/s ({vf / value:.3f}x)", file=sys.stderr, flush=True)
-    if not args.no_freepath_line and args.workload == "c2":
-        out["thick_target"] = thick_target_line(args, tables, torch)
-    if not args.no_fp64 and args.precision == "fp32":
-        w64 = _workload(args.workload, "fp64", args.steps)
-        w64["sort_every"] = w["sort_every"]
-        w64["brem_freepath"] = args.brem_freepath
-        r64 = run_gpu(w64, tables, args.steps, 0, torch, photons=True, kernel_times=True)
-        v64 = r64["stats"]["electron_steps"] / r64["wall_s"]
-        out["fp64"] = {"value": v64, "ms_per_step": r64["wall_s"] * 1e3 / args.steps,
-                       "kernel_avg_us": r64["step_kernel_ms"] * 1e3 / max(1, r64["step_launches"]),
-                       "events": r64["stats"]["events"], "kept": r64["stats"]["kept"]}
-        out["fp32_over_fp64"] = value / v64
-        out["fp32_vs_fp64"] = precision_check(r, r64)
-        # run-to-run spread of the full PIC run: FP64 with the next two seeds
-        refs = []
-        for k in (1, 2):
-            rref = run_gpu(dict(w64, seed=int(w64["seed"]) + k), tables, args.steps, 0, torch,
-                           photons=True, kernel_times=False)
-            refs.append(precision_check(rref, r64))
-        pc = out["fp32_vs_fp64"]
-        pc["reference_fp64_other_seeds"] = refs
-        dn = max(abs(q["photon_count"]["fp32"] - q["photon_count"]["fp64"]) for q in refs)
-        de = max(abs(q["radiated_energy"]["rel"]) for q in refs)
-        dk = max(q["spectrum_ks"]["statistic"] or 0.0 for q in refs)
-        n64 = pc["photon_count"]["fp64"]
-        pc["within_seed_spread"] = {
-            "photon_count": abs(pc["photon_count"]["fp32"] - n64) <= 2.0 * max(dn, 3.0 * n64 ** 0.5),
-            "radiated_energy": abs(pc["radiated_energy"]["rel"]) <= max(0.01, 2.0 * de),
-            "spectrum_ks": (pc["spectrum_ks"]["statistic"] or 0.0) <= 2.0 * dk}
-        print(f"[bench] fp64: {v64:.3e} e-steps/s; {out['fp32_vs_fp64']}", file=sys.stderr, flush=True)
-    if not args.no_serving and args.workload == "c2":
-        out["serving"] = serving(args, torch)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(_workload(args.workload, "fp64", args.steps))
-    print(json.dumps(out), flush=True)
+
+    def leg(name, fn):
+        try:
+            return fn()
+        except Exception as e:  # record the failure in the line and go on
+            out["errors"][name] = f"{type(e).__name__}: {e}"
+            traceback.print_exc()
+            return None
+
+    try:
+        r = run_window(w, tables, lead, k, torch, warmup=args.warmup)
+        st = r["stats"]
+        value = r["window_esteps"] / r["wall_s"]
+        out.update(value=value, ms_per_step=r["wall_s"] * 1e3 / k)
+        out["kernel_ms"] = {"electron_step": r["step_kernel_ms"], "field_solve": r["field_ms"],
+                            "sort": r["sort_ms"], "launches": r["step_launches"]}
+        out["time_share"] = {kk: v / r["profiled_ms"] for kk, v in
+                             (("electron_step", r["step_kernel_ms"]), ("field_solve", r["field_ms"]),
+                              ("sort", r["sort_ms"]))}
+        avg = r["step_kernel_ms"] * 1e3 / max(1, r["step_launches"])
+        bpe = STATE_BYTES[(args.precision, dims)]
+        out["headline_kernel"] = {
+            "kernel": f"k_electron_step<{'float' if args.precision == 'fp32' else 'double'}, {dims}>",
+            "kernel_avg_us": avg,
+            "hbm_GBs": bpe * r["window_esteps"] / (r["step_kernel_ms"] * 1e-3) / 1e9,
+            "note": "this state fits the 256 MB Infinity Cache: not an HBM figure"}
+        out["emission"] = {"events": st["events"], "kept": st["kept"],
+                           "dropped_ncs": st["dropped_ncs"], "overflow": st["overflow"],
+                           "e_rad_kept": st["e_rad_kept"],
+                           "untiled_fraction": st["untiled_steps"] / max(1, st["electron_steps"])}
+        log(f"{args.precision}: {value:.3e} e-steps/s over steps {lead}..{lead + k}, step kernel "
+            f"{avg:.1f} us")
+        if legs["fp64"] and args.precision == "fp32":
+            def fp64_window():
+                r64 = run_window(dict(w, precision="fp64"), tables, lead, k, torch)
+                v64 = r64["window_esteps"] / r64["wall_s"]
+                out["fp64"] = {"value": v64, "ms_per_step": r64["wall_s"] * 1e3 / k,
+                               "kernel_avg_us": r64["step_kernel_ms"] * 1e3 / max(1, r64["step_launches"])}
+                out["fp32_over_fp64"] = value / v64
+                out["fp32_vs_fp64_window"] = precision_check(r["stats"], r64["stats"])
+                log(f"fp64 window: {v64:.3e} e-steps/s (fp32 {value / v64:.2f}x)")
+            leg("fp64", fp64_window)
+        if legs["full"] and args.precision == "fp32":
+            out["full_run"] = leg("full_run", lambda: full_run_leg(w, tables, torch))
+        if legs["roofline"]:
+            def roof():
+                tb = tables if args.roofline_workload in ("c2", "c5") else \
+                    binding.pic_build_tables(int(_workload(args.roofline_workload, "fp32")["Z"]), 1.0, 16)
+                res = roofline_leg(args.roofline_workload, k, tb, torch, with_fp64=legs["fp64"])
+                out["roofline"] = res["roofline"]
+                if "fp32_vs_fp64_3d" in res:
+                    out["fp32_vs_fp64_3d"] = res["fp32_vs_fp64_3d"]
+            leg("roofline", roof)
+        if legs["thick"] and args.workload == "c2":
+            out["thick_target"] = leg("thick_target", lambda: thick_target_line(tables, torch))
+        if legs["serving"] and args.workload == "c2":
+            out["serving"] = leg("serving", lambda: serving(args))
+        if legs["cpu"]:
+            out["cpu_baseline"] = leg("cpu_baseline", lambda: cpu_baseline(
+                _workload(args.workload, "fp64"), lead, k))
+    except Exception as e:
+        out["errors"]["headline"] = f"{type(e).__name__}: {e}"
+        traceback.print_exc()
+    finally:
+        print(json.dumps(out), flush=True)
+    if "headline" in out["errors"]:
+        sys.exit(1)
 
 
 if __name__ == "__main__":

@@ -3,6 +3,7 @@ header declares, validates configs and builds tables (no GPU calls)."""
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import re
 import subprocess
@@ -205,3 +206,56 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stdout
+
+
+def _bench():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    m = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(m)
+    return m
+
+
+def _zero_stats():
+    return dict(kept=[0, 0], e_rad_kept=[0.0, 0.0], e_rad_dropped=0.0, events=[0, 0])
+
+
+def test_bench_precision_check_without_photons():
+    """A window that ends before anything radiates (no photons, zero
+    radiated energy) yields None figures, not an exception, all the way
+    through the seed-spread summary."""
+    import numpy as np
+    b = _bench()
+    empty = dict(energy=np.zeros(0))
+    pc = b.precision_check(_zero_stats(), _zero_stats(), empty, empty)
+    assert pc["radiated_energy"]["rel"] is None and pc["radiated_energy"]["pass"] is None
+    assert pc["spectrum_ks"]["statistic"] is None and pc["spectrum_ks"]["p"] is None
+    assert pc["photon_count"]["z"] == 0.0
+    refs = [b.precision_check(_zero_stats(), _zero_stats()) for _ in range(2)]
+    s = b.seed_spread(pc, refs)
+    assert s["radiated_energy"] is None and s["spectrum_ks"] is None
+    assert s["photon_count"] is True
+    # one side radiated, the other not
+    one = dict(_zero_stats(), kept=[3, 0], e_rad_kept=[5.0, 0.0])
+    pc = b.precision_check(one, _zero_stats())
+    assert pc["radiated_energy"]["rel"] is None and pc["photon_count"]["fp32"] == 3
+
+
+def test_bench_window_is_centred_on_the_interaction():
+    """The timed window of the 2D gold slab sits around the step at which
+    the envelope peak reaches the slab front, inside the run; a window as
+    long as the run starts at step 0."""
+    b = _bench()
+    from paper_1612_07592_amd import workloads as W
+    w = W.c2()
+    pk = b.peak_step(w)
+    # the peak leaves the source at 5 periods and crosses 2 um: 7 periods
+    assert abs(pk * b.step_dt(w) - 14 * math.pi) < b.step_dt(w)
+    lead, k = b.window(w, 20)
+    assert lead <= pk <= lead + k and lead + k <= w["steps"]
+    assert b.window(w, w["steps"]) == (0, w["steps"])
+    lead, k = b.window(w, 1990)
+    assert lead + k <= w["steps"]
+    w5 = W.c5()
+    lead, k = b.window(w5, 20)
+    assert lead <= b.peak_step(w5) <= lead + k
