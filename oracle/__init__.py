@@ -40,16 +40,22 @@ def build(force: bool = True) -> str:
     only when it is missing or older than its sources); returns its path."""
     if not force and not _stale():
         return LIB
-    src = os.path.join(HERE, "oracle.c")
     tmp = LIB + ".tmp"
+    compile_source(os.path.join(HERE, "oracle.c"), tmp)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+def compile_source(src: str, out: str) -> str:
+    """gcc of one oracle source file (oracle.h beside it) into a shared
+    object, with the oracle's flags."""
     # -fno-builtin-sin/-cos: keep sin and cos separate libm calls (gcc would
     # otherwise merge them into sincos, whose results can differ by an ulp)
     cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fno-fast-math",
-           "-fno-builtin-sin", "-fno-builtin-cos", "-fopenmp", "-fPIC", "-shared", src, "-o", tmp,
+           "-fno-builtin-sin", "-fno-builtin-cos", "-fopenmp", "-fPIC", "-shared", src, "-o", out,
            "-lm"]
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    return out
 
 
 class _Cfg(C.Structure):
@@ -81,15 +87,18 @@ class _Stats(C.Structure):
                 ("e_rad_kept", C.c_double * 2), ("e_rad_dropped", C.c_double)]
 
 
-_lib = None
+_libs = {}
 
 
-def _load():
-    global _lib
-    if _lib is None:
-        if _stale():
+def _load(path=None):
+    """The oracle library (built in place when stale), or the shared object
+    at `path` built from a copy of the same sources (the pins' planted-error
+    checks compile altered copies)."""
+    key = path or LIB
+    if key not in _libs:
+        if path is None and _stale():
             build()
-        L = C.CDLL(LIB)
+        L = C.CDLL(key)
         P = C.c_void_p
         L.or_create.restype = P
         L.or_create.argtypes = [C.POINTER(_Cfg), C.POINTER(_Tab), C.c_int]
@@ -115,8 +124,20 @@ def _load():
         L.or_get_derived.argtypes = [P, C.c_void_p]
         L.or_get_current.argtypes = [P, C.c_void_p]
         L.or_philox.argtypes = [C.c_uint32] * 6 + [C.c_void_p]
-        _lib = L
-    return _lib
+        L.or_set_fields.argtypes = [P, C.c_void_p]
+        L.or_probe_field.restype = C.c_double
+        L.or_probe_field.argtypes = [P, C.c_int, C.c_void_p]
+        L.or_probe_boris.argtypes = [P, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.or_probe_eta.restype = C.c_double
+        L.or_probe_eta.argtypes = [P, C.c_void_p, C.c_void_p, C.c_void_p]
+        for name in ("or_probe_ncs_dtau", "or_probe_ncs_xi", "or_probe_brem_sigma"):
+            getattr(L, name).restype = C.c_double
+            getattr(L, name).argtypes = [P, C.c_double, C.c_double]
+        L.or_probe_brem_sigma.argtypes = [P, C.c_double]
+        L.or_probe_brem_eps.restype = C.c_double
+        L.or_probe_brem_eps.argtypes = [P, C.c_double, C.c_double]
+        _libs[key] = L
+    return _libs[key]
 
 
 def philox(ctr, key):
@@ -149,8 +170,8 @@ def flags_from(w):
 class OracleSim:
     """One oracle run of a workload dict (see ``workloads.py``) and tables."""
 
-    def __init__(self, w: dict, tables: dict, nthreads: int | None = None):
-        L = _load()
+    def __init__(self, w: dict, tables: dict, nthreads: int | None = None, lib: str | None = None):
+        L = _load(lib)
         c = _Cfg()
         c.dims = int(w["dims"])
         c.flags = flags_from(w)
@@ -275,6 +296,47 @@ class OracleSim:
         out = np.zeros(3 * m, dtype=np.int64)
         self._L.or_get_current(self._h, out.ctypes.data)
         return out.reshape(3, m)
+
+    def set_fields(self, F):
+        """Overwrite E and B (shape (6, size), the layout of fields())."""
+        m = int(self._L.or_field_size(self._h))
+        F = np.ascontiguousarray(F, dtype=np.float64).reshape(6 * m)
+        self._L.or_set_fields(self._h, F.ctypes.data)
+
+    # --- probes of single steps of the method (pins) ----------------------
+    def probe_field(self, comp, x):
+        """Gathered component comp (0..2 E, 3..5 B) at position x[3]."""
+        x = np.ascontiguousarray(x, dtype=np.float64).reshape(3)
+        return float(self._L.or_probe_field(self._h, int(comp), x.ctypes.data))
+
+    def probe_boris(self, E, B, p):
+        E = np.ascontiguousarray(E, dtype=np.float64).reshape(3)
+        B = np.ascontiguousarray(B, dtype=np.float64).reshape(3)
+        q = np.array(p, dtype=np.float64).reshape(3)
+        self._L.or_probe_boris(self._h, E.ctypes.data, B.ctypes.data, q.ctypes.data)
+        return q
+
+    def probe_eta(self, E, B, p):
+        E = np.ascontiguousarray(E, dtype=np.float64).reshape(3)
+        B = np.ascontiguousarray(B, dtype=np.float64).reshape(3)
+        p = np.ascontiguousarray(p, dtype=np.float64).reshape(3)
+        return float(self._L.or_probe_eta(self._h, E.ctypes.data, B.ctypes.data, p.ctypes.data))
+
+    def probe_ncs_dtau(self, eta, gamma):
+        return float(self._L.or_probe_ncs_dtau(self._h, float(eta), float(gamma)))
+
+    def probe_ncs_xi(self, eta, u):
+        u = np.atleast_1d(np.asarray(u, dtype=np.float64))
+        f = self._L.or_probe_ncs_xi
+        return np.array([f(self._h, float(eta), float(v)) for v in u])
+
+    def probe_brem_sigma(self, T):
+        return float(self._L.or_probe_brem_sigma(self._h, float(T)))
+
+    def probe_brem_eps(self, T, u):
+        u = np.atleast_1d(np.asarray(u, dtype=np.float64))
+        f = self._L.or_probe_brem_eps
+        return np.array([f(self._h, float(T), float(v)) for v in u])
 
     def derived(self):
         o = np.zeros(8)

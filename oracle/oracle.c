@@ -314,6 +314,9 @@ static void b_half(or_sim* s) {
     int lim[3];
     for (int a = 0; a < 3; ++a) lim[a] = s->act[a] ? (BSTAG[c][a] ? s->n[a] : s->n[a] + 1) : 1;
     double* Bc = s->B[c];
+#ifdef _OPENMP
+#pragma omp parallel for collapse(2) schedule(static) num_threads(s->nthreads)
+#endif
     for (int k = 0; k < lim[2]; ++k)
       for (int j = 0; j < lim[1]; ++j)
         for (int i = 0; i < lim[0]; ++i) {
@@ -372,6 +375,9 @@ static void e_full(or_sim* s, double lsin, double lcos) {
     int lim[3];
     for (int a = 0; a < 3; ++a) lim[a] = s->act[a] ? (ESTAG[c][a] ? s->n[a] : s->n[a] + 1) : 1;
     /* interior */
+#ifdef _OPENMP
+#pragma omp parallel for collapse(2) schedule(static) num_threads(s->nthreads)
+#endif
     for (int k = 0; k < lim[2]; ++k)
       for (int j = 0; j < lim[1]; ++j)
         for (int i = 0; i < lim[0]; ++i) {
@@ -381,6 +387,9 @@ static void e_full(or_sim* s, double lsin, double lcos) {
           if (nb == 0) Fn[fidx(s, i, j, k)] = e_interior(s, c, i, j, k, lsin, lcos);
         }
     /* faces (Mur), using the already computed interior neighbour */
+#ifdef _OPENMP
+#pragma omp parallel for collapse(2) schedule(static) num_threads(s->nthreads)
+#endif
     for (int k = 0; k < lim[2]; ++k)
       for (int j = 0; j < lim[1]; ++j)
         for (int i = 0; i < lim[0]; ++i) {
@@ -428,6 +437,119 @@ typedef struct {
   int clamped;
 } eres;
 
+/* E and B at x (grid coordinates g = x/dx per axis) from the Yee arrays:
+ * component c of E (c < 3) or of B (c >= 3). */
+static double field_at(const or_sim* s, int c, const double* g) {
+  return c < 3 ? gather1(s, s->E[c], ESTAG[c], g) : gather1(s, s->B[c - 3], BSTAG[c - 3], g);
+}
+
+/* Relativistic Boris push of p (q = -1, m = 1) through E, B over dt. */
+static void boris(double hq, const double E[3], const double B[3], double* px, double* py, double* pz) {
+  double umx = *px + hq * E[0], umy = *py + hq * E[1], umz = *pz + hq * E[2];
+  double gm = sqrt(1.0 + (umx * umx + umy * umy + umz * umz));
+  double fq = hq / gm;
+  double tx = fq * B[0], ty = fq * B[1], tz = fq * B[2];
+  double sf = 2.0 / (1.0 + (tx * tx + ty * ty + tz * tz));
+  double sx = sf * tx, sy = sf * ty, sz = sf * tz;
+  double upx = umx + (umy * tz - umz * ty);
+  double upy = umy + (umz * tx - umx * tz);
+  double upz = umz + (umx * ty - umy * tx);
+  double uqx = umx + (upy * sz - upz * sy);
+  double uqy = umy + (upz * sx - upx * sz);
+  double uqz = umz + (upx * sy - upy * sx);
+  *px = uqx + hq * E[0]; *py = uqy + hq * E[1]; *pz = uqz + hq * E[2];
+}
+
+/* Quantum parameter eta of an electron of momentum p and energy gamma in E, B:
+ * the Lorentz invariant |gamma E + p x B|^2 - (p.E)^2, square-rooted and in
+ * units of the Schwinger field (Sec. II.A; READING of the printed form). */
+static double eta_of(const double E[3], const double B[3], double px, double py, double pz,
+                     double gamma, double iES) {
+  double cx = gamma * E[0] + (py * B[2] - pz * B[1]);
+  double cy = gamma * E[1] + (pz * B[0] - px * B[2]);
+  double cz = gamma * E[2] + (px * B[1] - py * B[0]);
+  double pe = px * E[0] + py * E[1] + pz * E[2];
+  double q2 = (cx * cx + cy * cy + cz * cz) - pe * pe;
+  if (q2 < 0.0) q2 = 0.0;
+  return sqrt(q2) * iES;
+}
+
+/* Position of eta on the NCS table: row i and fraction f in ln eta (clamped
+ * to the last interval above the grid).  Returns 0 below the first point:
+ * no emission there (READING). */
+static int ncs_row(const or_sim* s, double eta, int* i, double* f) {
+  double le = log(eta);
+  double sl = (le - s->ln_eta0) * s->idln_eta;
+  if (!(sl >= 0.0)) return 0;
+  if (sl >= (double)(s->n_eta - 1)) { *i = s->n_eta - 2; *f = 1.0; }
+  else { *i = (int)sl; *f = sl - (double)*i; }
+  return 1;
+}
+
+/* Optical depth used up in one step: dN/dt = K_N (eta/gamma) h(eta) with h
+ * linear in ln eta between table points (Sec. II.A, NCS "the same as EPOCH"). */
+static double ncs_dtau(const or_sim* s, int i, double f, double eta, double gamma) {
+  double h = s->h[i] + f * (s->h[i + 1] - s->h[i]);
+  return s->K_N * eta / gamma * h * s->dt;
+}
+
+/* Photon fraction xi = hbar w / (gamma m c^2) at uniform u: each of the two
+ * rows around eta inverted, blended in ln eta (READING). */
+static double ncs_xi(const or_sim* s, int i, double f, double u) {
+  double la = ncs_inv_row(s, i, u);
+  double lb = ncs_inv_row(s, i + 1, u);
+  double lx = la + f * (lb - la);
+  return exp(lx);
+}
+
+/* Position of the kinetic energy T on the bremsstrahlung table: row i,
+ * fraction f in ln T, ln T itself; clamps (and flags) above the last point.
+ * Returns 0 below the first point. */
+static int brem_row(const or_sim* s, double T, int* i, double* f, double* lt, int* clamped) {
+  *lt = log(T);
+  double sl = (*lt - s->ln_T0) * s->idln_T;
+  if (!(sl >= 0.0)) return 0;
+  if (sl >= (double)(s->n_T - 1)) { *i = s->n_T - 2; *f = 1.0; *clamped = 1; }
+  else { *i = (int)sl; *f = sl - (double)*i; }
+  return 1;
+}
+
+/* sigma(E) of Eq. (4): the Tsai cross-section of Eq. (1) integrated from the
+ * photon cut to T, in alpha r_e^2, linear in ln T between table points. */
+static double brem_sigma(const or_sim* s, int i, double f) {
+  return s->sigma[i] + f * (s->sigma[i + 1] - s->sigma[i]);
+}
+
+/* Photon energy of a bremsstrahlung event: sigma(y, E) = R2 sigma(E) solved
+ * on the two rows around T, blended in ln T, mapped from the scaled
+ * coordinate between ln k_cut and ln T, capped at T (Sec. II.B; READING). */
+static double brem_eps(const or_sim* s, int i, double f, double lt, double T, double u) {
+  double sa = br_inv_row(s, i, u);
+  double sb = br_inv_row(s, i + 1, u);
+  double sv = sa + f * (sb - sa);
+  double lk = log(s->k_cut);
+  double eps = exp(lk + sv * (lt - lk));
+  if (eps > T) eps = T;
+  return eps;
+}
+
+/* Recoil of an emission of energy eps: the electron keeps its direction and
+ * loses eps of its energy (READING: energy-conserving along p). */
+static void recoil(double eps, double pm, double* px, double* py, double* pz, double* gamma) {
+  double gn = *gamma - eps;
+  double pn = sqrt((gn - 1.0) * (gn + 1.0));
+  double sc = pn / pm;
+  *px = *px * sc; *py = *py * sc; *pz = *pz * sc; *gamma = gn;
+}
+
+static void add_photon(eres* out, const double* x, double px, double py, double pz, double pm,
+                       double eps, int proc, int keep) {
+  int k = out->nph++;
+  out->px[k][0] = x[0]; out->px[k][1] = x[1]; out->px[k][2] = x[2];
+  out->pk[k][0] = px / pm; out->pk[k][1] = py / pm; out->pk[k][2] = pz / pm;
+  out->pe[k] = eps; out->pproc[k] = proc; out->pkeep[k] = keep;
+}
+
 /* Steps in the order of the method: RNG, gather, Boris push, eta, NCS
  * (optical depth + inverse-CDF draw), bremsstrahlung (Eq. (4) test + R2 draw),
  * recoil, move.  Deposit, append and sums happen afterwards in id order. */
@@ -453,72 +575,28 @@ static void electron_one(or_sim* s, int64_t e, double tn, eres* out) {
     double g[3];
     for (int a = 0; a < 3; ++a) g[a] = x[a] * s->idx[a];
     for (int a = 0; a < 3; ++a) {
-      E[a] = gather1(s, s->E[a], ESTAG[a], g);
-      B[a] = gather1(s, s->B[a], BSTAG[a], g);
+      E[a] = field_at(s, a, g);
+      B[a] = field_at(s, 3 + a, g);
     }
   }
 
-  /* relativistic Boris push, q = -1, m = 1 */
-  double hq = -0.5 * s->dt;
-  double umx = p[0] + hq * E[0], umy = p[1] + hq * E[1], umz = p[2] + hq * E[2];
-  double gm = sqrt(1.0 + (umx * umx + umy * umy + umz * umz));
-  double fq = hq / gm;
-  double tx = fq * B[0], ty = fq * B[1], tz = fq * B[2];
-  double sf = 2.0 / (1.0 + (tx * tx + ty * ty + tz * tz));
-  double sx = sf * tx, sy = sf * ty, sz = sf * tz;
-  double upx = umx + (umy * tz - umz * ty);
-  double upy = umy + (umz * tx - umx * tz);
-  double upz = umz + (umx * ty - umy * tx);
-  double uqx = umx + (upy * sz - upz * sy);
-  double uqy = umy + (upz * sx - upx * sz);
-  double uqz = umz + (upx * sy - upy * sx);
-  double px = uqx + hq * E[0], py = uqy + hq * E[1], pz = uqz + hq * E[2];
+  double px = p[0], py = p[1], pz = p[2];
+  boris(-0.5 * s->dt, E, B, &px, &py, &pz);
   double gamma = sqrt(1.0 + (px * px + py * py + pz * pz));
-
-  /* quantum parameter: eta = |gamma E + p x B|_perp-invariant / E_S (Sec. II.A,
-   * READING of the printed form as the Lorentz invariant) */
-  double cx = gamma * E[0] + (py * B[2] - pz * B[1]);
-  double cy = gamma * E[1] + (pz * B[0] - px * B[2]);
-  double cz = gamma * E[2] + (px * B[1] - py * B[0]);
-  double pe = px * E[0] + py * E[1] + pz * E[2];
-  double q2 = (cx * cx + cy * cy + cz * cz) - pe * pe;
-  if (q2 < 0.0) q2 = 0.0;
-  double eta = sqrt(q2) * s->iES;
+  double eta = eta_of(E, B, px, py, pz, gamma, s->iES);
 
   /* nonlinear Compton scattering: optical-depth decrement, one emission at
    * most per step, photon fraction from the inverse cumulative spectrum */
-  if (c->flags & OR_NCS) {
-    double le = log(eta);
-    double sl = (le - s->ln_eta0) * s->idln_eta;
-    if (sl >= 0.0) {
-      int i; double f;
-      if (sl >= (double)(s->n_eta - 1)) { i = s->n_eta - 2; f = 1.0; }
-      else { i = (int)sl; f = sl - (double)i; }
-      double h = s->h[i] + f * (s->h[i + 1] - s->h[i]);
-      double dtau = s->K_N * eta / gamma * h * s->dt;
-      s->tau[e] = s->tau[e] - dtau;
-      if (s->tau[e] <= 0.0) {
-        double u2 = u32(r[2]);
-        double la = ncs_inv_row(s, i, u2);
-        double lb = ncs_inv_row(s, i + 1, u2);
-        double lx = la + f * (lb - la);
-        double xi = exp(lx);
-        double eps = xi * gamma;
-        if (eps > gamma - 1.0) eps = gamma - 1.0;
-        double pm = sqrt(px * px + py * py + pz * pz);
-        int k = out->nph++;
-        out->px[k][0] = x[0]; out->px[k][1] = x[1]; out->px[k][2] = x[2];
-        out->pk[k][0] = px / pm; out->pk[k][1] = py / pm; out->pk[k][2] = pz / pm;
-        out->pe[k] = eps; out->pproc[k] = 0;
-        out->pkeep[k] = eps >= c->photon_cut_mc2;
-        if (!(c->flags & OR_NO_RECOIL)) {
-          double gn = gamma - eps;
-          double pn = sqrt((gn - 1.0) * (gn + 1.0));
-          double sc = pn / pm;
-          px = px * sc; py = py * sc; pz = pz * sc; gamma = gn;
-        }
-        s->tau[e] = -log(u32(r[3]));
-      }
+  int i; double f;
+  if ((c->flags & OR_NCS) && ncs_row(s, eta, &i, &f)) {
+    s->tau[e] = s->tau[e] - ncs_dtau(s, i, f, eta, gamma);
+    if (s->tau[e] <= 0.0) {
+      double eps = ncs_xi(s, i, f, u32(r[2])) * gamma;
+      if (eps > gamma - 1.0) eps = gamma - 1.0;
+      double pm = sqrt(px * px + py * py + pz * pz);
+      add_photon(out, x, px, py, pz, pm, eps, 0, eps >= c->photon_cut_mc2);
+      if (!(c->flags & OR_NO_RECOIL)) recoil(eps, pm, &px, &py, &pz, &gamma);
+      s->tau[e] = -log(u32(r[3]));
     }
   }
 
@@ -543,49 +621,29 @@ static void electron_one(or_sim* s, int64_t e, double tn, eres* out) {
         ci[a] = q;
       }
       double ni = s->ni[ci[0] + (int64_t)s->n[0] * (ci[1] + (int64_t)s->n[1] * ci[2])];
-      if (ni > 0.0) {
-        double lt = log(T);
-        double sl = (lt - s->ln_T0) * s->idln_T;
-        if (sl >= 0.0) {
-          int i; double f;
-          if (sl >= (double)(s->n_T - 1)) { i = s->n_T - 2; f = 1.0; out->clamped = 1; }
-          else { i = (int)sl; f = sl - (double)i; }
-          double sig = s->sigma[i] + f * (s->sigma[i + 1] - s->sigma[i]);
-          if (sig > 0.0) {
-            double pm = sqrt(px * px + py * py + pz * pz);
-            double v = pm / gamma;
-            double X = s->K_BR * ni * sig * v * s->dt;
-            int hit;
-            if (c->flags & OR_BREM_FREEPATH) {
-              s->taub[e] = s->taub[e] - X;
-              hit = s->taub[e] <= 0.0;
-            } else {
-              double P = -expm1(-X);
-              hit = u52(r[0], r[1]) < P;
-            }
-            if (hit) {
-              uint32_t r2[4];
-              or_philox(s->id[e], n, 1u, 0u, s->key0, s->key1, r2);
-              /* the next free path: word 1 of the event's second draw */
-              if (c->flags & OR_BREM_FREEPATH) s->taub[e] = -log(u32(r2[1]));
-              double u = u32(r2[0]);
-              double sa = br_inv_row(s, i, u);
-              double sb = br_inv_row(s, i + 1, u);
-              double sv = sa + f * (sb - sa);
-              double lk = log(s->k_cut);
-              double eps = exp(lk + sv * (lt - lk));
-              if (eps > T) eps = T;
-              int k = out->nph++;
-              out->px[k][0] = x[0]; out->px[k][1] = x[1]; out->px[k][2] = x[2];
-              out->pk[k][0] = px / pm; out->pk[k][1] = py / pm; out->pk[k][2] = pz / pm;
-              out->pe[k] = eps; out->pproc[k] = 1; out->pkeep[k] = 1;
-              if (!(c->flags & OR_NO_RECOIL)) {
-                double gn = gamma - eps;
-                double pn = sqrt((gn - 1.0) * (gn + 1.0));
-                double sc = pn / pm;
-                px = px * sc; py = py * sc; pz = pz * sc; gamma = gn;
-              }
-            }
+      double lt;
+      if (ni > 0.0 && brem_row(s, T, &i, &f, &lt, &out->clamped)) {
+        double sig = brem_sigma(s, i, f);
+        if (sig > 0.0) {
+          double pm = sqrt(px * px + py * py + pz * pz);
+          double v = pm / gamma;
+          double X = s->K_BR * ni * sig * v * s->dt;
+          int hit;
+          if (c->flags & OR_BREM_FREEPATH) {
+            s->taub[e] = s->taub[e] - X;
+            hit = s->taub[e] <= 0.0;
+          } else {
+            double P = -expm1(-X);
+            hit = u52(r[0], r[1]) < P;
+          }
+          if (hit) {
+            uint32_t r2[4];
+            or_philox(s->id[e], n, 1u, 0u, s->key0, s->key1, r2);
+            /* the next free path: word 1 of the event's second draw */
+            if (c->flags & OR_BREM_FREEPATH) s->taub[e] = -log(u32(r2[1]));
+            double eps = brem_eps(s, i, f, lt, T, u32(r2[0]));
+            add_photon(out, x, px, py, pz, pm, eps, 1, 1);
+            if (!(c->flags & OR_NO_RECOIL)) recoil(eps, pm, &px, &py, &pz, &gamma);
           }
         }
       }
@@ -846,4 +904,49 @@ void or_get_current(const or_sim* s, int64_t* out) {
 void or_get_derived(const or_sim* s, double* o) {
   o[0] = s->dx[0]; o[1] = s->dx[1]; o[2] = s->dx[2]; o[3] = s->dt;
   o[4] = s->E_S; o[5] = s->K_N; o[6] = s->K_BR; o[7] = s->n_c;
+}
+
+/* ---------------- probes of single steps (for the pins) ------------------ */
+void or_set_fields(or_sim* s, const double* in) {
+  for (int c = 0; c < 3; ++c) memcpy(s->E[c], in + (int64_t)c * s->nfield, sizeof(double) * (size_t)s->nfield);
+  for (int c = 0; c < 3; ++c) memcpy(s->B[c], in + (int64_t)(3 + c) * s->nfield, sizeof(double) * (size_t)s->nfield);
+}
+
+double or_probe_field(const or_sim* s, int comp, const double x[3]) {
+  double g[3];
+  for (int a = 0; a < 3; ++a) g[a] = x[a] * s->idx[a];
+  return field_at(s, comp, g);
+}
+
+void or_probe_boris(const or_sim* s, const double E[3], const double B[3], double p[3]) {
+  boris(-0.5 * s->dt, E, B, &p[0], &p[1], &p[2]);
+}
+
+double or_probe_eta(const or_sim* s, const double E[3], const double B[3], const double p[3]) {
+  double gamma = sqrt(1.0 + (p[0] * p[0] + p[1] * p[1] + p[2] * p[2]));
+  return eta_of(E, B, p[0], p[1], p[2], gamma, s->iES);
+}
+
+double or_probe_ncs_dtau(const or_sim* s, double eta, double gamma) {
+  int i; double f;
+  if (!ncs_row(s, eta, &i, &f)) return 0.0;
+  return ncs_dtau(s, i, f, eta, gamma);
+}
+
+double or_probe_ncs_xi(const or_sim* s, double eta, double u) {
+  int i; double f;
+  if (!ncs_row(s, eta, &i, &f)) return 0.0;
+  return ncs_xi(s, i, f, u);
+}
+
+double or_probe_brem_sigma(const or_sim* s, double T) {
+  int i, cl = 0; double f, lt;
+  if (!(T >= s->k_cut) || !brem_row(s, T, &i, &f, &lt, &cl)) return 0.0;
+  return brem_sigma(s, i, f);
+}
+
+double or_probe_brem_eps(const or_sim* s, double T, double u) {
+  int i, cl = 0; double f, lt;
+  if (!(T >= s->k_cut) || !brem_row(s, T, &i, &f, &lt, &cl)) return 0.0;
+  return brem_eps(s, i, f, lt, T, u);
 }

@@ -79,4 +79,20 @@ void     or_get_derived(const or_sim* s, double* out8);  /* dx[3], dt, E_S, K_N,
 void     or_philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                    uint32_t k0, uint32_t k1, uint32_t out[4]);
 
+/* Probes of single steps of the method, on a run's tables and fields (test
+ * pins only).  field: component comp (0..2 E, 3..5 B) at position x by the
+ * gather of the step; boris: one push of p over the run's dt; eta: the quantum
+ * parameter of momentum p in E, B; ncs_dtau: the optical depth one step uses
+ * up (0 below the table); ncs_xi: the photon fraction at uniform u;
+ * brem_sigma: sigma(T) in alpha r_e^2 (0 below the cut or the table);
+ * brem_eps: the photon energy at uniform u. */
+void     or_set_fields(or_sim* s, const double* in);   /* 6*size: Ex,Ey,Ez,Bx,By,Bz */
+double   or_probe_field(const or_sim* s, int comp, const double x[3]);
+void     or_probe_boris(const or_sim* s, const double E[3], const double B[3], double p[3]);
+double   or_probe_eta(const or_sim* s, const double E[3], const double B[3], const double p[3]);
+double   or_probe_ncs_dtau(const or_sim* s, double eta, double gamma);
+double   or_probe_ncs_xi(const or_sim* s, double eta, double u);
+double   or_probe_brem_sigma(const or_sim* s, double T);
+double   or_probe_brem_eps(const or_sim* s, double T, double u);
+
 #endif
