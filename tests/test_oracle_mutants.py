@@ -1,0 +1,48 @@
+"""Each pin bites: a copy of the oracle with one planted mistake (see
+tests/mutants.py) fails the pin that covers the function it alters, while the
+oracle itself passes it (the pin's own test).  CPU only."""
+from __future__ import annotations
+
+import pytest
+
+import mutants
+import test_oracle_pins_emission as PE
+import test_oracle_pins_fields as PF
+
+# mutant -> the pin that must catch it
+CASES = [
+    ("deposit2d_jx_weight", PF.check_continuity),
+    ("deposit3d_T_weight", PF.check_continuity),
+    ("deposit2d_jz_weights", PF.check_jz_path_average),
+    ("current_quantum_2e-30", PF.check_continuity),
+    ("gather_stagger_sign", PF.check_gather_multilinear),
+    ("gather3d_z_fraction", PF.check_gather_multilinear),
+    ("bhalf_curl_sign", PF.check_yee_modes),
+    ("efull_curl_index", PF.check_yee_modes),
+    ("mur_coefficient_sign", PF.check_mur_absorbs),
+    ("source3d_amplitude", lambda lib: PF.check_gaussian_beam(3, lib)),
+    ("source2d_gouy", lambda lib: PF.check_gaussian_beam(2, lib)),
+    ("source_curvature_sign", lambda lib: PF.check_gaussian_beam(2, lib)),
+    ("eta_pxB_sign", PE.check_eta_closed_forms),
+    ("eta_pE_sign", PE.check_eta_closed_forms),
+    ("eta_gamma_dropped", PE.check_eta_closed_forms),
+    ("ncs_rate_blend", PE.check_ncs_rate_off_node),
+    ("ncs_row_blend", PE.check_ncs_sampling_quantum),
+    ("ncs_row_search", PE.check_ncs_sampling_quantum),
+    ("brem_sigma_blend", PE.check_brem_sigma_off_node),
+    ("brem_row_blend", PE.check_brem_sampling_off_node),
+    ("brem_energy_map", PE.check_brem_sampling_off_node),
+    ("K_BR_factor", PE.check_constants),
+    ("E_S_factor", PE.check_constants),
+]
+
+
+@pytest.mark.parametrize("name,check", CASES, ids=[c[0] for c in CASES])
+def test_planted_error_fails_its_pin(oracle_lib, name, check):
+    lib = mutants.build(name)
+    with pytest.raises(AssertionError):
+        check(lib)
+
+
+def test_every_mutant_has_a_pin():
+    assert sorted(mutants.MUTANTS) == sorted(c[0] for c in CASES)
