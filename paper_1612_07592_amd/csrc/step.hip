@@ -106,7 +106,13 @@ struct LdsCurrent32 {
   __device__ inline int s2() const { return e0 * e1; }
   __device__ inline void add(int c, int l, float v) const { atomicAdd(T + c * nodes + l, q32(v, scale)); }
   __device__ inline float qscale() const { return scale; }
-  __device__ inline void addq(int c, int l, float v) const { atomicAdd(T + c * nodes + l, (int)rintf(v)); }
+  // zero contributions are skipped: a wave whose lanes all carry zero for a
+  // node (electrons that did not move along the flux's axis) issues no LDS
+  // atomic at all
+  __device__ inline void addq(int c, int l, float v) const {
+    const int q = (int)rintf(v);
+    if (q != 0) atomicAdd(T + c * nodes + l, q);
+  }
 };
 
 // Field access: straight from the Yee arrays, or from the block's LDS box.
@@ -299,15 +305,96 @@ __device__ inline void deposit3(const StepParams<float>& P, const Acc& J, const 
   const float c0 = (float)(-w * P.invV) * J.qscale();
   float S0[3][3], S1[3][3];
   int m[3] = {0, 0, 0};
+  int i0s[3] = {0, 0, 0}, i1s[3] = {0, 0, 0};
+  float f0s[3] = {0.f, 0.f, 0.f}, f1s[3] = {0.f, 0.f, 0.f};
+  bool cross = false;
 #pragma unroll
   for (int a = 0; a < D; ++a) {
-    int i0, i1;
-    float f0, f1;
-    split_q(q0[a], 0, P.fb[a], P.iqs[a], i0, f0);
-    split_q(q1[a], 0, P.fb[a], P.iqs[a], i1, f1);
-    m[a] = min(i0, i1);
-    shape3(i0, f0, m[a], S0[a]);
-    shape3(i1, f1, m[a], S1[a]);
+    split_q(q0[a], 0, P.fb[a], P.iqs[a], i0s[a], f0s[a]);
+    split_q(q1[a], 0, P.fb[a], P.iqs[a], i1s[a], f1s[a]);
+    cross = cross || i0s[a] != i1s[a];
+  }
+  if (!cross) {
+    // The move stays inside one cell on every axis: every node weight is
+    // linear between the same two nodes, so the flux through the window's
+    // second face vanishes and the third node carries nothing.  Only the
+    // nodes {m, m+1} of each axis receive current: 4 of the 8 (1D), 8 of the
+    // 21 (2D), 12 of the 54 (3D) contributions of the general form.  Each
+    // axis's first-face flux is qa (f1 - f0) exactly, with no cancellation
+    // of rounded node weights.
+    const int base = J.lin(i0s[0], i0s[1], i0s[2]);
+    const int s1 = J.s1(), s2 = J.s2();
+    float A0[3], A1[3], B0[3], B1[3];  // node weights at x0 and x1 on {m, m+1}
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      A0[a] = 1.f - f0s[a]; A1[a] = f0s[a];
+      B0[a] = 1.f - f1s[a]; B1[a] = f1s[a];
+    }
+    if (D == 1) {
+      const float qx = c0 * (float)P.dxdt[0];
+      J.addq(0, base, qx * (f1s[0] - f0s[0]));
+      const float cy = 0.5f * c0 * v[1], cz = 0.5f * c0 * v[2];
+      const float s0 = A0[0] + B0[0], s1w = A1[0] + B1[0];
+      J.addq(1, base, cy * s0);
+      J.addq(1, base + 1, cy * s1w);
+      J.addq(2, base, cz * s0);
+      J.addq(2, base + 1, cz * s1w);
+    } else if (D == 2) {
+      const float qx = 0.5f * c0 * (float)P.dxdt[0], qy = 0.5f * c0 * (float)P.dxdt[1];
+      const float cz = c0 * v[2] * (1.f / 6.f);
+      const float Fx = qx * (f1s[0] - f0s[0]), Fy = qy * (f1s[1] - f0s[1]);
+      J.addq(0, base, Fx * (A0[1] + B0[1]));
+      J.addq(0, base + s1, Fx * (A1[1] + B1[1]));
+      J.addq(1, base, Fy * (A0[0] + B0[0]));
+      J.addq(1, base + 1, Fy * (A1[0] + B1[0]));
+      const float G0 = cz * __builtin_fmaf(2.f, A0[0], B0[0]), H0 = cz * __builtin_fmaf(2.f, B0[0], A0[0]);
+      const float G1 = cz * __builtin_fmaf(2.f, A1[0], B1[0]), H1 = cz * __builtin_fmaf(2.f, B1[0], A1[0]);
+      J.addq(2, base, __builtin_fmaf(G0, A0[1], H0 * B0[1]));
+      J.addq(2, base + 1, __builtin_fmaf(G1, A0[1], H1 * B0[1]));
+      J.addq(2, base + s1, __builtin_fmaf(G0, A1[1], H0 * B1[1]));
+      J.addq(2, base + s1 + 1, __builtin_fmaf(G1, A1[1], H1 * B1[1]));
+    } else {
+      if (q0[0] == q1[0] && q0[1] == q1[1] && q0[2] == q1[2]) return;  // no move: no current
+      float G[3][2], H[3][2], F[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        F[a] = c0 * (float)P.dxdt[a] * (f1s[a] - f0s[a]);
+        G[a][0] = (1.f / 6.f) * __builtin_fmaf(2.f, A0[a], B0[a]);
+        H[a][0] = (1.f / 6.f) * __builtin_fmaf(2.f, B0[a], A0[a]);
+        G[a][1] = (1.f / 6.f) * __builtin_fmaf(2.f, A1[a], B1[a]);
+        H[a][1] = (1.f / 6.f) * __builtin_fmaf(2.f, B1[a], A1[a]);
+      }
+      const float Z0[3] = {A0[0], A0[1], A0[2]}, Z1[3] = {A1[0], A1[1], A1[2]};
+      const float Y0[3] = {B0[0], B0[1], B0[2]}, Y1[3] = {B1[0], B1[1], B1[2]};
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const float sa0 = k ? Z1[2] : Z0[2], sa1 = k ? Y1[2] : Y0[2];
+          J.addq(0, base + j * s1 + k * s2, F[0] * __builtin_fmaf(G[1][j], sa0, H[1][j] * sa1));
+        }
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const float sa0 = k ? Z1[2] : Z0[2], sa1 = k ? Y1[2] : Y0[2];
+          J.addq(1, base + i + k * s2, F[1] * __builtin_fmaf(G[0][i], sa0, H[0][i] * sa1));
+        }
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const float sa0 = j ? Z1[1] : Z0[1], sa1 = j ? Y1[1] : Y0[1];
+          J.addq(2, base + i + j * s1, F[2] * __builtin_fmaf(G[0][i], sa0, H[0][i] * sa1));
+        }
+    }
+    return;
+  }
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    m[a] = min(i0s[a], i1s[a]);
+    shape3(i0s[a], f0s[a], m[a], S0[a]);
+    shape3(i1s[a], f1s[a], m[a], S1[a]);
   }
   // node (m0 + i, m1 + j, m2 + k) is base + i + j s1 + k s2
   const int base = J.lin(m[0], m[1], m[2]);
