@@ -273,6 +273,7 @@ Plan make_plan(Ctx& c) {
   P.add((void**)&c.ppar, pc * 4);
   P.add((void**)&c.pproc, pc * 4);
   P.add((void**)&c.pcount, 8);
+  P.add((void**)&c.pfull, 4);   // a line of its own: read by every chunk, written once
   const size_t nsl = (size_t)(c.nslots > 0 ? c.nslots : 1);
   P.add((void**)&c.slot_cnt, nsl * kSlotCnt * 8);
   P.add((void**)&c.slot_sum, nsl * kSlotSum * 8);
@@ -424,6 +425,7 @@ void fill_step_cold(const Ctx& c, StepCold<R>& C) {
   C.ppar = c.ppar;
   C.pproc = c.pproc;
   C.pcount = c.pcount;
+  C.pfull = c.pfull;
   C.slot_cnt = c.slot_cnt;
   C.slot_sum = c.slot_sum;
 }
@@ -838,8 +840,10 @@ pic_status pic_emission_stats(pic_ctx* ctx, pic_stats* out) {
   s.dropped_ncs = cnt[SC_DROPPED];
   s.brem_clamped = cnt[SC_CLAMPED];
   s.untiled_steps = cnt[SC_UNTILED];
+  // the device stops reserving slots once the buffer is full, so the
+  // counter can fall short of the kept photons: overflow = kept - stored
   s.photons_stored = pcount < c.pcap ? pcount : c.pcap;
-  s.overflow = pcount > c.pcap ? pcount - c.pcap : 0;
+  s.overflow = s.kept[0] + s.kept[1] - s.photons_stored;
   s.e_rad_kept[0] = sum[0];
   s.e_rad_kept[1] = sum[1];
   s.e_rad_dropped = sum[2];
@@ -1033,11 +1037,19 @@ pic_status pic_counts(pic_ctx* ctx, uint64_t* electrons, uint64_t* stored, uint6
   if (st) return st;
   Ctx& c = ctx->c;
   unsigned long long pc = 0;
+  // kept photons from the per-wave counts: the device's slot counter stops
+  // once the buffer is full
+  unsigned long long cnt[kSlotCnt + 1];
+  double sum[5];
+  if (kept) {
+    launch_stats_reduce(c, cnt, sum, nullptr, nullptr, nullptr, c.stream);
+    HIPCHK(c, hipGetLastError());
+  }
   HIPCHK(c, hipMemcpyAsync(&pc, c.pcount, 8, hipMemcpyDeviceToHost, c.stream));
   HIPCHK(c, hipStreamSynchronize(c.stream));
   if (electrons) *electrons = (uint64_t)c.N;
   if (stored) *stored = pc < c.pcap ? pc : c.pcap;
-  if (kept) *kept = pc;
+  if (kept) *kept = cnt[SC_KEPT_NCS] + cnt[SC_KEPT_BR];
   return PIC_OK;
 }
 

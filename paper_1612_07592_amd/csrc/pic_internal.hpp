@@ -109,6 +109,7 @@ struct StepCold {
   uint32_t* ppar;
   uint32_t* pproc;
   unsigned long long* pcount;
+  uint32_t* pfull;            // set once a reservation reached the capacity
   unsigned long long* slot_cnt;
   double* slot_sum;
 };
@@ -249,6 +250,7 @@ struct Ctx {
   uint32_t* ppar = nullptr;
   uint32_t* pproc = nullptr;
   unsigned long long* pcount = nullptr;
+  uint32_t* pfull = nullptr;  // photon buffer full (set by the step kernel)
   int64_t nslots = 0;
   int64_t nblocks_step = 0;   // step-kernel grid (a multiple of kGridQuantum)
   // cell-tile sort

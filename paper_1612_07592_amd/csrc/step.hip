@@ -6,7 +6,8 @@
 //   bremsstrahlung test of Eq. (4) against the cell's ion density and the
 //   R2 photon-energy draw -> recoil -> photon append -> move -> current deposit.
 // Photon append: one ballot per process and wave, one atomic per wave on the
-// photon counter, lane offsets from mbcnt (no per-lane atomics).
+// photon counter (none once the buffer is full), lane offsets from mbcnt (no
+// per-lane atomics).
 // Statistics: per-wave slots (exact u64 counts, FP64 Neumaier pairs), reduced
 // in a fixed order on demand.
 // Current: each contribution rounded to 2^-40 and added as a 64-bit integer,
@@ -632,27 +633,71 @@ struct Emit {
   R xo[3] = {R(0), R(0), R(0)};
 };
 
-// One electron: gather, Boris, eta, NCS, bremsstrahlung, recoil, move, deposit.
-template <class R, int D, class FA, class JA>
-__device__ inline void electron_physics(const StepParams<R>& P, int64_t e, uint32_t idv, double wgt,
-                                        const R* xin, const int* qin, const R* pin, double tau_in,
-                                        const FA& fld, const JA& cur, Emit<R>& out) {
+// Per-electron state carried from the push to the move (registers).
+template <class R>
+struct Lane {
+  R x[3] = {R(0), R(0), R(0)};   // absolute position (FP32: for records and the frozen plane wave)
+  R px = R(0), py = R(0), pz = R(0), gamma = R(1);
+  U4 r;                           // Philox words of (id, step), once drawn
+  bool have_r = false;
+  double taub = 0.0;              // collision optical depth at the start of the step
+};
+
+// Photon energy of an NCS emission: each of the two rows around eta inverted
+// at the uniform, blended in ln eta, xi = exp(.), eps = xi gamma capped at the
+// kinetic energy.
+template <class R>
+__device__ inline R ncs_eps(const StepParams<R>& P, int i, R f, R u2, R gamma) {
+  const ColdPtr<R> C = cold(P);
+  const int nxi = C->n_xi;
+  const R* ncs = C->ncs;
+  const R* lnxi = C->lnxi;
+  const uint8_t* gn = C->gncs;
+  const R la = ncs_inverse<R>(ncs + (int64_t)i * nxi, lnxi, nxi, u2, gn + i * (kGuide + 1));
+  const R lb = ncs_inverse<R>(ncs + (int64_t)(i + 1) * nxi, lnxi, nxi, u2, gn + (i + 1) * (kGuide + 1));
+  const R lx = la + f * (lb - la);
+  const R xi = m_exp(lx);
+  R eps = xi * gamma;
+  if (eps > gamma - R(1)) eps = gamma - R(1);
+  return eps;
+}
+
+// An NCS emission of energy eps: photon direction along p, the record cut,
+// recoil along p (energy conserving), and the next optical depth.
+template <class R>
+__device__ inline void ncs_finish(const StepParams<R>& P, int64_t e, Lane<R>& L, R eps, double tau_new,
+                                  Emit<R>& out) {
+  const R pm = m_sqrt(L.px * L.px + L.py * L.py + L.pz * L.pz);
+  out.ev_ncs = true;
+  out.e[0] = eps;
+  out.k[0][0] = m_div(L.px, pm); out.k[0][1] = m_div(L.py, pm); out.k[0][2] = m_div(L.pz, pm);
+  out.keep_ncs = (double)eps >= cold(P)->photon_cut;
+  if (!(P.flags & PIC_NO_RECOIL)) {
+    const R gn = L.gamma - eps;
+    const R pn = m_sqrt((gn - R(1)) * (gn + R(1)));
+    const R sc = m_div(pn, pm);
+    L.px = L.px * sc; L.py = L.py * sc; L.pz = L.pz * sc;
+    L.gamma = gn;
+  }
+  P.tau[e] = tau_new;
+}
+
+// First half of one electron's step: gather, Boris push, eta, the NCS
+// optical-depth decrement and, on an emission, the photon draw and recoil.
+template <class R, int D, class FA>
+__device__ inline void electron_push(const StepParams<R>& P, int64_t e, uint32_t idv, const R* xin,
+                                     const int* qin, const R* pin, double tau_in, const FA& fld,
+                                     Lane<R>& L, Emit<R>& out) {
   constexpr bool kF32 = sizeof(R) == 4;
   const uint32_t n = P.step;
-  // Philox words of (id, step): drawn only when a test or an event needs them
-  U4 r;
-  bool have_r = false;
-  auto draw = [&]() {
-    if (!have_r) { r = philox4x32_10(idv, n, 0u, 0u, P.key0, P.key1); have_r = true; }
-  };
   // absolute position (FP32 path: from the fixed point, for records and the
   // prescribed plane wave only; gather, cells and moves use the integers)
-  R x[3] = {xin[0], xin[1], xin[2]};
+  L.x[0] = xin[0]; L.x[1] = xin[1]; L.x[2] = xin[2];
   if constexpr (kF32) {
 #pragma unroll
-    for (int a = 0; a < D; ++a) x[a] = (float)qin[a] * P.iqd[a];
+    for (int a = 0; a < D; ++a) L.x[a] = (float)qin[a] * P.iqd[a];
   }
-  out.xo[0] = x[0]; out.xo[1] = x[1]; out.xo[2] = x[2];
+  out.xo[0] = L.x[0]; out.xo[1] = L.x[1]; out.xo[2] = L.x[2];
   // 3D: state prefetched by the caller; 1D/2D: loaded here, at first use
   R px, py, pz;
   if constexpr (D == 3) { px = pin[0]; py = pin[1]; pz = pin[2]; }
@@ -660,8 +705,7 @@ __device__ inline void electron_physics(const StepParams<R>& P, int64_t e, uint3
   // free-path collision depth: loaded here so that its latency overlaps the
   // gather and the push (measured on the 2D gold slab: a load at the test
   // costs 7 us per launch)
-  const bool fpath = (P.flags & PIC_BREM_FREEPATH) != 0;
-  const double taub_in = fpath ? P.taub[e] : 0.0;
+  L.taub = (P.flags & PIC_BREM_FREEPATH) ? P.taub[e] : 0.0;
 
   // ---- gather E^n, B^n at x^n ----------------------------------------------
   R E0, E1, E2, B0, B1, B2;
@@ -672,7 +716,7 @@ __device__ inline void electron_physics(const StepParams<R>& P, int64_t e, uint3
       B0 = R(C->fB[0]); B1 = R(C->fB[1]); B2 = R(C->fB[2]);
     } else {
       E0 = R(0); E1 = R(0); E2 = R(0); B0 = R(0); B1 = R(0); B2 = R(0);
-      const R phi = R(P.tn) - x[0];
+      const R phi = R(P.tn) - L.x[0];
       if (phi > R(0)) {
         const R v = R(C->fa) * m_sin(phi);
         E1 = v;
@@ -690,7 +734,7 @@ __device__ inline void electron_physics(const StepParams<R>& P, int64_t e, uint3
   } else {
     R g[3] = {R(0), R(0), R(0)};
 #pragma unroll
-    for (int a = 0; a < D; ++a) g[a] = x[a] * R(P.idx[a]);
+    for (int a = 0; a < D; ++a) g[a] = L.x[a] * R(P.idx[a]);
     E0 = gather<R, D, 1, 0, 0>(fld, 0, g);
     E1 = gather<R, D, 0, 1, 0>(fld, 1, g);
     E2 = gather<R, D, 0, 0, 1>(fld, 2, g);
@@ -713,16 +757,16 @@ __device__ inline void electron_physics(const StepParams<R>& P, int64_t e, uint3
   const R uqx = umx + (upy * sz - upz * sy);
   const R uqy = umy + (upz * sx - upx * sz);
   const R uqz = umz + (upx * sy - upy * sx);
-  px = uqx + hq * E0;
-  py = uqy + hq * E1;
-  pz = uqz + hq * E2;
-  R gamma = m_fsqrt(R(1) + (px * px + py * py + pz * pz));
+  L.px = uqx + hq * E0;
+  L.py = uqy + hq * E1;
+  L.pz = uqz + hq * E2;
+  L.gamma = m_fsqrt(R(1) + (L.px * L.px + L.py * L.py + L.pz * L.pz));
 
   // ---- quantum parameter eta (Lorentz invariant, Sec. II.A) -----------------
-  const R cx = gamma * E0 + (py * B2 - pz * B1);
-  const R cy = gamma * E1 + (pz * B0 - px * B2);
-  const R cz = gamma * E2 + (px * B1 - py * B0);
-  const R pe = px * E0 + py * E1 + pz * E2;
+  const R cx = L.gamma * E0 + (L.py * B2 - L.pz * B1);
+  const R cy = L.gamma * E1 + (L.pz * B0 - L.px * B2);
+  const R cz = L.gamma * E2 + (L.px * B1 - L.py * B0);
+  const R pe = L.px * E0 + L.py * E1 + L.pz * E2;
   R q2 = (cx * cx + cy * cy + cz * cz) - pe * pe;
   if (q2 < R(0)) q2 = R(0);
   const R eta = m_fsqrt(q2) * R(P.iES);
@@ -738,40 +782,30 @@ __device__ inline void electron_physics(const StepParams<R>& P, int64_t e, uint3
       if (sl >= R(P.n_eta - 1)) { i = P.n_eta - 2; f = R(1); }
       else { i = (int)sl; f = sl - R(i); }
       const R h = P.h[i] + f * (P.h[i + 1] - P.h[i]);
-      const R dtau = m_div(R(P.K_N) * eta, gamma) * h * R(P.dt);
-      double tau = (D == 3 ? tau_in : P.tau[e]) - (double)dtau;
+      const R dtau = m_div(R(P.K_N) * eta, L.gamma) * h * R(P.dt);
+      const double tau = (D == 3 ? tau_in : P.tau[e]) - (double)dtau;
       if (tau <= 0.0) {
-        draw();
-        const R u2 = unif<R>(r.v[2]);
-        const ColdPtr<R> C = cold(P);
-        const int nxi = C->n_xi;
-        const R* ncs = C->ncs;
-        const R* lnxi = C->lnxi;
-        const uint8_t* gn = C->gncs;
-        const R la = ncs_inverse<R>(ncs + (int64_t)i * nxi, lnxi, nxi, u2, gn + i * (kGuide + 1));
-        const R lb = ncs_inverse<R>(ncs + (int64_t)(i + 1) * nxi, lnxi, nxi, u2,
-                                    gn + (i + 1) * (kGuide + 1));
-        const R lx = la + f * (lb - la);
-        const R xi = m_exp(lx);
-        R eps = xi * gamma;
-        if (eps > gamma - R(1)) eps = gamma - R(1);
-        const R pm = m_sqrt(px * px + py * py + pz * pz);
-        out.ev_ncs = true;
-        out.e[0] = eps;
-        out.k[0][0] = m_div(px, pm); out.k[0][1] = m_div(py, pm); out.k[0][2] = m_div(pz, pm);
-        out.keep_ncs = (double)eps >= C->photon_cut;
-        if (!(P.flags & PIC_NO_RECOIL)) {
-          const R gn = gamma - eps;
-          const R pn = m_sqrt((gn - R(1)) * (gn + R(1)));
-          const R sc = m_div(pn, pm);
-          px = px * sc; py = py * sc; pz = pz * sc;
-          gamma = gn;
-        }
-        tau = -log(unif32(r.v[3]));
+        L.r = philox4x32_10(idv, n, 0u, 0u, P.key0, P.key1);
+        L.have_r = true;
+        const R eps = ncs_eps<R>(P, i, f, unif<R>(L.r.v[2]), L.gamma);
+        ncs_finish<R>(P, e, L, eps, -log(unif32(L.r.v[3])), out);
+      } else {
+        P.tau[e] = tau;
       }
-      P.tau[e] = tau;
     }
   }
+}
+
+// Second half: bremsstrahlung test of Eq. (4) with the R2 energy draw, recoil,
+// move, current deposit, absorbing walls.
+template <class R, int D, class JA>
+__device__ inline void electron_finish(const StepParams<R>& P, int64_t e, uint32_t idv, double wgt,
+                                       const int* qin, const JA& cur, Lane<R>& L, Emit<R>& out) {
+  constexpr bool kF32 = sizeof(R) == 4;
+  const uint32_t n = P.step;
+  const bool fpath = (P.flags & PIC_BREM_FREEPATH) != 0;
+  R px = L.px, py = L.py, pz = L.pz, gamma = L.gamma;
+  const R* x = L.x;
 
   // ---- bremsstrahlung: Eq. (4) test, R2 energy draw (Sec. II.B) -------------
   if (P.flags & PIC_BREM) {
@@ -805,12 +839,12 @@ __device__ inline void electron_physics(const StepParams<R>& P, int64_t e, uint3
             if (fpath) {
               // free path: X is the step's path in mean free paths; collide
               // when the electron's remaining depth runs out (no draw until then)
-              tb = taub_in - (double)X;
+              tb = L.taub - (double)X;
               hit = tb <= 0.0;
             } else {
               const R Pb = -m_expm1(-X);
-              draw();
-              hit = unif52(r.v[0], r.v[1]) < (double)Pb;
+              if (!L.have_r) { L.r = philox4x32_10(idv, n, 0u, 0u, P.key0, P.key1); L.have_r = true; }
+              hit = unif52(L.r.v[0], L.r.v[1]) < (double)Pb;
             }
             if (!hit) {
               if (fpath) P.taub[e] = tb;
@@ -902,6 +936,12 @@ __device__ __forceinline__ void step_chunk(const StepParams<R>& P, const uint32_
   constexpr uint32_t kRow = kBlock / kDeal;
   const int64_t e = (int64_t)chunk * kBlock + (int64_t)((t % kRow) * kDeal + t / kRow);
   const int64_t n_act = (int64_t)*P.n_active;
+  // whether the photon buffer is known to be full: a flag on a line of its
+  // own, set by the first reservation that reached the capacity (reading the
+  // counter itself, which every wave's atomic targets, doubled the launch
+  // time while the buffer was filling; a stale 0 only costs an unneeded
+  // reservation)
+  const bool buf_full = *(volatile const uint32_t*)cold(P)->pfull != 0u;
   const bool frozen = (P.flags & PIC_FIELDS_FROZEN) != 0;
   bool live = false;
   uint32_t idv = 0;
@@ -1002,40 +1042,38 @@ __device__ __forceinline__ void step_chunk(const StepParams<R>& P, const uint32_
   __syncthreads();
 
   Emit<R> out;
+  Lane<R> L;
   if (live) {
     if constexpr (!kEarly) wgt = P.w[e];
-    if (tiled) {
-      using FA = typename std::conditional<kFL, LdsField<R>, GlobalField<R>>::type;
-      FA fa;
-      if constexpr (kFL) fa = LdsField<R>{sF, lo[0], lo[1], lo[2], ext[0], ext[1], nodes};
-      else fa = GlobalField<R>{P.F, I};
-      if constexpr (kF32) {
-        const LdsCurrent32 ja{reinterpret_cast<int*>(sJ), lo[0], lo[1], lo[2], ext[0], ext[1], nodes,
-                              (float)ldexp(1.0, P.jbits)};
-        electron_physics<R, D>(P, e, idv, wgt, x, q, pin, tau_in, fa, ja, out);
+    if constexpr (kFL) {
+      if (tiled) {
+        const LdsField<R> fa{sF, lo[0], lo[1], lo[2], ext[0], ext[1], nodes};
+        electron_push<R, D>(P, e, idv, x, q, pin, tau_in, fa, L, out);
       } else {
-        const LdsCurrent ja{reinterpret_cast<unsigned long long*>(sJ), lo[0], lo[1], lo[2], ext[0], ext[1], nodes};
-        electron_physics<R, D>(P, e, idv, wgt, x, q, pin, tau_in, fa, ja, out);
-      }
-    } else if (jtiled) {
-      const GlobalField<R> fa{P.F, I};
-      if constexpr (kF32) {
-        const LdsCurrent32 ja{reinterpret_cast<int*>(sJ), lo[0], lo[1], lo[2], ext[0], ext[1], nodes,
-                              (float)ldexp(1.0, P.jbits)};
-        electron_physics<R, D>(P, e, idv, wgt, x, q, pin, tau_in, fa, ja, out);
-      } else {
-        const LdsCurrent ja{reinterpret_cast<unsigned long long*>(sJ), lo[0], lo[1], lo[2], ext[0], ext[1], nodes};
-        electron_physics<R, D>(P, e, idv, wgt, x, q, pin, tau_in, fa, ja, out);
+        electron_push<R, D>(P, e, idv, x, q, pin, tau_in, GlobalField<R>{P.F, I}, L, out);
       }
     } else {
-      const GlobalField<R> fa{P.F, I};
+      electron_push<R, D>(P, e, idv, x, q, pin, tau_in, GlobalField<R>{P.F, I}, L, out);
+    }
+  }
+  if (live) {
+    if (tiled || jtiled) {
+      if constexpr (kF32) {
+        const LdsCurrent32 ja{reinterpret_cast<int*>(sJ), lo[0], lo[1], lo[2], ext[0], ext[1], nodes,
+                              (float)ldexp(1.0, P.jbits)};
+        electron_finish<R, D>(P, e, idv, wgt, q, ja, L, out);
+      } else {
+        const LdsCurrent ja{reinterpret_cast<unsigned long long*>(sJ), lo[0], lo[1], lo[2], ext[0], ext[1], nodes};
+        electron_finish<R, D>(P, e, idv, wgt, q, ja, L, out);
+      }
+    } else {
       if constexpr (kF32) {
         const GlobalCurrent32 ja{{P.J[0], P.J[1], P.J[2]}, {P.gg[0], P.gg[1], P.gg[2], P.sz[0], P.sz[1]},
                                  (float)ldexp(1.0, P.jbits), 40 - P.jbits};
-        electron_physics<R, D>(P, e, idv, wgt, x, q, pin, tau_in, fa, ja, out);
+        electron_finish<R, D>(P, e, idv, wgt, q, ja, L, out);
       } else {
         const GlobalCurrent ja{{P.J[0], P.J[1], P.J[2]}, {P.gg[0], P.gg[1], P.gg[2], P.sz[0], P.sz[1]}};
-        electron_physics<R, D>(P, e, idv, wgt, x, q, pin, tau_in, fa, ja, out);
+        electron_finish<R, D>(P, e, idv, wgt, q, ja, L, out);
       }
     }
   }
@@ -1056,21 +1094,34 @@ __device__ __forceinline__ void step_chunk(const StepParams<R>& P, const uint32_
     }
   }
 
-  // ---- photon append: one atomic per wave and process ---------------------
+  // ---- photon records: one slot reservation per wave ----------------------
+  // NCS and bremsstrahlung records of the wave take consecutive slots from
+  // one atomic on the buffer's counter.  Once a reservation has reached the
+  // capacity (a flag read as the chunk starts), no slot can be had and the
+  // reservation is skipped: every such record is an overflow, and the
+  // overflow count is the kept count (per-wave statistics) minus the
+  // capacity.  (Every wave of the grid hammering the one counter after the
+  // buffer filled cost 4.9 ms of a 14.7 ms launch on the 3D gold slab in the
+  // interaction.)
   const uint32_t lane = __lane_id();
   const bool rec0 = out.ev_ncs && out.keep_ncs;
   const bool rec1 = out.ev_br;
-#pragma unroll
-  for (int proc = 0; proc < 2; ++proc) {
-    const bool rec = proc == 0 ? rec0 : rec1;
-    const unsigned long long mask = __ballot(rec);
-    if (mask == 0ull) continue;  // wave-uniform
-    unsigned long long base = 0;
+  const unsigned long long mr0 = __ballot(rec0), mr1 = __ballot(rec1);
+  if ((mr0 | mr1) != 0ull && !buf_full) {  // wave-uniform
     const ColdPtr<R> C = cold(P);
-    if (lane == 0) base = atomicAdd(C->pcount, (unsigned long long)__popcll(mask));
+    unsigned long long base = 0;
+    if (lane == 0) {
+      const unsigned long long nr = (unsigned long long)(__popcll(mr0) + __popcll(mr1));
+      base = atomicAdd(C->pcount, nr);
+      if (base + nr >= C->pcap) *(volatile uint32_t*)C->pfull = 1u;
+    }
     base = __shfl(base, 0, 64);
-    if (rec) {
-      const unsigned long long slot = base + lane_offset(mask);
+#pragma unroll
+    for (int proc = 0; proc < 2; ++proc) {
+      const bool rec = proc == 0 ? rec0 : rec1;
+      if (!rec) continue;
+      const unsigned long long slot =
+          proc == 0 ? base + lane_offset(mr0) : base + (unsigned long long)__popcll(mr0) + lane_offset(mr1);
       if (slot < C->pcap) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
