@@ -201,8 +201,8 @@ void pic_destroy(pic_ctx* ctx);
 
 /* ---- helpers (tests, tools, serving) ------------------------------------ */
 
-/* Last error message of ctx (or of the last failed pic_create when ctx is
- * NULL, per thread).  Never NULL. */
+/* Last error message of ctx (or, when ctx is NULL, of the last failed
+ * pic_create or pic_philox_noalloc of the calling thread).  Never NULL. */
 const char* pic_last_error(const pic_ctx* ctx);
 
 /* Device bytes pic_create would allocate for cfg (tables included). */
@@ -301,6 +301,18 @@ pic_status pic_build_tables(uint32_t Z, double k_cut_mc2, int32_t nthreads,
 /* Device Philox4x32-10 of n counters (ctr[4n]) under one key (key[2]) into
  * out[4n]; host buffers.  Exposes the generator the step kernels use. */
 pic_status pic_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, uint64_t n);
+
+/* pic_philox for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same generator and the same host-buffer arguments and results, staged
+ * through a fixed device array the library holds (2 MiB per GPU it runs on,
+ * for the life of the process) instead of per-call allocations.  Calls no
+ * hipMalloc or hipFree.  n <= 65536 counters; larger n returns
+ * PIC_ERR_INVALID (message in pic_last_error(NULL)).  Every call on a GPU
+ * uses that GPU's one array: calls that overlap on one GPU (from several
+ * threads) race and must be serialised by the caller.  Synchronous, on the
+ * current device's default stream.  Errors: PIC_ERR_INVALID, PIC_ERR_DEVICE. */
+pic_status pic_philox_noalloc(const uint32_t* ctr, const uint32_t* key, uint32_t* out, uint64_t n);
 
 /* Kernel timing with HIP events recorded on the context's stream around
  * every electron-step launch, every field-solve group and every tile sort

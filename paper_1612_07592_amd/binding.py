@@ -29,7 +29,7 @@ EXPORTS = ["pic_create", "pic_load_tables", "pic_step", "pic_emission_stats", "p
            "pic_step_many", "pic_server_create", "pic_server_destroy", "pic_server_clock",
            "pic_server_last_error", "pic_server_submit", "pic_server_run", "pic_server_poll",
            "pic_server_job_ctx", "pic_server_release", "pic_device_memory", "pic_synchronize",
-           "pic_copy_brem_depth", "pic_set_brem_depth", "pic_get_buffers"]
+           "pic_copy_brem_depth", "pic_set_brem_depth", "pic_get_buffers", "pic_philox_noalloc"]
 
 
 class pic_config(C.Structure):
@@ -123,6 +123,7 @@ def load() -> C.CDLL:
     L.pic_copy_fields.argtypes = [P, C.c_void_p]
     L.pic_build_tables.argtypes = [u32, dbl, i32] + [C.c_void_p] * 5 + [C.POINTER(pic_tables)]
     L.pic_philox.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, u64]
+    L.pic_philox_noalloc.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, u64]
     L.pic_derived.argtypes = [P, C.c_void_p]
     L.pic_copy_current.argtypes = [P, C.c_void_p]
     L.pic_profile.argtypes = [P, i32]
@@ -251,6 +252,18 @@ def pic_philox(ctr, key) -> np.ndarray:
     key = np.ascontiguousarray(key, dtype=np.uint32).reshape(2)
     out = np.zeros_like(ctr)
     _check("pic_philox", L.pic_philox(ctr.ctypes.data, key.ctypes.data, out.ctypes.data, ctr.shape[0]))
+    return out
+
+
+def pic_philox_noalloc(ctr, key) -> np.ndarray:
+    """pic_philox through the library's fixed device staging (no device
+    allocation); at most 65536 counters per call."""
+    L = load()
+    ctr = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
+    key = np.ascontiguousarray(key, dtype=np.uint32).reshape(2)
+    out = np.zeros_like(ctr)
+    _check("pic_philox_noalloc", L.pic_philox_noalloc(ctr.ctypes.data, key.ctypes.data, out.ctypes.data,
+                                                      ctr.shape[0]))
     return out
 
 

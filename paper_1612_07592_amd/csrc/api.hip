@@ -7,6 +7,7 @@
 #include <cstring>
 #include <algorithm>
 #include <new>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -1336,6 +1337,71 @@ pic_status pic_derived(pic_ctx* ctx, double* o) {
   const Ctx& c = ctx->c;
   o[0] = c.g.dx[0]; o[1] = c.g.dx[1]; o[2] = c.g.dx[2]; o[3] = c.g.dt;
   o[4] = c.E_S; o[5] = c.K_N; o[6] = c.K_BR; o[7] = c.n_c;
+  return PIC_OK;
+}
+
+// ---- Philox without device allocation --------------------------------------
+// Staging for pic_philox_noalloc: counters in the first half, outputs in the
+// second, kPhiloxScratchMax counters of 16 bytes each per half (2 MiB in all).
+// A file-scope device array: every GPU the library runs on holds its own
+// copy, for the life of the process.  In host code `scratch` is a host-side
+// stand-in, never a device address: kernels and copies get the address
+// hipGetSymbolAddress returns, fetched once per device.
+constexpr uint64_t kPhiloxScratchMax = 1ull << 16;
+static __device__ __align__(256) uint32_t scratch[2 * 4 * kPhiloxScratchMax];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};  // per device ordinal
+
+// Device address of this device's scratch array (set up on the device's
+// first call); nullptr with *err set on failure.
+uint32_t* scratch_ptr(std::string* err) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess || dev < 0 || dev >= 64) {
+    *err = std::string("hipGetDevice: ") + hipGetErrorString(e);
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      *err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  return static_cast<uint32_t*>(g_scratch_ptr[dev]);
+}
+}  // namespace
+
+pic_status pic_philox_noalloc(const uint32_t* ctr, const uint32_t* key, uint32_t* out, uint64_t n) {
+  if (!ctr || !key || !out) {
+    g_create_err = "pic_philox_noalloc: null argument";
+    return PIC_ERR_INVALID;
+  }
+  if (n == 0) return PIC_OK;
+  if (n > kPhiloxScratchMax) {
+    g_create_err = "pic_philox_noalloc: n = " + std::to_string(n) + " exceeds the staging capacity of " +
+                   std::to_string(kPhiloxScratchMax) + " counters";
+    return PIC_ERR_INVALID;
+  }
+  uint32_t* base = scratch_ptr(&g_create_err);
+  if (!base) return PIC_ERR_DEVICE;
+  uint32_t* dc = base;                            // counters
+  uint32_t* doo = base + 4 * kPhiloxScratchMax;   // outputs
+  hipError_t e = hipMemcpy(dc, ctr, n * 16, hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    launch_philox(dc, key[0], key[1], doo, n, nullptr);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpy(out, doo, n * 16, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) {
+    g_create_err = std::string("pic_philox_noalloc: ") + hipGetErrorString(e);
+    return PIC_ERR_DEVICE;
+  }
   return PIC_OK;
 }
 
