@@ -29,7 +29,8 @@
  *   - Host pointers are read during the call only; configs and tables are
  *     copied, so the caller may free them on return.
  *   - The context owns all device memory it allocates (hipMalloc at
- *     pic_create); pic_destroy frees it.  Device pointers are never exposed.
+ *     pic_create); pic_destroy frees it.  Device pointers are exposed only by
+ *     pic_get_buffers, borrowed and valid until the next step or destroy.
  *   - A context is not thread-safe; distinct contexts are independent and may
  *     be driven from different threads.
  *   - Work is enqueued on cfg->stream (a hipStream_t, NULL = the default
@@ -48,7 +49,7 @@ extern "C" {
 #endif
 
 #define PIC_ABI_VERSION 1u
-#define PIC_TABLES_VERSION 1u
+#define PIC_TABLES_VERSION 2u
 
 typedef struct pic_ctx pic_ctx; /* opaque; owned by the library */
 
@@ -151,6 +152,9 @@ typedef struct {
   double ln_T0, dln_T;
   const double* sigma;   /* n_T */
   const double* br_cdf;  /* n_T * n_y */
+  uint64_t checksum;     /* 64-bit FNV-1a of the bytes of h, ln_xi, ncs_cdf, sigma
+                            and br_cdf, in that order (pic_build_tables fills it);
+                            0 = not checked.  A mismatch is PIC_ERR_TABLES. */
 } pic_tables;
 
 /* Emission statistics.  Energies in mc^2 times the macro-particle weight
@@ -177,26 +181,44 @@ typedef struct {
 /* ---- the five calls of the hot path ------------------------------------- */
 
 /* Validate cfg, allocate the context's device memory and load the electrons
- * and ions on the device.  On success *out owns everything.
+ * and ions on the device: the laser-target set-up of Sec. III (a slab target
+ * of fully or partly ionised Al or Au at a given electron density, ppc
+ * macro-electrons per cell, the laser entering from the left boundary,
+ * absorbing boundaries).  On success *out owns everything.
  * Errors: PIC_ERR_INVALID (bad cfg), PIC_ERR_NOMEM, PIC_ERR_DEVICE. */
 pic_status pic_create(const pic_config* cfg, pic_ctx** out);
 
-/* Copy and check the emission tables (NCS tables of the quantum-synchrotron
- * spectrum; bremsstrahlung tables of Eq. (1) integrated as in Eq. (4)'s
- * sigma(E)).  Required before pic_step when PIC_NCS or PIC_BREM is set.
- * Errors: PIC_ERR_TABLES, PIC_ERR_INVALID, PIC_ERR_DEVICE. */
+/* Copy and check the emission tables: NCS tables of the quantum-synchrotron
+ * spectrum (Sec. II.A, the emission module "the same with EPOCH"), and
+ * bremsstrahlung tables of Tsai's cross-section, Eq. (1), integrated from the
+ * photon cut to give sigma(E) of Eq. (4) and its cumulative rows for the R2
+ * energy draw (Sec. II.B).  Required before pic_step when PIC_NCS or PIC_BREM
+ * is set.  Errors: PIC_ERR_TABLES (version, Z, sizes, a non-finite value, a
+ * CDF row not rising from its first entry to exactly 1, a checksum that does
+ * not match the arrays), PIC_ERR_INVALID,
+ * PIC_ERR_DEVICE. */
 pic_status pic_load_tables(pic_ctx* ctx, const pic_tables* t);
 
 /* Enqueue nsteps >= 0 full steps on the context's stream; returns without
- * waiting for the device.  Errors: PIC_ERR_STATE (no tables while emission
- * is on), PIC_ERR_INVALID, PIC_ERR_DEVICE. */
+ * waiting for the device.  One step of every live electron, in order:
+ * gather, Boris push, eta (Sec. II.A), NCS optical depth and photon draw
+ * (Sec. II.A-B), the bremsstrahlung collision test P = 1 - exp(-n sigma v dt)
+ * of Eq. (4) with the photon energy from sigma(y, E) = R2 sigma(E) and the
+ * cross-section of Eq. (1) (Sec. II.B), recoil, photon append (records of
+ * photons >= the cut, Sec. III), move and current deposit; then the field
+ * solve.  Errors: PIC_ERR_STATE (no tables while emission is on),
+ * PIC_ERR_INVALID, PIC_ERR_DEVICE. */
 pic_status pic_step(pic_ctx* ctx, int32_t nsteps);
 
-/* Wait for the context's stream and return the statistics.  Returns
- * PIC_ERR_OVERFLOW (with *out filled) when photons did not fit. */
+/* Wait for the context's stream and return the statistics: event and photon
+ * counts per process and the energy partition of Sec. III (energy radiated
+ * into kept and dropped photons per process, electron kinetic energy, field
+ * energy).  Returns PIC_ERR_OVERFLOW (with *out filled) when photons did not
+ * fit the buffer. */
 pic_status pic_emission_stats(pic_ctx* ctx, pic_stats* out);
 
-/* Release everything the context owns.  NULL is a no-op. */
+/* Release everything the context owns (no passage of the paper: resource
+ * management).  NULL is a no-op. */
 void pic_destroy(pic_ctx* ctx);
 
 /* ---- helpers (tests, tools, serving) ------------------------------------ */

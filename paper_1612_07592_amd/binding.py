@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpic.so")
 
 PIC_ABI_VERSION = 1
-PIC_TABLES_VERSION = 1
+PIC_TABLES_VERSION = 2
 PIC_FP64, PIC_FP32_MIXED = 0, 1
 PIC_NCS, PIC_BREM, PIC_FIELDS_FROZEN, PIC_NO_RECOIL, PIC_BREM_FREEPATH = 1, 2, 4, 16, 32
 PIC_FROZEN_UNIFORM, PIC_FROZEN_PLANE_WAVE = 0, 1
@@ -53,7 +53,7 @@ class pic_tables(C.Structure):
                 ("ln_xi", C.POINTER(C.c_double)), ("ncs_cdf", C.POINTER(C.c_double)),
                 ("n_T", C.c_int32), ("n_y", C.c_int32), ("ln_T0", C.c_double),
                 ("dln_T", C.c_double), ("sigma", C.POINTER(C.c_double)),
-                ("br_cdf", C.POINTER(C.c_double))]
+                ("br_cdf", C.POINTER(C.c_double)), ("checksum", C.c_uint64)]
 
 
 class pic_stats(C.Structure):
@@ -227,6 +227,7 @@ def tables_struct(t: dict):
         a = np.ascontiguousarray(t[name], dtype=np.float64)
         keep.append(a)
         setattr(s, name, a.ctypes.data_as(C.POINTER(C.c_double)))
+    s.checksum = int(t.get("checksum", 0))
     return s, keep
 
 
@@ -242,7 +243,7 @@ def pic_build_tables(Z: int, k_cut_mc2: float = 1.0, nthreads: int = 0) -> dict:
     return dict(Z=int(Z), k_cut=float(k_cut_mc2), n_eta=out.n_eta, n_xi=out.n_xi,
                 ln_eta0=out.ln_eta0, dln_eta=out.dln_eta, h=h, ln_xi=lx,
                 ncs_cdf=ncs.reshape(256, 256), n_T=out.n_T, n_y=out.n_y, ln_T0=out.ln_T0,
-                dln_T=out.dln_T, sigma=sig, br_cdf=br.reshape(128, 64))
+                dln_T=out.dln_T, sigma=sig, br_cdf=br.reshape(128, 64), checksum=int(out.checksum))
 
 
 def pic_philox(ctr, key) -> np.ndarray:

@@ -701,6 +701,8 @@ pic_status pic_load_tables(pic_ctx* ctx, const pic_tables* t) {
     for (int j = 1; j < t->n_xi; ++j)
       if (!(r[j] >= r[j - 1]) || !is_fin(r[j])) FAIL(c, PIC_ERR_TABLES, "NCS CDF row %d not monotone", i);
   }
+  if (t->checksum != 0 && tables_checksum(*t) != t->checksum)
+    FAIL(c, PIC_ERR_TABLES, "table checksum mismatch (arrays altered after they were built)");
   for (int i = 0; i < t->n_T; ++i) {
     if (!(t->sigma[i] >= 0.0) || !is_fin(t->sigma[i])) FAIL(c, PIC_ERR_TABLES, "sigma[%d] invalid", i);
     const double* r = t->br_cdf + (size_t)i * t->n_y;

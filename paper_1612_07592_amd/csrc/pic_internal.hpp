@@ -67,6 +67,25 @@ struct FieldJob {
   double lsin, lcos;
 };
 
+// 64-bit FNV-1a of the bytes of the five table arrays, in declaration order
+// (the pic_tables checksum).
+inline uint64_t tables_checksum(const pic_tables& t) {
+  uint64_t h = 0xcbf29ce484222325ull;
+  auto feed = [&](const double* a, size_t n) {
+    const unsigned char* b = reinterpret_cast<const unsigned char*>(a);
+    for (size_t i = 0; i < n * sizeof(double); ++i) {
+      h ^= b[i];
+      h *= 0x100000001b3ull;
+    }
+  };
+  feed(t.h, (size_t)t.n_eta);
+  feed(t.ln_xi, (size_t)t.n_xi);
+  feed(t.ncs_cdf, (size_t)t.n_eta * t.n_xi);
+  feed(t.sigma, (size_t)t.n_T);
+  feed(t.br_cdf, (size_t)t.n_T * t.n_y);
+  return h;
+}
+
 // Emission tables resident on the device (FP64 copy, FP32 copy).
 // Guide of an inverse-CDF row: kGuide + 1 entries, entry b is the largest
 // index j <= n - 2 with C[j] <= b / kGuide (0 if none).  A uniform u then has

@@ -7,8 +7,8 @@
 //      and the device reports enough free memory for the job's context
 //      (pic_memory_required) on top of the configured reserve;
 //   2. advances every resident job by up to quantum_steps steps in one
-//      pic_step_many call (one persistent electron-step kernel and one field
-//      launch per step for all of them; uneven jobs simply drop out of the
+//      pic_step_many call (per step, one batched launch of each kernel of the
+//      step covers every resident job; uneven jobs simply drop out of the
 //      later steps of the round);
 //   3. waits for the device, retires the jobs that reached their step count
 //      (statistics read back, context freed unless kept) and stamps their

@@ -16,6 +16,7 @@
 #include <thread>
 #include <vector>
 #include "../../include/pic.h"
+#include "pic_internal.hpp"
 
 namespace {
 
@@ -197,5 +198,6 @@ extern "C" pic_status pic_build_tables(uint32_t Z, double k_cut_mc2, int32_t nth
   out->dln_T = dln_T;
   out->sigma = sigma;
   out->br_cdf = br_cdf;
+  out->checksum = pic::tables_checksum(*out);
   return PIC_OK;
 }

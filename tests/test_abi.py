@@ -259,3 +259,22 @@ def test_bench_window_is_centred_on_the_interaction():
     w5 = W.c5()
     lead, k = b.window(w5, 20)
     assert lead <= b.peak_step(w5) <= lead + k
+
+
+def test_hot_path_declarations_cite_the_paper():
+    """Each of the calls of the hot path says which passage defines what it
+    computes (a section or an equation of the paper)."""
+    text = open(HEADER).read()
+    for name in ("pic_create", "pic_load_tables", "pic_step", "pic_emission_stats"):
+        m = re.search(r"/\*((?:(?!\*/).)*)\*/\s*pic_status\s+" + name + r"\(", text, flags=re.S)
+        assert m, name
+        assert re.search(r"Sec\. I|Eq\. \(", m.group(1)), name
+    m = re.search(r"/\*((?:(?!\*/).)*)\*/\s*void\s+pic_destroy\(", text, flags=re.S)
+    assert m and "no passage" in m.group(1)
+
+
+def test_device_pointer_convention_names_get_buffers():
+    text = open(HEADER).read()
+    head = text[:text.index("#ifndef LIBPIC_PIC_H")]
+    assert "never exposed." not in head
+    assert "pic_get_buffers" in head
