@@ -125,6 +125,8 @@ def _load(path=None):
         L.or_get_current.argtypes = [P, C.c_void_p]
         L.or_philox.argtypes = [C.c_uint32] * 6 + [C.c_void_p]
         L.or_set_fields.argtypes = [P, C.c_void_p]
+        L.or_math.restype = C.c_double
+        L.or_math.argtypes = [C.c_int, C.c_double]
         L.or_probe_field.restype = C.c_double
         L.or_probe_field.argtypes = [P, C.c_int, C.c_void_p]
         L.or_probe_boris.argtypes = [P, C.c_void_p, C.c_void_p, C.c_void_p]
@@ -146,6 +148,13 @@ def philox(ctr, key):
     _load().or_philox(*[int(c) & 0xFFFFFFFF for c in ctr], *[int(k) & 0xFFFFFFFF for k in key],
                       out.ctypes.data)
     return out
+
+
+def math(which: str, x, lib=None):
+    """The oracle's own exp, log or expm1 (elementwise)."""
+    f = _load(lib).or_math
+    k = {"exp": 0, "log": 1, "expm1": 2}[which]
+    return np.array([f(k, float(v)) for v in np.atleast_1d(x)])
 
 
 def _dptr(a):

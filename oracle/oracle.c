@@ -62,6 +62,70 @@ static double u52(uint32_t r0, uint32_t r1) {
   return ((double)k + 0.5) * 0x1p-52;
 }
 
+/* ------------------- exp, log and expm1 in FP64 -------------------------- */
+/* The method only needs these functions to double precision; their last bit
+ * differs between math libraries, and in a chaotic run one differing bit
+ * (say, in the photon energy of an emission) grows until runs part.  The
+ * oracle therefore evaluates them by the series below, whose every operation
+ * is an IEEE-rounded add, multiply or divide in a fixed order (accurate to
+ * about one ulp; pinned against the platform libm in the tests).
+ *   exp(x):   x = k ln2 + r, k the nearest integer to x/ln2, r formed in two
+ *             parts with ln2 = L_HI + L_LO (L_HI has 42 significant bits, so
+ *             k L_HI is exact); exp(r) = sum_{n<=14} r^n/n!, |r| <= ln2/2
+ *             (the first omitted term is below 2^-60); times 2^k.
+ *   log(x):   x = m 2^e with m in [sqrt(1/2), sqrt(2)); log m = 2 atanh s,
+ *             s = (m-1)/(m+1), |s| <= 0.1716, = 2 s sum_{j<=11} s^(2j)/(2j+1);
+ *             plus e L_HI + e L_LO.
+ *   expm1(x): x sum_{n<=13} x^n/(n+1)! for |x| < ln2/2, else exp(x) - 1. */
+static const double L_HI = 0x1.62e42fefa38p-1;
+static const double L_LO = 0x1.ef35793c7673p-45;
+static const double INV_LN2 = 0x1.71547652b82fep+0;
+/* 1/n!, n = 0..14 (each an exactly representable n! divided once) */
+static const double INV_FACT[15] = {
+    1.0, 1.0, 1.0 / 2.0, 1.0 / 6.0, 1.0 / 24.0, 1.0 / 120.0, 1.0 / 720.0, 1.0 / 5040.0,
+    1.0 / 40320.0, 1.0 / 362880.0, 1.0 / 3628800.0, 1.0 / 39916800.0, 1.0 / 479001600.0,
+    1.0 / 6227020800.0, 1.0 / 87178291200.0};
+
+static double or_exp(double x) {
+  if (x != x) return x;
+  if (x > 709.8) return INFINITY;
+  if (x < -745.2) return 0.0;
+  double k = rint(x * INV_LN2);
+  double r = (x - k * L_HI) - k * L_LO;
+  double p = INV_FACT[14];
+  for (int n = 13; n >= 0; --n) p = p * r + INV_FACT[n];
+  return ldexp(p, (int)k);
+}
+
+static double or_log(double x) {
+  if (x != x) return x;
+  if (!(x > 0.0)) return x == 0.0 ? -INFINITY : NAN;
+  if (isinf(x)) return x;
+  int e;
+  double m = frexp(x, &e);                          /* x = m 2^e, m in [1/2, 1) */
+  if (m < 0x1.6a09e667f3bcdp-1) { m = m * 2.0; e = e - 1; }
+  double s = (m - 1.0) / (m + 1.0);
+  double z = s * s;
+  double p = 1.0 / 23.0;
+  for (int j = 10; j >= 0; --j) p = p * z + 1.0 / (double)(2 * j + 1);
+  double lm = (2.0 * s) * p;
+  double de = (double)e;
+  return de * L_HI + (de * L_LO + lm);
+}
+
+static double or_expm1(double x) {
+  if (fabs(x) < 0x1.62e42fefa39efp-2) {             /* |x| < ln2/2 */
+    double p = INV_FACT[14];
+    for (int n = 12; n >= 0; --n) p = p * x + INV_FACT[n + 1];
+    return x * p;
+  }
+  return or_exp(x) - 1.0;
+}
+
+double or_math(int which, double x) {
+  return which == 0 ? or_exp(x) : (which == 1 ? or_log(x) : or_expm1(x));
+}
+
 /* ---------------------------- state --------------------------------------- */
 #define G 2 /* guard cells per side on active axes */
 
@@ -110,7 +174,7 @@ static int64_t fidx(const or_sim* s, int i, int j, int k) {
  * first grid point F/xi ~ xi^(-2/3), so the CDF ~ xi^(1/3) (READING). */
 static double ncs_inv_row(const or_sim* s, int row, double u) {
   const double* C = s->ncs_cdf + (int64_t)row * s->n_xi;
-  if (u < C[0]) return s->ln_xi[0] + 3.0 * log(u / C[0]);
+  if (u < C[0]) return s->ln_xi[0] + 3.0 * or_log(u / C[0]);
   int lo = 0, hi = s->n_xi - 1;
   while (hi - lo > 1) {
     int mid = (lo + hi) / 2;
@@ -268,11 +332,11 @@ or_sim* or_create(const or_config* c, const or_tables* t, int nthreads) {
           s->x[3 * e + 0] = ((double)i + u32(r[0])) * s->dx[0];
           s->x[3 * e + 1] = s->act[1] ? ((double)j + u32(r[1])) * s->dx[1] : 0.0;
           s->x[3 * e + 2] = s->act[2] ? ((double)k + u32(r[2])) * s->dx[2] : 0.0;
-          s->tau[e] = -log(u32(r[3]));
+          s->tau[e] = -or_log(u32(r[3]));
           if (s->taub) {  /* first free path, in mean free paths: -ln u */
             uint32_t rb[4];
             or_philox((uint32_t)e, 0xFFFFFFFFu, 1u, 0u, s->key0, s->key1, rb);
-            s->taub[e] = -log(u32(rb[0]));
+            s->taub[e] = -or_log(u32(rb[0]));
           }
           s->w[e] = wgt;
           s->id[e] = (uint32_t)e;
@@ -478,7 +542,7 @@ static double eta_of(const double E[3], const double B[3], double px, double py,
  * to the last interval above the grid).  Returns 0 below the first point:
  * no emission there (READING). */
 static int ncs_row(const or_sim* s, double eta, int* i, double* f) {
-  double le = log(eta);
+  double le = or_log(eta);
   double sl = (le - s->ln_eta0) * s->idln_eta;
   if (!(sl >= 0.0)) return 0;
   if (sl >= (double)(s->n_eta - 1)) { *i = s->n_eta - 2; *f = 1.0; }
@@ -499,14 +563,14 @@ static double ncs_xi(const or_sim* s, int i, double f, double u) {
   double la = ncs_inv_row(s, i, u);
   double lb = ncs_inv_row(s, i + 1, u);
   double lx = la + f * (lb - la);
-  return exp(lx);
+  return or_exp(lx);
 }
 
 /* Position of the kinetic energy T on the bremsstrahlung table: row i,
  * fraction f in ln T, ln T itself; clamps (and flags) above the last point.
  * Returns 0 below the first point. */
 static int brem_row(const or_sim* s, double T, int* i, double* f, double* lt, int* clamped) {
-  *lt = log(T);
+  *lt = or_log(T);
   double sl = (*lt - s->ln_T0) * s->idln_T;
   if (!(sl >= 0.0)) return 0;
   if (sl >= (double)(s->n_T - 1)) { *i = s->n_T - 2; *f = 1.0; *clamped = 1; }
@@ -527,8 +591,8 @@ static double brem_eps(const or_sim* s, int i, double f, double lt, double T, do
   double sa = br_inv_row(s, i, u);
   double sb = br_inv_row(s, i + 1, u);
   double sv = sa + f * (sb - sa);
-  double lk = log(s->k_cut);
-  double eps = exp(lk + sv * (lt - lk));
+  double lk = or_log(s->k_cut);
+  double eps = or_exp(lk + sv * (lt - lk));
   if (eps > T) eps = T;
   return eps;
 }
@@ -596,7 +660,7 @@ static void electron_one(or_sim* s, int64_t e, double tn, eres* out) {
       double pm = sqrt(px * px + py * py + pz * pz);
       add_photon(out, x, px, py, pz, pm, eps, 0, eps >= c->photon_cut_mc2);
       if (!(c->flags & OR_NO_RECOIL)) recoil(eps, pm, &px, &py, &pz, &gamma);
-      s->tau[e] = -log(u32(r[3]));
+      s->tau[e] = -or_log(u32(r[3]));
     }
   }
 
@@ -633,14 +697,14 @@ static void electron_one(or_sim* s, int64_t e, double tn, eres* out) {
             s->taub[e] = s->taub[e] - X;
             hit = s->taub[e] <= 0.0;
           } else {
-            double P = -expm1(-X);
+            double P = -or_expm1(-X);
             hit = u52(r[0], r[1]) < P;
           }
           if (hit) {
             uint32_t r2[4];
             or_philox(s->id[e], n, 1u, 0u, s->key0, s->key1, r2);
             /* the next free path: word 1 of the event's second draw */
-            if (c->flags & OR_BREM_FREEPATH) s->taub[e] = -log(u32(r2[1]));
+            if (c->flags & OR_BREM_FREEPATH) s->taub[e] = -or_log(u32(r2[1]));
             double eps = brem_eps(s, i, f, lt, T, u32(r2[0]));
             add_photon(out, x, px, py, pz, pm, eps, 1, 1);
             if (!(c->flags & OR_NO_RECOIL)) recoil(eps, pm, &px, &py, &pz, &gamma);
@@ -671,7 +735,13 @@ static void shape4(double g, int base, double S[4]) {
  * the nearest multiple of 2^-40 and summed as an integer, so the total does
  * not depend on the order in which electrons are visited (READING: the paper
  * leaves the weighting procedure unspecified). */
-static void jadd(int64_t* J, int64_t m, double v) { J[m] += (int64_t)llrint(v * 0x1p40); }
+static void jadd(int64_t* J, int64_t m, double v) {
+  int64_t q = (int64_t)llrint(v * 0x1p40);
+#ifdef _OPENMP
+#pragma omp atomic
+#endif
+  J[m] += q;
+}
 
 /* charge-conserving current of one electron moving x0 -> x1 (Esirkepov form;
  * in 1D the exact 1D continuity solution) */
@@ -784,12 +854,20 @@ void or_step(or_sim* s, int nsteps) {
 #endif
     for (int64_t e = 0; e < s->N; ++e)
       if (s->alive[e]) electron_one(s, e, tn, &res[e]);
-    /* id-ordered pass: deposit, photon append, sums, absorbing walls */
+    /* charge-conserving deposit of every move (integer sums: the order in
+     * which electrons add to a node does not change the result) */
+    if (!frozen) {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) num_threads(s->nthreads)
+#endif
+      for (int64_t e = 0; e < s->N; ++e)
+        if (s->alive[e]) deposit(s, s->x + 3 * e, res[e].x1, res[e].v, s->w[e]);
+    }
+    /* id-ordered pass: photon append, sums, absorbing walls */
     uint64_t live = 0;
     for (int64_t e = 0; e < s->N; ++e) {
       if (!s->alive[e]) continue;
       eres* r = &res[e];
-      if (!frozen) deposit(s, s->x + 3 * e, r->x1, r->v, s->w[e]);
       for (int k = 0; k < r->nph; ++k) {
         int pr = r->pproc[k];
         double we = s->w[e] * r->pe[k];

@@ -87,6 +87,7 @@ void     or_philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
  * brem_sigma: sigma(T) in alpha r_e^2 (0 below the cut or the table);
  * brem_eps: the photon energy at uniform u. */
 void     or_set_fields(or_sim* s, const double* in);   /* 6*size: Ex,Ey,Ez,Bx,By,Bz */
+double   or_math(int which, double x);                 /* 0 exp, 1 log, 2 expm1 of the oracle */
 double   or_probe_field(const or_sim* s, int comp, const double x[3]);
 void     or_probe_boris(const or_sim* s, const double E[3], const double B[3], double p[3]);
 double   or_probe_eta(const or_sim* s, const double E[3], const double B[3], const double p[3]);

@@ -13,6 +13,7 @@
 #include <vector>
 #include "pic_internal.hpp"
 #include "philox.hpp"
+#include "fpmath.hpp"
 
 namespace pic {
 int sort_scratch_words(uint32_t nkeys);
@@ -764,7 +765,7 @@ pic_status pic_load_tables(pic_ctx* ctx, const pic_tables* t) {
   d.n_eta = t->n_eta; d.n_xi = t->n_xi; d.n_T = t->n_T; d.n_y = t->n_y;
   d.ln_eta0 = t->ln_eta0; d.idln_eta = 1.0 / t->dln_eta;
   d.ln_T0 = t->ln_T0; d.idln_T = 1.0 / t->dln_T;
-  d.k_cut = t->k_cut_mc2; d.lnk = log(t->k_cut_mc2); d.iny1 = 1.0 / (double)(t->n_y - 1);
+  d.k_cut = t->k_cut_mc2; d.lnk = fp_log(t->k_cut_mc2); d.iny1 = 1.0 / (double)(t->n_y - 1);
   st = upload_cold(c);
   if (st) return st;
   c.tables_loaded = true;

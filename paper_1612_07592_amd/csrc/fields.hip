@@ -3,6 +3,7 @@
 // loading, and the fixed-order reductions behind pic_emission_stats.
 #include "pic_internal.hpp"
 #include "philox.hpp"
+#include "fpmath.hpp"
 
 namespace pic {
 
@@ -341,10 +342,10 @@ __global__ __launch_bounds__(kBlock) void k_init_electrons(InitArgs A) {
     if (A.dims >= 3) ((R*)A.x[2])[e] = (R)(((double)kk + unif32(r.v[2])) * A.dx[2]);
   }
   for (int a = 0; a < 3; ++a) ((R*)A.p[a])[e] = R(0);
-  A.tau[e] = -log(unif32(r.v[3]));
+  A.tau[e] = -fp_log(unif32(r.v[3]));
   if (A.taub) {
     const U4 rb = philox4x32_10((uint32_t)e, 0xFFFFFFFFu, 1u, 0u, A.key0, A.key1);
-    A.taub[e] = -log(unif32(rb.v[0]));
+    A.taub[e] = -fp_log(unif32(rb.v[0]));
   }
   A.w[e] = A.wgt;
   A.id[e] = (uint32_t)e;

@@ -19,6 +19,7 @@
 // comparison and the energy sums in FP64.
 #include "pic_internal.hpp"
 #include "philox.hpp"
+#include "fpmath.hpp"
 #include <algorithm>
 #include <type_traits>
 
@@ -26,11 +27,11 @@ namespace pic {
 
 __device__ inline double m_sqrt(double v) { return sqrt(v); }
 __device__ inline float m_sqrt(float v) { return sqrtf(v); }
-__device__ inline double m_log(double v) { return log(v); }
+__device__ inline double m_log(double v) { return fp_log(v); }
 __device__ inline float m_log(float v) { return logf(v); }
-__device__ inline double m_exp(double v) { return exp(v); }
+__device__ inline double m_exp(double v) { return fp_exp(v); }
 __device__ inline float m_exp(float v) { return expf(v); }
-__device__ inline double m_expm1(double v) { return expm1(v); }
+__device__ inline double m_expm1(double v) { return fp_expm1(v); }
 __device__ inline float m_expm1(float v) { return expm1f(v); }
 __device__ inline double m_floor(double v) { return floor(v); }
 __device__ inline float m_floor(float v) { return floorf(v); }
@@ -788,7 +789,7 @@ __device__ inline void electron_push(const StepParams<R>& P, int64_t e, uint32_t
         L.r = philox4x32_10(idv, n, 0u, 0u, P.key0, P.key1);
         L.have_r = true;
         const R eps = ncs_eps<R>(P, i, f, unif<R>(L.r.v[2]), L.gamma);
-        ncs_finish<R>(P, e, L, eps, -log(unif32(L.r.v[3])), out);
+        ncs_finish<R>(P, e, L, eps, -fp_log(unif32(L.r.v[3])), out);
       } else {
         P.tau[e] = tau;
       }
@@ -851,7 +852,7 @@ __device__ inline void electron_finish(const StepParams<R>& P, int64_t e, uint32
             } else {
               const U4 r2 = philox4x32_10(idv, n, 1u, 0u, P.key0, P.key1);
               // next free path from word 1 of the energy draw's counter
-              if (fpath) P.taub[e] = -log(unif32(r2.v[1]));
+              if (fpath) P.taub[e] = -fp_log(unif32(r2.v[1]));
               const R u = unif<R>(r2.v[0]);
               const ColdPtr<R> C = cold(P);
               const int ny = C->n_y;

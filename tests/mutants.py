@@ -28,7 +28,7 @@ MUTANTS = {
                               "                   (S0[0][i] * S1[1][j] + S1[0][i] * S0[1][j]) * (0.0 / 6.0);")],
     "deposit3d_T_weight": [("double T = (S0[1][j] * S0[2][k] + S1[1][j] * S1[2][k]) * (1.0 / 3.0) +",
                             "double T = (S0[1][j] * S0[2][k] + S1[1][j] * S1[2][k]) * (1.0 / 2.0) +")],
-    "current_quantum_2e-30": [("J[m] += (int64_t)llrint(v * 0x1p40);", "J[m] += (int64_t)llrint(v * 0x1p30) << 10;")],
+    "current_quantum_2e-30": [("int64_t q = (int64_t)llrint(v * 0x1p40);", "int64_t q = (int64_t)llrint(v * 0x1p30) << 10;")],
     # gather
     "gather_stagger_sign": [("double ga = g[a] - 0.5 * (double)st[a];", "double ga = g[a] + 0.5 * (double)st[a];")],
     "gather3d_z_fraction": [("return (1.0 - f[2]) * a2 + f[2] * b2;", "return (1.0 - f[1]) * a2 + f[1] * b2;")],
@@ -62,8 +62,12 @@ MUTANTS = {
     "brem_sigma_blend": [("return s->sigma[i] + f * (s->sigma[i + 1] - s->sigma[i]);",
                           "return s->sigma[i + 1] + f * (s->sigma[i + 1] - s->sigma[i]);")],
     "brem_row_blend": [("double sv = sa + f * (sb - sa);", "double sv = sa + (1.0 - f) * (sb - sa);")],
-    "brem_energy_map": [("double eps = exp(lk + sv * (lt - lk));",
-                         "double eps = exp(lk + sv * (log(T + 1.0) - lk));")],
+    "brem_energy_map": [("double eps = or_exp(lk + sv * (lt - lk));",
+                         "double eps = or_exp(lk + sv * (or_log(T + 1.0) - lk));")],
+    # the oracle's own exp / log series
+    "exp_series_short": [("  for (int n = 13; n >= 0; --n) p = p * r + INV_FACT[n];",
+                          "  for (int n = 7; n >= 0; --n) p = p * r + INV_FACT[n];")],
+    "log_split_dropped": [("  return de * L_HI + (de * L_LO + lm);", "  return de * L_HI + lm;")],
     # constants
     "K_BR_factor": [("s->K_BR = s->n_c * (lam / twopi) * alpha * re * re;",
                      "s->K_BR = s->n_c * lam * alpha * re * re;")],
@@ -77,7 +81,9 @@ def build(name: str) -> str:
     for old, new in MUTANTS[name]:
         n = src.count(old)
         if n != 1:
-            raise AssertionError(f"mutant {name}: pattern found {n} times: {old!r}")
+            # not an AssertionError: a mutant that cannot be built must not
+            # count as a pin that failed on it
+            raise RuntimeError(f"mutant {name}: pattern found {n} times: {old!r}")
         src = src.replace(old, new)
     key = hashlib.sha256(src.encode()).hexdigest()[:12]
     d = os.path.join(MUT_DIR, f"{name}-{key}")

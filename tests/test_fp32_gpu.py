@@ -8,7 +8,8 @@ Particle-only runs (prescribed fields) have no collective dynamics, so the
 two precisions see the same fields and the criteria apply as stated.  In the
 full 2D PIC run the laser-plasma interaction is chaotic: two FP64 runs that
 differ only in the seed already fail the Poisson count and KS criteria, so
-there the KS distance is judged against that seed-to-seed distance."""
+there the criteria are applied to an ensemble of seed pairs, which separates
+a systematic FP32 bias from the run-to-run spread."""
 from __future__ import annotations
 
 import numpy as np
@@ -67,26 +68,41 @@ def test_fp32_particle_only_plane_wave(gpu_lib, tables_al):
     assert ks.pvalue > 0.01
 
 
-def test_fp32_full_pic_2d_gold_a270(gpu_lib, tables_au):
-    """2048x1024 cells, Au q = 69 slab at 200 n_c, a0 = 270, 2000 steps.
-
-    The strict criteria are printed per result; the assertions hold each
-    FP32 difference to twice the largest difference between the FP64 run and
-    FP64 runs with the next two seeds (floored at the strict bounds)."""
+def test_fp32_full_pic_2d_gold_a270_ensemble(gpu_lib, tables_au):
+    """2048x1024 cells, Au q = 69 slab at 200 n_c, a0 = 270, 2000 steps, as an
+    ensemble: k seeds, each run in FP32 and in FP64 on the same Philox
+    streams (paired).  The laser-plasma interaction is chaotic, so one FP32
+    run and one FP64 run differ by the run-to-run spread; a systematic FP32
+    bias shows up instead in the mean of the paired differences:
+      kept photons   |mean(N32 - N64)| <= 3 SE of the paired differences
+      energy         |mean((E32 - E64) / E64)| <= 1%
+      spectrum       the fraction of photons in each decile of the pooled
+                     FP64 spectrum: |mean paired difference| <= 3.5 SE
+                     (ten bins); the two-sample KS test of the pooled
+                     spectra is printed.
+    Each single pair's strict criteria are printed too."""
+    k = 5
     w = W.c2(steps=2000)
-    r64 = _run(gpu_lib, dict(w, precision="fp64"), tables_au, 2000)
-    r32 = _run(gpu_lib, dict(w, precision="fp32"), tables_au, 2000)
-    z, rel, ks = _criteria(r32, r64, "2D Au a0=270 full PIC")
-    print(f"[fp32-vs-fp64] strict: count {'pass' if abs(z) <= 3 else 'FAIL'}, energy "
-          f"{'pass' if abs(rel) <= 0.01 else 'FAIL'}, KS {'pass' if ks.pvalue > 0.01 else 'FAIL'}")
-    dn, de, dk = [], [], []
-    for k in (1, 2):
-        ref = _run(gpu_lib, dict(w, precision="fp64", seed=w["seed"] + k), tables_au, 2000)
-        zr, relr, ksr = _criteria(ref, r64, f"2D Au a0=270 full PIC, FP64 seed +{k} (reference)")
-        dn.append(abs(ref["n"] - r64["n"]))
-        de.append(abs(relr))
-        dk.append(ksr.statistic)
-    assert r64["n"] > 100000
-    assert abs(r32["n"] - r64["n"]) <= 2.0 * max(max(dn), 3.0 * r64["n"] ** 0.5)
-    assert abs(rel) <= max(0.01, 2.0 * max(de))
-    assert ks.statistic <= 2.0 * max(dk)
+    r32, r64 = [], []
+    for j in range(k):
+        ws = dict(w, seed=int(w["seed"]) + 100 * j)
+        r64.append(_run(gpu_lib, dict(ws, precision="fp64"), tables_au, 2000))
+        r32.append(_run(gpu_lib, dict(ws, precision="fp32"), tables_au, 2000))
+        _criteria(r32[-1], r64[-1], f"2D Au a0=270 full PIC, seed pair {j}")
+    d = np.array([a["n"] - b["n"] for a, b in zip(r32, r64)], dtype=float)
+    se = d.std(ddof=1) / np.sqrt(k)
+    rel = np.array([(a["erad"] - b["erad"]) / b["erad"] for a, b in zip(r32, r64)])
+    edges = np.quantile(np.concatenate([b["eps"] for b in r64]), np.linspace(0, 1, 11)[1:-1])
+    frac = lambda e: np.bincount(np.searchsorted(edges, e), minlength=10) / max(len(e), 1)
+    fd = np.array([frac(a["eps"]) - frac(b["eps"]) for a, b in zip(r32, r64)])
+    fse = fd.std(axis=0, ddof=1) / np.sqrt(k)
+    ks = sst.ks_2samp(np.concatenate([a["eps"] for a in r32]), np.concatenate([b["eps"] for b in r64]))
+    print(f"\n[fp32-vs-fp64] ensemble of {k}: kept mean diff {d.mean():+.1f} (SE {se:.1f}, "
+          f"{d.mean() / se if se else 0:+.2f} SE), mean N64 {np.mean([b['n'] for b in r64]):.0f}; "
+          f"energy mean rel {rel.mean():+.2e}; spectrum decile diffs (in SE) "
+          f"{np.round(fd.mean(0) / np.maximum(fse, 1e-300), 2).tolist()}; pooled KS D = "
+          f"{ks.statistic:.5f} p = {ks.pvalue:.3g}", flush=True)
+    assert min(b["n"] for b in r64) > 100000
+    assert abs(d.mean()) <= 3.0 * se
+    assert abs(rel.mean()) <= 0.01
+    assert np.all(np.abs(fd.mean(0)) <= 3.5 * fse)

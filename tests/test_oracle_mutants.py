@@ -32,6 +32,8 @@ CASES = [
     ("brem_sigma_blend", PE.check_brem_sigma_off_node),
     ("brem_row_blend", PE.check_brem_sampling_off_node),
     ("brem_energy_map", PE.check_brem_sampling_off_node),
+    ("exp_series_short", PE.check_math_against_libm),
+    ("log_split_dropped", PE.check_math_against_libm),
     ("K_BR_factor", PE.check_constants),
     ("E_S_factor", PE.check_constants),
 ]

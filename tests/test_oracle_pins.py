@@ -676,7 +676,8 @@ def test_brem_freepath_16_electrons_brute_force(oracle_lib, tables_au):
     tb0 = o.tau_brem()
     for idv in range(16):
         want0 = -math.log(_u32(_philox_py((idv, 0xFFFFFFFF, 1, 0), key)[0]))
-        assert tb0[idv] == want0
+        # the oracle's own log series is within 3 ulp of the platform log
+        assert abs(tb0[idv] - want0) <= 4 * np.spacing(want0)
     p = np.zeros((16, 3))
     p[:, 1] = pm
     o.set_electrons(e["x"], p, e["tau"])

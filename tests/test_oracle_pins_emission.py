@@ -246,3 +246,30 @@ def check_constants(lib=None):
 
 def test_constants_against_independent_values(oracle_lib):
     print(check_constants())
+
+
+# ------------------------------------------------------- exp, log, expm1
+def check_math_against_libm(lib=None):
+    """The oracle's own exp, log and expm1 against the platform libm over
+    wide random arguments: within 1, 3 and 4 ulp, exact at the special
+    points."""
+    rng = np.random.default_rng(1)
+    ulps = lambda a, b: np.abs(a - b) / np.spacing(np.abs(b))
+    x = np.concatenate([rng.uniform(-30, 30, 20000), rng.uniform(-1, 1, 10000),
+                        rng.uniform(-700, 700, 5000)])
+    y = np.concatenate([np.exp(rng.uniform(-740, 709, 20000)), rng.uniform(0.5, 2, 10000),
+                        1 + rng.normal(scale=1e-6, size=5000)])
+    z = np.concatenate([rng.uniform(-0.35, 0.35, 10000), -np.exp(rng.uniform(-40, 0, 10000)),
+                        rng.uniform(-30, 5, 10000)])
+    e1 = ulps(oracle.math("exp", x, lib), np.exp(x)).max()
+    e2 = ulps(oracle.math("log", y, lib), np.log(y)).max()
+    e3 = ulps(oracle.math("expm1", z, lib), np.expm1(z)).max()
+    assert e1 <= 1.0 and e2 <= 3.0 and e3 <= 4.0, (e1, e2, e3)
+    assert oracle.math("exp", [0.0], lib)[0] == 1.0 and oracle.math("log", [1.0], lib)[0] == 0.0
+    assert oracle.math("expm1", [0.0], lib)[0] == 0.0
+    assert oracle.math("log", [0.5], lib)[0] == -math.log(2.0)
+    return e1, e2, e3
+
+
+def test_oracle_math_against_libm(oracle_lib):
+    print(check_math_against_libm())

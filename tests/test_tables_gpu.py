@@ -32,14 +32,19 @@ def test_bad_tables_rejected_and_context_survives(gpu_lib):
     cases["ncs row not monotone"] = _bad(good, ncs_cdf=c)
     b = good["br_cdf"].copy(); b[90, -1] = 0.999
     cases["brem row end"] = _bad(good, br_cdf=b)
-    s = good["sigma"].copy(); s[50] *= 1.0 + 1e-12
+    s = good["sigma"].copy(); s[100] *= 1.0 + 1e-12      # a row above the photon cut (sigma > 0)
+    assert s[100] != good["sigma"][100]
     cases["checksum"] = _bad(good, sigma=s)       # altered after it was built
     lx = good["ln_xi"].copy(); lx[10] = lx[9]
     cases["ln_xi not increasing"] = _bad(good, ln_xi=lx)
+    accepted = []
     for name, t in cases.items():
-        with pytest.raises(gpu_lib.PicError) as e:
+        try:
             g.pic_load_tables(t)
-        assert e.value.code == 6, (name, e.value)  # PIC_ERR_TABLES
+            accepted.append(name)
+        except gpu_lib.PicError as e:
+            assert e.code == 6, (name, e)           # PIC_ERR_TABLES
+    assert not accepted, accepted
     import ctypes as C
     ts, keep = gpu_lib.tables_struct(good)
     ts.version = 1
