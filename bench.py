@@ -59,7 +59,7 @@ ALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # rate operations counted 4; the conditional brem test and event sampling are
 # not included.  An estimate from the method, not a counter.
 ALU_OPS = {1: 292, 2: 548, 3: 1366}
-KERNEL_SOURCES = ["step.hip", "pic_internal.hpp", "philox.hpp"]
+KERNEL_SOURCES = ["step.hip", "pic_internal.hpp", "philox.hpp", "fpmath.hpp"]
 # algorithmic bytes per electron-step of the step kernel: the electron state
 # read once (positions, momenta, tau, weight, id) and written once (positions,
 # momenta, tau); fields and tables are amortised over the electrons of a cell
