@@ -68,7 +68,8 @@ class _Cfg(C.Structure):
                 ("x0_lambda", C.c_double), ("thickness_lambda", C.c_double),
                 ("photon_cut_mc2", C.c_double), ("frozen_E", C.c_double * 3),
                 ("frozen_B", C.c_double * 3), ("frozen_a", C.c_double),
-                ("seed", C.c_uint64), ("job_id", C.c_uint64), ("photon_capacity", C.c_uint64)]
+                ("seed", C.c_uint64), ("job_id", C.c_uint64), ("photon_capacity", C.c_uint64),
+                ("ion_ppc", C.c_int32), ("envelope", C.c_int32), ("ion_mass", C.c_double)]
 
 
 class _Tab(C.Structure):
@@ -84,7 +85,8 @@ class _Stats(C.Structure):
     _fields_ = [("steps", C.c_uint64), ("live", C.c_uint64), ("events", C.c_uint64 * 2),
                 ("kept", C.c_uint64 * 2), ("dropped_ncs", C.c_uint64),
                 ("overflow", C.c_uint64), ("brem_clamped", C.c_uint64),
-                ("e_rad_kept", C.c_double * 2), ("e_rad_dropped", C.c_double)]
+                ("e_rad_kept", C.c_double * 2), ("e_rad_dropped", C.c_double),
+                ("ions_live", C.c_uint64)]
 
 
 _libs = {}
@@ -125,6 +127,12 @@ def _load(path=None):
         L.or_get_current.argtypes = [P, C.c_void_p]
         L.or_philox.argtypes = [C.c_uint32] * 6 + [C.c_void_p]
         L.or_set_fields.argtypes = [P, C.c_void_p]
+        L.or_num_ions.restype = C.c_int64
+        L.or_num_ions.argtypes = [P]
+        L.or_get_ions.argtypes = [P, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.or_set_ions.argtypes = [P, C.c_void_p, C.c_void_p]
+        L.or_ion_kinetic_energy.restype = C.c_double
+        L.or_ion_kinetic_energy.argtypes = [P]
         L.or_math.restype = C.c_double
         L.or_math.argtypes = [C.c_int, C.c_double]
         L.or_probe_field.restype = C.c_double
@@ -212,6 +220,9 @@ class OracleSim:
         c.seed = int(w.get("seed", 1))
         c.job_id = int(w.get("job_id", 0))
         c.photon_capacity = int(w.get("photon_capacity", 1 << 20))
+        c.ion_ppc = int(w.get("ion_ppc", 0))
+        c.envelope = 1 if w.get("envelope", "sin2") == "flat" else 0
+        c.ion_mass = float(w.get("ion_mass_me", 0.0))
         self._keep = []
         t = _Tab()
         t.n_eta = int(tables["n_eta"]); t.n_xi = int(tables["n_xi"])
@@ -228,6 +239,7 @@ class OracleSim:
         self._L = L
         self.nthreads = nt
         self.N = int(L.or_num_electrons(self._h))
+        self.Ni = int(L.or_num_ions(self._h))
         self.workload = dict(w)
 
     def close(self):
@@ -258,6 +270,22 @@ class OracleSim:
         tau = np.ascontiguousarray(tau, dtype=np.float64).reshape(self.N)
         self._L.or_set_electrons(self._h, x.ctypes.data, p.ctypes.data, tau.ctypes.data)
 
+    def ions(self):
+        """Mobile ions in id order: x, p (per unit mass), alive."""
+        n = self.Ni
+        x = np.zeros((n, 3)); p = np.zeros((n, 3)); al = np.zeros(n, dtype=np.uint8)
+        if n:
+            self._L.or_get_ions(self._h, x.ctypes.data, p.ctypes.data, al.ctypes.data)
+        return dict(x=x, p=p, alive=al.astype(bool))
+
+    def set_ions(self, x, p):
+        x = np.ascontiguousarray(x, dtype=np.float64).reshape(self.Ni, 3)
+        p = np.ascontiguousarray(p, dtype=np.float64).reshape(self.Ni, 3)
+        self._L.or_set_ions(self._h, x.ctypes.data, p.ctypes.data)
+
+    def ion_kinetic_energy(self):
+        return float(self._L.or_ion_kinetic_energy(self._h))
+
     def tau_brem(self):
         """Collision optical depths of the free-path form, id order."""
         out = np.zeros(self.N)
@@ -286,7 +314,7 @@ class OracleSim:
                     kept=[s.kept[0], s.kept[1]], dropped_ncs=s.dropped_ncs,
                     overflow=s.overflow, brem_clamped=s.brem_clamped,
                     e_rad_kept=[s.e_rad_kept[0], s.e_rad_kept[1]],
-                    e_rad_dropped=s.e_rad_dropped)
+                    e_rad_dropped=s.e_rad_dropped, ions_live=s.ions_live)
 
     def kinetic_energy(self):
         return float(self._L.or_kinetic_energy(self._h))

@@ -155,6 +155,14 @@ struct or_sim {
   double* taub;      /* collision optical depth (free-path bremsstrahlung only) */
   uint32_t* id;
   uint8_t* alive;
+  /* mobile ions (id order): positions, momenta per unit mass, weight,
+   * charge, mass; the ion density of every cell, recomputed each step from
+   * the ions (count times iw / V) */
+  int64_t Ni;
+  double *ix, *ip;
+  uint8_t* ialive;
+  double iw, iwv, iq, imass;
+  uint32_t* icount;
   /* photons */
   int64_t pcap, pcount;
   double *ph_x, *ph_k, *ph_e, *ph_w;
@@ -345,6 +353,34 @@ or_sim* or_create(const or_config* c, const or_tables* t, int nthreads) {
       }
   s->st.live = (uint64_t)s->N;
 
+  /* mobile ions: ion_ppc per slab cell at uniform-random in-cell positions
+   * (Philox counter (j, 0xFFFFFFFE, 0, 0)), at rest, weight n_i V / ion_ppc */
+  if (c->ion_ppc > 0) {
+    s->Ni = (int64_t)nslab * s->n[1] * s->n[2] * c->ion_ppc;
+    s->ix = dalloc(3 * s->Ni); s->ip = dalloc(3 * s->Ni);
+    s->ialive = (uint8_t*)calloc((size_t)(s->Ni > 0 ? s->Ni : 1), 1);
+    s->icount = (uint32_t*)calloc((size_t)s->ncell_tot, 4);
+    s->iq = (double)c->charge_state;
+    s->imass = c->ion_mass;
+    s->iw = nion * V / (double)c->ion_ppc;
+    s->iwv = s->iw * s->invV;
+    for (int k = 0; k < s->n[2]; ++k)
+      for (int j = 0; j < s->n[1]; ++j)
+        for (int i = i0; i < i1; ++i) {
+          int64_t rank = ((int64_t)k * s->n[1] + j) * nslab + (i - i0);
+          for (int m = 0; m < c->ion_ppc; ++m) {
+            int64_t e = rank * c->ion_ppc + m;
+            uint32_t r[4];
+            or_philox((uint32_t)e, 0xFFFFFFFEu, 0u, 0u, s->key0, s->key1, r);
+            s->ix[3 * e + 0] = ((double)i + u32(r[0])) * s->dx[0];
+            s->ix[3 * e + 1] = s->act[1] ? ((double)j + u32(r[1])) * s->dx[1] : 0.0;
+            s->ix[3 * e + 2] = s->act[2] ? ((double)k + u32(r[2])) * s->dx[2] : 0.0;
+            s->ialive[e] = 1;
+          }
+        }
+    s->st.ions_live = (uint64_t)s->Ni;
+  }
+
   s->pcap = (int64_t)c->photon_capacity;
   s->ph_x = dalloc(3 * s->pcap); s->ph_k = dalloc(3 * s->pcap);
   s->ph_e = dalloc(s->pcap); s->ph_w = dalloc(s->pcap);
@@ -362,6 +398,7 @@ void or_destroy(or_sim* s) {
   free(s->x); free(s->p); free(s->tau); free(s->taub); free(s->w); free(s->id); free(s->alive);
   free(s->ph_x); free(s->ph_k); free(s->ph_e); free(s->ph_w);
   free(s->ph_step); free(s->ph_parent); free(s->ph_proc);
+  free(s->ix); free(s->ip); free(s->ialive); free(s->icount);
   free(s);
 }
 
@@ -743,10 +780,11 @@ static void jadd(int64_t* J, int64_t m, double v) {
   J[m] += q;
 }
 
-/* charge-conserving current of one electron moving x0 -> x1 (Esirkepov form;
- * in 1D the exact 1D continuity solution) */
-static void deposit(or_sim* s, const double* x0, const double* x1, const double* v, double w) {
-  double c0 = -w * s->invV;
+/* charge-conserving current of one particle of charge times weight qw (-w
+ * for an electron) moving x0 -> x1 (Esirkepov form; in 1D the exact 1D
+ * continuity solution) */
+static void deposit(or_sim* s, const double* x0, const double* x1, const double* v, double qw) {
+  double c0 = qw * s->invV;
   double S0[3][4], S1[3][4];
   int b[3] = {0, 0, 0};
   for (int a = 0; a < s->dims; ++a) {
@@ -831,11 +869,96 @@ static void deposit(or_sim* s, const double* x0, const double* x1, const double*
     }
 }
 
+/* Ion density of every cell for the collision test of Eq. (4): the number
+ * of live ions whose position lies in the cell (nearest grid cell), times
+ * the ion weight over the cell volume. */
+static void ion_density(or_sim* s) {
+  memset(s->icount, 0, sizeof(uint32_t) * (size_t)s->ncell_tot);
+  for (int64_t e = 0; e < s->Ni; ++e) {
+    if (!s->ialive[e]) continue;
+    int ci[3] = {0, 0, 0};
+    for (int a = 0; a < s->dims; ++a) {
+      int q = (int)floor(s->ix[3 * e + a] * s->idx[a]);
+      if (q < 0) q = 0;
+      if (q > s->n[a] - 1) q = s->n[a] - 1;
+      ci[a] = q;
+    }
+    s->icount[ci[0] + (int64_t)s->n[0] * (ci[1] + (int64_t)s->n[1] * ci[2])]++;
+  }
+  for (int64_t m = 0; m < s->ncell_tot; ++m) s->ni[m] = (double)s->icount[m] * s->iwv;
+}
+
+/* Mobile ions (Sec. III): gather, Boris push with charge q and mass M (the
+ * momentum is per unit mass, p/(M c)), move, charge-conserving deposit of
+ * charge +q w, absorbing walls.  No photon emission. */
+static void ion_step(or_sim* s, double tn, int frozen) {
+  const or_config* c = &s->c;
+  const double hq = 0.5 * s->dt * (s->iq / s->imass);
+  double* x1 = dalloc(3 * s->Ni);
+  double* vv = dalloc(3 * s->Ni);
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) num_threads(s->nthreads)
+#endif
+  for (int64_t e = 0; e < s->Ni; ++e) {
+    if (!s->ialive[e]) continue;
+    double* x = s->ix + 3 * e;
+    double* p = s->ip + 3 * e;
+    double E[3] = {0, 0, 0}, B[3] = {0, 0, 0};
+    if (frozen) {
+      if (c->frozen_kind == OR_FROZEN_UNIFORM) {
+        for (int a = 0; a < 3; ++a) { E[a] = c->frozen_E[a]; B[a] = c->frozen_B[a]; }
+      } else {
+        double phi = tn - x[0];
+        if (phi > 0.0) { double v = c->frozen_a * sin(phi); E[1] = v; B[2] = v; }
+      }
+    } else {
+      double g[3];
+      for (int a = 0; a < 3; ++a) g[a] = x[a] * s->idx[a];
+      for (int a = 0; a < 3; ++a) {
+        E[a] = field_at(s, a, g);
+        B[a] = field_at(s, 3 + a, g);
+      }
+    }
+    double px = p[0], py = p[1], pz = p[2];
+    boris(hq, E, B, &px, &py, &pz);
+    double gamma = sqrt(1.0 + (px * px + py * py + pz * pz));
+    p[0] = px; p[1] = py; p[2] = pz;
+    double ig = 1.0 / gamma;
+    double* v = vv + 3 * e;
+    v[0] = px * ig; v[1] = py * ig; v[2] = pz * ig;
+    for (int a = 0; a < 3; ++a)
+      x1[3 * e + a] = s->act[a] ? x[a] + v[a] * s->dt : x[a];
+  }
+  if (!frozen) {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) num_threads(s->nthreads)
+#endif
+    for (int64_t e = 0; e < s->Ni; ++e)
+      if (s->ialive[e]) deposit(s, s->ix + 3 * e, x1 + 3 * e, vv + 3 * e, s->iq * s->iw);
+  }
+  uint64_t live = 0;
+  for (int64_t e = 0; e < s->Ni; ++e) {
+    if (!s->ialive[e]) continue;
+    int out = 0;
+    for (int a = 0; a < s->dims; ++a) {
+      s->ix[3 * e + a] = x1[3 * e + a];
+      if (x1[3 * e + a] < 0.0 || x1[3 * e + a] >= s->L[a]) out = 1;
+    }
+    if (out) s->ialive[e] = 0; else ++live;
+  }
+  s->st.ions_live = live;
+  free(x1);
+  free(vv);
+}
+
 static void laser_scalars(const or_sim* s, uint64_t step, double* lsin, double* lcos) {
   double t = ((double)step + 0.5) * s->dt;
   double TL = s->c.duration_cycles * (2.0 * M_PI);
   double env = 0.0;
-  if (t >= 0.0 && t <= TL) { env = sin(M_PI * t / TL); env = env * env; }
+  if (t >= 0.0 && t <= TL) {
+    if (s->c.envelope == OR_ENV_FLAT) env = 1.0;   /* constant over the pulse (Sec. III) */
+    else { env = sin(M_PI * t / TL); env = env * env; }
+  }
   *lsin = s->c.a0 * env * sin(t);
   *lcos = s->c.a0 * env * cos(t);
 }
@@ -849,11 +972,13 @@ void or_step(or_sim* s, int nsteps) {
       for (int a = 0; a < 3; ++a) memset(s->J[a], 0, sizeof(int64_t) * (size_t)s->nfield);
       b_half(s);                                  /* B^{n-1/2} -> B^n */
     }
+    if (s->Ni > 0) ion_density(s);               /* n of Eq. (4) from the ions at x^n */
 #ifdef _OPENMP
 #pragma omp parallel for schedule(static) num_threads(s->nthreads)
 #endif
     for (int64_t e = 0; e < s->N; ++e)
       if (s->alive[e]) electron_one(s, e, tn, &res[e]);
+    if (s->Ni > 0) ion_step(s, tn, frozen);
     /* charge-conserving deposit of every move (integer sums: the order in
      * which electrons add to a node does not change the result) */
     if (!frozen) {
@@ -861,7 +986,7 @@ void or_step(or_sim* s, int nsteps) {
 #pragma omp parallel for schedule(static) num_threads(s->nthreads)
 #endif
       for (int64_t e = 0; e < s->N; ++e)
-        if (s->alive[e]) deposit(s, s->x + 3 * e, res[e].x1, res[e].v, s->w[e]);
+        if (s->alive[e]) deposit(s, s->x + 3 * e, res[e].x1, res[e].v, -s->w[e]);
     }
     /* id-ordered pass: photon append, sums, absorbing walls */
     uint64_t live = 0;
@@ -947,6 +1072,32 @@ void or_get_photons(const or_sim* s, double* x, double* k, double* eps, double* 
 }
 
 void or_get_stats(const or_sim* s, or_stats* out) { *out = s->st; }
+
+int64_t or_num_ions(const or_sim* s) { return s->Ni; }
+
+void or_get_ions(const or_sim* s, double* x, double* p, uint8_t* alive) {
+  if (s->Ni == 0) return;
+  memcpy(x, s->ix, sizeof(double) * 3 * (size_t)s->Ni);
+  memcpy(p, s->ip, sizeof(double) * 3 * (size_t)s->Ni);
+  memcpy(alive, s->ialive, (size_t)s->Ni);
+}
+
+void or_set_ions(or_sim* s, const double* x, const double* p) {
+  if (s->Ni == 0) return;
+  memcpy(s->ix, x, sizeof(double) * 3 * (size_t)s->Ni);
+  memcpy(s->ip, p, sizeof(double) * 3 * (size_t)s->Ni);
+}
+
+double or_ion_kinetic_energy(const or_sim* s) {
+  double sum = 0.0;
+  for (int64_t e = 0; e < s->Ni; ++e) {
+    if (!s->ialive[e]) continue;
+    const double* p = s->ip + 3 * e;
+    double g = sqrt(1.0 + (p[0] * p[0] + p[1] * p[1] + p[2] * p[2]));
+    sum += s->iw * s->imass * (g - 1.0);
+  }
+  return sum;
+}
 
 double or_kinetic_energy(const or_sim* s) {
   double sum = 0.0;

@@ -33,7 +33,12 @@ typedef struct {
   double photon_cut_mc2;
   double frozen_E[3], frozen_B[3], frozen_a;
   uint64_t seed, job_id, photon_capacity;
+  /* mobile ions (paper Sec. III): ion_ppc per slab cell (0 = static ions),
+   * charge charge_state, mass ion_mass in electron masses */
+  int32_t ion_ppc, envelope;          /* envelope: OR_ENV_SIN2 or OR_ENV_FLAT */
+  double ion_mass;
 } or_config;
+enum { OR_ENV_SIN2 = 0, OR_ENV_FLAT = 1 };
 
 typedef struct {
   int32_t n_eta, n_xi;
@@ -47,6 +52,7 @@ typedef struct {
 typedef struct {
   uint64_t steps, live, events[2], kept[2], dropped_ncs, overflow, brem_clamped;
   double e_rad_kept[2], e_rad_dropped;
+  uint64_t ions_live;
 } or_stats;
 
 typedef struct or_sim or_sim;
@@ -88,6 +94,12 @@ void     or_philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
  * brem_eps: the photon energy at uniform u. */
 void     or_set_fields(or_sim* s, const double* in);   /* 6*size: Ex,Ey,Ez,Bx,By,Bz */
 double   or_math(int which, double x);                 /* 0 exp, 1 log, 2 expm1 of the oracle */
+/* mobile ions: count, state in id order (x, p per unit mass, alive),
+ * sum w M (gamma - 1) over live ions */
+int64_t  or_num_ions(const or_sim* s);
+void     or_get_ions(const or_sim* s, double* x, double* p, uint8_t* alive);
+void     or_set_ions(or_sim* s, const double* x, const double* p);
+double   or_ion_kinetic_energy(const or_sim* s);
 double   or_probe_field(const or_sim* s, int comp, const double x[3]);
 void     or_probe_boris(const or_sim* s, const double E[3], const double B[3], double p[3]);
 double   or_probe_eta(const or_sim* s, const double E[3], const double B[3], const double p[3]);

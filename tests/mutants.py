@@ -68,6 +68,15 @@ MUTANTS = {
     "exp_series_short": [("  for (int n = 13; n >= 0; --n) p = p * r + INV_FACT[n];",
                           "  for (int n = 7; n >= 0; --n) p = p * r + INV_FACT[n];")],
     "log_split_dropped": [("  return de * L_HI + (de * L_LO + lm);", "  return de * L_HI + lm;")],
+    # mobile ions
+    "ion_push_charge_sign": [("const double hq = 0.5 * s->dt * (s->iq / s->imass);",
+                              "const double hq = -0.5 * s->dt * (s->iq / s->imass);")],
+    "ion_mass_dropped": [("const double hq = 0.5 * s->dt * (s->iq / s->imass);",
+                          "const double hq = 0.5 * s->dt * s->iq;")],
+    "ion_deposit_charge": [("deposit(s, s->ix + 3 * e, x1 + 3 * e, vv + 3 * e, s->iq * s->iw);",
+                            "deposit(s, s->ix + 3 * e, x1 + 3 * e, vv + 3 * e, s->iw);")],
+    "ion_density_volume": [("for (int64_t m = 0; m < s->ncell_tot; ++m) s->ni[m] = (double)s->icount[m] * s->iwv;",
+                            "for (int64_t m = 0; m < s->ncell_tot; ++m) s->ni[m] = (double)s->icount[m] * s->iw;")],
     # constants
     "K_BR_factor": [("s->K_BR = s->n_c * (lam / twopi) * alpha * re * re;",
                      "s->K_BR = s->n_c * lam * alpha * re * re;")],

@@ -8,6 +8,7 @@ import pytest
 import mutants
 import test_oracle_pins_emission as PE
 import test_oracle_pins_fields as PF
+import test_oracle_pins_ions as PI
 
 # mutant -> the pin that must catch it
 CASES = [
@@ -34,6 +35,10 @@ CASES = [
     ("brem_energy_map", PE.check_brem_sampling_off_node),
     ("exp_series_short", PE.check_math_against_libm),
     ("log_split_dropped", PE.check_math_against_libm),
+    ("ion_push_charge_sign", PI.check_ion_gyration),
+    ("ion_mass_dropped", PI.check_two_fluid_plasma_frequency),
+    ("ion_deposit_charge", PI.check_continuity_with_ions),
+    ("ion_density_volume", PI.check_brem_with_counted_ion_density),
     ("K_BR_factor", PE.check_constants),
     ("E_S_factor", PE.check_constants),
 ]
