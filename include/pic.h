@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define PIC_ABI_VERSION 1u
+#define PIC_ABI_VERSION 2u
 #define PIC_TABLES_VERSION 2u
 
 typedef struct pic_ctx pic_ctx; /* opaque; owned by the library */
@@ -85,12 +85,22 @@ enum {
                                   the electrons are re-sorted: two buffers). */
 };
 enum { PIC_FROZEN_UNIFORM = 0, PIC_FROZEN_PLANE_WAVE = 1 };
+/* laser temporal envelope over [0, duration]: sin^2, or constant (the flat
+   30 fs pulse of Sec. III) */
+enum { PIC_ENV_SIN2 = 0, PIC_ENV_FLAT = 1 };
 
 /* Run configuration.  Lengths in laser wavelengths unless stated.
  * Electrons are loaded cold (p = 0), ppc per cell at uniform-random in-cell
  * positions from the run's Philox stream, in the slab cells
  * [round(x0/dx), round(x0/dx) + round(thickness/dx)) x all transverse cells;
- * static ions fill the same cells at n_i = ne_over_nc / charge_state. */
+ * ions fill the same cells at n_i = ne_over_nc / charge_state: static (a
+ * fixed background density), or, with ion_ppc > 0, mobile macro-ions of
+ * Sec. III (ion_ppc per slab cell at uniform-random in-cell positions, at
+ * rest, charge charge_state, mass ion_mass_me electron masses, weight
+ * n_i V / ion_ppc; Boris push, charge-conserving deposit, absorbing walls;
+ * always FP64).  With mobile ions, n of Eq. (4) in a cell is the count of
+ * live ions in it (nearest cell) times their weight over the cell volume,
+ * taken before each step's push. */
 typedef struct {
   uint32_t abi_version;     /* must be PIC_ABI_VERSION */
   uint32_t dims;            /* 1, 2 or 3 (x, then y, then z) */
@@ -107,7 +117,7 @@ typedef struct {
   double lambda_m;          /* laser wavelength in metres (sets n_c, E_S, K_BR) */
   double a0;                /* peak normalised laser amplitude, linear pol. along y */
   double w0_lambda;         /* Gaussian waist (2D/3D); <= 0 means plane wave */
-  double duration_cycles;   /* full length of the sin^2 envelope in laser periods */
+  double duration_cycles;   /* full length of the envelope in laser periods */
   double focus_x_lambda;    /* focal plane */
   double ne_over_nc;        /* electron density in the slab */
   double x0_lambda;         /* slab front */
@@ -122,6 +132,9 @@ typedef struct {
   int32_t sort_every;       /* re-sort electrons by cell tile every this many steps;
                                0 = default for dims, < 0 = never (results do not
                                depend on it) */
+  int32_t ion_ppc;          /* mobile macro-ions per slab cell; 0 = static ions */
+  double ion_mass_me;       /* ion mass in electron masses (>= 1; mobile ions only) */
+  uint32_t envelope;        /* PIC_ENV_SIN2 or PIC_ENV_FLAT */
   uint32_t reserved0;       /* must be 0 */
   void* stream;             /* hipStream_t of the HIP runtime libpic links
                                (/opt/rocm), or NULL for its default stream */
@@ -176,6 +189,8 @@ typedef struct {
   double e_rad_dropped;      /* sum w*eps of dropped NCS photons */
   double e_kin_e;            /* sum w*(gamma-1) over live electrons (snapshot) */
   double e_field;            /* (1/2) sum (E^2 + B^2) dV (snapshot) */
+  uint64_t ions_live;        /* mobile ions inside the box (0 with static ions) */
+  double e_kin_i;            /* sum w M (gamma - 1) over live mobile ions (snapshot) */
 } pic_stats;
 
 /* ---- the five calls of the hot path ------------------------------------- */
@@ -252,6 +267,16 @@ pic_status pic_copy_electrons(pic_ctx* ctx, double* x, double* p, double* tau,
  * id, layout as pic_copy_electrons).  For tests that set up beams. */
 pic_status pic_set_electrons(pic_ctx* ctx, const double* x, const double* p,
                              const double* tau);
+
+/* Mobile ions (ion_ppc > 0): their number (live or not; 0 with static
+ * ions), a copy of all of them ordered by id (x[3n] with unused axes 0,
+ * p[3n] the momentum per unit mass p/(M c), alive[n] 0/1; any pointer may
+ * be NULL; synchronises), and an overwrite of positions and momenta (same
+ * layout; the cell counts behind n of Eq. (4) are rebuilt).  Errors:
+ * PIC_ERR_INVALID (no mobile ions for copy/set, null arrays for set). */
+pic_status pic_ion_count(pic_ctx* ctx, uint64_t* ions);
+pic_status pic_copy_ions(pic_ctx* ctx, double* x, double* p, uint8_t* alive);
+pic_status pic_set_ions(pic_ctx* ctx, const double* x, const double* p);
 
 /* Borrowed device pointers to the context's live buffers, for callers that
  * read them in place (on libpic's HIP runtime).  Valid until the next
@@ -364,7 +389,9 @@ const char* pic_batch_last_error(const pic_batch* b);
  * issues, for the runs with nsteps[j] > s: their due tile sorts, then one
  * batched launch per kernel of the step (B half step, electron step per
  * dims and precision, B half step, E step) whose workgroups walk a table of
- * the runs' parameters.  Each run's electrons, fields, photons and
+ * the runs' parameters (runs with mobile ions add their ion density pass
+ * before, and their ion push after, the electron step, one launch each).
+ * Each run's electrons, ions, fields, photons and
  * statistics end bit-identical to pic_step(ctxs[j], nsteps[j]) (up to the
  * order of photon records and of FP64 sums inside a wave slot, which no
  * result depends on beyond rounding).  The runs must be distinct.  Nothing

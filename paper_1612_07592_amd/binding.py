@@ -13,11 +13,12 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpic.so")
 
-PIC_ABI_VERSION = 1
+PIC_ABI_VERSION = 2
 PIC_TABLES_VERSION = 2
 PIC_FP64, PIC_FP32_MIXED = 0, 1
 PIC_NCS, PIC_BREM, PIC_FIELDS_FROZEN, PIC_NO_RECOIL, PIC_BREM_FREEPATH = 1, 2, 4, 16, 32
 PIC_FROZEN_UNIFORM, PIC_FROZEN_PLANE_WAVE = 0, 1
+PIC_ENV_SIN2, PIC_ENV_FLAT = 0, 1
 STATUS = {0: "PIC_OK", 1: "PIC_ERR_INVALID", 2: "PIC_ERR_NOMEM", 3: "PIC_ERR_DEVICE",
           4: "PIC_ERR_STATE", 5: "PIC_ERR_OVERFLOW", 6: "PIC_ERR_TABLES"}
 
@@ -29,7 +30,8 @@ EXPORTS = ["pic_create", "pic_load_tables", "pic_step", "pic_emission_stats", "p
            "pic_step_many", "pic_server_create", "pic_server_destroy", "pic_server_clock",
            "pic_server_last_error", "pic_server_submit", "pic_server_run", "pic_server_poll",
            "pic_server_job_ctx", "pic_server_release", "pic_device_memory", "pic_synchronize",
-           "pic_copy_brem_depth", "pic_set_brem_depth", "pic_get_buffers", "pic_philox_noalloc"]
+           "pic_copy_brem_depth", "pic_set_brem_depth", "pic_get_buffers", "pic_philox_noalloc",
+           "pic_ion_count", "pic_copy_ions", "pic_set_ions"]
 
 
 class pic_config(C.Structure):
@@ -43,7 +45,8 @@ class pic_config(C.Structure):
                 ("photon_cut_mc2", C.c_double), ("frozen_E", C.c_double * 3),
                 ("frozen_B", C.c_double * 3), ("frozen_a", C.c_double),
                 ("photon_capacity", C.c_uint64), ("seed", C.c_uint64), ("job_id", C.c_uint64),
-                ("sort_every", C.c_int32), ("reserved0", C.c_uint32), ("stream", C.c_void_p)]
+                ("sort_every", C.c_int32), ("ion_ppc", C.c_int32), ("ion_mass_me", C.c_double),
+                ("envelope", C.c_uint32), ("reserved0", C.c_uint32), ("stream", C.c_void_p)]
 
 
 class pic_tables(C.Structure):
@@ -63,7 +66,8 @@ class pic_stats(C.Structure):
                 ("brem_clamped", C.c_uint64), ("photons_stored", C.c_uint64),
                 ("untiled_steps", C.c_uint64),
                 ("e_rad_kept", C.c_double * 2), ("e_rad_dropped", C.c_double),
-                ("e_kin_e", C.c_double), ("e_field", C.c_double)]
+                ("e_kin_e", C.c_double), ("e_field", C.c_double),
+                ("ions_live", C.c_uint64), ("e_kin_i", C.c_double)]
 
 
 class pic_server_config(C.Structure):
@@ -125,6 +129,9 @@ def load() -> C.CDLL:
     L.pic_philox.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, u64]
     L.pic_philox_noalloc.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, u64]
     L.pic_derived.argtypes = [P, C.c_void_p]
+    L.pic_ion_count.argtypes = [P, C.POINTER(u64)]
+    L.pic_copy_ions.argtypes = [P, C.c_void_p, C.c_void_p, C.c_void_p]
+    L.pic_set_ions.argtypes = [P, C.c_void_p, C.c_void_p]
     L.pic_copy_current.argtypes = [P, C.c_void_p]
     L.pic_profile.argtypes = [P, i32]
     L.pic_profile_read.argtypes = [P, C.c_void_p, C.c_void_p]
@@ -208,6 +215,9 @@ def config_from(w: dict, stream=None) -> pic_config:
     c.seed = int(w.get("seed", 1))
     c.job_id = int(w.get("job_id", 0))
     c.sort_every = int(w.get("sort_every", 0))
+    c.ion_ppc = int(w.get("ion_ppc", 0))
+    c.ion_mass_me = float(w.get("ion_mass_me", 0.0))
+    c.envelope = PIC_ENV_FLAT if w.get("envelope", "sin2") == "flat" else PIC_ENV_SIN2
     c.stream = stream
     return c
 
@@ -284,7 +294,7 @@ def stats_dict(s: pic_stats, code: int = 0) -> dict:
                 untiled_steps=s.untiled_steps,
                 e_rad_kept=[s.e_rad_kept[0], s.e_rad_kept[1]],
                 e_rad_dropped=s.e_rad_dropped, e_kin_e=s.e_kin_e, e_field=s.e_field,
-                status=STATUS.get(code, code))
+                ions_live=s.ions_live, e_kin_i=s.e_kin_i, status=STATUS.get(code, code))
 
 
 def pic_device_memory():
@@ -327,6 +337,9 @@ class Sim:
         n = C.c_uint64()
         _check("pic_counts", L.pic_counts(self._h, C.byref(n), None, None), self._h)
         self.N = int(n.value)
+        ni = C.c_uint64()
+        _check("pic_ion_count", L.pic_ion_count(self._h, C.byref(ni)), self._h)
+        self.Ni = int(ni.value)
         if tables is not None:
             self.pic_load_tables(tables)
 
@@ -386,6 +399,19 @@ class Sim:
         tau = np.ascontiguousarray(tau, dtype=np.float64).reshape(self.N)
         _check("pic_set_electrons", self._L.pic_set_electrons(self._h, x.ctypes.data, p.ctypes.data,
                                                               tau.ctypes.data), self._h)
+
+    def ions(self) -> dict:
+        """Mobile ions in id order: x[n,3], p[n,3] (per unit mass), alive[n]."""
+        n = self.Ni
+        x = np.zeros((n, 3)); p = np.zeros((n, 3)); al = np.zeros(n, dtype=np.uint8)
+        _check("pic_copy_ions", self._L.pic_copy_ions(self._h, x.ctypes.data, p.ctypes.data,
+                                                      al.ctypes.data), self._h)
+        return dict(x=x, p=p, alive=al.astype(bool))
+
+    def set_ions(self, x, p):
+        x = np.ascontiguousarray(x, dtype=np.float64).reshape(self.Ni, 3)
+        p = np.ascontiguousarray(p, dtype=np.float64).reshape(self.Ni, 3)
+        _check("pic_set_ions", self._L.pic_set_ions(self._h, x.ctypes.data, p.ctypes.data), self._h)
 
     def buffers(self) -> dict:
         """Borrowed device pointers (ints) and sizes, valid until the next step."""

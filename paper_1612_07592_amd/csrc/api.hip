@@ -95,6 +95,10 @@ std::string derive(const pic_config& cfg, Ctx& c) {
     if (!is_fin(cfg.frozen_E[a]) || !is_fin(cfg.frozen_B[a])) return "non-finite frozen field";
   if (cfg.frozen_kind > PIC_FROZEN_PLANE_WAVE) return "unknown frozen_kind";
   if (cfg.photon_capacity > (1ull << 40)) return "photon_capacity too large";
+  if (cfg.envelope > PIC_ENV_FLAT) return "unknown envelope";
+  if (cfg.ion_ppc < 0 || cfg.ion_ppc > 4096) return "ion_ppc must be in [0, 4096]";
+  if (cfg.ion_ppc > 0 && !(cfg.ion_mass_me >= 1.0 && is_fin(cfg.ion_mass_me)))
+    return "ion_mass_me must be finite and >= 1 with mobile ions";
   Grid& g = c.g;
   g.dims = (int)cfg.dims;
   const double twopi = 2.0 * M_PI;
@@ -151,6 +155,13 @@ std::string derive(const pic_config& cfg, Ctx& c) {
   if (g.i_src + 2 >= g.n[0]) return "grid too short for the laser source plane";
   c.N = N;
   c.wgt = cfg.ne_over_nc * V / (double)cfg.ppc;
+  // mobile ions: ion_ppc per slab cell, weight n_i V / ion_ppc
+  const int64_t Ni = (int64_t)(i1 - i0) * g.n[1] * g.n[2] * cfg.ion_ppc;
+  if (Ni >= ((int64_t)1 << 31)) return "too many ions (more than 2^31 - 1)";
+  c.Ni = Ni;
+  c.iq = (double)cfg.charge_state;
+  c.imass = cfg.ion_mass_me;
+  c.iw = cfg.ion_ppc > 0 ? (cfg.ne_over_nc / (double)cfg.charge_state) * V / (double)cfg.ion_ppc : 0.0;
   c.fp32 = cfg.precision == PIC_FP32_MIXED;
   c.pcap = cfg.photon_capacity;
   const int64_t per_chunk = chunk_electrons(c.fp32, g.dims);
@@ -249,6 +260,15 @@ Plan make_plan(Ctx& c) {
   if (fp) P.add((void**)&c.taub, N * 8);
   P.add((void**)&c.w, N * 8);
   P.add((void**)&c.id, N * 4);
+  if (c.Ni > 0) {
+    const size_t Ni = (size_t)c.Ni;
+    for (int a = 0; a < 3; ++a) {
+      if (a < g.dims) P.add((void**)&c.ix[a], Ni * 8);
+      P.add((void**)&c.ip[a], Ni * 8);
+    }
+    P.add((void**)&c.ialive, Ni);
+    P.add((void**)&c.icount, ncell * 4);
+  }
   if (c.sort_every > 0) {  // second SoA buffer and sort scratch
     for (int a = 0; a < 3; ++a) {
       if (a < g.dims) P.add(&c.x2[a], N * rs);
@@ -333,8 +353,12 @@ void laser_scalars(const Ctx& c, uint64_t step, double* ls, double* lc) {
   const double TL = c.cfg.duration_cycles * (2.0 * M_PI);
   double env = 0.0;
   if (t >= 0.0 && t <= TL) {
-    env = sin(M_PI * t / TL);
-    env = env * env;
+    if (c.cfg.envelope == PIC_ENV_FLAT) {
+      env = 1.0;  // constant over the pulse (Sec. III)
+    } else {
+      env = sin(M_PI * t / TL);
+      env = env * env;
+    }
   }
   *ls = c.cfg.a0 * env * sin(t);
   *lc = c.cfg.a0 * env * cos(t);
@@ -535,7 +559,8 @@ struct pic_batch {
 namespace {
 
 struct BatchLaunch {
-  int kind;          // 0 sort, 1 both B half steps + clear J, 2 electron step, 4 E step
+  int kind;          // 0 sort, 1 both B half steps + clear J, 2 electron step, 4 E step,
+                     // 5 ion density, 6 ion step (one run each)
   int dims = 0;
   bool fp32 = false;
   size_t tab = 0, first = 0;
@@ -543,6 +568,7 @@ struct BatchLaunch {
   uint32_t total = 0;
   int lds_nodes = 0;
   SortArgs sort{};
+  IonArgs ion{};
   hipStream_t stream = nullptr;
 };
 
@@ -654,6 +680,11 @@ pic_status pic_create(const pic_config* cfg, pic_ctx** out) {
   if (he == hipSuccess) he = hipMemcpyAsync(c.n_active, n_act, 16, hipMemcpyHostToDevice, c.stream);
   if (he == hipSuccess) {
     launch_init_electrons(c, c.stream);
+    if (c.Ni > 0) {
+      IonArgs A{};
+      fill_ion_args(c, A);
+      launch_ion_init(A, c.stream);
+    }
     he = hipGetLastError();
   }
   if (he == hipSuccess) he = hipStreamSynchronize(c.stream);
@@ -797,6 +828,11 @@ pic_status pic_step(pic_ctx* ctx, int32_t nsteps) {
     mark(1);
     if (!frozen) launch_b_both(c, c.stream);  // B^n (into En), B^{n+1/2}, J <- 0
     mark(1);
+    IonArgs IA{};
+    if (c.Ni > 0) {
+      fill_ion_args(c, IA);
+      launch_ion_density(IA, c.stream);       // n of Eq. (4) from the ions at x^n
+    }
     mark(0);
     if (c.fp32) {
       StepParams<float> P{};
@@ -808,6 +844,7 @@ pic_status pic_step(pic_ctx* ctx, int32_t nsteps) {
       launch_step(c.g.dims, false, &P, c.stream);
     }
     mark(0);
+    if (c.Ni > 0) launch_ion_step(IA, c.stream);
     mark(1);
     if (!frozen) {
       double ls, lc;
@@ -826,10 +863,10 @@ pic_status pic_emission_stats(pic_ctx* ctx, pic_stats* out) {
   if (st) return st;
   Ctx& c = ctx->c;
   if (!out) FAIL(c, PIC_ERR_INVALID, "null output");
-  unsigned long long cnt[kSlotCnt + 1];
-  double sum[5];
+  unsigned long long cnt[kRedCnt];
+  double sum[kRedSum];
   unsigned long long pcount = 0;
-  launch_stats_reduce(c, cnt, sum, nullptr, nullptr, nullptr, c.stream);
+  launch_stats_reduce(c, cnt, sum, c.stream);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipMemcpyAsync(&pcount, c.pcount, 8, hipMemcpyDeviceToHost, c.stream));
   HIPCHK(c, hipStreamSynchronize(c.stream));
@@ -853,6 +890,8 @@ pic_status pic_emission_stats(pic_ctx* ctx, pic_stats* out) {
   s.e_rad_dropped = sum[2];
   s.e_kin_e = sum[3];
   s.e_field = 0.5 * sum[4] * (1.0 / c.g.invV);
+  s.ions_live = cnt[kSlotCnt + 1];
+  s.e_kin_i = sum[5];
   *out = s;
   return s.overflow ? PIC_ERR_OVERFLOW : PIC_OK;
 }
@@ -953,10 +992,21 @@ pic_status pic_step_many(pic_batch* b, pic_ctx* const* ctxs, const int32_t* nste
     }
     for (int f = 0; f < 2; ++f)
       if (have_f[f]) { BatchLaunch l = fl[f]; l.kind = 1; L.push_back(l); }
+    std::vector<BatchLaunch> ion_steps;
+    for (Ctx* c : act)
+      if (c->Ni > 0) {
+        BatchLaunch l{};
+        fill_ion_args(*c, l.ion);
+        l.kind = 5;
+        L.push_back(l);
+        l.kind = 6;
+        ion_steps.push_back(l);
+      }
     for (int d = 1; d <= 3; ++d) {
       stage_step_group<float>(st, L, act, d);
       stage_step_group<double>(st, L, act, d);
     }
+    for (const BatchLaunch& l : ion_steps) L.push_back(l);
     for (int f = 0; f < 2; ++f)
       if (have_f[f]) { BatchLaunch l = fl[f]; l.kind = 4; L.push_back(l); }
     for (Ctx* c : act) {
@@ -1009,6 +1059,8 @@ pic_status pic_step_many(pic_batch* b, pic_ctx* const* ctxs, const int32_t* nste
   for (const BatchLaunch& l : L) {
     switch (l.kind) {
       case 0: launch_sort(l.sort, l.fp32, b->stream); break;
+      case 5: launch_ion_density(l.ion, b->stream); break;
+      case 6: launch_ion_step(l.ion, b->stream); break;
       case 1:
         launch_b_both_batch(l.fp32, (const FieldJob*)(D + l.tab), (const uint32_t*)(D + l.first),
                             l.njobs, l.total, b->stream);
@@ -1043,10 +1095,10 @@ pic_status pic_counts(pic_ctx* ctx, uint64_t* electrons, uint64_t* stored, uint6
   unsigned long long pc = 0;
   // kept photons from the per-wave counts: the device's slot counter stops
   // once the buffer is full
-  unsigned long long cnt[kSlotCnt + 1];
-  double sum[5];
+  unsigned long long cnt[kRedCnt];
+  double sum[kRedSum];
   if (kept) {
-    launch_stats_reduce(c, cnt, sum, nullptr, nullptr, nullptr, c.stream);
+    launch_stats_reduce(c, cnt, sum, c.stream);
     HIPCHK(c, hipGetLastError());
   }
   HIPCHK(c, hipMemcpyAsync(&pc, c.pcount, 8, hipMemcpyDeviceToHost, c.stream));
@@ -1192,6 +1244,83 @@ pic_status pic_set_electrons(pic_ctx* ctx, const double* x, const double* p, con
   std::vector<double> t8(N);
   for (size_t e = 0; e < N; ++e) t8[e] = tau[ids[e] & ~kDead];
   HIPCHK(c, hipMemcpyAsync(c.tau, t8.data(), N * 8, hipMemcpyHostToDevice, c.stream));
+  HIPCHK(c, hipStreamSynchronize(c.stream));
+  return PIC_OK;
+}
+
+pic_status pic_ion_count(pic_ctx* ctx, uint64_t* ions) {
+  pic_status st = check_ctx(ctx);
+  if (st) return st;
+  Ctx& c = ctx->c;
+  if (!ions) FAIL(c, PIC_ERR_INVALID, "null output");
+  *ions = (uint64_t)c.Ni;
+  return PIC_OK;
+}
+
+pic_status pic_copy_ions(pic_ctx* ctx, double* x, double* p, uint8_t* alive) {
+  pic_status st = check_ctx(ctx);
+  if (st) return st;
+  Ctx& c = ctx->c;
+  if (c.Ni <= 0) FAIL(c, PIC_ERR_INVALID, "run has no mobile ions");
+  const size_t N = (size_t)c.Ni;
+  std::vector<double> v(N);
+  for (int a = 0; a < 3; ++a) {
+    if (x) {
+      if (a < c.g.dims) {
+        HIPCHK(c, hipMemcpyAsync(v.data(), c.ix[a], N * 8, hipMemcpyDeviceToHost, c.stream));
+        HIPCHK(c, hipStreamSynchronize(c.stream));
+      } else {
+        std::fill(v.begin(), v.end(), 0.0);
+      }
+      for (size_t e = 0; e < N; ++e) x[3 * e + a] = v[e];
+    }
+    if (p) {
+      HIPCHK(c, hipMemcpyAsync(v.data(), c.ip[a], N * 8, hipMemcpyDeviceToHost, c.stream));
+      HIPCHK(c, hipStreamSynchronize(c.stream));
+      for (size_t e = 0; e < N; ++e) p[3 * e + a] = v[e];
+    }
+  }
+  if (alive) {
+    HIPCHK(c, hipMemcpyAsync(alive, c.ialive, N, hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(c, hipStreamSynchronize(c.stream));
+  }
+  return PIC_OK;
+}
+
+pic_status pic_set_ions(pic_ctx* ctx, const double* x, const double* p) {
+  pic_status st = check_ctx(ctx);
+  if (st) return st;
+  Ctx& c = ctx->c;
+  if (c.Ni <= 0) FAIL(c, PIC_ERR_INVALID, "run has no mobile ions");
+  if (!x || !p) FAIL(c, PIC_ERR_INVALID, "null argument");
+  const size_t N = (size_t)c.Ni;
+  std::vector<uint8_t> al(N);
+  HIPCHK(c, hipMemcpyAsync(al.data(), c.ialive, N, hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(c, hipStreamSynchronize(c.stream));
+  for (size_t e = 0; e < N; ++e) {
+    for (int a = 0; a < 3; ++a)
+      if (!is_fin(x[3 * e + a]) || !is_fin(p[3 * e + a])) FAIL(c, PIC_ERR_INVALID, "non-finite ion state");
+    // the gather and deposit stencils assume every live ion is inside the box
+    if (al[e])
+      for (int a = 0; a < c.g.dims; ++a)
+        if (!(x[3 * e + a] >= 0.0 && x[3 * e + a] < c.g.L[a]))
+          FAIL(c, PIC_ERR_INVALID, "ion %zu outside the box on axis %d", e, a);
+  }
+  std::vector<double> v(N);
+  for (int a = 0; a < 3; ++a) {
+    if (a < c.g.dims) {
+      for (size_t e = 0; e < N; ++e) v[e] = x[3 * e + a];
+      HIPCHK(c, hipMemcpyAsync(c.ix[a], v.data(), N * 8, hipMemcpyHostToDevice, c.stream));
+      HIPCHK(c, hipStreamSynchronize(c.stream));
+    }
+    for (size_t e = 0; e < N; ++e) v[e] = p[3 * e + a];
+    HIPCHK(c, hipMemcpyAsync(c.ip[a], v.data(), N * 8, hipMemcpyHostToDevice, c.stream));
+    HIPCHK(c, hipStreamSynchronize(c.stream));
+  }
+  IonArgs A{};
+  fill_ion_args(c, A);
+  launch_ion_recount(A, c.stream);
+  HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(c.stream));
   return PIC_OK;
 }

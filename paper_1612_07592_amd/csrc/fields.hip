@@ -421,59 +421,93 @@ __device__ inline void block_reduce(double (&s)[NS], double (&c)[NS], unsigned l
   for (int q = 0; q < NC; ++q) n[q] = sn[q][0];
 }
 
-// Pass 1: per-block partial sums of the wave slots, the electrons' kinetic
-// energy and live count, and the field energy.  Contiguous chunks per block.
+// Pass 1: per-block partial sums of the wave slots, the electrons' and mobile
+// ions' kinetic energy and live counts, and the field energy.  Contiguous
+// chunks per block.
+struct RedArgs {
+  const unsigned long long* scnt;
+  const double* ssum;
+  int64_t nslots;
+  const void* p[3];
+  const double* w;
+  const uint32_t* id;
+  int64_t N;
+  const void* F[6];
+  int64_t nfield;
+  const double* ip[3];
+  const uint8_t* ialive;
+  int64_t Ni;
+  double iwm;   // ion weight times mass (electron masses)
+  unsigned long long* out_cnt;
+  double* out_sum;
+};
+
 template <class R>
-__global__ __launch_bounds__(kRedThreads) void k_reduce_partial(
-    const unsigned long long* __restrict__ scnt, const double* __restrict__ ssum, int64_t nslots,
-    const R* px, const R* py, const R* pz, const double* __restrict__ w, const uint32_t* __restrict__ id,
-    int64_t N, const R* E0, const R* E1, const R* E2, const R* B0, const R* B1, const R* B2,
-    int64_t nfield, unsigned long long* out_cnt, double* out_sum) {
-  constexpr int NS = 5;   // kept0, kept1, dropped, e_kin, field
-  constexpr int NC = kSlotCnt + 1;
-  double s[NS] = {0, 0, 0, 0, 0}, c[NS] = {0, 0, 0, 0, 0};
+__global__ __launch_bounds__(kRedThreads) void k_reduce_partial(const RedArgs A) {
+  constexpr int NS = kRedSum;   // kept0, kept1, dropped, e_kin, field, e_kin ions
+  constexpr int NC = kRedCnt;
+  double s[NS], c[NS];
+  for (int q = 0; q < NS; ++q) { s[q] = 0.0; c[q] = 0.0; }
   unsigned long long n[NC];
   for (int q = 0; q < NC; ++q) n[q] = 0ull;
   const int b = blockIdx.x, t = threadIdx.x;
   // slots
   {
-    const int64_t per = (nslots + gridDim.x - 1) / gridDim.x;
-    const int64_t lo = (int64_t)b * per, hi = min(nslots, lo + per);
+    const int64_t per = (A.nslots + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = (int64_t)b * per, hi = min(A.nslots, lo + per);
     for (int64_t q = lo + t; q < hi; q += kRedThreads) {
-      for (int z = 0; z < kSlotCnt; ++z) n[z] += scnt[q * kSlotCnt + z];
+      for (int z = 0; z < kSlotCnt; ++z) n[z] += A.scnt[q * kSlotCnt + z];
       for (int z = 0; z < 3; ++z) {
-        neu_add(s[z], c[z], ssum[q * kSlotSum + 2 * z]);
-        c[z] += ssum[q * kSlotSum + 2 * z + 1];
+        neu_add(s[z], c[z], A.ssum[q * kSlotSum + 2 * z]);
+        c[z] += A.ssum[q * kSlotSum + 2 * z + 1];
       }
     }
   }
   // electrons
   {
-    const int64_t per = (N + gridDim.x - 1) / gridDim.x;
-    const int64_t lo = (int64_t)b * per, hi = min(N, lo + per);
+    const R* px = (const R*)A.p[0];
+    const R* py = (const R*)A.p[1];
+    const R* pz = (const R*)A.p[2];
+    const int64_t per = (A.N + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = (int64_t)b * per, hi = min(A.N, lo + per);
     for (int64_t e = lo + t; e < hi; e += kRedThreads) {
-      if (id[e] & kDead) continue;
+      if (A.id[e] & kDead) continue;
       const double a = (double)px[e], bb = (double)py[e], cc = (double)pz[e];
       const double g = sqrt(1.0 + (a * a + bb * bb + cc * cc));
-      neu_add(s[3], c[3], w[e] * (g - 1.0));
+      neu_add(s[3], c[3], A.w[e] * (g - 1.0));
       n[kSlotCnt] += 1ull;
+    }
+  }
+  // mobile ions
+  {
+    const int64_t per = (A.Ni + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = (int64_t)b * per, hi = min(A.Ni, lo + per);
+    for (int64_t e = lo + t; e < hi; e += kRedThreads) {
+      if (!A.ialive[e]) continue;
+      const double a = A.ip[0][e], bb = A.ip[1][e], cc = A.ip[2][e];
+      const double g = sqrt(1.0 + (a * a + bb * bb + cc * cc));
+      neu_add(s[5], c[5], A.iwm * (g - 1.0));
+      n[kSlotCnt + 1] += 1ull;
     }
   }
   // fields
   {
-    const int64_t per = (nfield + gridDim.x - 1) / gridDim.x;
-    const int64_t lo = (int64_t)b * per, hi = min(nfield, lo + per);
+    const R* const* F = (const R* const*)A.F;
+    const int64_t per = (A.nfield + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = (int64_t)b * per, hi = min(A.nfield, lo + per);
     for (int64_t m = lo + t; m < hi; m += kRedThreads) {
-      const double v = (double)E0[m] * (double)E0[m] + (double)E1[m] * (double)E1[m] +
-                       (double)E2[m] * (double)E2[m] + (double)B0[m] * (double)B0[m] +
-                       (double)B1[m] * (double)B1[m] + (double)B2[m] * (double)B2[m];
+      double v = 0.0;
+      for (int q = 0; q < 6; ++q) v += (double)F[q][m] * (double)F[q][m];
       neu_add(s[4], c[4], v);
     }
   }
   block_reduce<NS, NC>(s, c, n);
   if (t == 0) {
-    for (int q = 0; q < NC; ++q) out_cnt[(int64_t)b * NC + q] = n[q];
-    for (int q = 0; q < NS; ++q) { out_sum[(int64_t)b * 2 * NS + 2 * q] = s[q]; out_sum[(int64_t)b * 2 * NS + 2 * q + 1] = c[q]; }
+    for (int q = 0; q < NC; ++q) A.out_cnt[(int64_t)b * NC + q] = n[q];
+    for (int q = 0; q < NS; ++q) {
+      A.out_sum[(int64_t)b * 2 * NS + 2 * q] = s[q];
+      A.out_sum[(int64_t)b * 2 * NS + 2 * q + 1] = c[q];
+    }
   }
 }
 
@@ -482,9 +516,10 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_final(const unsigned lon
                                                               const double* in_sum, int nblk,
                                                               unsigned long long* out_cnt,
                                                               double* out_sum) {
-  constexpr int NS = 5;
-  constexpr int NC = kSlotCnt + 1;
-  double s[NS] = {0, 0, 0, 0, 0}, c[NS] = {0, 0, 0, 0, 0};
+  constexpr int NS = kRedSum;
+  constexpr int NC = kRedCnt;
+  double s[NS], c[NS];
+  for (int q = 0; q < NS; ++q) { s[q] = 0.0; c[q] = 0.0; }
   unsigned long long n[NC];
   for (int q = 0; q < NC; ++q) n[q] = 0ull;
   const int t = threadIdx.x;
@@ -503,32 +538,37 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_final(const unsigned lon
   }
 }
 
-int reduce_scratch_cnt() { return kRedBlocks * (kSlotCnt + 1) + (kSlotCnt + 1); }
-int reduce_scratch_sum() { return kRedBlocks * 10 + 5; }
+int reduce_scratch_cnt() { return kRedBlocks * kRedCnt + kRedCnt; }
+int reduce_scratch_sum() { return kRedBlocks * 2 * kRedSum + kRedSum; }
 
-// out_cnt[0..kSlotCnt) slot counters, out_cnt[kSlotCnt] live electrons;
-// out_sum: kept0, kept1, dropped, e_kin, sum(E^2+B^2).
-void launch_stats_reduce(const Ctx& c, unsigned long long* cnt_out, double* sum_out, double*,
-                         double*, unsigned long long*, hipStream_t s) {
-  unsigned long long* pc = c.red_cnt;
-  double* ps = c.red_sum;
-  unsigned long long* fc = pc + kRedBlocks * (kSlotCnt + 1);
-  double* fs = ps + kRedBlocks * 10;
-  if (c.fp32)
-    hipLaunchKernelGGL(k_reduce_partial<float>, dim3(kRedBlocks), dim3(kRedThreads), 0, s,
-                       c.slot_cnt, c.slot_sum, c.nslots, (const float*)c.p[0], (const float*)c.p[1],
-                       (const float*)c.p[2], c.w, c.id, c.N, (const float*)c.E[0],
-                       (const float*)c.E[1], (const float*)c.E[2], (const float*)c.B[0],
-                       (const float*)c.B[1], (const float*)c.B[2], c.g.nfield, pc, ps);
-  else
-    hipLaunchKernelGGL(k_reduce_partial<double>, dim3(kRedBlocks), dim3(kRedThreads), 0, s,
-                       c.slot_cnt, c.slot_sum, c.nslots, (const double*)c.p[0], (const double*)c.p[1],
-                       (const double*)c.p[2], c.w, c.id, c.N, (const double*)c.E[0],
-                       (const double*)c.E[1], (const double*)c.E[2], (const double*)c.B[0],
-                       (const double*)c.B[1], (const double*)c.B[2], c.g.nfield, pc, ps);
-  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kRedThreads), 0, s, pc, ps, kRedBlocks, fc, fs);
-  hipMemcpyAsync(cnt_out, fc, sizeof(unsigned long long) * (kSlotCnt + 1), hipMemcpyDeviceToHost, s);
-  hipMemcpyAsync(sum_out, fs, sizeof(double) * 5, hipMemcpyDeviceToHost, s);
+void launch_stats_reduce(const Ctx& c, unsigned long long* cnt_out, double* sum_out, hipStream_t s) {
+  RedArgs A{};
+  A.scnt = c.slot_cnt;
+  A.ssum = c.slot_sum;
+  A.nslots = c.nslots;
+  A.w = c.w;
+  A.id = c.id;
+  A.N = c.N;
+  for (int a = 0; a < 3; ++a) {
+    A.p[a] = c.p[a];
+    A.F[a] = c.E[a];
+    A.F[3 + a] = c.B[a];
+    A.ip[a] = c.ip[a];
+  }
+  A.nfield = c.g.nfield;
+  A.ialive = c.ialive;
+  A.Ni = c.Ni;
+  A.iwm = c.iw * c.imass;
+  A.out_cnt = c.red_cnt;
+  A.out_sum = c.red_sum;
+  unsigned long long* fc = c.red_cnt + kRedBlocks * kRedCnt;
+  double* fs = c.red_sum + kRedBlocks * 2 * kRedSum;
+  if (c.fp32) hipLaunchKernelGGL(k_reduce_partial<float>, dim3(kRedBlocks), dim3(kRedThreads), 0, s, A);
+  else hipLaunchKernelGGL(k_reduce_partial<double>, dim3(kRedBlocks), dim3(kRedThreads), 0, s, A);
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kRedThreads), 0, s, c.red_cnt, c.red_sum,
+                     kRedBlocks, fc, fs);
+  hipMemcpyAsync(cnt_out, fc, sizeof(unsigned long long) * kRedCnt, hipMemcpyDeviceToHost, s);
+  hipMemcpyAsync(sum_out, fs, sizeof(double) * kRedSum, hipMemcpyDeviceToHost, s);
 }
 
 // ---- Philox exposure -------------------------------------------------------

@@ -210,6 +210,34 @@ struct SortArgs {
 };
 void launch_sort(const SortArgs& A, bool fp32, hipStream_t s);
 
+// Mobile ions (always FP64): one thread per ion, id order (never sorted).
+struct IonArgs {
+  int64_t Ni;
+  int dims, ion_ppc, nslab, i0, ny;
+  int n[3], gg[3], sz[3];
+  uint32_t flags, frozen_kind, key0, key1;
+  int fp32;                 // field arrays are float
+  double dx[3], idx[3], L[3], dxdt[3], invV, dt;
+  double hq;                // (dt / 2) (q / M)
+  double qw;                // -(q w): the deposit's weight argument (charge density +q w / V)
+  double iwv;               // w / V: density of one ion in its cell
+  double tn;                // t^n (prescribed plane wave)
+  double fE[3], fB[3], fa;
+  const void* F[6];         // E^n, B^n
+  unsigned long long* J[3];
+  double* x[3];
+  double* p[3];
+  uint8_t* alive;
+  uint32_t* count;          // live ions per cell (for the next step's density)
+  double* ni;
+  int64_t ncell;
+};
+void fill_ion_args(const struct Ctx& c, IonArgs& A);
+void launch_ion_init(const IonArgs& A, hipStream_t s);     // load, then count
+void launch_ion_recount(const IonArgs& A, hipStream_t s);  // clear and count again
+void launch_ion_density(const IonArgs& A, hipStream_t s);  // ni <- count w / V, count <- 0
+void launch_ion_step(const IonArgs& A, hipStream_t s);     // push, deposit, walls, count
+
 void launch_step(int dims, bool fp32, const void* params, hipStream_t s);
 int chunk_electrons(bool fp32, int dims);   // electrons per step-kernel workgroup
 // batched forms (device-resident tables of per-run entries; first[] is the
@@ -225,8 +253,12 @@ void fill_field_job(const struct Ctx& c, double lsin, double lcos, FieldJob& F);
 void launch_init_electrons(const struct Ctx& c, hipStream_t s);
 void launch_b_both(const struct Ctx& c, hipStream_t s);
 void launch_e_full(struct Ctx& c, double lsin, double lcos, hipStream_t s);
+// Statistics reduction: cnt_out[kRedCnt] = the kSlotCnt slot counters, live
+// electrons, live mobile ions; sum_out[kRedSum] = kept NCS, kept brem,
+// dropped NCS, electron kinetic, sum (E^2 + B^2), ion kinetic energy.
+constexpr int kRedCnt = kSlotCnt + 2;
+constexpr int kRedSum = 6;
 void launch_stats_reduce(const struct Ctx& c, unsigned long long* cnt_out, double* sum_out,
-                         double* ekin_out, double* efield_out, unsigned long long* live_out,
                          hipStream_t s);
 void launch_philox(const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out, uint64_t n,
                    hipStream_t s);
@@ -243,6 +275,8 @@ struct Ctx {
   uint32_t key0 = 0, key1 = 0;
   uint64_t step = 0;
   int64_t N = 0;            // electrons loaded
+  int64_t Ni = 0;           // mobile ions loaded (0: static ions)
+  double iw = 0, iq = 0, imass = 0;
   int i0 = 0, i1 = 0;       // slab cells [i0, i1)
   double wgt = 0;           // electron weight
   // device memory (one arena of allocations, freed in ~Ctx)
@@ -260,6 +294,10 @@ struct Ctx {
   double* taub = nullptr;     // free-path bremsstrahlung only
   double* w = nullptr;
   uint32_t* id = nullptr;
+  double* ix[3] = {};         // mobile ions: positions (active axes), momenta per unit mass
+  double* ip[3] = {};
+  uint8_t* ialive = nullptr;
+  uint32_t* icount = nullptr; // live ions per cell
   uint64_t pcap = 0;
   void* px[3] = {};
   void* pk[3] = {};

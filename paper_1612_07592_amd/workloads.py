@@ -4,7 +4,8 @@ This module holds parameters only (no step arithmetic) and imports nothing
 from the rest of the package, so both the HIP path and the CPU oracle can be
 driven from the same recipe.  Every input is synthetic and seeded: electrons
 are loaded cold (p = 0) at uniform-random in-cell positions drawn from the
-run's own Philox stream, the ions are static with n_i = n_e / charge_state,
+run's own Philox stream, the ions have n_i = n_e / charge_state (static, or
+mobile macro-ions loaded the same way at rest),
 and the laser enters from the left boundary (Sec. III of the paper sets up the
 same geometry: linear polarisation along y, propagation along x, a slab target
 of Al or Au).
@@ -16,7 +17,8 @@ Keys (lengths in laser wavelengths, lambda = 1 um):
   length), focus_x_lambda, photon_cut_mc2 (NCS record cut; Sec. III keeps
   photons of at least m_e c^2), ncs, brem, frozen (particle-only mode),
   frozen_kind/frozen_E/frozen_B/frozen_a, seed, job_id, photon_capacity,
-  precision ("fp64" or "fp32").
+  precision ("fp64" or "fp32"), ion_ppc (mobile ions per slab cell, 0 =
+  static), ion_mass_me, envelope ("sin2" or "flat").
 """
 from __future__ import annotations
 
@@ -127,6 +129,55 @@ def thick_target(steps=2000, precision="fp32", energy_mev=100.0, electrons=2_097
                  frozen_E=[0.0, 0.0, 0.0], frozen_B=[0.0, 0.0, 0.0], steps=steps, seed=9,
                  photon_capacity=40_000_000, precision=precision, sort_every=-1,
                  beam_energy_mev=energy_mev)
+
+
+# Solid targets of Sec. III: fully ionised at solid density
+U_ME = 1822.888486                      # atomic mass unit in electron masses
+SOLID = {
+    "al": dict(Z=13, charge_state=13, ne_over_nc=711.0, ion_mass_me=26.9815385 * U_ME,
+               cells=1000),
+    "au": dict(Z=79, charge_state=79, ne_over_nc=4177.0, ion_mass_me=196.966569 * U_ME,
+               cells=2000),
+}
+# peak intensities of the four runs (W/cm^2) and the a0 of a linearly
+# polarised 1 um laser: a0 = 0.855 sqrt(I / 1e18 W/cm^2)
+SOLID_INTENSITIES = (1e21, 1e22, 1e23, 1e24)
+
+
+def a0_of_intensity(intensity_w_cm2, lambda_um=1.0):
+    return 0.855 * lambda_um * math.sqrt(intensity_w_cm2 / 1e18)
+
+
+def solid(target="au", intensity=1e22, process="both", cells=None, ppc=80, ion_ppc=20,
+          steps=None, precision="fp32", photon_capacity=None, seed=31):
+    """The laser-solid runs of Sec. III: 2D3V, a 6 x 6 um box (1000^2 cells
+    for Al, 2000^2 for Au; `cells` overrides the count per axis), a fully
+    ionised slab 1 um thick from x = 2 um at n_e = 711 n_c (Al) or 4177 n_c
+    (Au), 80 electrons and 20 mobile ions per cell, a laser polarised along y
+    with a flat 30 fs envelope and a Gaussian transverse profile of 1 um
+    waist focused on the slab front, photons kept from m_e c^2 up.
+    `process` = "ncs" or "brem" switches one emission off (the paper's
+    separate runs), "both" keeps both.  The default run length covers the
+    pulse's transit to the slab, its 30 fs and one more period."""
+    t = SOLID[target]
+    n = int(cells or t["cells"])
+    dx = 6.0 / n
+    duration = 30e-15 * 299792458.0 / 1e-6      # 30 fs in periods of a 1 um laser
+    if steps is None:
+        dt = 0.95 / math.sqrt(2.0 / (2 * math.pi * dx) ** 2)
+        steps = int(math.ceil((duration + 2.0 + 1.0 + 1.0) * 2 * math.pi / dt))
+    a0 = a0_of_intensity(intensity)
+    if photon_capacity is None:
+        slab = int(round(1.0 / dx)) * n
+        photon_capacity = min(400_000_000, max(1 << 20, slab * ppc * 8))
+    return _base(name=f"solid-{target}-I{intensity:.0e}-{process}", dims=2, n=[n, n],
+                 dx_lambda=[dx, dx], ppc=ppc, ion_ppc=ion_ppc, x0_lambda=2.0,
+                 thickness_lambda=1.0, a0=a0, w0_lambda=1.0, focus_x_lambda=2.0,
+                 duration_cycles=duration, envelope="flat", steps=steps,
+                 ncs=process in ("ncs", "both"), brem=process in ("brem", "both"),
+                 photon_capacity=photon_capacity, precision=precision, seed=seed,
+                 Z=t["Z"], charge_state=t["charge_state"], ne_over_nc=t["ne_over_nc"],
+                 ion_mass_me=t["ion_mass_me"])
 
 
 def num_electrons(w):

@@ -64,3 +64,30 @@ def small_3d(steps=80, a0=60.0, precision="fp64"):
                 ppc=2, x0_lambda=1.0, thickness_lambda=0.5, a0=a0, w0_lambda=0.4,
                 focus_x_lambda=1.0, steps=steps, precision=precision, Z=79, charge_state=69,
                 ne_over_nc=40.0, seed=4)
+
+
+def ions_1d(steps=300, precision="fp64"):
+    """1D laser-slab run with mobile ions light enough (q/M = 0.016) to move
+    within the run, in a dense gold-like slab."""
+    dx = 1 / 128
+    return base(name="ions-1d", dims=1, n=[1024], dx_lambda=[dx], ppc=32, ion_ppc=8,
+                ion_mass_me=5000.0, x0_lambda=0.25, thickness_lambda=1.0, a0=270.0,
+                duration_cycles=3.0, envelope="flat", steps=steps, precision=precision,
+                Z=79, charge_state=79, ne_over_nc=400.0, seed=41)
+
+
+def ions_2d(steps=160, precision="fp64"):
+    """2D laser-slab run with mobile ions, flat envelope."""
+    return base(name="ions-2d", dims=2, n=[128, 64], dx_lambda=[1 / 32, 1 / 32], ppc=4,
+                ion_ppc=2, ion_mass_me=2000.0, x0_lambda=1.0, thickness_lambda=0.5, a0=120.0,
+                w0_lambda=0.8, focus_x_lambda=1.0, duration_cycles=2.0, envelope="flat",
+                steps=steps, precision=precision, Z=79, charge_state=79, ne_over_nc=60.0,
+                seed=43)
+
+
+def frozen_dense_ions(B=50.0, steps=150):
+    """Particle-only mode at a very high density with mobile ions gyrating in
+    a uniform B: many bremsstrahlung events, each decided against the counted
+    ion density of the electron's cell."""
+    return frozen_B_beam(B=B, ne=5e7, Z=79, charge_state=79, ion_ppc=4, ion_mass_me=200.0,
+                         steps=steps)

@@ -99,6 +99,30 @@ def test_invalid_configs_rejected(field, value):
     assert msg and len(msg) > 3
 
 
+def test_mobile_ion_configs():
+    """The Sec. III solid runs fit one GPU; mobile ions add their arrays and
+    per-cell counts; bad ion parameters are refused."""
+    code, n_au = _mem(W.solid("au"))
+    assert code == 0 and n_au < 64 * 2**30, n_au
+    w = W.solid("al", cells=200)
+    code, with_ions = _mem(w)
+    assert code == 0
+    w0 = dict(w, ion_ppc=0)
+    code, without = _mem(w0)
+    ni = W.num_electrons(w) // w["ppc"] * w["ion_ppc"]
+    assert with_ions - without >= ni * (2 * 8 + 3 * 8 + 1)
+    for k, v in (("ion_ppc", -1), ("ion_ppc", 5000), ("ion_mass_me", 0.5),
+                 ("ion_mass_me", float("nan"))):
+        assert _mem(dict(w, **{k: v}))[0] == 1, (k, v)
+    c = B.config_from(w)
+    c.envelope = 2
+    n = C.c_uint64()
+    assert B.load().pic_memory_required(C.byref(c), C.byref(n)) == 1
+    c = B.config_from(w)
+    c.reserved0 = 1
+    assert B.load().pic_memory_required(C.byref(c), C.byref(n)) == 1
+
+
 def test_invalid_grid_rejected():
     w = W.c1()
     w["n"] = [4]
