@@ -34,7 +34,10 @@ Beside the headline, the JSON line carries (each leg's failure is recorded in
                          time from HIP events on the kernel's stream;
   cpu_baseline           the FP64 oracle on the host over the same window of a
                          transverse slice of the headline workload;
-  serving, thick_target  scan-job server runs and the bremsstrahlung benchmark.
+  serving, thick_target  scan-job server runs and the bremsstrahlung benchmark;
+  solid                  (--only solid) the laser-solid study of Sec. III at
+                         its own size, with mobile ions: throughput and energy
+                         partition of every run.
 """
 from __future__ import annotations
 
@@ -208,7 +211,7 @@ def run_window(w, tables, lead, k, torch, warmup=0, photons=False, events=True, 
         s.pic_destroy()
         out.update(window_esteps=int(st["electron_steps"]) - e0,
                    step_kernel_ms=float(ms[0]), field_ms=float(ms[1]), sort_ms=float(ms[2]),
-                   step_launches=int(n[0]), profiled_ms=float(ms.sum()))
+                   ion_ms=float(ms[3]), step_launches=int(n[0]), profiled_ms=float(ms.sum()))
     return out
 
 
@@ -373,6 +376,64 @@ def thick_target_line(tables, torch):
     return res
 
 
+def laser_energy(w):
+    """Energy the laser source injects over the pulse, in the statistics'
+    units (n_c m c^2 (c/omega0)^dims): a flat envelope of length T carries a
+    time-averaged flux a0^2 / 2 through a 2D Gaussian profile of integral
+    w0 sqrt(pi / 2) over y (per unit length in z)."""
+    T = w["duration_cycles"] * 2.0 * math.pi
+    w0 = w["w0_lambda"] * 2.0 * math.pi
+    assert w["dims"] == 2 and w.get("envelope") == "flat" and w0 > 0
+    return 0.5 * w["a0"] ** 2 * w0 * math.sqrt(math.pi / 2.0) * T
+
+
+def solid_leg(torch, targets=("al", "au"), intensities=None, processes=("ncs", "brem"),
+              precision="fp32"):
+    """The laser-solid study of Sec. III at its own size: Al (1000^2 cells,
+    13.4M electrons, 3.3M mobile ions) and Au (2000^2 cells, 53.3M electrons,
+    13.3M ions), 80 electrons and 20 ions per cell, flat 30 fs pulse, one
+    NCS-only and one brem-only run per intensity, each run to its end.  Per
+    run: throughput, kernel time shares, and the energy partition as fractions
+    of the injected laser energy (radiated by the run's process, electrons,
+    ions, field left in the box)."""
+    from paper_1612_07592_amd import binding
+    from paper_1612_07592_amd import workloads as W
+    intensities = intensities or W.SOLID_INTENSITIES
+    tb = {}
+    runs = []
+    for tgt in targets:
+        for I in intensities:
+            for proc in processes:
+                w = W.solid(tgt, I, proc, precision=precision)
+                Z = int(w["Z"])
+                if Z not in tb:
+                    tb[Z] = binding.pic_build_tables(Z, 1.0, 16)
+                r = run_window(w, tb[Z], 0, int(w["steps"]), torch, events=True, wall=True)
+                st = r["stats"]
+                EL = laser_energy(w)
+                pr = 0 if proc == "ncs" else 1
+                rec = {"run": w["name"], "steps": int(w["steps"]), "electrons": _num_electrons(w),
+                       "ions": _num_electrons(w) // w["ppc"] * w["ion_ppc"],
+                       "value": r["window_esteps"] / r["wall_s"], "wall_s": r["wall_s"],
+                       "kernel_ms": {"electron_step": r["step_kernel_ms"], "field_solve": r["field_ms"],
+                                     "sort": r["sort_ms"], "ions": r["ion_ms"]},
+                       "events": st["events"][pr], "photons_kept": st["kept"][pr],
+                       "overflow": st["overflow"],
+                       "fraction_of_laser_energy": {
+                           "photons": (st["e_rad_kept"][pr] + (st["e_rad_dropped"] if pr == 0 else 0.0)) / EL,
+                           "photons_kept": st["e_rad_kept"][pr] / EL,
+                           "electrons": st["e_kin_e"] / EL, "ions": st["e_kin_i"] / EL,
+                           "field_in_box": st["e_field"] / EL},
+                       "ions_live": st["ions_live"], "electrons_live": st["live"]}
+                f = rec["fraction_of_laser_energy"]
+                log(f"solid {w['name']}: {rec['value']:.3e} e-steps/s over {w['steps']} steps "
+                    f"({r['wall_s']:.1f} s); photons {f['photons']:.2e}, e {f['electrons']:.3f}, "
+                    f"i {f['ions']:.3f} of the laser energy")
+                runs.append(rec)
+    return {"runs": runs, "laser_energy_note": "a0^2/2 * w0 sqrt(pi/2) * T (flat pulse, 2D)",
+            "precision": precision}
+
+
 def serving(args):
     """Scan jobs through the continuous-batching server: the 8-job
     intensity x target batch (FP32, FP64, and FP32 one job after another),
@@ -485,7 +546,10 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the scan-job server runs")
     ap.add_argument("--no-thick", action="store_true", help="skip the thick-target runs")
     ap.add_argument("--only", default=None,
-                    help="run only the headline and this leg (roofline, full, cpu, serving, thick)")
+                    help="run only the headline and this leg (roofline, full, cpu, serving, thick, "
+                         "solid)")
+    ap.add_argument("--solid-targets", default="al,au")
+    ap.add_argument("--solid-intensities", default="1e21,1e22,1e23,1e24")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of this many MiB (HBM counter calibration)")
     ap.add_argument("--c3-steps", type=int, default=1000)
@@ -500,7 +564,7 @@ def main():
         sys.exit(2)
     legs = {"roofline": not args.no_roofline, "full": not args.no_full_run and not args.no_fp64,
             "cpu": not args.no_cpu_baseline, "serving": not args.no_serving,
-            "thick": not args.no_thick, "fp64": not args.no_fp64}
+            "thick": not args.no_thick, "fp64": not args.no_fp64, "solid": False}
     if args.only:
         legs = {k: (k == args.only) for k in legs}
     import torch
@@ -555,7 +619,7 @@ def main():
                             "sort": r["sort_ms"], "launches": r["step_launches"]}
         out["time_share"] = {kk: v / r["profiled_ms"] for kk, v in
                              (("electron_step", r["step_kernel_ms"]), ("field_solve", r["field_ms"]),
-                              ("sort", r["sort_ms"]))}
+                              ("sort", r["sort_ms"]), ("ions", r["ion_ms"]))}
         avg = r["step_kernel_ms"] * 1e3 / max(1, r["step_launches"])
         bpe = STATE_BYTES[(args.precision, dims)]
         out["headline_kernel"] = {
@@ -594,6 +658,10 @@ def main():
             out["thick_target"] = leg("thick_target", lambda: thick_target_line(tables, torch))
         if legs["serving"] and args.workload == "c2":
             out["serving"] = leg("serving", lambda: serving(args))
+        if legs["solid"]:
+            out["solid"] = leg("solid", lambda: solid_leg(
+                torch, tuple(args.solid_targets.split(",")),
+                tuple(float(v) for v in args.solid_intensities.split(","))))
         if legs["cpu"]:
             out["cpu_baseline"] = leg("cpu_baseline", lambda: cpu_baseline(
                 _workload(args.workload, "fp64"), lead, k))

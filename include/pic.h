@@ -364,10 +364,11 @@ pic_status pic_philox_noalloc(const uint32_t* ctr, const uint32_t* key, uint32_t
 /* Kernel timing with HIP events recorded on the context's stream around
  * every electron-step launch, every field-solve group and every tile sort
  * (enable != 0 starts a fresh accumulation).  pic_profile_read synchronises
- * and returns the summed milliseconds and launch counts in ms3/launches3:
- * [0] electron step, [1] field solve, [2] sort. */
+ * and returns the summed milliseconds and launch counts in ms4/launches4:
+ * [0] electron step, [1] field solve, [2] sort, [3] mobile ions (density
+ * pass and push). */
 pic_status pic_profile(pic_ctx* ctx, int32_t enable);
-pic_status pic_profile_read(pic_ctx* ctx, double* ms3, uint64_t* launches3);
+pic_status pic_profile_read(pic_ctx* ctx, double* ms4, uint64_t* launches4);
 
 /* Derived constants of ctx: dx[3], dt, E_S, K_N, K_BR, n_c (8 doubles). */
 pic_status pic_derived(pic_ctx* ctx, double* out8);

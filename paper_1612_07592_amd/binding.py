@@ -457,9 +457,9 @@ class Sim:
         _check("pic_profile", self._L.pic_profile(self._h, 1 if enable else 0), self._h)
 
     def profile_read(self):
-        """ms and launch counts: [electron step, field solve, sort]."""
-        ms = np.zeros(3)
-        n = np.zeros(3, dtype=np.uint64)
+        """ms and launch counts: [electron step, field solve, sort, ions]."""
+        ms = np.zeros(4)
+        n = np.zeros(4, dtype=np.uint64)
         _check("pic_profile_read", self._L.pic_profile_read(self._h, ms.ctypes.data, n.ctypes.data), self._h)
         return ms, n
 

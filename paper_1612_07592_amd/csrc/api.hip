@@ -831,7 +831,9 @@ pic_status pic_step(pic_ctx* ctx, int32_t nsteps) {
     IonArgs IA{};
     if (c.Ni > 0) {
       fill_ion_args(c, IA);
+      mark(3);
       launch_ion_density(IA, c.stream);       // n of Eq. (4) from the ions at x^n
+      mark(3);
     }
     mark(0);
     if (c.fp32) {
@@ -844,7 +846,11 @@ pic_status pic_step(pic_ctx* ctx, int32_t nsteps) {
       launch_step(c.g.dims, false, &P, c.stream);
     }
     mark(0);
-    if (c.Ni > 0) launch_ion_step(IA, c.stream);
+    if (c.Ni > 0) {
+      mark(3);
+      launch_ion_step(IA, c.stream);
+      mark(3);
+    }
     mark(1);
     if (!frozen) {
       double ls, lc;
@@ -1438,8 +1444,10 @@ pic_status pic_profile_read(pic_ctx* ctx, double* ms2, uint64_t* n2) {
   Ctx& c = ctx->c;
   if (!ms2 || !n2) FAIL(c, PIC_ERR_INVALID, "null output");
   HIPCHK(c, hipStreamSynchronize(c.stream));
-  ms2[0] = ms2[1] = ms2[2] = 0.0;
-  n2[0] = n2[1] = n2[2] = 0;
+  for (int k = 0; k < 4; ++k) {
+    ms2[k] = 0.0;
+    n2[k] = 0;
+  }
   for (size_t i = 0; i + 1 < c.ev_used; i += 2) {
     float ms = 0.f;
     HIPCHK(c, hipEventElapsedTime(&ms, c.ev_pool[i], c.ev_pool[i + 1]));

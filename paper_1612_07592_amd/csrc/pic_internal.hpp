@@ -339,7 +339,7 @@ struct Ctx {
   // optional kernel timing (pairs of events per launch group)
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
-  std::vector<int> ev_kind;   // 0 electron step, 1 field solve, 2 sort
+  std::vector<int> ev_kind;   // 0 electron step, 1 field solve, 2 sort, 3 ions
   size_t ev_used = 0;
   DevTables t{};
   std::vector<void*> allocs;

@@ -302,3 +302,23 @@ def test_device_pointer_convention_names_get_buffers():
     head = text[:text.index("#ifndef LIBPIC_PIC_H")]
     assert "never exposed." not in head
     assert "pic_get_buffers" in head
+
+
+def test_bench_laser_energy_is_what_the_source_injects():
+    """The laser energy the Sec. III energy fractions are taken of: a flat
+    pulse of 30 fs through a 1 um Gaussian waist, a0^2/2 w0 sqrt(pi/2) T,
+    equals the field energy of an oracle vacuum run at the moment the last of
+    the pulse has left the source (box wide enough to hold the beam)."""
+    import oracle
+    import conftest
+    import scenarios as S
+    b = _bench()
+    w = S.base(name="vacuum", dims=2, n=[512, 384], dx_lambda=[1 / 32, 1 / 32], ppc=1,
+               x0_lambda=0.0, thickness_lambda=0.0, a0=10.0, w0_lambda=1.0,
+               focus_x_lambda=2.0, duration_cycles=30e-15 * 299792458.0 / 1e-6,
+               envelope="flat", ncs=False, brem=False, ne_over_nc=0.0)
+    o = oracle.OracleSim(w, conftest.oracle_tables(13))
+    assert o.N == 0
+    T = w["duration_cycles"] * 2 * math.pi
+    o.step(int(T / o.derived()["dt"]))
+    assert abs(o.field_energy() / b.laser_energy(w) - 1.0) < 0.01

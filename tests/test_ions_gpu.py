@@ -91,6 +91,27 @@ def test_ions_2d_flat_pulse(oracle_lib, gpu_lib, tables_au):
     assert rep["ions_live"] < g.Ni   # some ions left through the walls
 
 
+def test_ions_2d_scattered_global_path(oracle_lib, gpu_lib, tables_au):
+    """Ions shuffled over the slab, so that a workgroup's ions span more
+    nodes than its LDS box holds: current and counts go to global memory."""
+    _announce("ions: 2D shuffled ions (global-memory path)")
+    w = S.ions_2d(steps=120)
+    o, g = _pair(oracle_lib, gpu_lib, w, tables_au)
+    x = o.ions()["x"]
+    x = x[np.random.default_rng(9).permutation(o.Ni)]
+    p = np.zeros_like(x)
+    o.set_ions(x, p)
+    g.set_ions(x, p)
+    o.step(w["steps"])
+    g.step(w["steps"])
+    rep = compare(o, g, label="ions-2d-shuffled")
+    rep.update(compare_ions(o, g, "ions-2d-shuffled"))
+    fo, fg = o.fields(), g.fields()
+    rep["max_dfield"] = float(np.abs(fo - fg).max())
+    print(rep, flush=True)
+    assert rep["max_dfield"] <= 1e-12 * max(1.0, np.abs(fo).max())
+
+
 def test_brem_against_counted_ion_density(oracle_lib, gpu_lib, tables_au):
     """Particle-only mode, very dense: thousands of collisions, each decided
     against the density counted from the (moving) ions of the electron's
