@@ -25,6 +25,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
 
 OR_NCS, OR_BREM, OR_FROZEN, OR_NO_RECOIL, OR_BREM_FREEPATH = 1, 2, 4, 16, 32
+OR_BW, OR_BH = 64, 128
 FROZEN_UNIFORM, FROZEN_PLANE_WAVE = 0, 1
 
 
@@ -69,7 +70,8 @@ class _Cfg(C.Structure):
                 ("photon_cut_mc2", C.c_double), ("frozen_E", C.c_double * 3),
                 ("frozen_B", C.c_double * 3), ("frozen_a", C.c_double),
                 ("seed", C.c_uint64), ("job_id", C.c_uint64), ("photon_capacity", C.c_uint64),
-                ("ion_ppc", C.c_int32), ("envelope", C.c_int32), ("ion_mass", C.c_double)]
+                ("ion_ppc", C.c_int32), ("envelope", C.c_int32), ("ion_mass", C.c_double),
+                ("pair_capacity", C.c_uint64)]
 
 
 class _Tab(C.Structure):
@@ -78,7 +80,12 @@ class _Tab(C.Structure):
                 ("ln_xi", C.POINTER(C.c_double)), ("ncs_cdf", C.POINTER(C.c_double)),
                 ("n_T", C.c_int32), ("n_y", C.c_int32), ("ln_T0", C.c_double),
                 ("dln_T", C.c_double), ("k_cut", C.c_double),
-                ("sigma", C.POINTER(C.c_double)), ("br_cdf", C.POINTER(C.c_double))]
+                ("sigma", C.POINTER(C.c_double)), ("br_cdf", C.POINTER(C.c_double)),
+                ("n_chi", C.c_int32), ("n_xp", C.c_int32), ("ln_chi0", C.c_double),
+                ("dln_chi", C.c_double), ("bw_lnT", C.POINTER(C.c_double)),
+                ("bw_cdf", C.POINTER(C.c_double)), ("n_k", C.c_int32), ("n_s", C.c_int32),
+                ("ln_k0", C.c_double), ("dln_k", C.c_double),
+                ("bh_sigma", C.POINTER(C.c_double)), ("bh_cdf", C.POINTER(C.c_double))]
 
 
 class _Stats(C.Structure):
@@ -86,7 +93,8 @@ class _Stats(C.Structure):
                 ("kept", C.c_uint64 * 2), ("dropped_ncs", C.c_uint64),
                 ("overflow", C.c_uint64), ("brem_clamped", C.c_uint64),
                 ("e_rad_kept", C.c_double * 2), ("e_rad_dropped", C.c_double),
-                ("ions_live", C.c_uint64)]
+                ("ions_live", C.c_uint64), ("pairs", C.c_uint64 * 2),
+                ("pairs_overflow", C.c_uint64), ("e_pair", C.c_double * 2)]
 
 
 _libs = {}
@@ -115,6 +123,11 @@ def _load(path=None):
         L.or_get_tau_brem.argtypes = [P, C.c_void_p]
         L.or_set_tau_brem.argtypes = [P, C.c_void_p]
         L.or_get_photons.argtypes = [P] + [C.c_void_p] * 7
+        L.or_num_pairs.restype = C.c_int64
+        L.or_num_pairs.argtypes = [P]
+        L.or_get_pairs.argtypes = [P] + [C.c_void_p] * 9
+        L.or_add_photons.argtypes = [P, C.c_int64] + [C.c_void_p] * 5
+        L.or_get_flight.argtypes = [P] + [C.c_void_p] * 3
         L.or_get_stats.argtypes = [P, C.POINTER(_Stats)]
         L.or_kinetic_energy.restype = C.c_double
         L.or_kinetic_energy.argtypes = [P]
@@ -181,6 +194,10 @@ def flags_from(w):
         f |= OR_NO_RECOIL
     if w.get("brem_freepath", False):
         f |= OR_BREM_FREEPATH
+    if w.get("bw", False):
+        f |= OR_BW
+    if w.get("bh", False):
+        f |= OR_BH
     return f
 
 
@@ -223,6 +240,7 @@ class OracleSim:
         c.ion_ppc = int(w.get("ion_ppc", 0))
         c.envelope = 1 if w.get("envelope", "sin2") == "flat" else 0
         c.ion_mass = float(w.get("ion_mass_me", 0.0))
+        c.pair_capacity = int(w.get("pair_capacity", 1 << 16))
         self._keep = []
         t = _Tab()
         t.n_eta = int(tables["n_eta"]); t.n_xi = int(tables["n_xi"])
@@ -234,6 +252,17 @@ class OracleSim:
             a = np.ascontiguousarray(tables[name], dtype=np.float64)
             self._keep.append(a)
             setattr(t, name, _dptr(a))
+        if "bw_lnT" in tables:
+            t.n_chi = int(tables["n_chi"]); t.n_xp = int(tables["n_xp"])
+            t.ln_chi0 = float(tables["ln_chi0"]); t.dln_chi = float(tables["dln_chi"])
+            t.n_k = int(tables["n_k"]); t.n_s = int(tables["n_s"])
+            t.ln_k0 = float(tables["ln_k0"]); t.dln_k = float(tables["dln_k"])
+            for name in ("bw_lnT", "bw_cdf", "bh_sigma", "bh_cdf"):
+                a = np.ascontiguousarray(tables[name], dtype=np.float64)
+                self._keep.append(a)
+                setattr(t, name, _dptr(a))
+        elif flags_from(w) & (OR_BW | OR_BH):
+            raise ValueError("pair production needs the pair tables (oracle.tables.build_bw/build_bh)")
         nt = nthreads if nthreads is not None else min(os.cpu_count() or 1, 16)
         self._h = L.or_create(C.byref(c), C.byref(t), int(nt))
         self._L = L
@@ -307,6 +336,38 @@ class OracleSim:
                                    w.ctypes.data, st.ctypes.data, par.ctypes.data, pr.ctypes.data)
         return dict(x=x, k=k, energy=e, w=w, step=st, parent=par, proc=pr)
 
+    def pairs(self):
+        n_all = int(self._L.or_num_pairs(self._h))
+        n = min(n_all, int(self.workload.get("pair_capacity", 1 << 16)))
+        x = np.zeros((n, 3)); k = np.zeros((n, 3)); em = np.zeros(n); ep = np.zeros(n)
+        w = np.zeros(n)
+        st, par, pst, pr = (np.zeros(n, dtype=np.uint32) for _ in range(4))
+        if n:
+            self._L.or_get_pairs(self._h, x.ctypes.data, k.ctypes.data, em.ctypes.data,
+                                 ep.ctypes.data, w.ctypes.data, st.ctypes.data, par.ctypes.data,
+                                 pst.ctypes.data, pr.ctypes.data)
+        return dict(x=x, k=k, e_minus=em, e_plus=ep, w=w, step=st, parent=par, pstep=pst,
+                    proc=pr)
+
+    def add_photons(self, x, k, eps, w, parent):
+        """Append photons as records of the coming step (test hook)."""
+        x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 3)
+        n = x.shape[0]
+        k = np.ascontiguousarray(k, dtype=np.float64).reshape(n, 3)
+        eps = np.ascontiguousarray(eps, dtype=np.float64).reshape(n)
+        w = np.ascontiguousarray(w, dtype=np.float64).reshape(n)
+        parent = np.ascontiguousarray(parent, dtype=np.uint32).reshape(n)
+        self._L.or_add_photons(self._h, n, x.ctypes.data, k.ctypes.data, eps.ctypes.data,
+                               w.ctypes.data, parent.ctypes.data)
+
+    def flight(self):
+        """Photons in flight: position, pair optical depth, state."""
+        n = min(int(self._L.or_num_photons(self._h)), int(self.workload.get("photon_capacity", 1 << 20)))
+        x = np.zeros((n, 3)); tau = np.zeros(n); st = np.zeros(n, dtype=np.uint8)
+        if n:
+            self._L.or_get_flight(self._h, x.ctypes.data, tau.ctypes.data, st.ctypes.data)
+        return dict(x=x, tau=tau, state=st)
+
     def stats(self):
         s = _Stats()
         self._L.or_get_stats(self._h, C.byref(s))
@@ -314,7 +375,9 @@ class OracleSim:
                     kept=[s.kept[0], s.kept[1]], dropped_ncs=s.dropped_ncs,
                     overflow=s.overflow, brem_clamped=s.brem_clamped,
                     e_rad_kept=[s.e_rad_kept[0], s.e_rad_kept[1]],
-                    e_rad_dropped=s.e_rad_dropped, ions_live=s.ions_live)
+                    e_rad_dropped=s.e_rad_dropped, ions_live=s.ions_live,
+                    pairs=[s.pairs[0], s.pairs[1]], pairs_overflow=s.pairs_overflow,
+                    e_pair=[s.e_pair[0], s.e_pair[1]])
 
     def kinetic_energy(self):
         return float(self._L.or_kinetic_energy(self._h))

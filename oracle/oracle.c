@@ -135,6 +135,9 @@ struct or_sim {
   int n_eta, n_xi, n_T, n_y;
   double ln_eta0, dln_eta, idln_eta, ln_T0, dln_T, idln_T, k_cut, iny1;
   double *h, *ln_xi, *ncs_cdf, *sigma, *br_cdf;
+  int n_chi, n_xp, n_k, n_s;
+  double ln_chi0, idln_chi, ln_k0, idln_k;
+  double *bw_lnT, *bw_cdf, *bh_sigma, *bh_cdf;
   /* derived */
   int dims, n[3], act[3], gg[3], sz[3];
   double dx[3], idx[3], L[3], dt, invV, E_S, iES, K_N, K_BR, n_c;
@@ -167,6 +170,15 @@ struct or_sim {
   int64_t pcap, pcount;
   double *ph_x, *ph_k, *ph_e, *ph_w;
   uint32_t *ph_step, *ph_parent, *ph_proc;
+  /* photons in flight (OR_BW / OR_BH): position, pair optical depth, state
+   * (0 not yet started, 1 travelling, 2 converted, 3 left the box, 4 below
+   * the pair threshold) */
+  double *gx, *gtau;
+  uint8_t* gst;
+  /* pairs */
+  int64_t rcap, rcount;
+  double *pr_x, *pr_k, *pr_em, *pr_ep, *pr_w;
+  uint32_t *pr_step, *pr_parent, *pr_pstep, *pr_proc;
   or_stats st;
   uint64_t step;
   int nthreads;
@@ -259,6 +271,20 @@ or_sim* or_create(const or_config* c, const or_tables* t, int nthreads) {
   s->sigma = dalloc(s->n_T); memcpy(s->sigma, t->sigma, sizeof(double) * s->n_T);
   s->br_cdf = dalloc((int64_t)s->n_T * s->n_y);
   memcpy(s->br_cdf, t->br_cdf, sizeof(double) * (size_t)s->n_T * s->n_y);
+  if (c->flags & OR_BW) {
+    s->n_chi = t->n_chi; s->n_xp = t->n_xp;
+    s->ln_chi0 = t->ln_chi0; s->idln_chi = 1.0 / t->dln_chi;
+    s->bw_lnT = dalloc(s->n_chi); memcpy(s->bw_lnT, t->bw_lnT, sizeof(double) * s->n_chi);
+    s->bw_cdf = dalloc((int64_t)s->n_chi * s->n_xp);
+    memcpy(s->bw_cdf, t->bw_cdf, sizeof(double) * (size_t)s->n_chi * s->n_xp);
+  }
+  if (c->flags & OR_BH) {
+    s->n_k = t->n_k; s->n_s = t->n_s;
+    s->ln_k0 = t->ln_k0; s->idln_k = 1.0 / t->dln_k;
+    s->bh_sigma = dalloc(s->n_k); memcpy(s->bh_sigma, t->bh_sigma, sizeof(double) * s->n_k);
+    s->bh_cdf = dalloc((int64_t)s->n_k * s->n_s);
+    memcpy(s->bh_cdf, t->bh_cdf, sizeof(double) * (size_t)s->n_k * s->n_s);
+  }
 
   /* fields */
   s->nfield = (int64_t)s->sz[0] * s->sz[1] * s->sz[2];
@@ -387,6 +413,17 @@ or_sim* or_create(const or_config* c, const or_tables* t, int nthreads) {
   s->ph_step = (uint32_t*)calloc((size_t)(s->pcap > 0 ? s->pcap : 1), 4);
   s->ph_parent = (uint32_t*)calloc((size_t)(s->pcap > 0 ? s->pcap : 1), 4);
   s->ph_proc = (uint32_t*)calloc((size_t)(s->pcap > 0 ? s->pcap : 1), 4);
+  if (c->flags & (OR_BW | OR_BH)) {
+    s->gx = dalloc(3 * s->pcap); s->gtau = dalloc(s->pcap);
+    s->gst = (uint8_t*)calloc((size_t)(s->pcap > 0 ? s->pcap : 1), 1);
+    s->rcap = (int64_t)c->pair_capacity;
+    s->pr_x = dalloc(3 * s->rcap); s->pr_k = dalloc(3 * s->rcap);
+    s->pr_em = dalloc(s->rcap); s->pr_ep = dalloc(s->rcap); s->pr_w = dalloc(s->rcap);
+    s->pr_step = (uint32_t*)calloc((size_t)(s->rcap > 0 ? s->rcap : 1), 4);
+    s->pr_parent = (uint32_t*)calloc((size_t)(s->rcap > 0 ? s->rcap : 1), 4);
+    s->pr_pstep = (uint32_t*)calloc((size_t)(s->rcap > 0 ? s->rcap : 1), 4);
+    s->pr_proc = (uint32_t*)calloc((size_t)(s->rcap > 0 ? s->rcap : 1), 4);
+  }
   return s;
 }
 
@@ -398,6 +435,10 @@ void or_destroy(or_sim* s) {
   free(s->x); free(s->p); free(s->tau); free(s->taub); free(s->w); free(s->id); free(s->alive);
   free(s->ph_x); free(s->ph_k); free(s->ph_e); free(s->ph_w);
   free(s->ph_step); free(s->ph_parent); free(s->ph_proc);
+  free(s->bw_lnT); free(s->bw_cdf); free(s->bh_sigma); free(s->bh_cdf);
+  free(s->gx); free(s->gtau); free(s->gst);
+  free(s->pr_x); free(s->pr_k); free(s->pr_em); free(s->pr_ep); free(s->pr_w);
+  free(s->pr_step); free(s->pr_parent); free(s->pr_pstep); free(s->pr_proc);
   free(s->ix); free(s->ip); free(s->ialive); free(s->icount);
   free(s);
 }
@@ -951,6 +992,176 @@ static void ion_step(or_sim* s, double tn, int frozen) {
   free(vv);
 }
 
+/* ------------------------ pair production --------------------------------- */
+/* Quantum parameter of a photon of energy eps (mc^2) travelling along the
+ * unit vector k in E, B: eps |E_perp + k x B| / E_S, i.e. the electron's
+ * invariant with p = eps k and gamma = eps. */
+static double chi_of(const double E[3], const double B[3], const double* k, double eps, double iES) {
+  double cx = E[0] + (k[1] * B[2] - k[2] * B[1]);
+  double cy = E[1] + (k[2] * B[0] - k[0] * B[2]);
+  double cz = E[2] + (k[0] * B[1] - k[1] * B[0]);
+  double ke = k[0] * E[0] + k[1] * E[1] + k[2] * E[2];
+  double q2 = (cx * cx + cy * cy + cz * cz) - ke * ke;
+  if (q2 < 0.0) q2 = 0.0;
+  return eps * sqrt(q2) * iES;
+}
+
+/* Share of a uniform-grid CDF row on [0, 1] at u (linear between points). */
+static double share_inv_row(const double* C, int n, double u) {
+  int lo = 0, hi = n - 1;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) / 2;
+    if (C[mid] <= u) lo = mid; else hi = mid;
+  }
+  double t = (u - C[lo]) / (C[lo + 1] - C[lo]);
+  return ((double)lo + t) / (double)(n - 1);
+}
+
+/* Photons in flight.  Every recorded photon of at least 2 mc^2 travels on
+ * along its direction at c from the step after its emission (Breit-Wheeler
+ * and Bethe-Heitler, the pair channels the paper names beside its two; the
+ * latter "similar to the bremsstrahlung", Sec. II.B):
+ *   Breit-Wheeler: a pair optical depth, -ln u at the start, used up at
+ *     dN/dt = alpha (m c^2 / hbar) (chi / eps) T(chi) with ln T linear in
+ *     ln chi between table points (none below the first point); the photon
+ *     converts when it runs out;
+ *   Bethe-Heitler: the Eq. (4) trial with the pair cross-section,
+ *     P = 1 - exp(-n sigma_BH(k) c dt), n the ion density of the photon's
+ *     cell, against the 52-bit uniform of the step's draw;
+ *   the pair energies from the inverse CDF rows (electron share for
+ *   Breit-Wheeler, positron share for Bethe-Heitler), the two rows around
+ *   chi or k blended in its logarithm; both members keep at least mc^2;
+ *   the pair record at the photon's position, along its direction;
+ *   a photon that converts stops; the others move x += k dt, and are
+ *   absorbed at the walls (READINGS).
+ * Random numbers: Philox counter (parent, emission step, 2 + process, n)
+ * per step, (.., 0xFFFFFFFF) for the initial depth. */
+static void photon_step(or_sim* s, double tn, int frozen) {
+  const or_config* c = &s->c;
+  const uint32_t n = (uint32_t)s->step;
+  const int64_t nst = s->pcount < s->pcap ? s->pcount : s->pcap;
+  const double K_P = 7.2973525693e-3 * s->E_S;   /* alpha m c^2 / (hbar w0) */
+  for (int64_t q = 0; q < nst; ++q) {
+    uint8_t st = s->gst[q];
+    const uint32_t par = s->ph_parent[q], pst = s->ph_step[q], pr = s->ph_proc[q];
+    if (st == 0) {
+      if (pst == n) continue;                      /* emitted in this step */
+      for (int a = 0; a < 3; ++a) s->gx[3 * q + a] = s->ph_x[3 * q + a];
+      if (s->ph_e[q] >= 2.0) {
+        uint32_t r0[4];
+        or_philox(par, pst, 2u + pr, 0xFFFFFFFFu, s->key0, s->key1, r0);
+        s->gtau[q] = -or_log(u32(r0[0]));
+        st = 1;
+      } else {
+        st = 4;
+      }
+      s->gst[q] = st;
+    }
+    if (st != 1) continue;
+    double* x = s->gx + 3 * q;
+    const double* k = s->ph_k + 3 * q;
+    const double eps = s->ph_e[q];
+    int conv = -1, bi = 0;
+    double bf = 0.0;
+    uint32_t r[4];
+    int have_r = 0;
+    if (c->flags & OR_BW) {
+      double E[3] = {0, 0, 0}, B[3] = {0, 0, 0};
+      if (frozen) {
+        if (c->frozen_kind == OR_FROZEN_UNIFORM) {
+          for (int a = 0; a < 3; ++a) { E[a] = c->frozen_E[a]; B[a] = c->frozen_B[a]; }
+        } else {
+          double phi = tn - x[0];
+          if (phi > 0.0) { double v = c->frozen_a * sin(phi); E[1] = v; B[2] = v; }
+        }
+      } else {
+        double g[3];
+        for (int a = 0; a < 3; ++a) g[a] = x[a] * s->idx[a];
+        for (int a = 0; a < 3; ++a) { E[a] = field_at(s, a, g); B[a] = field_at(s, 3 + a, g); }
+      }
+      double chi = chi_of(E, B, k, eps, s->iES);
+      if (chi > 0.0) {
+        double sl = (or_log(chi) - s->ln_chi0) * s->idln_chi;
+        if (sl >= 0.0) {
+          if (sl >= (double)(s->n_chi - 1)) { bi = s->n_chi - 2; bf = 1.0; }
+          else { bi = (int)sl; bf = sl - (double)bi; }
+          double lT = s->bw_lnT[bi] + bf * (s->bw_lnT[bi + 1] - s->bw_lnT[bi]);
+          double dtau = K_P * chi / eps * or_exp(lT) * s->dt;
+          s->gtau[q] = s->gtau[q] - dtau;
+          if (s->gtau[q] <= 0.0) conv = 0;
+        }
+      }
+    }
+    int ki = 0;
+    double kf = 0.0;
+    if (conv < 0 && (c->flags & OR_BH)) {
+      int ci[3] = {0, 0, 0};
+      for (int a = 0; a < s->dims; ++a) {
+        int qq = (int)floor(x[a] * s->idx[a]);
+        if (qq < 0) qq = 0;
+        if (qq > s->n[a] - 1) qq = s->n[a] - 1;
+        ci[a] = qq;
+      }
+      double ni = s->ni[ci[0] + (int64_t)s->n[0] * (ci[1] + (int64_t)s->n[1] * ci[2])];
+      double sl = (or_log(eps) - s->ln_k0) * s->idln_k;
+      if (ni > 0.0 && sl >= 0.0) {
+        if (sl >= (double)(s->n_k - 1)) { ki = s->n_k - 2; kf = 1.0; }
+        else { ki = (int)sl; kf = sl - (double)ki; }
+        double sig = s->bh_sigma[ki] + kf * (s->bh_sigma[ki + 1] - s->bh_sigma[ki]);
+        if (sig > 0.0) {
+          double X = s->K_BR * ni * sig * s->dt;
+          double P = -or_expm1(-X);
+          or_philox(par, pst, 2u + pr, n, s->key0, s->key1, r);
+          have_r = 1;
+          if (u52(r[0], r[1]) < P) conv = 1;
+        }
+      }
+    }
+    if (conv >= 0) {
+      if (!have_r) or_philox(par, pst, 2u + pr, n, s->key0, s->key1, r);
+      double em, ep;
+      if (conv == 0) {   /* electron share xi */
+        double xa = share_inv_row(s->bw_cdf + (int64_t)bi * s->n_xp, s->n_xp, u32(r[2]));
+        double xb = share_inv_row(s->bw_cdf + (int64_t)(bi + 1) * s->n_xp, s->n_xp, u32(r[2]));
+        double xi = xa + bf * (xb - xa);
+        double lo = 1.0 / eps, hi = 1.0 - lo;
+        if (xi < lo) xi = lo;
+        if (xi > hi) xi = hi;
+        em = xi * eps;
+        ep = eps - em;
+      } else {           /* positron share x on s = (x - 1/k) / (1 - 2/k) */
+        double sa = share_inv_row(s->bh_cdf + (int64_t)ki * s->n_s, s->n_s, u32(r[3]));
+        double sb = share_inv_row(s->bh_cdf + (int64_t)(ki + 1) * s->n_s, s->n_s, u32(r[3]));
+        double sv = sa + kf * (sb - sa);
+        double lo = 1.0 / eps;
+        double xp = lo + sv * (1.0 - 2.0 * lo);
+        ep = xp * eps;
+        em = eps - ep;
+      }
+      s->st.pairs[conv]++;
+      s->st.e_pair[conv] += s->ph_w[q] * eps;
+      if (s->rcount < s->rcap) {
+        int64_t m = s->rcount;
+        for (int a = 0; a < 3; ++a) { s->pr_x[3 * m + a] = x[a]; s->pr_k[3 * m + a] = k[a]; }
+        s->pr_em[m] = em; s->pr_ep[m] = ep; s->pr_w[m] = s->ph_w[q];
+        s->pr_step[m] = n; s->pr_parent[m] = par; s->pr_pstep[m] = pst;
+        s->pr_proc[m] = pr | ((uint32_t)conv << 1);
+      } else {
+        s->st.pairs_overflow++;
+      }
+      s->rcount++;
+      s->gst[q] = 2;
+      continue;
+    }
+    int out = 0;
+    for (int a = 0; a < s->dims; ++a) {
+      x[a] = x[a] + k[a] * s->dt;
+      if (x[a] < 0.0 || x[a] >= s->L[a]) out = 1;
+    }
+    if (out) s->gst[q] = 3;
+  }
+}
+
 static void laser_scalars(const or_sim* s, uint64_t step, double* lsin, double* lcos) {
   double t = ((double)step + 0.5) * s->dt;
   double TL = s->c.duration_cycles * (2.0 * M_PI);
@@ -1019,6 +1230,7 @@ void or_step(or_sim* s, int nsteps) {
       if (out) s->alive[e] = 0; else ++live;
     }
     s->st.live = live;
+    if (s->c.flags & (OR_BW | OR_BH)) photon_step(s, tn, frozen);  /* E^n, B^n, n at x^n */
     if (!frozen) {
       double ls, lc;
       laser_scalars(s, s->step, &ls, &lc);
@@ -1072,6 +1284,48 @@ void or_get_photons(const or_sim* s, double* x, double* k, double* eps, double* 
 }
 
 void or_get_stats(const or_sim* s, or_stats* out) { *out = s->st; }
+
+/* Test hook: n photons appended as NCS records of the coming step (they
+ * start travelling one step later), with the caller's parent ids. */
+void or_add_photons(or_sim* s, int64_t n, const double* x, const double* k, const double* eps,
+                    const double* w, const uint32_t* parent) {
+  for (int64_t j = 0; j < n; ++j) {
+    if (s->pcount < s->pcap) {
+      int64_t q = s->pcount;
+      for (int a = 0; a < 3; ++a) { s->ph_x[3 * q + a] = x[3 * j + a]; s->ph_k[3 * q + a] = k[3 * j + a]; }
+      s->ph_e[q] = eps[j]; s->ph_w[q] = w[j];
+      s->ph_step[q] = (uint32_t)s->step; s->ph_parent[q] = parent[j]; s->ph_proc[q] = 0u;
+    }
+    s->pcount++;
+  }
+}
+
+/* Test hook: the photons' state in flight (positions, pair optical depths,
+ * states; min(count, capacity) of each). */
+void or_get_flight(const or_sim* s, double* x, double* tau, uint8_t* st) {
+  int64_t n = s->pcount < s->pcap ? s->pcount : s->pcap;
+  if (!s->gx || n <= 0) return;
+  memcpy(x, s->gx, sizeof(double) * 3 * (size_t)n);
+  memcpy(tau, s->gtau, sizeof(double) * (size_t)n);
+  memcpy(st, s->gst, (size_t)n);
+}
+
+int64_t or_num_pairs(const or_sim* s) { return s->rcount; }
+
+void or_get_pairs(const or_sim* s, double* x, double* k, double* e_minus, double* e_plus,
+                  double* w, uint32_t* step, uint32_t* parent, uint32_t* pstep, uint32_t* proc) {
+  int64_t n = s->rcount < s->rcap ? s->rcount : s->rcap;
+  if (n <= 0) return;
+  memcpy(x, s->pr_x, sizeof(double) * 3 * (size_t)n);
+  memcpy(k, s->pr_k, sizeof(double) * 3 * (size_t)n);
+  memcpy(e_minus, s->pr_em, sizeof(double) * (size_t)n);
+  memcpy(e_plus, s->pr_ep, sizeof(double) * (size_t)n);
+  memcpy(w, s->pr_w, sizeof(double) * (size_t)n);
+  memcpy(step, s->pr_step, 4 * (size_t)n);
+  memcpy(parent, s->pr_parent, 4 * (size_t)n);
+  memcpy(pstep, s->pr_pstep, 4 * (size_t)n);
+  memcpy(proc, s->pr_proc, 4 * (size_t)n);
+}
 
 int64_t or_num_ions(const or_sim* s) { return s->Ni; }
 

@@ -19,7 +19,11 @@
 /* OR_BREM_FREEPATH: bremsstrahlung by a per-electron free path (collision
  * optical depth) instead of a fresh Eq. (4) trial every step; the same
  * per-step event law, see electron_one. */
-enum { OR_NCS = 1, OR_BREM = 2, OR_FROZEN = 4, OR_NO_RECOIL = 16, OR_BREM_FREEPATH = 32 };
+/* OR_BW / OR_BH: recorded photons of at least 2 mc^2 travel on at c and may
+ * turn into an electron-positron pair, in the fields (Breit-Wheeler) or on a
+ * nucleus (Bethe-Heitler); see photon_step. */
+enum { OR_NCS = 1, OR_BREM = 2, OR_FROZEN = 4, OR_NO_RECOIL = 16, OR_BREM_FREEPATH = 32,
+       OR_BW = 64, OR_BH = 128 };
 enum { OR_FROZEN_UNIFORM = 0, OR_FROZEN_PLANE_WAVE = 1 };
 
 typedef struct {
@@ -37,6 +41,7 @@ typedef struct {
    * charge charge_state, mass ion_mass in electron masses */
   int32_t ion_ppc, envelope;          /* envelope: OR_ENV_SIN2 or OR_ENV_FLAT */
   double ion_mass;
+  uint64_t pair_capacity;             /* pair records held (OR_BW / OR_BH) */
 } or_config;
 enum { OR_ENV_SIN2 = 0, OR_ENV_FLAT = 1 };
 
@@ -47,12 +52,26 @@ typedef struct {
   int32_t n_T, n_y;
   double ln_T0, dln_T, k_cut;
   const double *sigma, *br_cdf;        /* n_T, n_T*n_y */
+  /* pair production (read only with OR_BW / OR_BH):
+   * Breit-Wheeler ln T(chi) on chi_i = exp(ln_chi0 + i dln_chi) and CDF rows
+   * of the electron share xi on the uniform grid j/(n_xp-1) of [0, 1];
+   * Bethe-Heitler sigma(k) in alpha r_e^2 on k_i = exp(ln_k0 + i dln_k) and
+   * CDF rows of the positron share on s = (x - 1/k)/(1 - 2/k), uniform grid */
+  int32_t n_chi, n_xp;
+  double ln_chi0, dln_chi;
+  const double *bw_lnT, *bw_cdf;       /* n_chi, n_chi*n_xp */
+  int32_t n_k, n_s;
+  double ln_k0, dln_k;
+  const double *bh_sigma, *bh_cdf;     /* n_k, n_k*n_s */
 } or_tables;
 
 typedef struct {
   uint64_t steps, live, events[2], kept[2], dropped_ncs, overflow, brem_clamped;
   double e_rad_kept[2], e_rad_dropped;
   uint64_t ions_live;
+  uint64_t pairs[2];                   /* [0] Breit-Wheeler, [1] Bethe-Heitler */
+  uint64_t pairs_overflow;             /* pairs not stored (buffer full) */
+  double e_pair[2];                    /* sum w eps of the converted photons */
 } or_stats;
 
 typedef struct or_sim or_sim;
@@ -74,6 +93,20 @@ void     or_get_photons(const or_sim* s, double* x, double* k, double* eps,
                         double* w, uint32_t* step, uint32_t* parent,
                         uint32_t* proc);
 void     or_get_stats(const or_sim* s, or_stats* out);
+/* pair records (min(count, capacity) of them): position, photon direction,
+ * electron and positron total energies (mc^2), weight, step, the photon's
+ * parent electron and emission step, and proc = photon process | 2 * pair
+ * process (0 Breit-Wheeler, 1 Bethe-Heitler) */
+int64_t  or_num_pairs(const or_sim* s);          /* may exceed capacity */
+/* test hooks: append photons as NCS records of the coming step (they start
+ * travelling a step later); read the state in flight (0 not started,
+ * 1 travelling, 2 converted, 3 left the box, 4 below 2 mc^2) */
+void     or_add_photons(or_sim* s, int64_t n, const double* x, const double* k,
+                        const double* eps, const double* w, const uint32_t* parent);
+void     or_get_flight(const or_sim* s, double* x, double* tau, uint8_t* st);
+void     or_get_pairs(const or_sim* s, double* x, double* k, double* e_minus,
+                      double* e_plus, double* w, uint32_t* step, uint32_t* parent,
+                      uint32_t* pstep, uint32_t* proc);
 double   or_kinetic_energy(const or_sim* s);
 double   or_field_energy(const or_sim* s);
 /* full field arrays incl. guard cells, component order Ex,Ey,Ez,Bx,By,Bz */

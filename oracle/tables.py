@@ -242,7 +242,142 @@ def build_brem(Z, k_cut_mc2=1.0):
                 k_cut=float(k_cut_mc2), Z=int(Z))
 
 
+# --- pair production (the channels the paper names beside its two) ---------
+# Breit-Wheeler, a photon of energy eps (mc^2) with quantum parameter chi
+# turning into a pair in the laser field (named in Sec. I and II.A as the
+# companion of NCS in the QED-PIC codes it builds on): with xi the electron's
+# share of eps and y = 2 / (3 chi xi (1 - xi)),
+#
+#     d2N/(dt dxi) = alpha m c^2 / (sqrt(3) pi hbar eps)
+#                    * [ int_y^inf K_{1/3}(t) dt + (xi/(1-xi) + (1-xi)/xi) K_{2/3}(y) ],
+#
+# so dN/dt = alpha (m c^2/hbar) (chi/eps) T(chi) with
+# T(chi) = 1/(sqrt(3) pi chi) int_0^1 [..] dxi.
+N_CHI, CHI_MIN, CHI_MAX = 128, 1e-2, 1e3
+N_XP = 128
+# Bethe-Heitler, a photon of energy k pair-converting on a nucleus ("similar
+# to the bremsstrahlung", Sec. II.B): Tsai's cross-section, the crossing of
+# Eq. (1), with x the positron's share of k and the screening variables at
+# E+ E- = x (1 - x) k^2:
+#
+#     dsigma/dx = alpha r_e^2 { [x^2 + (1-x)^2 + 2/3 x (1-x)] [Z^2 (phi1 - 4/3 ln Z - 4 f)
+#                               + Z (psi1 - 8/3 ln Z)]
+#                               - 2/3 x (1-x) [Z^2 (phi1 - phi2) + Z (psi1 - psi2)] },
+#
+# both pair members above rest (1/k < x < 1 - 1/k).
+N_K, K_MIN, K_MAX = 128, 2.0, 2.0e4
+N_S = 64
+
+
+def int_k13(y):
+    """int_y^inf K_{1/3}(t) dt for an array of y > 0 (0 where it underflows)."""
+    y = np.asarray(y, dtype=np.float64)
+    out = np.zeros_like(y)
+    ok = y < 700.0
+    yy = y[ok]
+    if yy.size == 0:
+        return out
+    smax = np.arccosh(np.maximum(60.0 / yy, 1.0)) + 2.0
+    npan = 24
+    edges = smax[:, None] * np.linspace(0.0, 1.0, npan + 1)[None, :]
+    s, w = _gl_nodes(edges[:, :-1], edges[:, 1:], _GL8)
+    ch = np.cosh(s)
+    f = np.exp(-yy[:, None, None] * ch) * np.cosh(s * (1.0 / 3.0)) / ch
+    out[ok] = np.sum(f * w, axis=(1, 2))
+    return out
+
+
+def bw_bracket(chi, xi):
+    """The square bracket of the Breit-Wheeler spectrum; xi in (0, 1)."""
+    xi = np.asarray(xi, dtype=np.float64)
+    y = 2.0 / (3.0 * chi * xi * (1.0 - xi))
+    big = y > 700.0
+    ys = np.where(big, 1.0, y)
+    val = int_k13(ys) + (xi / (1.0 - xi) + (1.0 - xi) / xi) * kv(2.0 / 3.0, ys)
+    return np.where(big, 0.0, val)
+
+
+def _bw_row(chi):
+    """Cumulative integral of the bracket over the xi grid, and T(chi)."""
+    xg = np.linspace(0.0, 1.0, N_XP)
+    f = lambda u: bw_bracket(chi, u)
+    # the bracket diverges like xi^(-1/3) at both ends: panels on a graded mesh
+    scale = np.sum(_gl_panel(f, xg[:-1], xg[1:]))
+    per = adaptive_integrals(f, xg[:-1], xg[1:], atol=1e-16 * max(scale, 1e-300))
+    cum = np.concatenate([[0.0], np.cumsum(per)])
+    T = cum[-1] / (math.sqrt(3.0) * math.pi * chi)
+    return cum, T
+
+
+def bw_T(chi):
+    return _bw_row(float(chi))[1]
+
+
+def build_bw():
+    """ln T on the chi grid and CDF rows of the electron share xi (uniform
+    grid on [0, 1], symmetric about 1/2)."""
+    ln_chi0 = math.log(CHI_MIN)
+    dln_chi = math.log(CHI_MAX / CHI_MIN) / (N_CHI - 1)
+    lnT = np.empty(N_CHI)
+    cdf = np.empty((N_CHI, N_XP))
+    for i in range(N_CHI):
+        chi = math.exp(ln_chi0 + i * dln_chi)
+        cum, T = _bw_row(chi)
+        lnT[i] = math.log(T)
+        c = cum / cum[-1]
+        c[-1] = 1.0
+        cdf[i] = c
+    return dict(n_chi=N_CHI, ln_chi0=ln_chi0, dln_chi=dln_chi, bw_lnT=lnT, n_xp=N_XP,
+                bw_cdf=cdf)
+
+
+def bh_dcs(x, k, Z, clamp=True):
+    """Curly bracket of the pair cross-section: dsigma/dx = alpha r_e^2 * B."""
+    x = np.asarray(x, dtype=np.float64)
+    q = x * (1.0 - x)
+    gs = 100.0 / (k * q * Z ** (1.0 / 3.0))
+    es = 100.0 / (k * q * Z ** (2.0 / 3.0))
+    phi1, phi2, psi1, psi2 = screening(gs, es)
+    lnZ = math.log(Z)
+    fz = coulomb_f(Z)
+    B = (x * x + (1.0 - x) ** 2 + 2.0 / 3.0 * q) * (Z * Z * (phi1 - 4.0 / 3.0 * lnZ - 4.0 * fz)
+                                                    + Z * (psi1 - 8.0 / 3.0 * lnZ)) \
+        - 2.0 / 3.0 * q * (Z * Z * (phi1 - phi2) + Z * (psi1 - psi2))
+    return np.maximum(B, 0.0) if clamp else B
+
+
+def build_bh(Z):
+    """sigma(k) in alpha r_e^2 on a ln k grid from 2 mc^2, and CDF rows of
+    the positron share on s = (x - 1/k) / (1 - 2/k), 64 points."""
+    ln_k0 = math.log(K_MIN)
+    dln_k = math.log(K_MAX / K_MIN) / (N_K - 1)
+    sig = np.zeros(N_K)
+    cdf = np.empty((N_K, N_S))
+    sgrid = np.arange(N_S) / (N_S - 1.0)
+    for i in range(N_K):
+        k = math.exp(ln_k0 + i * dln_k)
+        lo, hi = 1.0 / k, 1.0 - 1.0 / k
+        if not (hi > lo):
+            cdf[i] = sgrid
+            continue
+        xg = lo + sgrid * (hi - lo)
+        f = lambda u, k=k: bh_dcs(u, k, Z)
+        scale = np.sum(_gl_panel(f, xg[:-1], xg[1:]))
+        if not (scale > 0.0):
+            cdf[i] = sgrid
+            continue
+        per = adaptive_integrals(f, xg[:-1], xg[1:], atol=1e-16 * scale)
+        cum = np.concatenate([[0.0], np.cumsum(per)])
+        sig[i] = cum[-1]
+        c = cum / cum[-1]
+        c[-1] = 1.0
+        cdf[i] = c
+    return dict(n_k=N_K, ln_k0=ln_k0, dln_k=dln_k, bh_sigma=sig, n_s=N_S, bh_cdf=cdf)
+
+
 def build_tables(Z, k_cut_mc2=1.0):
     t = build_ncs()
     t.update(build_brem(Z, k_cut_mc2))
+    t.update(build_bw())
+    t.update(build_bh(Z))
     return t

@@ -77,6 +77,17 @@ MUTANTS = {
                             "deposit(s, s->ix + 3 * e, x1 + 3 * e, vv + 3 * e, s->iw);")],
     "ion_density_volume": [("for (int64_t m = 0; m < s->ncell_tot; ++m) s->ni[m] = (double)s->icount[m] * s->iwv;",
                             "for (int64_t m = 0; m < s->ncell_tot; ++m) s->ni[m] = (double)s->icount[m] * s->iw;")],
+    # pair production
+    "chi_cross_sign": [("  double cy = E[1] + (k[2] * B[0] - k[0] * B[2]);",
+                        "  double cy = E[1] - (k[2] * B[0] - k[0] * B[2]);")],
+    "bw_rate_alpha": [("const double K_P = 7.2973525693e-3 * s->E_S;", "const double K_P = s->E_S;")],
+    "bh_density_dropped": [("double X = s->K_BR * ni * sig * s->dt;\n          double P = -or_expm1(-X);\n          or_philox(par",
+                            "double X = s->K_BR * sig * s->dt;\n          double P = -or_expm1(-X);\n          or_philox(par")],
+    "bw_share_row_length": [("double xa = share_inv_row(s->bw_cdf + (int64_t)bi * s->n_xp, s->n_xp, u32(r[2]));",
+                             "double xa = share_inv_row(s->bw_cdf + (int64_t)bi * s->n_xp, s->n_s, u32(r[2]));"),
+                            ("double xb = share_inv_row(s->bw_cdf + (int64_t)(bi + 1) * s->n_xp, s->n_xp, u32(r[2]));",
+                             "double xb = share_inv_row(s->bw_cdf + (int64_t)(bi + 1) * s->n_xp, s->n_s, u32(r[2]));")],
+    "photon_move_sign": [("      x[a] = x[a] + k[a] * s->dt;", "      x[a] = x[a] - k[a] * s->dt;")],
     # constants
     "K_BR_factor": [("s->K_BR = s->n_c * (lam / twopi) * alpha * re * re;",
                      "s->K_BR = s->n_c * lam * alpha * re * re;")],

@@ -9,6 +9,7 @@ import mutants
 import test_oracle_pins_emission as PE
 import test_oracle_pins_fields as PF
 import test_oracle_pins_ions as PI
+import test_oracle_pins_pairs as PP
 
 # mutant -> the pin that must catch it
 CASES = [
@@ -39,6 +40,11 @@ CASES = [
     ("ion_mass_dropped", PI.check_two_fluid_plasma_frequency),
     ("ion_deposit_charge", PI.check_continuity_with_ions),
     ("ion_density_volume", PI.check_brem_with_counted_ion_density),
+    ("chi_cross_sign", PP.check_bw_conversion_law),
+    ("bw_rate_alpha", PP.check_bw_conversion_law),
+    ("bh_density_dropped", PP.check_bh_conversion_law),
+    ("bw_share_row_length", PP.check_pair_shares),
+    ("photon_move_sign", PP.check_pair_kinematics),
     ("K_BR_factor", PE.check_constants),
     ("E_S_factor", PE.check_constants),
 ]
