@@ -72,7 +72,7 @@ enum {
   PIC_FIELDS_FROZEN = 1u << 2, /* particle-only mode: prescribed fields, no field
                                   solve, no deposit (the benchmark mode of Sec. II.B) */
   PIC_NO_RECOIL = 1u << 4,     /* emit without changing the electron (tests only) */
-  PIC_BREM_FREEPATH = 1u << 5  /* with PIC_BREM: collision by free path.  Each electron
+  PIC_BREM_FREEPATH = 1u << 5, /* with PIC_BREM: collision by free path.  Each electron
                                   carries its collision optical depth (the mean free
                                   paths left to its next collision, -ln u at load and
                                   after each collision); a step uses up the exponent
@@ -83,7 +83,25 @@ enum {
                                   with the per-step form in distribution, not event
                                   by event.  8 more bytes per electron (16 when
                                   the electrons are re-sorted: two buffers). */
+  PIC_BW = 1u << 6,            /* photons in flight: Breit-Wheeler pairs in the fields */
+  PIC_BH = 1u << 7             /* photons in flight: Bethe-Heitler pairs on the nuclei */
 };
+/* Pair production (PIC_BW, PIC_BH; the channels the paper names beside NCS
+ * and bremsstrahlung, Sec. I, II.A and II.B, where Bethe-Heitler is "similar
+ * to the bremsstrahlung").  Every stored photon record of at least 2 mc^2
+ * travels on along its direction at c from the step after its emission:
+ *   Breit-Wheeler: a pair optical depth (-ln u at the start) used up at
+ *     dN/dt = alpha (m c^2/hbar) (chi/eps) T(chi), chi = eps |E_perp + k x B|
+ *     / E_S, ln T linear in ln chi between table points; converts when it
+ *     runs out;
+ *   Bethe-Heitler: the per-step trial of Eq. (4) with the pair
+ *     cross-section, P = 1 - exp(-n sigma_BH(eps) c dt), n as for the
+ *     bremsstrahlung;
+ *   the pair's energies from the inverse-CDF rows of the pair tables; the
+ *   pair is recorded (position, direction, electron and positron energies,
+ *   weight, step, the photon's parent and emission step, process), not
+ *   pushed; a photon that converts stops, the others are absorbed at the
+ *   walls.  Photons beyond the photon buffer's capacity are not followed. */
 enum { PIC_FROZEN_UNIFORM = 0, PIC_FROZEN_PLANE_WAVE = 1 };
 /* laser temporal envelope over [0, duration]: sin^2, or constant (the flat
    30 fs pulse of Sec. III) */
@@ -134,6 +152,7 @@ typedef struct {
                                depend on it) */
   int32_t ion_ppc;          /* mobile macro-ions per slab cell; 0 = static ions */
   double ion_mass_me;       /* ion mass in electron masses (>= 1; mobile ions only) */
+  uint64_t pair_capacity;   /* pair records the pair buffer holds (PIC_BW / PIC_BH) */
   uint32_t envelope;        /* PIC_ENV_SIN2 or PIC_ENV_FLAT */
   uint32_t reserved0;       /* must be 0 */
   void* stream;             /* hipStream_t of the HIP runtime libpic links
@@ -170,6 +189,33 @@ typedef struct {
                             0 = not checked.  A mismatch is PIC_ERR_TABLES. */
 } pic_tables;
 
+/* Pair-production tables (host arrays, copied by pic_load_pair_tables;
+ * required before pic_step when PIC_BW or PIC_BH is set).
+ * Breit-Wheeler: chi_i = exp(ln_chi0 + i dln_chi), i < n_chi; bw_lnT[i] =
+ *   ln T(chi_i) with T(chi) = (sqrt(3) pi chi)^-1 Int_0^1 [Int_y^inf K_{1/3}
+ *   + (xi/(1-xi) + (1-xi)/xi) K_{2/3}(y)] dxi, y = 2/(3 chi xi (1-xi));
+ *   bw_cdf[i*n_xp + j] = fraction of that integral below xi = j/(n_xp-1)
+ *   (the electron's share of the photon energy); rows 0 .. 1.
+ * Bethe-Heitler: k_i = exp(ln_k0 + i dln_k) photon energy in mc^2;
+ *   bh_sigma[i] = Int dsigma/dx over 1/k < x < 1 - 1/k in alpha r_e^2 (Tsai's
+ *   pair cross-section, the crossing of Eq. (1)); bh_cdf[i*n_s + j] =
+ *   fraction below the positron share x = 1/k + s (1 - 2/k), s = j/(n_s-1). */
+#define PIC_PAIR_TABLES_VERSION 1u
+typedef struct {
+  uint32_t version;          /* PIC_PAIR_TABLES_VERSION */
+  uint32_t Z;                /* must equal the config's Z */
+  int32_t n_chi, n_xp;       /* 128, 128 */
+  double ln_chi0, dln_chi;
+  const double* bw_lnT;      /* n_chi */
+  const double* bw_cdf;      /* n_chi * n_xp */
+  int32_t n_k, n_s;          /* 128, 64 */
+  double ln_k0, dln_k;
+  const double* bh_sigma;    /* n_k */
+  const double* bh_cdf;      /* n_k * n_s */
+  uint64_t checksum;         /* 64-bit FNV-1a of the bytes of bw_lnT, bw_cdf,
+                                bh_sigma and bh_cdf, in that order; 0 = not checked */
+} pic_pair_tables;
+
 /* Emission statistics.  Energies in mc^2 times the macro-particle weight
  * unit (n_c (c/w0)^dims).  Counts are exact; sums are FP64 with Neumaier
  * compensation per wave slot, reduced in a fixed order. */
@@ -191,6 +237,10 @@ typedef struct {
   double e_field;            /* (1/2) sum (E^2 + B^2) dV (snapshot) */
   uint64_t ions_live;        /* mobile ions inside the box (0 with static ions) */
   double e_kin_i;            /* sum w M (gamma - 1) over live mobile ions (snapshot) */
+  uint64_t pairs[2];         /* pairs created: [0] Breit-Wheeler, [1] Bethe-Heitler */
+  uint64_t pairs_stored;     /* pair records in the pair buffer */
+  uint64_t pairs_overflow;   /* pairs that did not fit the buffer */
+  double e_pair[2];          /* sum w eps of the photons that converted, per process */
 } pic_stats;
 
 /* ---- the five calls of the hot path ------------------------------------- */
@@ -325,6 +375,34 @@ pic_status pic_copy_photons(pic_ctx* ctx, uint64_t off, uint64_t n, double* x,
                             double* k, double* eps, double* w, uint32_t* step,
                             uint32_t* parent, uint32_t* proc);
 
+/* Pair production (PIC_BW / PIC_BH; PIC_ERR_STATE without them).
+ * pic_load_pair_tables: copy and check the pair tables (PIC_ERR_TABLES on a
+ *   wrong version, Z or size, a non-finite value, a row not rising from 0 to
+ *   exactly 1, or a checksum that does not match).
+ * pic_pair_counts: records in the pair buffer and pairs created so far.
+ * pic_copy_pairs: pair records [off, off+n): x[3n] position, k[3n] photon
+ *   direction, e_minus[n], e_plus[n] total energies (mc^2), w[n], step[n]
+ *   of the conversion, parent[n] and pstep[n] the photon's parent electron
+ *   and emission step, proc[n] = photon process | 2 * pair process
+ *   (0 Breit-Wheeler, 1 Bethe-Heitler); device append order.
+ * pic_copy_flight: the state in flight of photon records [off, off+n), in
+ *   record order: position x[3n], pair optical depth tau[n], state[n]
+ *   (0 not started, 1 travelling, 2 converted, 3 absorbed, 4 below 2 mc^2).
+ * pic_add_photons: for tests, append n photon records (NCS, emitted in the
+ *   coming step, so they start travelling one step later) with the
+ *   caller's positions, unit directions, energies, weights and parent ids
+ *   ((parent, step) must not repeat); PIC_ERR_OVERFLOW when the photon
+ *   buffer cannot take them all (nothing is added). */
+pic_status pic_load_pair_tables(pic_ctx* ctx, const pic_pair_tables* t);
+pic_status pic_pair_counts(pic_ctx* ctx, uint64_t* stored, uint64_t* created);
+pic_status pic_copy_pairs(pic_ctx* ctx, uint64_t off, uint64_t n, double* x, double* k,
+                          double* e_minus, double* e_plus, double* w, uint32_t* step,
+                          uint32_t* parent, uint32_t* pstep, uint32_t* proc);
+pic_status pic_copy_flight(pic_ctx* ctx, uint64_t off, uint64_t n, double* x, double* tau,
+                           uint8_t* state);
+pic_status pic_add_photons(pic_ctx* ctx, uint64_t n, const double* x, const double* k,
+                           const double* eps, const double* w, const uint32_t* parent);
+
 /* Size (elements per component, guard cells included) of the field arrays
  * and a copy of Ex,Ey,Ez,Bx,By,Bz (6*size doubles) in the library layout:
  * index (i+g) + sx*((j+g) + sy*(k+g)), g = 2 on active axes.  After n steps
@@ -345,6 +423,11 @@ pic_status pic_build_tables(uint32_t Z, double k_cut_mc2, int32_t nthreads,
                             double* h, double* ln_xi, double* ncs_cdf,
                             double* sigma, double* br_cdf, pic_tables* out);
 
+/* Build the pair-production tables the same way: caller arrays bw_lnT[128],
+ * bw_cdf[128*128], bh_sigma[128], bh_cdf[128*64]. */
+pic_status pic_build_pair_tables(uint32_t Z, int32_t nthreads, double* bw_lnT, double* bw_cdf,
+                                 double* bh_sigma, double* bh_cdf, pic_pair_tables* out);
+
 /* Device Philox4x32-10 of n counters (ctr[4n]) under one key (key[2]) into
  * out[4n]; host buffers.  Exposes the generator the step kernels use. */
 pic_status pic_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, uint64_t n);
@@ -364,11 +447,11 @@ pic_status pic_philox_noalloc(const uint32_t* ctr, const uint32_t* key, uint32_t
 /* Kernel timing with HIP events recorded on the context's stream around
  * every electron-step launch, every field-solve group and every tile sort
  * (enable != 0 starts a fresh accumulation).  pic_profile_read synchronises
- * and returns the summed milliseconds and launch counts in ms4/launches4:
+ * and returns the summed milliseconds and launch counts in ms5/launches5:
  * [0] electron step, [1] field solve, [2] sort, [3] mobile ions (density
- * pass and push). */
+ * pass and push), [4] photons in flight. */
 pic_status pic_profile(pic_ctx* ctx, int32_t enable);
-pic_status pic_profile_read(pic_ctx* ctx, double* ms4, uint64_t* launches4);
+pic_status pic_profile_read(pic_ctx* ctx, double* ms5, uint64_t* launches5);
 
 /* Derived constants of ctx: dx[3], dt, E_S, K_N, K_BR, n_c (8 doubles). */
 pic_status pic_derived(pic_ctx* ctx, double* out8);

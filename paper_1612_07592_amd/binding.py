@@ -17,6 +17,8 @@ PIC_ABI_VERSION = 2
 PIC_TABLES_VERSION = 2
 PIC_FP64, PIC_FP32_MIXED = 0, 1
 PIC_NCS, PIC_BREM, PIC_FIELDS_FROZEN, PIC_NO_RECOIL, PIC_BREM_FREEPATH = 1, 2, 4, 16, 32
+PIC_BW, PIC_BH = 64, 128
+PIC_PAIR_TABLES_VERSION = 1
 PIC_FROZEN_UNIFORM, PIC_FROZEN_PLANE_WAVE = 0, 1
 PIC_ENV_SIN2, PIC_ENV_FLAT = 0, 1
 STATUS = {0: "PIC_OK", 1: "PIC_ERR_INVALID", 2: "PIC_ERR_NOMEM", 3: "PIC_ERR_DEVICE",
@@ -31,7 +33,9 @@ EXPORTS = ["pic_create", "pic_load_tables", "pic_step", "pic_emission_stats", "p
            "pic_server_last_error", "pic_server_submit", "pic_server_run", "pic_server_poll",
            "pic_server_job_ctx", "pic_server_release", "pic_device_memory", "pic_synchronize",
            "pic_copy_brem_depth", "pic_set_brem_depth", "pic_get_buffers", "pic_philox_noalloc",
-           "pic_ion_count", "pic_copy_ions", "pic_set_ions"]
+           "pic_ion_count", "pic_copy_ions", "pic_set_ions", "pic_build_pair_tables",
+           "pic_load_pair_tables", "pic_pair_counts", "pic_copy_pairs", "pic_copy_flight",
+           "pic_add_photons"]
 
 
 class pic_config(C.Structure):
@@ -45,7 +49,7 @@ class pic_config(C.Structure):
                 ("photon_cut_mc2", C.c_double), ("frozen_E", C.c_double * 3),
                 ("frozen_B", C.c_double * 3), ("frozen_a", C.c_double),
                 ("photon_capacity", C.c_uint64), ("seed", C.c_uint64), ("job_id", C.c_uint64),
-                ("sort_every", C.c_int32), ("ion_ppc", C.c_int32), ("ion_mass_me", C.c_double),
+                ("sort_every", C.c_int32), ("ion_ppc", C.c_int32), ("ion_mass_me", C.c_double), ("pair_capacity", C.c_uint64),
                 ("envelope", C.c_uint32), ("reserved0", C.c_uint32), ("stream", C.c_void_p)]
 
 
@@ -67,7 +71,18 @@ class pic_stats(C.Structure):
                 ("untiled_steps", C.c_uint64),
                 ("e_rad_kept", C.c_double * 2), ("e_rad_dropped", C.c_double),
                 ("e_kin_e", C.c_double), ("e_field", C.c_double),
-                ("ions_live", C.c_uint64), ("e_kin_i", C.c_double)]
+                ("ions_live", C.c_uint64), ("e_kin_i", C.c_double),
+                ("pairs", C.c_uint64 * 2), ("pairs_stored", C.c_uint64),
+                ("pairs_overflow", C.c_uint64), ("e_pair", C.c_double * 2)]
+
+
+class pic_pair_tables(C.Structure):
+    _fields_ = [("version", C.c_uint32), ("Z", C.c_uint32), ("n_chi", C.c_int32),
+                ("n_xp", C.c_int32), ("ln_chi0", C.c_double), ("dln_chi", C.c_double),
+                ("bw_lnT", C.POINTER(C.c_double)), ("bw_cdf", C.POINTER(C.c_double)),
+                ("n_k", C.c_int32), ("n_s", C.c_int32), ("ln_k0", C.c_double),
+                ("dln_k", C.c_double), ("bh_sigma", C.POINTER(C.c_double)),
+                ("bh_cdf", C.POINTER(C.c_double)), ("checksum", C.c_uint64)]
 
 
 class pic_server_config(C.Structure):
@@ -130,6 +145,12 @@ def load() -> C.CDLL:
     L.pic_philox_noalloc.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, u64]
     L.pic_derived.argtypes = [P, C.c_void_p]
     L.pic_ion_count.argtypes = [P, C.POINTER(u64)]
+    L.pic_build_pair_tables.argtypes = [u32, i32] + [C.c_void_p] * 4 + [C.POINTER(pic_pair_tables)]
+    L.pic_load_pair_tables.argtypes = [P, C.POINTER(pic_pair_tables)]
+    L.pic_pair_counts.argtypes = [P, C.POINTER(u64), C.POINTER(u64)]
+    L.pic_copy_pairs.argtypes = [P, u64, u64] + [C.c_void_p] * 9
+    L.pic_copy_flight.argtypes = [P, u64, u64] + [C.c_void_p] * 3
+    L.pic_add_photons.argtypes = [P, u64] + [C.c_void_p] * 5
     L.pic_copy_ions.argtypes = [P, C.c_void_p, C.c_void_p, C.c_void_p]
     L.pic_set_ions.argtypes = [P, C.c_void_p, C.c_void_p]
     L.pic_copy_current.argtypes = [P, C.c_void_p]
@@ -185,6 +206,8 @@ def config_from(w: dict, stream=None) -> pic_config:
     f |= PIC_FIELDS_FROZEN if w.get("frozen", False) else 0
     f |= PIC_NO_RECOIL if w.get("no_recoil", False) else 0
     f |= PIC_BREM_FREEPATH if w.get("brem_freepath", False) else 0
+    f |= PIC_BW if w.get("bw", False) else 0
+    f |= PIC_BH if w.get("bh", False) else 0
     c.flags = f
     n = list(w["n"]) + [1] * (3 - len(w["n"]))
     dx = list(w["dx_lambda"]) + [1.0] * (3 - len(w["dx_lambda"]))
@@ -217,6 +240,7 @@ def config_from(w: dict, stream=None) -> pic_config:
     c.sort_every = int(w.get("sort_every", 0))
     c.ion_ppc = int(w.get("ion_ppc", 0))
     c.ion_mass_me = float(w.get("ion_mass_me", 0.0))
+    c.pair_capacity = int(w.get("pair_capacity", 1 << 16))
     c.envelope = PIC_ENV_FLAT if w.get("envelope", "sin2") == "flat" else PIC_ENV_SIN2
     c.stream = stream
     return c
@@ -239,6 +263,39 @@ def tables_struct(t: dict):
         setattr(s, name, a.ctypes.data_as(C.POINTER(C.c_double)))
     s.checksum = int(t.get("checksum", 0))
     return s, keep
+
+
+def pair_tables_struct(t: dict):
+    """pic_pair_tables pointing at the pair arrays of a table dict; (struct, keepalive)."""
+    s = pic_pair_tables()
+    s.version = PIC_PAIR_TABLES_VERSION
+    s.Z = int(t["Z"])
+    s.n_chi, s.n_xp = int(t["n_chi"]), int(t["n_xp"])
+    s.ln_chi0, s.dln_chi = float(t["ln_chi0"]), float(t["dln_chi"])
+    s.n_k, s.n_s = int(t["n_k"]), int(t["n_s"])
+    s.ln_k0, s.dln_k = float(t["ln_k0"]), float(t["dln_k"])
+    keep = []
+    for name in ("bw_lnT", "bw_cdf", "bh_sigma", "bh_cdf"):
+        a = np.ascontiguousarray(t[name], dtype=np.float64)
+        keep.append(a)
+        setattr(s, name, a.ctypes.data_as(C.POINTER(C.c_double)))
+    s.checksum = int(t.get("pair_checksum", 0))
+    return s, keep
+
+
+def pic_build_pair_tables(Z: int, nthreads: int = 0) -> dict:
+    """The library's own pair-production tables as a dict of numpy arrays
+    (merge into the emission-table dict for runs with PIC_BW / PIC_BH)."""
+    L = load()
+    bwT = np.zeros(128); bwC = np.zeros(128 * 128); bhS = np.zeros(128); bhC = np.zeros(128 * 64)
+    out = pic_pair_tables()
+    _check("pic_build_pair_tables", L.pic_build_pair_tables(int(Z), int(nthreads), bwT.ctypes.data,
+                                                            bwC.ctypes.data, bhS.ctypes.data,
+                                                            bhC.ctypes.data, C.byref(out)))
+    return dict(Z=int(Z), n_chi=out.n_chi, n_xp=out.n_xp, ln_chi0=out.ln_chi0, dln_chi=out.dln_chi,
+                bw_lnT=bwT, bw_cdf=bwC.reshape(128, 128), n_k=out.n_k, n_s=out.n_s,
+                ln_k0=out.ln_k0, dln_k=out.dln_k, bh_sigma=bhS, bh_cdf=bhC.reshape(128, 64),
+                pair_checksum=int(out.checksum))
 
 
 def pic_build_tables(Z: int, k_cut_mc2: float = 1.0, nthreads: int = 0) -> dict:
@@ -294,7 +351,9 @@ def stats_dict(s: pic_stats, code: int = 0) -> dict:
                 untiled_steps=s.untiled_steps,
                 e_rad_kept=[s.e_rad_kept[0], s.e_rad_kept[1]],
                 e_rad_dropped=s.e_rad_dropped, e_kin_e=s.e_kin_e, e_field=s.e_field,
-                ions_live=s.ions_live, e_kin_i=s.e_kin_i, status=STATUS.get(code, code))
+                ions_live=s.ions_live, e_kin_i=s.e_kin_i, pairs=[s.pairs[0], s.pairs[1]],
+                pairs_stored=s.pairs_stored, pairs_overflow=s.pairs_overflow,
+                e_pair=[s.e_pair[0], s.e_pair[1]], status=STATUS.get(code, code))
 
 
 def pic_device_memory():
@@ -345,8 +404,56 @@ class Sim:
 
     # --- the five calls ---------------------------------------------------
     def pic_load_tables(self, tables: dict):
+        """Emission tables; with PIC_BW / PIC_BH also the pair tables of the
+        same dict (pic_load_pair_tables)."""
         s, keep = tables_struct(tables)
         _check("pic_load_tables", self._L.pic_load_tables(self._h, C.byref(s)), self._h)
+        if (self.workload.get("bw") or self.workload.get("bh")) and "bw_lnT" in tables:
+            self.pic_load_pair_tables(tables)
+
+    def pic_load_pair_tables(self, tables: dict):
+        s, keep = pair_tables_struct(tables)
+        _check("pic_load_pair_tables", self._L.pic_load_pair_tables(self._h, C.byref(s)), self._h)
+
+    def pair_counts(self):
+        st, cr = C.c_uint64(), C.c_uint64()
+        _check("pic_pair_counts", self._L.pic_pair_counts(self._h, C.byref(st), C.byref(cr)), self._h)
+        return int(st.value), int(cr.value)
+
+    def pairs(self) -> dict:
+        """Pair records (device append order)."""
+        n, _ = self.pair_counts()
+        x = np.zeros((n, 3)); k = np.zeros((n, 3)); em = np.zeros(n); ep = np.zeros(n)
+        w = np.zeros(n)
+        st, par, pst, pr = (np.zeros(n, dtype=np.uint32) for _ in range(4))
+        if n:
+            _check("pic_copy_pairs", self._L.pic_copy_pairs(
+                self._h, 0, n, x.ctypes.data, k.ctypes.data, em.ctypes.data, ep.ctypes.data,
+                w.ctypes.data, st.ctypes.data, par.ctypes.data, pst.ctypes.data, pr.ctypes.data),
+                self._h)
+        return dict(x=x, k=k, e_minus=em, e_plus=ep, w=w, step=st, parent=par, pstep=pst, proc=pr)
+
+    def flight(self) -> dict:
+        """State in flight of the stored photon records (record order)."""
+        _, n, _ = self.counts()
+        x = np.zeros((n, 3)); tau = np.zeros(n); state = np.zeros(n, dtype=np.uint8)
+        if n:
+            _check("pic_copy_flight", self._L.pic_copy_flight(self._h, 0, n, x.ctypes.data,
+                                                              tau.ctypes.data, state.ctypes.data),
+                   self._h)
+        return dict(x=x, tau=tau, state=state)
+
+    def add_photons(self, x, k, eps, w, parent):
+        """Append photon records of the coming step (test hook)."""
+        x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 3)
+        n = x.shape[0]
+        k = np.ascontiguousarray(k, dtype=np.float64).reshape(n, 3)
+        eps = np.ascontiguousarray(eps, dtype=np.float64).reshape(n)
+        w = np.ascontiguousarray(w, dtype=np.float64).reshape(n)
+        parent = np.ascontiguousarray(parent, dtype=np.uint32).reshape(n)
+        _check("pic_add_photons", self._L.pic_add_photons(self._h, n, x.ctypes.data, k.ctypes.data,
+                                                          eps.ctypes.data, w.ctypes.data,
+                                                          parent.ctypes.data), self._h)
 
     def pic_step(self, n: int = 1):
         _check("pic_step", self._L.pic_step(self._h, int(n)), self._h)
@@ -457,9 +564,9 @@ class Sim:
         _check("pic_profile", self._L.pic_profile(self._h, 1 if enable else 0), self._h)
 
     def profile_read(self):
-        """ms and launch counts: [electron step, field solve, sort, ions]."""
-        ms = np.zeros(4)
-        n = np.zeros(4, dtype=np.uint64)
+        """ms and launch counts: [electron step, field solve, sort, ions, photons]."""
+        ms = np.zeros(5)
+        n = np.zeros(5, dtype=np.uint64)
         _check("pic_profile_read", self._L.pic_profile_read(self._h, ms.ctypes.data, n.ctypes.data), self._h)
         return ms, n
 

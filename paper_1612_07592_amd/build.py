@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 OUT = os.path.join(HERE, "libpic.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["step.hip", "ions.hip", "fields.hip", "sort.hip", "api.hip", "serve.hip", "tables.cpp"]
+SOURCES = ["step.hip", "ions.hip", "photons.hip", "fields.hip", "sort.hip", "api.hip", "serve.hip", "tables.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

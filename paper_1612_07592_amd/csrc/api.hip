@@ -76,7 +76,8 @@ std::string derive(const pic_config& cfg, Ctx& c) {
   if (cfg.abi_version != PIC_ABI_VERSION) return "abi_version mismatch";
   if (cfg.dims < 1 || cfg.dims > 3) return "dims must be 1, 2 or 3";
   if (cfg.precision != PIC_FP64 && cfg.precision != PIC_FP32_MIXED) return "unknown precision";
-  if (cfg.flags & ~(uint32_t)(PIC_NCS | PIC_BREM | PIC_FIELDS_FROZEN | PIC_NO_RECOIL | PIC_BREM_FREEPATH))
+  if (cfg.flags & ~(uint32_t)(PIC_NCS | PIC_BREM | PIC_FIELDS_FROZEN | PIC_NO_RECOIL | PIC_BREM_FREEPATH |
+                              PIC_BW | PIC_BH))
     return "unknown flag bits";
   if ((cfg.flags & PIC_BREM_FREEPATH) && !(cfg.flags & PIC_BREM)) return "PIC_BREM_FREEPATH needs PIC_BREM";
   if (cfg.ppc < 1) return "ppc must be >= 1";
@@ -95,6 +96,7 @@ std::string derive(const pic_config& cfg, Ctx& c) {
     if (!is_fin(cfg.frozen_E[a]) || !is_fin(cfg.frozen_B[a])) return "non-finite frozen field";
   if (cfg.frozen_kind > PIC_FROZEN_PLANE_WAVE) return "unknown frozen_kind";
   if (cfg.photon_capacity > (1ull << 40)) return "photon_capacity too large";
+  if (cfg.pair_capacity > (1ull << 36)) return "pair_capacity too large";
   if (cfg.envelope > PIC_ENV_FLAT) return "unknown envelope";
   if (cfg.ion_ppc < 0 || cfg.ion_ppc > 4096) return "ion_ppc must be in [0, 4096]";
   if (cfg.ion_ppc > 0 && !(cfg.ion_mass_me >= 1.0 && is_fin(cfg.ion_mass_me)))
@@ -164,6 +166,7 @@ std::string derive(const pic_config& cfg, Ctx& c) {
   c.iw = cfg.ion_ppc > 0 ? (cfg.ne_over_nc / (double)cfg.charge_state) * V / (double)cfg.ion_ppc : 0.0;
   c.fp32 = cfg.precision == PIC_FP32_MIXED;
   c.pcap = cfg.photon_capacity;
+  c.rcap = (cfg.flags & (PIC_BW | PIC_BH)) ? cfg.pair_capacity : 0;
   const int64_t per_chunk = chunk_electrons(c.fp32, g.dims);
   c.nblocks_step = ((N + per_chunk - 1) / per_chunk + kGridQuantum - 1) / kGridQuantum * kGridQuantum;
   c.nslots = c.nblocks_step * (kBlock / 64);
@@ -296,6 +299,27 @@ Plan make_plan(Ctx& c) {
   P.add((void**)&c.pproc, pc * 4);
   P.add((void**)&c.pcount, 8);
   P.add((void**)&c.pfull, 4);   // a line of its own: read by every chunk, written once
+  if (c.cfg.flags & (PIC_BW | PIC_BH)) {  // photons in flight, pair records
+    for (int a = 0; a < 3; ++a) P.add(&c.gx[a], pc * rs);
+    P.add((void**)&c.gtau, pc * 8);
+    P.add((void**)&c.gst, pc);
+    const size_t rc = (size_t)(c.rcap > 0 ? c.rcap : 1);
+    for (int a = 0; a < 3; ++a) {
+      P.add(&c.rx[a], rc * rs);
+      P.add(&c.rk[a], rc * rs);
+    }
+    P.add(&c.rem, rc * rs);
+    P.add(&c.rep, rc * rs);
+    P.add((void**)&c.rw, rc * 8);
+    P.add((void**)&c.rstep, rc * 4);
+    P.add((void**)&c.rpar, rc * 4);
+    P.add((void**)&c.rpst, rc * 4);
+    P.add((void**)&c.rproc, rc * 4);
+    P.add((void**)&c.rcount, 8);
+    P.add((void**)&c.rfull, 4);
+    P.add((void**)&c.rev, 16);
+    P.add((void**)&c.resum, 16);
+  }
   const size_t nsl = (size_t)(c.nslots > 0 ? c.nslots : 1);
   P.add((void**)&c.slot_cnt, nsl * kSlotCnt * 8);
   P.add((void**)&c.slot_sum, nsl * kSlotSum * 8);
@@ -508,6 +532,8 @@ pic_status step_ready(Ctx& c, int32_t nsteps) {
   if (nsteps < 0) FAIL(c, PIC_ERR_INVALID, "nsteps < 0");
   if ((c.cfg.flags & (PIC_NCS | PIC_BREM)) && !c.tables_loaded)
     FAIL(c, PIC_ERR_STATE, "emission enabled but no tables loaded");
+  if ((c.cfg.flags & (PIC_BW | PIC_BH)) && !c.pair_tables_loaded)
+    FAIL(c, PIC_ERR_STATE, "pair production enabled but no pair tables loaded");
   if (c.step + (uint64_t)nsteps >= 0xFFFFFFFFull) FAIL(c, PIC_ERR_INVALID, "step counter exhausted");
   return PIC_OK;
 }
@@ -560,7 +586,7 @@ namespace {
 
 struct BatchLaunch {
   int kind;          // 0 sort, 1 both B half steps + clear J, 2 electron step, 4 E step,
-                     // 5 ion density, 6 ion step (one run each)
+                     // 5 ion density, 6 ion step, 7 photons in flight (one run each)
   int dims = 0;
   bool fp32 = false;
   size_t tab = 0, first = 0;
@@ -569,6 +595,7 @@ struct BatchLaunch {
   int lds_nodes = 0;
   SortArgs sort{};
   IonArgs ion{};
+  PhotonArgs ph{};
   hipStream_t stream = nullptr;
 };
 
@@ -803,6 +830,65 @@ pic_status pic_load_tables(pic_ctx* ctx, const pic_tables* t) {
   return PIC_OK;
 }
 
+pic_status pic_load_pair_tables(pic_ctx* ctx, const pic_pair_tables* t) {
+  pic_status st = check_ctx(ctx);
+  if (st) return st;
+  Ctx& c = ctx->c;
+  if (!(c.cfg.flags & (PIC_BW | PIC_BH))) FAIL(c, PIC_ERR_STATE, "run has no pair production");
+  if (!t) FAIL(c, PIC_ERR_INVALID, "null tables");
+  if (t->version != PIC_PAIR_TABLES_VERSION)
+    FAIL(c, PIC_ERR_TABLES, "pair tables version %u != %u", t->version, PIC_PAIR_TABLES_VERSION);
+  if (t->Z != c.cfg.Z) FAIL(c, PIC_ERR_TABLES, "pair tables built for Z=%u, config has Z=%u", t->Z, c.cfg.Z);
+  if (t->n_chi != 128 || t->n_xp != 128 || t->n_k != 128 || t->n_s != 64)
+    FAIL(c, PIC_ERR_TABLES, "pair table sizes must be 128x128 (Breit-Wheeler) and 128x64 (Bethe-Heitler)");
+  if (!t->bw_lnT || !t->bw_cdf || !t->bh_sigma || !t->bh_cdf) FAIL(c, PIC_ERR_TABLES, "null table array");
+  if (!(t->dln_chi > 0.0) || !(t->dln_k > 0.0) || !is_fin(t->ln_chi0) || !is_fin(t->ln_k0))
+    FAIL(c, PIC_ERR_TABLES, "bad pair table grid");
+  for (int i = 0; i < t->n_chi; ++i)
+    if (!is_fin(t->bw_lnT[i])) FAIL(c, PIC_ERR_TABLES, "bw_lnT[%d] not finite", i);
+  for (int i = 0; i < t->n_k; ++i)
+    if (!(t->bh_sigma[i] >= 0.0) || !is_fin(t->bh_sigma[i])) FAIL(c, PIC_ERR_TABLES, "bh_sigma[%d] invalid", i);
+  auto rows_ok = [](const double* C, int nrow, int n) {
+    for (int i = 0; i < nrow; ++i) {
+      const double* r = C + (size_t)i * n;
+      if (r[0] != 0.0 || r[n - 1] != 1.0) return false;
+      for (int j = 1; j < n; ++j)
+        if (!(r[j] >= r[j - 1]) || !std::isfinite(r[j])) return false;
+    }
+    return true;
+  };
+  if (!rows_ok(t->bw_cdf, t->n_chi, t->n_xp) || !rows_ok(t->bh_cdf, t->n_k, t->n_s))
+    FAIL(c, PIC_ERR_TABLES, "pair CDF rows must rise from 0 to exactly 1");
+  if (t->checksum != 0 && pair_tables_checksum(*t) != t->checksum)
+    FAIL(c, PIC_ERR_TABLES, "pair table checksum mismatch (arrays altered after they were built)");
+  DevTables& d = c.t;
+  auto upload = [&](double** dd, float** df, const double* src, size_t n) -> hipError_t {
+    if (!*dd) {
+      hipError_t e = hipMalloc((void**)dd, n * 8);
+      if (e != hipSuccess) return e;
+      c.allocs.push_back(*dd);
+      e = hipMalloc((void**)df, n * 4);
+      if (e != hipSuccess) return e;
+      c.allocs.push_back(*df);
+    }
+    std::vector<float> f(n);
+    for (size_t i = 0; i < n; ++i) f[i] = (float)src[i];
+    hipError_t e = hipMemcpy(*dd, src, n * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(*df, f.data(), n * 4, hipMemcpyHostToDevice);
+    return e;
+  };
+  HIPCHK(c, hipStreamSynchronize(c.stream));
+  HIPCHK(c, upload(&d.bwT, &d.bwTf, t->bw_lnT, t->n_chi));
+  HIPCHK(c, upload(&d.bwC, &d.bwCf, t->bw_cdf, (size_t)t->n_chi * t->n_xp));
+  HIPCHK(c, upload(&d.bhS, &d.bhSf, t->bh_sigma, t->n_k));
+  HIPCHK(c, upload(&d.bhC, &d.bhCf, t->bh_cdf, (size_t)t->n_k * t->n_s));
+  d.n_chi = t->n_chi; d.n_xp = t->n_xp; d.n_k = t->n_k; d.n_s = t->n_s;
+  d.ln_chi0 = t->ln_chi0; d.idln_chi = 1.0 / t->dln_chi;
+  d.ln_k0 = t->ln_k0; d.idln_k = 1.0 / t->dln_k;
+  c.pair_tables_loaded = true;
+  return PIC_OK;
+}
+
 pic_status pic_step(pic_ctx* ctx, int32_t nsteps) {
   pic_status st = check_ctx(ctx);
   if (st) return st;
@@ -851,6 +937,13 @@ pic_status pic_step(pic_ctx* ctx, int32_t nsteps) {
       launch_ion_step(IA, c.stream);
       mark(3);
     }
+    if (c.cfg.flags & (PIC_BW | PIC_BH)) {     // photons in flight: E^n, B^n, n at x^n
+      mark(4);
+      PhotonArgs PA{};
+      fill_photon_args(c, PA);
+      launch_photon_step(PA, c.fp32, c.stream);
+      mark(4);
+    }
     mark(1);
     if (!frozen) {
       double ls, lc;
@@ -871,10 +964,16 @@ pic_status pic_emission_stats(pic_ctx* ctx, pic_stats* out) {
   if (!out) FAIL(c, PIC_ERR_INVALID, "null output");
   unsigned long long cnt[kRedCnt];
   double sum[kRedSum];
-  unsigned long long pcount = 0;
+  unsigned long long pcount = 0, rcount = 0, rev[2] = {0, 0};
+  double resum[2] = {0.0, 0.0};
   launch_stats_reduce(c, cnt, sum, c.stream);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipMemcpyAsync(&pcount, c.pcount, 8, hipMemcpyDeviceToHost, c.stream));
+  if (c.rcount) {
+    HIPCHK(c, hipMemcpyAsync(&rcount, c.rcount, 8, hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(c, hipMemcpyAsync(rev, c.rev, 16, hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(c, hipMemcpyAsync(resum, c.resum, 16, hipMemcpyDeviceToHost, c.stream));
+  }
   HIPCHK(c, hipStreamSynchronize(c.stream));
   pic_stats s{};
   s.steps = c.step;
@@ -898,6 +997,12 @@ pic_status pic_emission_stats(pic_ctx* ctx, pic_stats* out) {
   s.e_field = 0.5 * sum[4] * (1.0 / c.g.invV);
   s.ions_live = cnt[kSlotCnt + 1];
   s.e_kin_i = sum[5];
+  s.pairs[0] = rev[0];
+  s.pairs[1] = rev[1];
+  s.pairs_stored = rcount < c.rcap ? rcount : c.rcap;
+  s.pairs_overflow = rev[0] + rev[1] - s.pairs_stored;
+  s.e_pair[0] = resum[0];
+  s.e_pair[1] = resum[1];
   *out = s;
   return s.overflow ? PIC_ERR_OVERFLOW : PIC_OK;
 }
@@ -1013,6 +1118,14 @@ pic_status pic_step_many(pic_batch* b, pic_ctx* const* ctxs, const int32_t* nste
       stage_step_group<double>(st, L, act, d);
     }
     for (const BatchLaunch& l : ion_steps) L.push_back(l);
+    for (Ctx* c : act)
+      if (c->cfg.flags & (PIC_BW | PIC_BH)) {
+        BatchLaunch l{};
+        fill_photon_args(*c, l.ph);
+        l.kind = 7;
+        l.fp32 = c->fp32;
+        L.push_back(l);
+      }
     for (int f = 0; f < 2; ++f)
       if (have_f[f]) { BatchLaunch l = fl[f]; l.kind = 4; L.push_back(l); }
     for (Ctx* c : act) {
@@ -1067,6 +1180,7 @@ pic_status pic_step_many(pic_batch* b, pic_ctx* const* ctxs, const int32_t* nste
       case 0: launch_sort(l.sort, l.fp32, b->stream); break;
       case 5: launch_ion_density(l.ion, b->stream); break;
       case 6: launch_ion_step(l.ion, b->stream); break;
+      case 7: launch_photon_step(l.ph, l.fp32, b->stream); break;
       case 1:
         launch_b_both_batch(l.fp32, (const FieldJob*)(D + l.tab), (const uint32_t*)(D + l.first),
                             l.njobs, l.total, b->stream);
@@ -1331,6 +1445,133 @@ pic_status pic_set_ions(pic_ctx* ctx, const double* x, const double* p) {
   return PIC_OK;
 }
 
+pic_status pic_pair_counts(pic_ctx* ctx, uint64_t* stored, uint64_t* created) {
+  pic_status st = check_ctx(ctx);
+  if (st) return st;
+  Ctx& c = ctx->c;
+  if (!c.rcount) FAIL(c, PIC_ERR_STATE, "run has no pair production");
+  unsigned long long rc = 0, ev[2] = {0, 0};
+  HIPCHK(c, hipMemcpyAsync(&rc, c.rcount, 8, hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(c, hipMemcpyAsync(ev, c.rev, 16, hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(c, hipStreamSynchronize(c.stream));
+  if (stored) *stored = rc < c.rcap ? rc : c.rcap;
+  if (created) *created = ev[0] + ev[1];
+  return PIC_OK;
+}
+
+pic_status pic_copy_pairs(pic_ctx* ctx, uint64_t off, uint64_t n, double* x, double* k,
+                          double* e_minus, double* e_plus, double* w, uint32_t* step,
+                          uint32_t* parent, uint32_t* pstep, uint32_t* proc) {
+  pic_status st = check_ctx(ctx);
+  if (st) return st;
+  Ctx& c = ctx->c;
+  uint64_t stored = 0;
+  if ((st = pic_pair_counts(ctx, &stored, nullptr))) return st;
+  if (off > stored || n > stored - off) FAIL(c, PIC_ERR_INVALID, "pair range beyond the stored records");
+  if (!n) return PIC_OK;
+  std::vector<double> v;
+  for (int a = 0; a < 3; ++a) {
+    if (x) {
+      if ((st = copy_any(c, (const char*)c.rx[a] + off * real_size(c.cfg), n, v))) return st;
+      for (uint64_t i = 0; i < n; ++i) x[3 * i + a] = v[i];
+    }
+    if (k) {
+      if ((st = copy_any(c, (const char*)c.rk[a] + off * real_size(c.cfg), n, v))) return st;
+      for (uint64_t i = 0; i < n; ++i) k[3 * i + a] = v[i];
+    }
+  }
+  if (e_minus) {
+    if ((st = copy_any(c, (const char*)c.rem + off * real_size(c.cfg), n, v))) return st;
+    std::copy(v.begin(), v.end(), e_minus);
+  }
+  if (e_plus) {
+    if ((st = copy_any(c, (const char*)c.rep + off * real_size(c.cfg), n, v))) return st;
+    std::copy(v.begin(), v.end(), e_plus);
+  }
+  if (w) HIPCHK(c, hipMemcpyAsync(w, c.rw + off, n * 8, hipMemcpyDeviceToHost, c.stream));
+  if (step) HIPCHK(c, hipMemcpyAsync(step, c.rstep + off, n * 4, hipMemcpyDeviceToHost, c.stream));
+  if (parent) HIPCHK(c, hipMemcpyAsync(parent, c.rpar + off, n * 4, hipMemcpyDeviceToHost, c.stream));
+  if (pstep) HIPCHK(c, hipMemcpyAsync(pstep, c.rpst + off, n * 4, hipMemcpyDeviceToHost, c.stream));
+  if (proc) HIPCHK(c, hipMemcpyAsync(proc, c.rproc + off, n * 4, hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(c, hipStreamSynchronize(c.stream));
+  return PIC_OK;
+}
+
+pic_status pic_copy_flight(pic_ctx* ctx, uint64_t off, uint64_t n, double* x, double* tau,
+                           uint8_t* state) {
+  pic_status st = check_ctx(ctx);
+  if (st) return st;
+  Ctx& c = ctx->c;
+  if (!c.gst) FAIL(c, PIC_ERR_STATE, "run has no pair production");
+  unsigned long long pc = 0;
+  HIPCHK(c, hipMemcpyAsync(&pc, c.pcount, 8, hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(c, hipStreamSynchronize(c.stream));
+  const uint64_t stored = pc < c.pcap ? pc : c.pcap;
+  if (off > stored || n > stored - off) FAIL(c, PIC_ERR_INVALID, "photon range beyond the stored records");
+  if (!n) return PIC_OK;
+  std::vector<double> v;
+  if (x)
+    for (int a = 0; a < 3; ++a) {
+      if ((st = copy_any(c, (const char*)c.gx[a] + off * real_size(c.cfg), n, v))) return st;
+      for (uint64_t i = 0; i < n; ++i) x[3 * i + a] = v[i];
+    }
+  if (tau) HIPCHK(c, hipMemcpyAsync(tau, c.gtau + off, n * 8, hipMemcpyDeviceToHost, c.stream));
+  if (state) HIPCHK(c, hipMemcpyAsync(state, c.gst + off, n, hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(c, hipStreamSynchronize(c.stream));
+  return PIC_OK;
+}
+
+pic_status pic_add_photons(pic_ctx* ctx, uint64_t n, const double* x, const double* k,
+                           const double* eps, const double* w, const uint32_t* parent) {
+  pic_status st = check_ctx(ctx);
+  if (st) return st;
+  Ctx& c = ctx->c;
+  if (!c.gst) FAIL(c, PIC_ERR_STATE, "run has no pair production");
+  if (n && (!x || !k || !eps || !w || !parent)) FAIL(c, PIC_ERR_INVALID, "null argument");
+  for (uint64_t i = 0; i < n; ++i) {
+    for (int a = 0; a < 3; ++a)
+      if (!is_fin(x[3 * i + a]) || !is_fin(k[3 * i + a])) FAIL(c, PIC_ERR_INVALID, "non-finite photon");
+    if (!(eps[i] > 0.0) || !is_fin(eps[i]) || !is_fin(w[i])) FAIL(c, PIC_ERR_INVALID, "bad photon energy or weight");
+    for (int a = 0; a < c.g.dims; ++a)
+      if (!(x[3 * i + a] >= 0.0 && x[3 * i + a] < c.g.L[a]))
+        FAIL(c, PIC_ERR_INVALID, "photon %llu outside the box", (unsigned long long)i);
+  }
+  unsigned long long pc = 0;
+  HIPCHK(c, hipMemcpyAsync(&pc, c.pcount, 8, hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(c, hipStreamSynchronize(c.stream));
+  if (pc > c.pcap || n > c.pcap - pc) {
+    c.err = "photon buffer cannot take the photons";
+    return PIC_ERR_OVERFLOW;
+  }
+  if (!n) return PIC_OK;
+  const size_t rs = real_size(c.cfg);
+  std::vector<unsigned char> buf(n * 8);
+  auto put_real = [&](void* dev, const double* src, int stride, int a) -> hipError_t {
+    for (uint64_t i = 0; i < n; ++i) {
+      const double v = src[(size_t)stride * i + a];
+      if (rs == 4) { const float f = (float)v; std::memcpy(&buf[i * 4], &f, 4); }
+      else std::memcpy(&buf[i * 8], &v, 8);
+    }
+    hipError_t e = hipMemcpyAsync((char*)dev + pc * rs, buf.data(), n * rs, hipMemcpyHostToDevice, c.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
+    return e;
+  };
+  for (int a = 0; a < 3; ++a) {
+    HIPCHK(c, put_real(c.px[a], x, 3, a));
+    HIPCHK(c, put_real(c.pk[a], k, 3, a));
+  }
+  HIPCHK(c, put_real(c.pe, eps, 1, 0));
+  std::vector<uint32_t> stp(n, (uint32_t)c.step), prc(n, 0u);
+  HIPCHK(c, hipMemcpyAsync(c.pw + pc, w, n * 8, hipMemcpyHostToDevice, c.stream));
+  HIPCHK(c, hipMemcpyAsync(c.pstep + pc, stp.data(), n * 4, hipMemcpyHostToDevice, c.stream));
+  HIPCHK(c, hipMemcpyAsync(c.ppar + pc, parent, n * 4, hipMemcpyHostToDevice, c.stream));
+  HIPCHK(c, hipMemcpyAsync(c.pproc + pc, prc.data(), n * 4, hipMemcpyHostToDevice, c.stream));
+  const unsigned long long np = pc + n;
+  HIPCHK(c, hipMemcpyAsync(c.pcount, &np, 8, hipMemcpyHostToDevice, c.stream));
+  HIPCHK(c, hipStreamSynchronize(c.stream));
+  return PIC_OK;
+}
+
 pic_status pic_copy_brem_depth(pic_ctx* ctx, double* out) {
   pic_status st = check_ctx(ctx);
   if (st) return st;
@@ -1444,7 +1685,7 @@ pic_status pic_profile_read(pic_ctx* ctx, double* ms2, uint64_t* n2) {
   Ctx& c = ctx->c;
   if (!ms2 || !n2) FAIL(c, PIC_ERR_INVALID, "null output");
   HIPCHK(c, hipStreamSynchronize(c.stream));
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < 5; ++k) {
     ms2[k] = 0.0;
     n2[k] = 0;
   }

@@ -86,6 +86,24 @@ inline uint64_t tables_checksum(const pic_tables& t) {
   return h;
 }
 
+// 64-bit FNV-1a of the bytes of the four pair-table arrays, in declaration
+// order (the pic_pair_tables checksum).
+inline uint64_t pair_tables_checksum(const pic_pair_tables& t) {
+  uint64_t h = 0xcbf29ce484222325ull;
+  auto feed = [&](const double* a, size_t n) {
+    const unsigned char* b = reinterpret_cast<const unsigned char*>(a);
+    for (size_t i = 0; i < n * sizeof(double); ++i) {
+      h ^= b[i];
+      h *= 0x100000001b3ull;
+    }
+  };
+  feed(t.bw_lnT, (size_t)t.n_chi);
+  feed(t.bw_cdf, (size_t)t.n_chi * t.n_xp);
+  feed(t.bh_sigma, (size_t)t.n_k);
+  feed(t.bh_cdf, (size_t)t.n_k * t.n_s);
+  return h;
+}
+
 // Emission tables resident on the device (FP64 copy, FP32 copy).
 // Guide of an inverse-CDF row: kGuide + 1 entries, entry b is the largest
 // index j <= n - 2 with C[j] <= b / kGuide (0 if none).  A uniform u then has
@@ -101,6 +119,11 @@ struct DevTables {
   float *hf = nullptr, *lnxif = nullptr, *ncsf = nullptr, *sigf = nullptr, *brf = nullptr;
   // guides of the CDF rows as compared in each precision (row-major, kGuide + 1 per row)
   uint8_t *gncs = nullptr, *gncsf = nullptr, *gbr = nullptr, *gbrf = nullptr;
+  // pair production (FP64 and FP32 copies)
+  int n_chi = 0, n_xp = 0, n_k = 0, n_s = 0;
+  double ln_chi0 = 0, idln_chi = 0, ln_k0 = 0, idln_k = 0;
+  double *bwT = nullptr, *bwC = nullptr, *bhS = nullptr, *bhC = nullptr;
+  float *bwTf = nullptr, *bwCf = nullptr, *bhSf = nullptr, *bhCf = nullptr;
 };
 
 // Parameters the electron-step kernel needs only on rare paths (prescribed
@@ -238,6 +261,55 @@ void launch_ion_recount(const IonArgs& A, hipStream_t s);  // clear and count ag
 void launch_ion_density(const IonArgs& A, hipStream_t s);  // ni <- count w / V, count <- 0
 void launch_ion_step(const IonArgs& A, hipStream_t s);     // push, deposit, walls, count
 
+// Photons in flight and pair production (PIC_BW / PIC_BH), precision of the
+// run; one grid-stride pass over the stored photon records per step.
+struct PhotonArgs {
+  int dims;
+  uint32_t flags, frozen_kind, step, key0, key1;
+  int n[3], gg[3], sz[3];
+  double idx[3], L[3], dt, tn, iES, K_P, K_BR;
+  double fE[3], fB[3], fa;
+  const void* F[6];           // E^n, B^n
+  const double* ni;
+  // photon records and their state in flight
+  const unsigned long long* pcount;
+  uint64_t pcap;
+  const void* px[3];
+  const void* pk[3];
+  const void* pe;
+  const double* pw;
+  const uint32_t* pstep;
+  const uint32_t* ppar;
+  const uint32_t* pproc;
+  void* gx[3];
+  double* gtau;
+  uint8_t* gst;
+  // tables (precision of the run)
+  int n_chi, n_xp, n_k, n_s;
+  double ln_chi0, idln_chi, ln_k0, idln_k;
+  const void* bwT;
+  const void* bwC;
+  const void* bhS;
+  const void* bhC;
+  // pair records
+  uint64_t rcap;
+  unsigned long long* rcount;
+  uint32_t* rfull;
+  void* rx[3];
+  void* rk[3];
+  void* rem;
+  void* rep;
+  double* rw;
+  uint32_t* rstep;
+  uint32_t* rpar;
+  uint32_t* rpst;
+  uint32_t* rproc;
+  unsigned long long* ev;    // [2] pairs created per process
+  double* esum;              // [2] sum w eps per process
+};
+void fill_photon_args(const struct Ctx& c, PhotonArgs& A);
+void launch_photon_step(const PhotonArgs& A, bool fp32, hipStream_t s);
+
 void launch_step(int dims, bool fp32, const void* params, hipStream_t s);
 int chunk_electrons(bool fp32, int dims);   // electrons per step-kernel workgroup
 // batched forms (device-resident tables of per-run entries; first[] is the
@@ -308,6 +380,25 @@ struct Ctx {
   uint32_t* pproc = nullptr;
   unsigned long long* pcount = nullptr;
   uint32_t* pfull = nullptr;  // photon buffer full (set by the step kernel)
+  // photons in flight and pair records (PIC_BW / PIC_BH)
+  void* gx[3] = {};
+  double* gtau = nullptr;
+  uint8_t* gst = nullptr;
+  uint64_t rcap = 0;
+  void* rx[3] = {};
+  void* rk[3] = {};
+  void* rem = nullptr;
+  void* rep = nullptr;
+  double* rw = nullptr;
+  uint32_t* rstep = nullptr;
+  uint32_t* rpar = nullptr;
+  uint32_t* rpst = nullptr;
+  uint32_t* rproc = nullptr;
+  unsigned long long* rcount = nullptr;   // [0] count; then rfull, ev[2], esum[2] in one block
+  uint32_t* rfull = nullptr;
+  unsigned long long* rev = nullptr;
+  double* resum = nullptr;
+  bool pair_tables_loaded = false;
   int64_t nslots = 0;
   int64_t nblocks_step = 0;   // step-kernel grid (a multiple of kGridQuantum)
   // cell-tile sort
@@ -339,7 +430,7 @@ struct Ctx {
   // optional kernel timing (pairs of events per launch group)
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
-  std::vector<int> ev_kind;   // 0 electron step, 1 field solve, 2 sort, 3 ions
+  std::vector<int> ev_kind;   // 0 electron step, 1 field solve, 2 sort, 3 ions, 4 photons
   size_t ev_used = 0;
   DevTables t{};
   std::vector<void*> allocs;

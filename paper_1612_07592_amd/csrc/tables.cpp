@@ -12,6 +12,13 @@
 // Bremsstrahlung (Sec. II.B, Eq. (1)): Tsai's bracket with his screening
 // functions and the Coulomb correction; sigma(T) = Int_{k_cut}^{T} B d ln k in
 // alpha r_e^2; cumulative rows on s = ln(k/k_cut)/ln(T/k_cut).
+//
+// Pairs: the Breit-Wheeler spectrum bracket Int_y^inf K_{1/3} + (xi/(1-xi) +
+// (1-xi)/xi) K_{2/3}(y), y = 2/(3 chi xi (1-xi)), integrated over the
+// electron share xi on a uniform grid (T(chi) = Int / (sqrt(3) pi chi)); the
+// Bethe-Heitler cross-section in Tsai's form for pair production (the same
+// screening functions and Coulomb correction, arguments at E+ E- =
+// x (1-x) k^2), integrated over the positron share x between 1/k and 1 - 1/k.
 #include <cmath>
 #include <thread>
 #include <vector>
@@ -25,6 +32,8 @@ constexpr double kEtaMin = 1e-4, kEtaMax = 1e2, kXiMin = 1e-12;
 constexpr double kMc2MeV = 0.51099895000;
 constexpr double kTMinMeV = 1e-3, kTMaxMeV = 1e3;
 constexpr double kAlpha = 7.2973525693e-3;
+constexpr int kNchi = 128, kNxp = 128, kNk = 128, kNs = 64;
+constexpr double kChiMin = 1e-2, kChiMax = 1e3, kKMin = 2.0, kKMax = 2.0e4;
 
 // K_{2/3}(y) and Int_y^inf K_{5/3}(t) dt by the trapezoid rule in t.
 void bessel_pair(double y, double* k23, double* i53) {
@@ -108,11 +117,10 @@ void ncs_row(double eta, const double* lnxi, double* h_out, double* cdf) {
   cdf[kNxi - 1] = 1.0;
 }
 
-// Tsai screening functions (of gamma and epsilon) and Coulomb correction.
-double tsai_B(double y, double E, double Z) {
-  const double k = y * E, Ep = E - k;
-  const double gs = 100.0 * k / (E * Ep * std::cbrt(Z));
-  const double es = 100.0 * k / (E * Ep * std::cbrt(Z * Z));
+// Tsai's screening terms at the screening variables gs (gamma) and es
+// (epsilon): the unscreened-charge bracket A = Z^2 (phi1 - 4/3 ln Z - 4 f) +
+// Z (psi1 - 8/3 ln Z) and the difference D = Z^2 (phi1 - phi2) + Z (psi1 - psi2).
+void tsai_terms(double gs, double es, double Z, double* A, double* D) {
   const double phi1 = 20.863 - 2.0 * std::log(1.0 + (0.55846 * gs) * (0.55846 * gs)) -
                       4.0 * (1.0 - 0.6 * std::exp(-0.9 * gs) - 0.4 * std::exp(-1.5 * gs));
   const double phi2 = phi1 - (2.0 / 3.0) / (1.0 + 6.5 * gs + 6.0 * gs * gs);
@@ -122,10 +130,100 @@ double tsai_B(double y, double E, double Z) {
   const double a2 = (kAlpha * Z) * (kAlpha * Z);
   const double fz = a2 * (1.0 / (1.0 + a2) + 0.20206 - 0.0369 * a2 + 0.0083 * a2 * a2 - 0.002 * a2 * a2 * a2);
   const double lnZ = std::log(Z);
-  const double B = (4.0 / 3.0 - (4.0 / 3.0) * y + y * y) *
-                       (Z * Z * (phi1 - (4.0 / 3.0) * lnZ - 4.0 * fz) + Z * (psi1 - (8.0 / 3.0) * lnZ)) +
-                   (2.0 / 3.0) * (1.0 - y) * (Z * Z * (phi1 - phi2) + Z * (psi1 - psi2));
+  *A = Z * Z * (phi1 - (4.0 / 3.0) * lnZ - 4.0 * fz) + Z * (psi1 - (8.0 / 3.0) * lnZ);
+  *D = Z * Z * (phi1 - phi2) + Z * (psi1 - psi2);
+}
+
+// Bremsstrahlung bracket of Eq. (1) at y = k/E.
+double tsai_B(double y, double E, double Z) {
+  const double k = y * E, Ep = E - k;
+  double A, D;
+  tsai_terms(100.0 * k / (E * Ep * std::cbrt(Z)), 100.0 * k / (E * Ep * std::cbrt(Z * Z)), Z, &A, &D);
+  const double B = (4.0 / 3.0 - (4.0 / 3.0) * y + y * y) * A + (2.0 / 3.0) * (1.0 - y) * D;
   return B > 0.0 ? B : 0.0;
+}
+
+// Pair-production bracket at positron share x of a photon k (mc^2).
+double tsai_pair(double x, double k, double Z) {
+  const double q = x * (1.0 - x);
+  double A, D;
+  tsai_terms(100.0 / (k * q * std::cbrt(Z)), 100.0 / (k * q * std::cbrt(Z * Z)), Z, &A, &D);
+  const double B = (1.0 - (4.0 / 3.0) * q) * A - (2.0 / 3.0) * q * D;
+  return B > 0.0 ? B : 0.0;
+}
+
+// K_{2/3}(y) and Int_y^inf K_{1/3}(t) dt by the trapezoid rule in t.
+void bessel_bw(double y, double* k23, double* i13) {
+  if (y > 700.0) { *k23 = 0.0; *i13 = 0.0; return; }
+  const double h = 1.0 / 32.0;
+  double a = 0.5 * std::exp(-y), b = a;
+  for (int k = 1;; ++k) {
+    const double t = k * h;
+    const double ch = std::cosh(t);
+    const double ex = std::exp(-y * ch);
+    const double ta = ex * std::cosh(t * (2.0 / 3.0));
+    const double tb = ex * std::cosh(t * (1.0 / 3.0)) / ch;
+    a += ta;
+    b += tb;
+    if (y * ch > 40.0 && ta < 1e-18 * a) break;
+    if (k > 200000) break;
+  }
+  *k23 = a * h;
+  *i13 = b * h;
+}
+
+double bw_bracket(double chi, double xi) {
+  if (!(xi > 0.0 && xi < 1.0)) return 0.0;
+  const double y = 2.0 / (3.0 * chi * xi * (1.0 - xi));
+  if (y > 700.0) return 0.0;
+  double k23, i13;
+  bessel_bw(y, &k23, &i13);
+  return i13 + (xi / (1.0 - xi) + (1.0 - xi) / xi) * k23;
+}
+
+void bw_row(double chi, double* lnT, double* cdf) {
+  auto f = [chi](double xi) { return bw_bracket(chi, xi); };
+  double coarse = 0.0;
+  for (int q = 0; q < 512; ++q) {
+    const double a = (double)q / 512, b = (double)(q + 1) / 512;
+    coarse += (b - a) / 6.0 * (f(a) + 4.0 * f(0.5 * (a + b)) + f(b));
+  }
+  const double dens = 1e-15 * coarse;
+  double cum = 0.0;
+  cdf[0] = 0.0;
+  for (int j = 0; j + 1 < kNxp; ++j) {
+    cum += integrate(f, (double)j / (kNxp - 1), (double)(j + 1) / (kNxp - 1), dens);
+    cdf[j + 1] = cum;
+  }
+  *lnT = std::log(cum / (std::sqrt(3.0) * M_PI * chi));
+  for (int j = 0; j < kNxp; ++j) cdf[j] /= cum;
+  cdf[kNxp - 1] = 1.0;
+}
+
+void bh_row(double k, double Z, double* sigma, double* cdf) {
+  const double lo = 1.0 / k, hi = 1.0 - 1.0 / k;
+  auto f = [k, Z](double x) { return tsai_pair(x, k, Z); };
+  double coarse = 0.0;
+  if (hi > lo)
+    for (int q = 0; q < 256; ++q) {
+      const double a = lo + (hi - lo) * q / 256, b = lo + (hi - lo) * (q + 1) / 256;
+      coarse += (b - a) / 6.0 * (f(a) + 4.0 * f(0.5 * (a + b)) + f(b));
+    }
+  if (!(coarse > 0.0)) {
+    *sigma = 0.0;
+    for (int j = 0; j < kNs; ++j) cdf[j] = (double)j / (kNs - 1);
+    return;
+  }
+  const double dens = 1e-15 * coarse / (hi - lo);
+  double cum = 0.0;
+  cdf[0] = 0.0;
+  for (int j = 0; j + 1 < kNs; ++j) {
+    cum += integrate(f, lo + (hi - lo) * j / (kNs - 1), lo + (hi - lo) * (j + 1) / (kNs - 1), dens);
+    cdf[j + 1] = cum;
+  }
+  *sigma = cum;
+  for (int j = 0; j < kNs; ++j) cdf[j] /= cum;
+  cdf[kNs - 1] = 1.0;
 }
 
 void brem_row(int i, double Z, double kcut, double ln_T0, double dln_T, double* sigma, double* cdf) {
@@ -199,5 +297,42 @@ extern "C" pic_status pic_build_tables(uint32_t Z, double k_cut_mc2, int32_t nth
   out->sigma = sigma;
   out->br_cdf = br_cdf;
   out->checksum = pic::tables_checksum(*out);
+  return PIC_OK;
+}
+
+extern "C" pic_status pic_build_pair_tables(uint32_t Z, int32_t nthreads, double* bw_lnT,
+                                            double* bw_cdf, double* bh_sigma, double* bh_cdf,
+                                            pic_pair_tables* out) {
+  if (!bw_lnT || !bw_cdf || !bh_sigma || !bh_cdf || !out) return PIC_ERR_INVALID;
+  if (Z < 1 || Z > 120) return PIC_ERR_INVALID;
+  const double ln_chi0 = std::log(kChiMin), dln_chi = std::log(kChiMax / kChiMin) / (kNchi - 1);
+  const double ln_k0 = std::log(kKMin), dln_k = std::log(kKMax / kKMin) / (kNk - 1);
+  int nt = nthreads > 0 ? nthreads : (int)std::thread::hardware_concurrency();
+  if (nt < 1) nt = 1;
+  if (nt > 64) nt = 64;
+  std::vector<std::thread> pool;
+  for (int w = 0; w < nt; ++w)
+    pool.emplace_back([=]() {
+      for (int i = w; i < kNchi; i += nt)
+        bw_row(std::exp(ln_chi0 + i * dln_chi), &bw_lnT[i], bw_cdf + (size_t)i * kNxp);
+      for (int i = w; i < kNk; i += nt)
+        bh_row(std::exp(ln_k0 + i * dln_k), (double)Z, &bh_sigma[i], bh_cdf + (size_t)i * kNs);
+    });
+  for (auto& t : pool) t.join();
+  out->version = PIC_PAIR_TABLES_VERSION;
+  out->Z = Z;
+  out->n_chi = kNchi;
+  out->n_xp = kNxp;
+  out->ln_chi0 = ln_chi0;
+  out->dln_chi = dln_chi;
+  out->bw_lnT = bw_lnT;
+  out->bw_cdf = bw_cdf;
+  out->n_k = kNk;
+  out->n_s = kNs;
+  out->ln_k0 = ln_k0;
+  out->dln_k = dln_k;
+  out->bh_sigma = bh_sigma;
+  out->bh_cdf = bh_cdf;
+  out->checksum = pic::pair_tables_checksum(*out);
   return PIC_OK;
 }

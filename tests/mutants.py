@@ -58,7 +58,10 @@ MUTANTS = {
     "ncs_rate_blend": [("double h = s->h[i] + f * (s->h[i + 1] - s->h[i]);",
                         "double h = s->h[i] + (1.0 - f) * (s->h[i + 1] - s->h[i]);")],
     "ncs_row_blend": [("double lx = la + f * (lb - la);", "double lx = la + (1.0 - f) * (lb - la);")],
-    "ncs_row_search": [("if (C[mid] <= u) lo = mid; else hi = mid;", "if (C[mid] < u) hi = mid; else lo = mid;")],
+    "ncs_row_search": [("int lo = 0, hi = s->n_xi - 1;\n  while (hi - lo > 1) {\n    int mid = (lo + hi) / 2;\n"
+                        "    if (C[mid] <= u) lo = mid; else hi = mid;",
+                        "int lo = 0, hi = s->n_xi - 1;\n  while (hi - lo > 1) {\n    int mid = (lo + hi) / 2;\n"
+                        "    if (C[mid] < u) hi = mid; else lo = mid;")],
     "brem_sigma_blend": [("return s->sigma[i] + f * (s->sigma[i + 1] - s->sigma[i]);",
                           "return s->sigma[i + 1] + f * (s->sigma[i + 1] - s->sigma[i]);")],
     "brem_row_blend": [("double sv = sa + f * (sb - sa);", "double sv = sa + (1.0 - f) * (sb - sa);")],

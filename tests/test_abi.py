@@ -191,6 +191,21 @@ def test_library_tables_match_oracle_tables(tables_au):
     assert np.max(np.abs(t["br_cdf"] - tables_au["br_cdf"])) < 1e-9
 
 
+def test_library_pair_tables_match_oracle_tables(tables_au):
+    """Two independent quadratures of the pair spectra and cross-sections
+    (library: trapezoid Bessel sums + adaptive Simpson; oracle: scipy K and
+    adaptive Gauss-Legendre) agree."""
+    t = B.pic_build_pair_tables(79, 8)
+    assert t["pair_checksum"] != 0
+    assert abs(t["ln_chi0"] - tables_au["ln_chi0"]) < 1e-15 and abs(t["ln_k0"] - tables_au["ln_k0"]) < 1e-15
+    assert np.abs(t["bw_lnT"] - tables_au["bw_lnT"]).max() < 1e-9
+    assert np.abs(t["bw_cdf"] - tables_au["bw_cdf"]).max() < 1e-9
+    pos = tables_au["bh_sigma"] > 0
+    assert np.array_equal(t["bh_sigma"] > 0, pos)
+    assert np.max(np.abs(t["bh_sigma"][pos] / tables_au["bh_sigma"][pos] - 1)) < 1e-8
+    assert np.abs(t["bh_cdf"] - tables_au["bh_cdf"]).max() < 1e-8
+
+
 def test_build_tables_rejects_bad_args():
     L = B.load()
     out = B.pic_tables()
