@@ -37,7 +37,9 @@ Beside the headline, the JSON line carries (each leg's failure is recorded in
   serving, thick_target  scan-job server runs and the bremsstrahlung benchmark;
   solid                  (--only solid) the laser-solid study of Sec. III at
                          its own size, with mobile ions: throughput and energy
-                         partition of every run.
+                         partition of every run;
+  pairs                  (--only pairs) the gold run at 10^24 W/cm^2 with
+                         photons in flight and pair production.
 """
 from __future__ import annotations
 
@@ -211,7 +213,8 @@ def run_window(w, tables, lead, k, torch, warmup=0, photons=False, events=True, 
         s.pic_destroy()
         out.update(window_esteps=int(st["electron_steps"]) - e0,
                    step_kernel_ms=float(ms[0]), field_ms=float(ms[1]), sort_ms=float(ms[2]),
-                   ion_ms=float(ms[3]), step_launches=int(n[0]), profiled_ms=float(ms.sum()))
+                   ion_ms=float(ms[3]), photon_ms=float(ms[4]), step_launches=int(n[0]),
+                   profiled_ms=float(ms.sum()))
     return out
 
 
@@ -455,6 +458,39 @@ def solid_leg(torch, targets=("al", "au"), intensities=None, processes=("ncs", "
             "without_laser": reference, "precision": precision}
 
 
+def pairs_leg(torch, precision="fp32"):
+    """Pair production on the Sec. III gold run at 10^24 W/cm^2 (NCS and
+    bremsstrahlung on, photons from 1 mc^2 kept and followed, Breit-Wheeler
+    and Bethe-Heitler on): the cost of photons in flight beside the rest of
+    the step, the pairs made, and the same run without them."""
+    from paper_1612_07592_amd import binding
+    from paper_1612_07592_amd import workloads as W
+    w = W.solid("au", 1e24, "both", precision=precision)
+    w.update(bw=True, bh=True, pair_capacity=50_000_000)
+    Z = int(w["Z"])
+    tb = dict(binding.pic_build_tables(Z, 1.0, 16))
+    tb.update(binding.pic_build_pair_tables(Z, 16))
+    out = {"run": w["name"] + "-pairs", "steps": int(w["steps"]), "electrons": _num_electrons(w)}
+    r = run_window(w, tb, 0, int(w["steps"]), torch, events=True, wall=True)
+    st = r["stats"]
+    EL = laser_energy(w)
+    out.update(value=r["window_esteps"] / r["wall_s"], wall_s=r["wall_s"],
+               kernel_ms={"electron_step": r["step_kernel_ms"], "field_solve": r["field_ms"],
+                          "sort": r["sort_ms"], "ions": r["ion_ms"], "photons": r["photon_ms"]},
+               photons_stored=st["photons_stored"], overflow=st["overflow"],
+               pairs=st["pairs"], pairs_stored=st["pairs_stored"],
+               fraction_of_laser_energy={"into_pairs_bw": st["e_pair"][0] / EL,
+                                         "into_pairs_bh": st["e_pair"][1] / EL,
+                                         "photons_kept": [v / EL for v in st["e_rad_kept"]]})
+    w0 = dict(w, bw=False, bh=False)
+    r0 = run_window(w0, tb, 0, int(w["steps"]), torch, events=False, wall=True)
+    out["without_pairs"] = {"value": r0["window_esteps"] / r0["wall_s"], "wall_s": r0["wall_s"]}
+    log(f"pairs {out['run']}: {out['value']:.3e} e-steps/s ({r['wall_s']:.1f} s; without pair "
+        f"production {r0['wall_s']:.1f} s); pairs BW {st['pairs'][0]}, BH {st['pairs'][1]}; photons "
+        f"in flight {r['photon_ms'] / int(w['steps']) * 1e3:.0f} us per step")
+    return out
+
+
 def serving(args):
     """Scan jobs through the continuous-batching server: the 8-job
     intensity x target batch (FP32, FP64, and FP32 one job after another),
@@ -568,7 +604,7 @@ def main():
     ap.add_argument("--no-thick", action="store_true", help="skip the thick-target runs")
     ap.add_argument("--only", default=None,
                     help="run only the headline and this leg (roofline, full, cpu, serving, thick, "
-                         "solid)")
+                         "solid, pairs)")
     ap.add_argument("--solid-targets", default="al,au")
     ap.add_argument("--solid-intensities", default="1e21,1e22,1e23,1e24")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -585,7 +621,7 @@ def main():
         sys.exit(2)
     legs = {"roofline": not args.no_roofline, "full": not args.no_full_run and not args.no_fp64,
             "cpu": not args.no_cpu_baseline, "serving": not args.no_serving,
-            "thick": not args.no_thick, "fp64": not args.no_fp64, "solid": False}
+            "thick": not args.no_thick, "fp64": not args.no_fp64, "solid": False, "pairs": False}
     if args.only:
         legs = {k: (k == args.only) for k in legs}
     import torch
@@ -683,6 +719,8 @@ def main():
             out["solid"] = leg("solid", lambda: solid_leg(
                 torch, tuple(args.solid_targets.split(",")),
                 tuple(float(v) for v in args.solid_intensities.split(","))))
+        if legs["pairs"]:
+            out["pairs"] = leg("pairs", lambda: pairs_leg(torch))
         if legs["cpu"]:
             out["cpu_baseline"] = leg("cpu_baseline", lambda: cpu_baseline(
                 _workload(args.workload, "fp64"), lead, k))
