@@ -64,7 +64,7 @@ ALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # rate operations counted 4; the conditional brem test and event sampling are
 # not included.  An estimate from the method, not a counter.
 ALU_OPS = {1: 292, 2: 548, 3: 1366}
-KERNEL_SOURCES = ["step.hip", "pic_internal.hpp", "philox.hpp", "fpmath.hpp"]
+KERNEL_SOURCES = ["step.hip", "particle.hpp", "pic_internal.hpp", "philox.hpp", "fpmath.hpp"]
 # algorithmic bytes per electron-step of the step kernel: the electron state
 # read once (positions, momenta, tau, weight, id) and written once (positions,
 # momenta, tau); fields and tables are amortised over the electrons of a cell
@@ -239,9 +239,31 @@ def precision_check(s32, s64, p32=None, p64=None):
         ks = {"statistic": float(r.statistic), "p": float(r.pvalue),
               "n": [len(p32["energy"]), len(p64["energy"])], "pass": float(r.pvalue) > 0.01}
     out["spectrum_ks"] = ks
+    out["spectrum_all_kept"] = binned_spectra(s32, s64)
     if n64 == 0 and n32 == 0:
         out["note"] = "no photons kept in this window"
     return out
+
+
+def binned_spectra(s32, s64):
+    """The kept-photon spectra of the statistics (every kept photon, stored
+    in the buffer or not, in quarter-octave bins; NCS and bremsstrahlung
+    pooled): the largest difference of the two binned distribution
+    functions and the chi-square homogeneity p-value of the 2 x bins table."""
+    import numpy as np
+    a = np.asarray(s32.get("spectrum", np.zeros((2, 64))), dtype=np.float64).sum(axis=0)
+    b = np.asarray(s64.get("spectrum", np.zeros((2, 64))), dtype=np.float64).sum(axis=0)
+    res = {"n": [int(a.sum()), int(b.sum())], "D": None, "chi2_p": None, "pass": None}
+    if a.sum() == 0 or b.sum() == 0:
+        return res
+    D = float(np.abs(np.cumsum(a) / a.sum() - np.cumsum(b) / b.sum()).max())
+    keep = (a + b) > 0
+    from scipy import stats as sst
+    chi2, p, _, _ = sst.chi2_contingency(np.vstack([a[keep], b[keep]]))
+    res.update(D=D, chi2_p=float(p), pass_=None)
+    res.pop("pass_")
+    res["pass"] = float(p) > 0.01
+    return res
 
 
 def _max_or_none(vals):
@@ -259,7 +281,10 @@ def seed_spread(pc, refs):
     dk = _max_or_none([q["spectrum_ks"]["statistic"] for q in refs])
     rel = pc["radiated_energy"]["rel"]
     ks = pc["spectrum_ks"]["statistic"]
+    db = _max_or_none([q.get("spectrum_all_kept", {}).get("D") for q in refs])
+    bd = pc.get("spectrum_all_kept", {}).get("D")
     return {
+        "spectrum_all_kept": (bd <= 2.0 * db) if (bd is not None and db) else None,
         "photon_count": abs(pc["photon_count"]["fp32"] - n64) <= 2.0 * max(dn or 0, 3.0 * n64 ** 0.5),
         "radiated_energy": (abs(rel) <= max(0.01, 2.0 * (de or 0.0))) if rel is not None else None,
         "spectrum_ks": (ks <= 2.0 * dk) if (ks is not None and dk) else None}
@@ -353,7 +378,8 @@ def roofline_leg(name, k, tables, torch, with_fp64=True):
         v64 = r64["window_esteps"] / r64["wall_s"]
         v32 = r32["window_esteps"] / r32["wall_s"]
         out["fp32_vs_fp64_3d"] = {"workload": w["name"], "lead_in_steps": lead, "steps": k,
-                                  "fp32": v32, "fp64": v64, "fp32_over_fp64": v32 / v64}
+                                  "fp32": v32, "fp64": v64, "fp32_over_fp64": v32 / v64,
+                                  "precision": precision_check(r32["stats"], r64["stats"])}
         log(f"3D window: fp32 {v32:.3e}, fp64 {v64:.3e} e-steps/s")
     return out
 

@@ -50,6 +50,7 @@ extern "C" {
 
 #define PIC_ABI_VERSION 2u
 #define PIC_TABLES_VERSION 2u
+#define PIC_SPECTRUM_BINS 64
 
 typedef struct pic_ctx pic_ctx; /* opaque; owned by the library */
 
@@ -241,6 +242,10 @@ typedef struct {
   uint64_t pairs_stored;     /* pair records in the pair buffer */
   uint64_t pairs_overflow;   /* pairs that did not fit the buffer */
   double e_pair[2];          /* sum w eps of the photons that converted, per process */
+  uint64_t spectrum[2][PIC_SPECTRUM_BINS]; /* kept photons per process by energy, stored
+                                or not: bin b holds 2^((b-8)/4) <= eps/mc^2 < 2^((b-7)/4)
+                                (quarter octaves from 0.25 mc^2; the first and last
+                                bins take everything below and above) */
 } pic_stats;
 
 /* ---- the five calls of the hot path ------------------------------------- */

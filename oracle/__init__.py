@@ -94,7 +94,8 @@ class _Stats(C.Structure):
                 ("overflow", C.c_uint64), ("brem_clamped", C.c_uint64),
                 ("e_rad_kept", C.c_double * 2), ("e_rad_dropped", C.c_double),
                 ("ions_live", C.c_uint64), ("pairs", C.c_uint64 * 2),
-                ("pairs_overflow", C.c_uint64), ("e_pair", C.c_double * 2)]
+                ("pairs_overflow", C.c_uint64), ("e_pair", C.c_double * 2),
+                ("spectrum", (C.c_uint64 * 64) * 2)]
 
 
 _libs = {}
@@ -377,7 +378,8 @@ class OracleSim:
                     e_rad_kept=[s.e_rad_kept[0], s.e_rad_kept[1]],
                     e_rad_dropped=s.e_rad_dropped, ions_live=s.ions_live,
                     pairs=[s.pairs[0], s.pairs[1]], pairs_overflow=s.pairs_overflow,
-                    e_pair=[s.e_pair[0], s.e_pair[1]])
+                    e_pair=[s.e_pair[0], s.e_pair[1]],
+                    spectrum=np.array([list(s.spectrum[0]), list(s.spectrum[1])], dtype=np.uint64))
 
     def kinetic_energy(self):
         return float(self._L.or_kinetic_energy(self._h))

@@ -1162,6 +1162,22 @@ static void photon_step(or_sim* s, double tn, int frozen) {
   }
 }
 
+/* Quarter-octave bin of a photon energy: eps = m 2^e with 1 <= m < 2 gives
+ * 4 (e + 2) plus the number of the thresholds 2^(1/4), 2^(1/2), 2^(3/4)
+ * (rounded to double) that m reaches; clamped to [0, 64). */
+static int spectrum_bin(double eps) {
+  int e;
+  double m = 2.0 * frexp(eps, &e);
+  e = e - 1;
+  int b = 4 * (e + 2);
+  if (m >= 0x1.306fe0a31b715p+0) b++;
+  if (m >= 0x1.6a09e667f3bcdp+0) b++;
+  if (m >= 0x1.ae89f995ad3adp+0) b++;
+  if (b < 0) b = 0;
+  if (b > 63) b = 63;
+  return b;
+}
+
 static void laser_scalars(const or_sim* s, uint64_t step, double* lsin, double* lcos) {
   double t = ((double)step + 0.5) * s->dt;
   double TL = s->c.duration_cycles * (2.0 * M_PI);
@@ -1211,6 +1227,7 @@ void or_step(or_sim* s, int nsteps) {
         if (!r->pkeep[k]) { s->st.dropped_ncs++; s->st.e_rad_dropped += we; continue; }
         s->st.kept[pr]++;
         s->st.e_rad_kept[pr] += we;
+        s->st.spectrum[pr][spectrum_bin(r->pe[k])]++;
         if (s->pcount < s->pcap) {
           int64_t q = s->pcount;
           for (int a = 0; a < 3; ++a) { s->ph_x[3 * q + a] = r->px[k][a]; s->ph_k[3 * q + a] = r->pk[k][a]; }

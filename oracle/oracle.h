@@ -72,6 +72,9 @@ typedef struct {
   uint64_t pairs[2];                   /* [0] Breit-Wheeler, [1] Bethe-Heitler */
   uint64_t pairs_overflow;             /* pairs not stored (buffer full) */
   double e_pair[2];                    /* sum w eps of the converted photons */
+  /* kept photons per process by energy: bin b holds 2^((b-8)/4) <= eps <
+   * 2^((b-7)/4) (mc^2), the first and last bins open */
+  uint64_t spectrum[2][64];
 } or_stats;
 
 typedef struct or_sim or_sim;

@@ -73,7 +73,8 @@ class pic_stats(C.Structure):
                 ("e_kin_e", C.c_double), ("e_field", C.c_double),
                 ("ions_live", C.c_uint64), ("e_kin_i", C.c_double),
                 ("pairs", C.c_uint64 * 2), ("pairs_stored", C.c_uint64),
-                ("pairs_overflow", C.c_uint64), ("e_pair", C.c_double * 2)]
+                ("pairs_overflow", C.c_uint64), ("e_pair", C.c_double * 2),
+                ("spectrum", (C.c_uint64 * 64) * 2)]
 
 
 class pic_pair_tables(C.Structure):
@@ -353,7 +354,9 @@ def stats_dict(s: pic_stats, code: int = 0) -> dict:
                 e_rad_dropped=s.e_rad_dropped, e_kin_e=s.e_kin_e, e_field=s.e_field,
                 ions_live=s.ions_live, e_kin_i=s.e_kin_i, pairs=[s.pairs[0], s.pairs[1]],
                 pairs_stored=s.pairs_stored, pairs_overflow=s.pairs_overflow,
-                e_pair=[s.e_pair[0], s.e_pair[1]], status=STATUS.get(code, code))
+                e_pair=[s.e_pair[0], s.e_pair[1]],
+                spectrum=np.array([list(s.spectrum[0]), list(s.spectrum[1])], dtype=np.uint64),
+                status=STATUS.get(code, code))
 
 
 def pic_device_memory():

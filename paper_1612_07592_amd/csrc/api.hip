@@ -299,6 +299,7 @@ Plan make_plan(Ctx& c) {
   P.add((void**)&c.pproc, pc * 4);
   P.add((void**)&c.pcount, 8);
   P.add((void**)&c.pfull, 4);   // a line of its own: read by every chunk, written once
+  P.add((void**)&c.spec, (size_t)kSpecCopies * 2 * PIC_SPECTRUM_BINS * 8);
   if (c.cfg.flags & (PIC_BW | PIC_BH)) {  // photons in flight, pair records
     for (int a = 0; a < 3; ++a) P.add(&c.gx[a], pc * rs);
     P.add((void**)&c.gtau, pc * 8);
@@ -476,6 +477,7 @@ void fill_step_cold(const Ctx& c, StepCold<R>& C) {
   C.pproc = c.pproc;
   C.pcount = c.pcount;
   C.pfull = c.pfull;
+  C.spec = c.spec;
   C.slot_cnt = c.slot_cnt;
   C.slot_sum = c.slot_sum;
 }
@@ -966,17 +968,20 @@ pic_status pic_emission_stats(pic_ctx* ctx, pic_stats* out) {
   double sum[kRedSum];
   unsigned long long pcount = 0, rcount = 0, rev[2] = {0, 0};
   double resum[2] = {0.0, 0.0};
+  pic_stats s{};
   launch_stats_reduce(c, cnt, sum, c.stream);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipMemcpyAsync(&pcount, c.pcount, 8, hipMemcpyDeviceToHost, c.stream));
+  std::vector<unsigned long long> spec((size_t)kSpecCopies * 2 * PIC_SPECTRUM_BINS);
+  HIPCHK(c, hipMemcpyAsync(spec.data(), c.spec, spec.size() * 8, hipMemcpyDeviceToHost, c.stream));
   if (c.rcount) {
     HIPCHK(c, hipMemcpyAsync(&rcount, c.rcount, 8, hipMemcpyDeviceToHost, c.stream));
     HIPCHK(c, hipMemcpyAsync(rev, c.rev, 16, hipMemcpyDeviceToHost, c.stream));
     HIPCHK(c, hipMemcpyAsync(resum, c.resum, 16, hipMemcpyDeviceToHost, c.stream));
   }
   HIPCHK(c, hipStreamSynchronize(c.stream));
-  pic_stats s{};
   s.steps = c.step;
+  for (size_t q = 0; q < spec.size(); ++q) (&s.spectrum[0][0])[q % (2 * PIC_SPECTRUM_BINS)] += spec[q];
   s.electrons_live = cnt[kSlotCnt];
   s.electron_steps = cnt[SC_ESTEPS];
   s.events[0] = cnt[SC_EV_NCS];

@@ -19,6 +19,7 @@ constexpr int kSlotCnt = 8;               // u64 counters per wave slot
 constexpr uint32_t kXcdGroup = 16;
 constexpr int64_t kGridQuantum = 8 * kXcdGroup;
 constexpr int kSlotSum = 6;               // doubles per wave slot (3 Neumaier pairs)
+constexpr int kSpecCopies = 2048;         // copies of the kept-photon spectrum (by chunk)
 constexpr double kJScale = 0x1p40;        // current fixed point: units of 2^-40
 constexpr double kJInv = 0x1p-40;
 
@@ -152,6 +153,7 @@ struct StepCold {
   uint32_t* pproc;
   unsigned long long* pcount;
   uint32_t* pfull;            // set once a reservation reached the capacity
+  unsigned long long* spec;   // kept-photon spectrum, kSpecCopies x [2][PIC_SPECTRUM_BINS]
   unsigned long long* slot_cnt;
   double* slot_sum;
 };
@@ -380,6 +382,7 @@ struct Ctx {
   uint32_t* pproc = nullptr;
   unsigned long long* pcount = nullptr;
   uint32_t* pfull = nullptr;  // photon buffer full (set by the step kernel)
+  unsigned long long* spec = nullptr;  // kept-photon spectrum [2][PIC_SPECTRUM_BINS]
   // photons in flight and pair records (PIC_BW / PIC_BH)
   void* gx[3] = {};
   double* gtau = nullptr;

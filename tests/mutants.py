@@ -91,6 +91,8 @@ MUTANTS = {
                             ("double xb = share_inv_row(s->bw_cdf + (int64_t)(bi + 1) * s->n_xp, s->n_xp, u32(r[2]));",
                              "double xb = share_inv_row(s->bw_cdf + (int64_t)(bi + 1) * s->n_xp, s->n_s, u32(r[2]));")],
     "photon_move_sign": [("      x[a] = x[a] + k[a] * s->dt;", "      x[a] = x[a] - k[a] * s->dt;")],
+    "spectrum_bin_offset": [("  int b = 4 * (e + 2);\n  if (m >= 0x1.306fe0a31b715p+0) b++;",
+                             "  int b = 4 * (e + 1);\n  if (m >= 0x1.306fe0a31b715p+0) b++;")],
     # constants
     "K_BR_factor": [("s->K_BR = s->n_c * (lam / twopi) * alpha * re * re;",
                      "s->K_BR = s->n_c * lam * alpha * re * re;")],

@@ -53,6 +53,7 @@ def compare(o, g, p_tol=P_TOL, label="", check_tau=True, p_scale=None):
     assert so["dropped_ncs"] == sg["dropped_ncs"], label
     assert so["overflow"] == sg["overflow"], label
     assert so["live"] == sg["live"], label
+    assert np.array_equal(so["spectrum"], sg["spectrum"]), f"{label}: kept-photon spectra differ"
     for i in range(2):
         assert abs(sg["e_rad_kept"][i] - so["e_rad_kept"][i]) <= SUM_TOL * max(abs(so["e_rad_kept"][i]), 1e-300), label
     assert abs(sg["e_rad_dropped"] - so["e_rad_dropped"]) <= SUM_TOL * max(abs(so["e_rad_dropped"]), 1e-300), label

@@ -45,6 +45,7 @@ CASES = [
     ("bh_density_dropped", PP.check_bh_conversion_law),
     ("bw_share_row_length", PP.check_pair_shares),
     ("photon_move_sign", PP.check_pair_kinematics),
+    ("spectrum_bin_offset", PE.check_spectrum_bins),
     ("K_BR_factor", PE.check_constants),
     ("E_S_factor", PE.check_constants),
 ]

@@ -273,3 +273,29 @@ def check_math_against_libm(lib=None):
 
 def test_oracle_math_against_libm(oracle_lib):
     print(check_math_against_libm())
+
+
+def check_spectrum_bins(lib=None):
+    """The kept-photon spectrum of the statistics counts every kept photon in
+    its quarter octave: against floor(4 log2(eps)) + 8 of the stored records
+    (a run with every photon stored), per process."""
+    import conftest
+    w = S.frozen_B_beam(B=50.0, ne=5e7, Z=79, charge_state=79, photon_cut_mc2=0.0,
+                        photon_capacity=1 << 20)
+    o = oracle.OracleSim(w, conftest.oracle_tables(79), nthreads=1, lib=lib)
+    e = o.electrons()
+    o.set_electrons(e["x"], S.beam_momenta(o.N, 5.0, 2000.0, 22), e["tau"])
+    o.step(60)
+    st = o.stats()
+    ph = o.photons()
+    assert st["overflow"] == 0 and len(ph["energy"]) == sum(st["kept"])
+    ref = np.zeros((2, 64), dtype=np.uint64)
+    b = np.clip(np.floor(4.0 * np.log2(ph["energy"])).astype(np.int64) + 8, 0, 63)
+    np.add.at(ref, (ph["proc"].astype(np.int64), b), 1)
+    assert np.array_equal(st["spectrum"], ref), np.nonzero(st["spectrum"] != ref)
+    assert ref[0].sum() > 1000 and ref[1].sum() > 1000
+    return ref.sum(axis=1)
+
+
+def test_kept_photon_spectrum_bins(oracle_lib):
+    print(check_spectrum_bins())

@@ -295,4 +295,22 @@ def test_get_buffers(gpu_lib, tables_al):
     b1 = g.buffers()
     assert b1["E"] != b0["E"]
     assert b1["B"] == b0["B"]
+    # past a tile sort (1D: every 16 steps) the borrowed pointers still name
+    # the live, re-ordered arrays: read id and x through them with the HIP
+    # runtime libpic uses, and compare with pic_copy_electrons by id
+    import ctypes as C
+    g.step(20)
+    b2 = g.buffers()
+    hip = C.CDLL("/opt/rocm/lib/libamdhip64.so")
+    hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+    n = int(b2["electrons"])
+    ids = np.zeros(n, dtype=np.uint32)
+    xs = np.zeros(n)
+    assert hip.hipMemcpy(ids.ctypes.data, b2["id"], 4 * n, 2) == 0
+    assert hip.hipMemcpy(xs.ctypes.data, b2["x"][0], 8 * n, 2) == 0
+    e = g.electrons()
+    own = ids & 0x7FFFFFFF
+    assert np.array_equal(np.sort(own), np.arange(n))
+    assert np.array_equal(xs, e["x"][own, 0])
+    assert np.array_equal((ids >> 31) == 0, e["alive"][own])
     g.close()
