@@ -430,24 +430,7 @@ def solid_leg(torch, targets=("al", "au"), intensities=None, processes=("ncs", "
     intensities = intensities or W.SOLID_INTENSITIES
     tb = {}
     runs = []
-    reference = {}
     for tgt in targets:
-        # the same target without the laser: with cold electrons at solid
-        # density and linear shapes on this grid the plasma heats itself (the
-        # finite-grid instability), which the fractions below are also given
-        # net of
-        w0 = W.solid(tgt, 1e21, "both", precision=precision)
-        w0["a0"] = 0.0
-        Z = int(w0["Z"])
-        if Z not in tb:
-            tb[Z] = binding.pic_build_tables(Z, 1.0, 16)
-        r0 = run_window(w0, tb[Z], 0, int(w0["steps"]), torch, events=False, wall=True)
-        s0 = r0["stats"]
-        reference[tgt] = {"e_kin_e": s0["e_kin_e"], "e_kin_i": s0["e_kin_i"], "e_field": s0["e_field"],
-                          "events": s0["events"], "wall_s": r0["wall_s"],
-                          "value": r0["window_esteps"] / r0["wall_s"]}
-        log(f"solid {tgt} without laser: electrons {s0['e_kin_e']:.4g}, ions {s0['e_kin_i']:.4g}, "
-            f"field {s0['e_field']:.4g} (heating of the cold plasma on the grid)")
         for I in intensities:
             for proc in processes:
                 w = W.solid(tgt, I, proc, precision=precision)
@@ -471,17 +454,13 @@ def solid_leg(torch, targets=("al", "au"), intensities=None, processes=("ncs", "
                            "electrons": st["e_kin_e"] / EL, "ions": st["e_kin_i"] / EL,
                            "field_in_box": st["e_field"] / EL},
                        "ions_live": st["ions_live"], "electrons_live": st["live"]}
-                ref = reference[tgt]
-                rec["fraction_of_laser_energy_net_of_heating"] = {
-                    "electrons": (st["e_kin_e"] - ref["e_kin_e"]) / EL,
-                    "ions": (st["e_kin_i"] - ref["e_kin_i"]) / EL}
                 f = rec["fraction_of_laser_energy"]
                 log(f"solid {w['name']}: {rec['value']:.3e} e-steps/s over {w['steps']} steps "
                     f"({r['wall_s']:.1f} s); photons {f['photons']:.2e}, e {f['electrons']:.3f}, "
                     f"i {f['ions']:.3f} of the laser energy")
                 runs.append(rec)
     return {"runs": runs, "laser_energy_note": "a0^2/2 * w0 sqrt(pi/2) * T (flat pulse, 2D)",
-            "without_laser": reference, "precision": precision}
+            "precision": precision}
 
 
 def pairs_leg(torch, precision="fp32"):

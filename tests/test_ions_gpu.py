@@ -176,6 +176,31 @@ def test_step_many_with_ions_matches_step(gpu_lib, tables_au):
     batch.close()
 
 
+def test_every_ion_leaves(oracle_lib, gpu_lib, tables_au):
+    """Ions set moving fast towards the right wall: all are absorbed within
+    the run (live count 0, kinetic energy 0), the density of Eq. (4) falls to
+    zero and no collision happens after that; parity throughout."""
+    _announce("ions: every ion leaves the box")
+    w = S.frozen_dense_ions(B=0.0, steps=600)
+    w["ncs"] = False
+    o, g = _pair(oracle_lib, gpu_lib, w, tables_au)
+    e = o.electrons()
+    pe = S.beam_momenta(o.N, 5.0, 2000.0, 23)
+    o.set_electrons(e["x"], pe, e["tau"])
+    g.set_electrons(e["x"], pe, e["tau"])
+    x = o.ions()["x"]
+    p = np.zeros_like(x)
+    p[:, 0] = 30.0                      # v = 0.9995 c along +x
+    o.set_ions(x, p)
+    g.set_ions(x, p)
+    o.step(600)
+    g.step(600)
+    rep = compare(o, g, label="ions-leave", p_scale=np.linalg.norm(pe, axis=1))
+    rep.update(compare_ions(o, g, "ions-leave"))
+    print(rep, flush=True)
+    assert rep["ions_live"] == 0 and g.stats()["e_kin_i"] == 0.0
+
+
 def test_ion_config_errors(gpu_lib):
     _announce("ions: config and call errors")
     from paper_1612_07592_amd.binding import PicError

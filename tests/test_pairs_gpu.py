@@ -186,6 +186,32 @@ def test_step_many_with_pairs_matches_step(gpu_lib, tables_au):
     batch.close()
 
 
+def test_pair_buffer_overflow(oracle_lib, gpu_lib, tables_al):
+    """A pair buffer of 100 records: every pair is still counted (and its
+    energy summed), 100 are stored, none is written beyond; the stored ones
+    are pairs the oracle made (its buffer large enough for all)."""
+    _announce("pairs: pair buffer overflow")
+    w = PP._bw_w()
+    o = oracle_lib.OracleSim(w, tables_al)
+    g = gpu_lib.Sim(dict(w, pair_capacity=100), tables_al)
+    x0 = 0.5 * 1024 * o.derived()["dx"][0]
+    ph = PP._field_photons(1500, 2400.0, x0)
+    o.add_photons(*ph)
+    g.add_photons(*ph)
+    o.step(60)
+    g.step(60)
+    so, sg = o.stats(), g.stats()
+    assert sg["pairs"] == so["pairs"] and sg["pairs"][0] > 100
+    assert sg["pairs_stored"] == 100 and sg["pairs_overflow"] == sg["pairs"][0] - 100
+    assert abs(sg["e_pair"][0] - so["e_pair"][0]) <= SUM_TOL * so["e_pair"][0]
+    po, pg = o.pairs(), g.pairs()
+    assert len(pg["e_minus"]) == 100
+    ko = {(int(a), int(b), int(c)): (em, ep) for a, b, c, em, ep in
+          zip(po["parent"], po["pstep"], po["proc"], po["e_minus"], po["e_plus"])}
+    for a, b, c, em, ep in zip(pg["parent"], pg["pstep"], pg["proc"], pg["e_minus"], pg["e_plus"]):
+        assert ko[(int(a), int(b), int(c))] == (em, ep)
+
+
 def test_pair_call_errors(gpu_lib, tables_au):
     _announce("pairs: call errors")
     from paper_1612_07592_amd.binding import PicError
