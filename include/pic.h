@@ -534,6 +534,8 @@ const char* pic_server_last_error(const pic_server* s);
  * nsteps steps, with tables t (deep-copied; NULL if no emission is on).
  * t_arrival < 0 stamps the current server time, otherwise it is taken as the
  * arrival time for latency.  Thread-safe with respect to pic_server_run.
+ * Jobs may have mobile ions; pair production (PIC_BW / PIC_BH) is refused,
+ * since a job carries no pair tables.
  * Errors: PIC_ERR_INVALID (bad cfg: nothing queued), PIC_ERR_TABLES. */
 pic_status pic_server_submit(pic_server* s, const pic_config* cfg, const pic_tables* t,
                              int32_t nsteps, double t_arrival, uint64_t* job);

@@ -43,6 +43,7 @@ using namespace pic;
 
 struct pic_ctx {
   Ctx c;
+  uint64_t injected = 0;  // photon records added by pic_add_photons (not kept by the method)
 };
 
 static thread_local std::string g_create_err;
@@ -994,7 +995,7 @@ pic_status pic_emission_stats(pic_ctx* ctx, pic_stats* out) {
   // the device stops reserving slots once the buffer is full, so the
   // counter can fall short of the kept photons: overflow = kept - stored
   s.photons_stored = pcount < c.pcap ? pcount : c.pcap;
-  s.overflow = s.kept[0] + s.kept[1] - s.photons_stored;
+  s.overflow = s.kept[0] + s.kept[1] + ctx->injected - s.photons_stored;
   s.e_rad_kept[0] = sum[0];
   s.e_rad_kept[1] = sum[1];
   s.e_rad_dropped = sum[2];
@@ -1574,6 +1575,7 @@ pic_status pic_add_photons(pic_ctx* ctx, uint64_t n, const double* x, const doub
   const unsigned long long np = pc + n;
   HIPCHK(c, hipMemcpyAsync(c.pcount, &np, 8, hipMemcpyHostToDevice, c.stream));
   HIPCHK(c, hipStreamSynchronize(c.stream));
+  ctx->injected += n;
   return PIC_OK;
 }
 

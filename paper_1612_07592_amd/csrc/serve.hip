@@ -172,6 +172,11 @@ const char* pic_server_last_error(const pic_server* s) { return s ? s->err.c_str
 pic_status pic_server_submit(pic_server* s, const pic_config* cfg, const pic_tables* t,
                              int32_t nsteps, double t_arrival, uint64_t* job) {
   if (!s || !cfg || !job || nsteps < 0) return PIC_ERR_INVALID;
+  if (cfg->flags & (PIC_BW | PIC_BH)) {  // a job carries emission tables only
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->err = "pair production is not served (jobs carry no pair tables)";
+    return PIC_ERR_INVALID;
+  }
   std::unique_ptr<Job> j(new (std::nothrow) Job);
   if (!j) return PIC_ERR_NOMEM;
   j->cfg = *cfg;

@@ -91,3 +91,11 @@ def frozen_dense_ions(B=50.0, steps=150):
     ion density of the electron's cell."""
     return frozen_B_beam(B=B, ne=5e7, Z=79, charge_state=79, ion_ppc=4, ion_mass_me=200.0,
                          steps=steps)
+
+
+def ions_3d(steps=80, precision="fp64"):
+    """3D laser-slab run with mobile ions (small box, several tiles)."""
+    return base(name="ions-3d", dims=3, n=[64, 16, 16], dx_lambda=[1 / 16, 1 / 16, 1 / 16], ppc=2,
+                ion_ppc=1, ion_mass_me=1000.0, x0_lambda=1.0, thickness_lambda=0.5, a0=150.0,
+                w0_lambda=0.6, focus_x_lambda=1.0, duration_cycles=2.0, envelope="flat",
+                steps=steps, precision=precision, Z=79, charge_state=79, ne_over_nc=30.0, seed=45)

@@ -91,6 +91,21 @@ def test_ions_2d_flat_pulse(oracle_lib, gpu_lib, tables_au):
     assert rep["ions_live"] < g.Ni   # some ions left through the walls
 
 
+def test_ions_3d_laser_slab(oracle_lib, gpu_lib, tables_au):
+    _announce("ions: 3D laser slab 80 steps")
+    w = S.ions_3d()
+    o, g = _pair(oracle_lib, gpu_lib, w, tables_au)
+    o.step(w["steps"])
+    g.step(w["steps"])
+    rep = compare(o, g, label="ions-3d")
+    rep.update(compare_ions(o, g, "ions-3d"))
+    fo, fg = o.fields(), g.fields()
+    rep["max_dfield"] = float(np.abs(fo - fg).max())
+    print(rep, flush=True)
+    assert rep["max_dfield"] <= 1e-12 * max(1.0, np.abs(fo).max())
+    assert rep["e_kin_i"] > 0.0
+
+
 def test_ions_2d_scattered_global_path(oracle_lib, gpu_lib, tables_au):
     """Ions shuffled over the slab, so that a workgroup's ions span more
     nodes than its LDS box holds: current and counts go to global memory."""

@@ -86,6 +86,8 @@ def test_breit_wheeler_in_prescribed_fields(oracle_lib, gpu_lib, tables_al):
     rep.update(compare_flight(o, g, "bw"))
     print(rep, flush=True)
     assert rep["pairs"][0] > 1000
+    # injected photons are stored records, not photons lost to a full buffer
+    assert g.stats()["overflow"] == 0 == o.stats()["overflow"]
 
 
 def test_bethe_heitler_on_a_dense_target(oracle_lib, gpu_lib, tables_au):

@@ -29,6 +29,7 @@ def _mix(tables_al, tables_au):
         (c1, tables_al, 64),
         (c1f, tables_al, 50),
         (S.small_3d(precision="fp32"), tables_au, 30),
+        (S.ions_2d(steps=40), tables_au, 40),            # a run with mobile ions
     ]
     return out
 
@@ -144,6 +145,16 @@ def test_server_results_same_alone_and_in_mix(gpu_lib, tables_al, tables_au):
         assert_same_run(a, mixed, f"served {w['name']}/{w['precision']}")
         a.close()
         srv.release(job)
+    srv.close()
+
+
+def test_server_refuses_pair_production(gpu_lib, tables_au):
+    from paper_1612_07592_amd.binding import PicError
+    srv = gpu_lib.Server(max_jobs=2, quantum_steps=8, hbm_reserve_bytes=0)
+    w = dict(S.small_2d(), bw=True, bh=True)
+    with pytest.raises(PicError) as e:
+        srv.submit(w, tables_au, 10)
+    assert e.value.code == 1
     srv.close()
 
 
