@@ -445,6 +445,17 @@ struct Lane {
   double taub = 0.0;              // collision optical depth at the start of the step
 };
 
+// The move of one electron, kept for the current deposit, which runs after
+// the wave's photon records and statistics are out (so that these inputs are
+// all the deposit holds in registers).
+template <class R>
+struct Move {
+  int q0[3] = {0, 0, 0}, q1[3] = {0, 0, 0};  // FP32: fixed-point positions before and after
+  R x0[3] = {R(0), R(0), R(0)};              // FP64: positions before and after
+  R x1[3] = {R(0), R(0), R(0)};
+  R v[3] = {R(0), R(0), R(0)};               // velocity of the move
+};
+
 // Photon energy of an NCS emission: each of the two rows around eta inverted
 // at the uniform, blended in ln eta, xi = exp(.), eps = xi gamma capped at the
 // kinetic energy.
@@ -602,10 +613,11 @@ __device__ inline void electron_push(const StepParams<R>& P, int64_t e, uint32_t
 }
 
 // Second half: bremsstrahlung test of Eq. (4) with the R2 energy draw, recoil,
-// move, current deposit, absorbing walls.
-template <class R, int D, class JA>
-__device__ inline void electron_finish(const StepParams<R>& P, int64_t e, uint32_t idv, double wgt,
-                                       const int* qin, const JA& cur, Lane<R>& L, Emit<R>& out) {
+// move, absorbing walls.  The current of the move is deposited later
+// (electron_deposit).
+template <class R, int D>
+__device__ inline void electron_move(const StepParams<R>& P, int64_t e, uint32_t idv, const int* qin,
+                                     Lane<R>& L, Emit<R>& out, Move<R>& mv) {
   constexpr bool kF32 = sizeof(R) == 4;
   const uint32_t n = P.step;
   const bool fpath = (P.flags & PIC_BREM_FREEPATH) != 0;
@@ -688,42 +700,49 @@ __device__ inline void electron_finish(const StepParams<R>& P, int64_t e, uint32
     }
   }
 
-  // ---- move, deposit, absorbing walls ---------------------------------------
+  // ---- move, absorbing walls -----------------------------------------------
   P.p[0][e] = px; P.p[1][e] = py; P.p[2][e] = pz;
   const R ig = m_div(R(1), gamma);
-  const R v[3] = {px * ig, py * ig, pz * ig};
+  mv.v[0] = px * ig; mv.v[1] = py * ig; mv.v[2] = pz * ig;
   bool outside = false;
   if constexpr (kF32) {
     // fixed-point move: displacement rounded to 2^-fb cell; the deposit sees
     // exactly the stored move, so charge is conserved on the stored positions
-    int q1[3] = {qin[0], qin[1], qin[2]};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) { mv.q0[a] = qin[a]; mv.q1[a] = qin[a]; }
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      q1[a] = qin[a] + (int)rintf(v[a] * P.mvq[a]);
-      if (q1[a] < 0 || q1[a] >= (P.n[a] << P.fb[a])) outside = true;
+      mv.q1[a] = qin[a] + (int)rintf(mv.v[a] * P.mvq[a]);
+      if (mv.q1[a] < 0 || mv.q1[a] >= (P.n[a] << P.fb[a])) outside = true;
     }
-    if (!(P.flags & PIC_FIELDS_FROZEN)) deposit3<D>(P, cur, qin, q1, v, wgt);
 #pragma unroll
-    for (int a = 0; a < D; ++a) reinterpret_cast<int*>(P.x[a])[e] = q1[a];
+    for (int a = 0; a < D; ++a) reinterpret_cast<int*>(P.x[a])[e] = mv.q1[a];
   } else {
-    R x1[3] = {x[0], x[1], x[2]};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) { mv.x0[a] = x[a]; mv.x1[a] = x[a]; }
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      x1[a] = x[a] + v[a] * R(P.dt);
-      if (x1[a] < R(0) || x1[a] >= R(P.L[a])) outside = true;
+      mv.x1[a] = x[a] + mv.v[a] * R(P.dt);
+      if (mv.x1[a] < R(0) || mv.x1[a] >= R(P.L[a])) outside = true;
     }
-    if (!(P.flags & PIC_FIELDS_FROZEN)) deposit<R, D>(P, cur, x, x1, v, wgt);
 #pragma unroll
-    for (int a = 0; a < D; ++a) P.x[a][e] = x1[a];
+    for (int a = 0; a < D; ++a) P.x[a][e] = mv.x1[a];
   }
   if (outside) P.id[e] = idv | kDead;
 }
 
+// Charge-conserving current of the move x^n -> x^{n+1} of one electron.
+template <class R, int D, class JA>
+__device__ inline void electron_deposit(const StepParams<R>& P, const JA& cur, const Move<R>& mv,
+                                        double wgt) {
+  if (P.flags & PIC_FIELDS_FROZEN) return;
+  if constexpr (sizeof(R) == 4) deposit3<D>(P, cur, mv.q0, mv.q1, mv.v, wgt);
+  else deposit<R, D>(P, cur, mv.x0, mv.x1, mv.v, wgt);
+}
+
 // One workgroup = one chunk of 256 consecutive electrons of the (tile-sorted)
-// SoA (chunk_of_block spreads the chunks over the XCDs).  Inside a chunk
-// electrons are dealt to lanes with a stride (16 in 1D, 4 in 2D, 8 in 3D), so the
-// 64 lanes of a wave come from many cells and rarely hit the same LDS current
-// node at once.
+// SoA (chunk_of_block spreads the chunks over the XCDs); lane t of the
+// workgroup takes electron t of the chunk.
 // When the chunk's cells fit the LDS box, the fields of the box are staged in
 // LDS and the current is accumulated there (FP64: int64 in units of 2^-40;
 // FP32: int32 in units of 2^-jbits); otherwise both go to global memory.
@@ -734,28 +753,25 @@ __device__ __forceinline__ void step_chunk(const StepParams<R>& P, const uint32_
   constexpr bool kF32 = sizeof(R) == 4;
   using JT = typename std::conditional<kF32, int, unsigned long long>::type;
   const uint32_t t = threadIdx.x;
-  // electrons are dealt to lanes with stride kDeal (lane t of the workgroup
-  // takes local electron (t mod (256/kDeal)) kDeal + t div (256/kDeal));
-  // measured: 2D gold slab 70.2 us per launch at stride 4 against 74.3 at 16,
-  // 73.7 at 2 and 83.4 unstrided; 3D gold slab 9.83 ms at 8, 9.92 at 32,
-  // 9.94 at 16, 10.14 at 64 and 11.6 at 4
-  constexpr uint32_t kDeal = D == 2 ? 4u : (D == 3 ? 8u : 16u);
-  constexpr uint32_t kRow = kBlock / kDeal;
-  const int64_t e = (int64_t)chunk * kBlock + (int64_t)((t % kRow) * kDeal + t / kRow);
+  // Consecutive lanes take consecutive electrons, so every state load and
+  // store of a wave covers whole cache lines.  (Dealing electrons to lanes
+  // with a stride, so that a wave's lanes came from many cells and rarely hit
+  // the same LDS current node at once, made each wave touch four times the
+  // lines; with the deposit holding only its inputs in registers it lost:
+  // 3D gold slab 4.94 -> 3.31 ms per launch before the laser arrives and
+  // 9.64 -> 8.46 ms at its peak against stride 8; 2D gold slab 4-5% against
+  // stride 4; 1D unchanged.)
+  const int64_t e = (int64_t)chunk * kBlock + (int64_t)t;
   const int64_t n_act = (int64_t)*P.n_active;
   // whether the photon buffer is known to be full: a flag on a line of its
   // own, set by the first reservation that reached the capacity (reading the
   // counter itself, which every wave's atomic targets, doubled the launch
   // time while the buffer was filling; a stale 0 only costs an unneeded
-  // reservation)
-  const bool buf_full = *(volatile const uint32_t*)cold(P)->pfull != 0u;
+  // reservation).  A relaxed load, first used at the append: a volatile
+  // load here made every wave wait for it before issuing anything else.
+  const uint32_t full_flag = __hip_atomic_load(cold(P)->pfull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const bool frozen = (P.flags & PIC_FIELDS_FROZEN) != 0;
-  bool live = false;
-  uint32_t idv = 0;
-  if (e < n_act) {
-    idv = P.id[e];
-    live = (idv & kDead) == 0;
-  }
+  uint32_t idv = kDead;
   R x[3] = {R(0), R(0), R(0)};
   int q[3] = {0, 0, 0};
   int bb[3] = {0, 0, 0};
@@ -765,7 +781,11 @@ __device__ __forceinline__ void step_chunk(const StepParams<R>& P, const uint32_
   constexpr bool kEarly = D == 3;
   R pin[3] = {R(0), R(0), R(0)};
   double tau_in = 0.0, wgt = 0.0;
-  if (live) {
+  // The state is loaded together with the id, not after it: every index
+  // below n_act holds an electron (an absorbed one's state is read and not
+  // used), so the loads need not wait for the id's round trip.
+  if (e < n_act) {
+    idv = P.id[e];
     if constexpr (kEarly) {
 #pragma unroll
       for (int a = 0; a < 3; ++a) pin[a] = P.p[a][e];
@@ -774,13 +794,16 @@ __device__ __forceinline__ void step_chunk(const StepParams<R>& P, const uint32_
     }
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      if constexpr (kF32) {
-        q[a] = reinterpret_cast<const int*>(P.x[a])[e];
-        bb[a] = (q[a] >> P.fb[a]) - 1;
-      } else {
-        x[a] = P.x[a][e];
-        bb[a] = (int)m_floor(x[a] * R(P.idx[a])) - 1;
-      }
+      if constexpr (kF32) q[a] = reinterpret_cast<const int*>(P.x[a])[e];
+      else x[a] = P.x[a][e];
+    }
+  }
+  const bool live = (idv & kDead) == 0;
+  if (live) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      if constexpr (kF32) bb[a] = (q[a] >> P.fb[a]) - 1;
+      else bb[a] = (int)m_floor(x[a] * R(P.idx[a])) - 1;
     }
   }
   // ---- the chunk's box of nodes (deposit windows cover the gathers) --------
@@ -851,6 +874,7 @@ __device__ __forceinline__ void step_chunk(const StepParams<R>& P, const uint32_
 
   Emit<R> out;
   Lane<R> L;
+  Move<R> mv;
   if (live) {
     if constexpr (!kEarly) wgt = P.w[e];
     if constexpr (kFL) {
@@ -863,45 +887,8 @@ __device__ __forceinline__ void step_chunk(const StepParams<R>& P, const uint32_
     } else {
       electron_push<R, D>(P, e, idv, x, q, pin, tau_in, GlobalField<R>{P.F, I}, L, out);
     }
+    electron_move<R, D>(P, e, idv, q, L, out, mv);
   }
-  if (live) {
-    if (tiled || jtiled) {
-      if constexpr (kF32) {
-        const LdsCurrent32 ja{reinterpret_cast<int*>(sJ), lo[0], lo[1], lo[2], ext[0], ext[1], nodes,
-                              (float)ldexp(1.0, P.jbits)};
-        electron_finish<R, D>(P, e, idv, wgt, q, ja, L, out);
-      } else {
-        const LdsCurrent ja{reinterpret_cast<unsigned long long*>(sJ), lo[0], lo[1], lo[2], ext[0], ext[1], nodes};
-        electron_finish<R, D>(P, e, idv, wgt, q, ja, L, out);
-      }
-    } else {
-      if constexpr (kF32) {
-        const GlobalCurrent32 ja{{P.J[0], P.J[1], P.J[2]}, {P.gg[0], P.gg[1], P.gg[2], P.sz[0], P.sz[1]},
-                                 (float)ldexp(1.0, P.jbits), 40 - P.jbits};
-        electron_finish<R, D>(P, e, idv, wgt, q, ja, L, out);
-      } else {
-        const GlobalCurrent ja{{P.J[0], P.J[1], P.J[2]}, {P.gg[0], P.gg[1], P.gg[2], P.sz[0], P.sz[1]}};
-        electron_finish<R, D>(P, e, idv, wgt, q, ja, L, out);
-      }
-    }
-  }
-  __syncthreads();
-  if (tiled || jtiled) {  // flush the LDS current: one global atomic per touched node
-    for (int l = t; l < nodes; l += kBlock) {
-      int i, j, k;
-      decode(l, i, j, k);
-      const int64_t m = I(i, j, k);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const JT q = sJ[c * nodes + l];
-        if (q != JT(0)) {
-          if constexpr (kF32) atomicAdd(P.J[c] + m, (unsigned long long)((long long)q << (40 - P.jbits)));
-          else atomicAdd(P.J[c] + m, q);
-        }
-      }
-    }
-  }
-
   // ---- photon records: one slot reservation per wave ----------------------
   // NCS and bremsstrahlung records of the wave take consecutive slots from
   // one atomic on the buffer's counter.  Once a reservation has reached the
@@ -916,18 +903,18 @@ __device__ __forceinline__ void step_chunk(const StepParams<R>& P, const uint32_
   const bool rec1 = out.ev_br;
   const unsigned long long mr0 = __ballot(rec0), mr1 = __ballot(rec1);
   // spectrum of every kept photon, stored or not (quarter-octave bins): LDS
-  // counts of the chunk, added after the append stage to one of kSpecCopies
+  // counts of the chunk, added at the chunk's end to one of kSpecCopies
   // copies in memory (per-lane atomics on a few global bins cost 14 ms of a
   // 24 ms launch on the 3D gold slab at the laser peak)
   if (rec0) atomicAdd(s_spec + spectrum_bin<R>(out.e[0]), 1u);
   if (rec1) atomicAdd(s_spec + PIC_SPECTRUM_BINS + spectrum_bin<R>(out.e[1]), 1u);
-  if ((mr0 | mr1) != 0ull && !buf_full) {  // wave-uniform
+  if ((mr0 | mr1) != 0ull && full_flag == 0u) {  // wave-uniform
     const ColdPtr<R> C = cold(P);
     unsigned long long base = 0;
     if (lane == 0) {
       const unsigned long long nr = (unsigned long long)(__popcll(mr0) + __popcll(mr1));
       base = atomicAdd(C->pcount, nr);
-      if (base + nr >= C->pcap) *(volatile uint32_t*)C->pfull = 1u;
+      if (base + nr >= C->pcap) __hip_atomic_store(C->pfull, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     base = __shfl(base, 0, 64);
 #pragma unroll
@@ -951,45 +938,85 @@ __device__ __forceinline__ void step_chunk(const StepParams<R>& P, const uint32_
     }
   }
 
-  if (__syncthreads_or((int)(rec0 || rec1)) && t < 2 * PIC_SPECTRUM_BINS) {  // block-uniform
+  // ---- per-wave statistics slot --------------------------------------------
+  const unsigned long long m_live = __ballot(live);
+  if (m_live != 0ull) {  // wave-uniform
+    const int64_t slot = (int64_t)chunk * (kBlock / 64) + (t >> 6);
+    const unsigned long long m_ncs = __ballot(out.ev_ncs);
+    const unsigned long long m_br = __ballot(out.ev_br);
+    const unsigned long long m_cl = __ballot(out.clamped);
+    unsigned long long* C = cold(P)->slot_cnt + slot * kSlotCnt;
+    // the slot is this wave's alone; the counts go in as atomics whose result
+    // is not used, so the wave does not wait for a read of the old value
+    auto bump = [&](int k, unsigned long long v) { if (v) atomicAdd(C + k, v); };
+    if (lane == 0) {
+      bump(SC_ESTEPS, (unsigned long long)__popcll(m_live));
+      if (!tiled && !jtiled && !frozen) bump(SC_UNTILED, (unsigned long long)__popcll(m_live));
+    }
+    if ((m_ncs | m_br | m_cl) != 0ull) {  // wave-uniform
+      const unsigned long long m_keep = __ballot(rec0);
+      const double e_keep0 = rec0 ? wgt * (double)out.e[0] : 0.0;
+      const double e_drop = (out.ev_ncs && !out.keep_ncs) ? wgt * (double)out.e[0] : 0.0;
+      const double e_keep1 = out.ev_br ? wgt * (double)out.e[1] : 0.0;
+      const double s0 = wave_sum(e_keep0), s1 = wave_sum(e_keep1), s2 = wave_sum(e_drop);
+      if (lane == 0) {
+        bump(SC_EV_NCS, (unsigned long long)__popcll(m_ncs));
+        bump(SC_EV_BR, (unsigned long long)__popcll(m_br));
+        bump(SC_KEPT_NCS, (unsigned long long)__popcll(m_keep));
+        bump(SC_KEPT_BR, (unsigned long long)__popcll(m_br));
+        bump(SC_DROPPED, (unsigned long long)__popcll(m_ncs & ~m_keep));
+        bump(SC_CLAMPED, (unsigned long long)__popcll(m_cl));
+        double* Sm = cold(P)->slot_sum + slot * kSlotSum;
+        if (m_keep) neumaier(Sm + 0, Sm + 1, s0);
+        if (m_br) neumaier(Sm + 2, Sm + 3, s1);
+        if (m_ncs & ~m_keep) neumaier(Sm + 4, Sm + 5, s2);
+      }
+    }
+  }
+
+  // ---- current deposit: last, so that its inputs are all that is live -----
+  if (live) {
+    if (tiled || jtiled) {
+      if constexpr (kF32) {
+        const LdsCurrent32 ja{reinterpret_cast<int*>(sJ), lo[0], lo[1], lo[2], ext[0], ext[1], nodes,
+                              (float)ldexp(1.0, P.jbits)};
+        electron_deposit<R, D>(P, ja, mv, wgt);
+      } else {
+        const LdsCurrent ja{reinterpret_cast<unsigned long long*>(sJ), lo[0], lo[1], lo[2], ext[0], ext[1], nodes};
+        electron_deposit<R, D>(P, ja, mv, wgt);
+      }
+    } else {
+      if constexpr (kF32) {
+        const GlobalCurrent32 ja{{P.J[0], P.J[1], P.J[2]}, {P.gg[0], P.gg[1], P.gg[2], P.sz[0], P.sz[1]},
+                                 (float)ldexp(1.0, P.jbits), 40 - P.jbits};
+        electron_deposit<R, D>(P, ja, mv, wgt);
+      } else {
+        const GlobalCurrent ja{{P.J[0], P.J[1], P.J[2]}, {P.gg[0], P.gg[1], P.gg[2], P.sz[0], P.sz[1]}};
+        electron_deposit<R, D>(P, ja, mv, wgt);
+      }
+    }
+  }
+  const int any_rec = __syncthreads_or((int)(rec0 || rec1));
+  if (tiled || jtiled) {  // flush the LDS current: one global atomic per touched node
+    for (int l = t; l < nodes; l += kBlock) {
+      int i, j, k;
+      decode(l, i, j, k);
+      const int64_t m = I(i, j, k);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const JT q = sJ[c * nodes + l];
+        if (q != JT(0)) {
+          if constexpr (kF32) atomicAdd(P.J[c] + m, (unsigned long long)((long long)q << (40 - P.jbits)));
+          else atomicAdd(P.J[c] + m, q);
+        }
+      }
+    }
+  }
+  if (any_rec && t < 2 * PIC_SPECTRUM_BINS) {  // block-uniform
     const uint32_t v = s_spec[t];
     if (v)
       atomicAdd(cold(P)->spec + (size_t)(chunk % kSpecCopies) * (2 * PIC_SPECTRUM_BINS) + t,
                 (unsigned long long)v);
-  }
-
-  // ---- per-wave statistics slot --------------------------------------------
-  const unsigned long long m_live = __ballot(live);
-  if (m_live == 0ull) return;  // wave-uniform
-  const int64_t slot = (int64_t)chunk * (kBlock / 64) + (t >> 6);
-  const unsigned long long m_ncs = __ballot(out.ev_ncs);
-  const unsigned long long m_br = __ballot(out.ev_br);
-  const unsigned long long m_cl = __ballot(out.clamped);
-  unsigned long long* C = cold(P)->slot_cnt + slot * kSlotCnt;
-  // the slot is this wave's alone; the counts go in as atomics whose result
-  // is not used, so the wave does not wait for a read of the old value
-  auto bump = [&](int k, unsigned long long v) { if (v) atomicAdd(C + k, v); };
-  if (lane == 0) {
-    bump(SC_ESTEPS, (unsigned long long)__popcll(m_live));
-    if (!tiled && !jtiled && !frozen) bump(SC_UNTILED, (unsigned long long)__popcll(m_live));
-  }
-  if ((m_ncs | m_br | m_cl) == 0ull) return;  // wave-uniform
-  const unsigned long long m_keep = __ballot(rec0);
-  const double e_keep0 = rec0 ? wgt * (double)out.e[0] : 0.0;
-  const double e_drop = (out.ev_ncs && !out.keep_ncs) ? wgt * (double)out.e[0] : 0.0;
-  const double e_keep1 = out.ev_br ? wgt * (double)out.e[1] : 0.0;
-  const double s0 = wave_sum(e_keep0), s1 = wave_sum(e_keep1), s2 = wave_sum(e_drop);
-  if (lane == 0) {
-    bump(SC_EV_NCS, (unsigned long long)__popcll(m_ncs));
-    bump(SC_EV_BR, (unsigned long long)__popcll(m_br));
-    bump(SC_KEPT_NCS, (unsigned long long)__popcll(m_keep));
-    bump(SC_KEPT_BR, (unsigned long long)__popcll(m_br));
-    bump(SC_DROPPED, (unsigned long long)__popcll(m_ncs & ~m_keep));
-    bump(SC_CLAMPED, (unsigned long long)__popcll(m_cl));
-    double* Sm = cold(P)->slot_sum + slot * kSlotSum;
-    if (m_keep) neumaier(Sm + 0, Sm + 1, s0);
-    if (m_br) neumaier(Sm + 2, Sm + 3, s1);
-    if (m_ncs & ~m_keep) neumaier(Sm + 4, Sm + 5, s2);
   }
 }
 
