@@ -33,6 +33,15 @@ __device__ inline ColdPtr<R> cold(const StepParams<R>& P) { return (ColdPtr<R>)P
 // FP32 path: contribution -> multiple of 2^-jbits in float arithmetic.
 __device__ inline int q32(float v, float scale) { return (int)rintf(v * scale); }
 
+// a b rounded to the nearest integer (ties to even) in one rounding: the fma
+// adds 1.5 2^23, whose unit in the last place is 1, and the integer is read
+// from the low bits.  Exact for |a b| < 2^22, which the current quantum
+// guarantees for every contribution (one chunk's sum at a node stays below
+// 2^30, 256 contributions of at most 2^22 each).
+__device__ inline int round_prod(float a, float b) {
+  return __float_as_int(__builtin_fmaf(a, b, 12582912.0f)) - 0x4B400000;
+}
+
 // The FP32 accessors also offer a linear form: lin(i, j, k) gives a node's
 // index once, neighbours are lin + 1, lin + s1, lin + s2 (32-bit indices; the
 // field arrays hold fewer than 2^31 nodes).
@@ -58,6 +67,10 @@ struct GlobalCurrent32 {
     const int q = (int)rintf(v);
     if (q != 0) atomicAdd(J[c] + l, (unsigned long long)((long long)q << shift));
   }
+  __device__ inline void addq2(int c, int l, float a, float b) const {
+    const int q = round_prod(a, b);
+    if (q != 0) atomicAdd(J[c] + l, (unsigned long long)((long long)q << shift));
+  }
 };
 
 struct LdsCurrent32 {
@@ -78,6 +91,10 @@ struct LdsCurrent32 {
   // atomic at all
   __device__ inline void addq(int c, int l, float v) const {
     const int q = (int)rintf(v);
+    if (q != 0) atomicAdd(T + c * nodes + l, q);
+  }
+  __device__ inline void addq2(int c, int l, float a, float b) const {
+    const int q = round_prod(a, b);
     if (q != 0) atomicAdd(T + c * nodes + l, q);
   }
 };
@@ -212,21 +229,21 @@ __device__ inline void deposit3(const StepParams<float>& P, const Acc& J, const 
     }
     if (D == 1) {
       const float qx = c0 * (float)P.dxdt[0];
-      J.addq(0, base, qx * (f1s[0] - f0s[0]));
+      J.addq2(0, base, qx, f1s[0] - f0s[0]);
       const float cy = 0.5f * c0 * v[1], cz = 0.5f * c0 * v[2];
       const float s0 = A0[0] + B0[0], s1w = A1[0] + B1[0];
-      J.addq(1, base, cy * s0);
-      J.addq(1, base + 1, cy * s1w);
-      J.addq(2, base, cz * s0);
-      J.addq(2, base + 1, cz * s1w);
+      J.addq2(1, base, cy, s0);
+      J.addq2(1, base + 1, cy, s1w);
+      J.addq2(2, base, cz, s0);
+      J.addq2(2, base + 1, cz, s1w);
     } else if (D == 2) {
       const float qx = 0.5f * c0 * (float)P.dxdt[0], qy = 0.5f * c0 * (float)P.dxdt[1];
       const float cz = c0 * v[2] * (1.f / 6.f);
       const float Fx = qx * (f1s[0] - f0s[0]), Fy = qy * (f1s[1] - f0s[1]);
-      J.addq(0, base, Fx * (A0[1] + B0[1]));
-      J.addq(0, base + s1, Fx * (A1[1] + B1[1]));
-      J.addq(1, base, Fy * (A0[0] + B0[0]));
-      J.addq(1, base + 1, Fy * (A1[0] + B1[0]));
+      J.addq2(0, base, Fx, A0[1] + B0[1]);
+      J.addq2(0, base + s1, Fx, A1[1] + B1[1]);
+      J.addq2(1, base, Fy, A0[0] + B0[0]);
+      J.addq2(1, base + 1, Fy, A1[0] + B1[0]);
       const float G0 = cz * __builtin_fmaf(2.f, A0[0], B0[0]), H0 = cz * __builtin_fmaf(2.f, B0[0], A0[0]);
       const float G1 = cz * __builtin_fmaf(2.f, A1[0], B1[0]), H1 = cz * __builtin_fmaf(2.f, B1[0], A1[0]);
       J.addq(2, base, __builtin_fmaf(G0, A0[1], H0 * B0[1]));
@@ -251,21 +268,21 @@ __device__ inline void deposit3(const StepParams<float>& P, const Acc& J, const 
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
           const float sa0 = k ? Z1[2] : Z0[2], sa1 = k ? Y1[2] : Y0[2];
-          J.addq(0, base + j * s1 + k * s2, F[0] * __builtin_fmaf(G[1][j], sa0, H[1][j] * sa1));
+          J.addq2(0, base + j * s1 + k * s2, F[0], __builtin_fmaf(G[1][j], sa0, H[1][j] * sa1));
         }
 #pragma unroll
       for (int k = 0; k < 2; ++k)
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
           const float sa0 = k ? Z1[2] : Z0[2], sa1 = k ? Y1[2] : Y0[2];
-          J.addq(1, base + i + k * s2, F[1] * __builtin_fmaf(G[0][i], sa0, H[0][i] * sa1));
+          J.addq2(1, base + i + k * s2, F[1], __builtin_fmaf(G[0][i], sa0, H[0][i] * sa1));
         }
 #pragma unroll
       for (int j = 0; j < 2; ++j)
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
           const float sa0 = j ? Z1[1] : Z0[1], sa1 = j ? Y1[1] : Y0[1];
-          J.addq(2, base + i + j * s1, F[2] * __builtin_fmaf(G[0][i], sa0, H[0][i] * sa1));
+          J.addq2(2, base + i + j * s1, F[2], __builtin_fmaf(G[0][i], sa0, H[0][i] * sa1));
         }
     }
     return;
@@ -294,8 +311,8 @@ __device__ inline void deposit3(const StepParams<float>& P, const Acc& J, const 
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       const float sa = S0[0][i] + S1[0][i];
-      J.addq(1, base + i, cy * sa);
-      J.addq(2, base + i, cz * sa);
+      J.addq2(1, base + i, cy, sa);
+      J.addq2(2, base + i, cz, sa);
     }
   } else if (D == 2) {
     const float qx = 0.5f * c0 * (float)P.dxdt[0], qy = 0.5f * c0 * (float)P.dxdt[1];
@@ -315,11 +332,11 @@ __device__ inline void deposit3(const StepParams<float>& P, const Acc& J, const 
 #pragma unroll
     for (int j = 0; j < 3; ++j)
 #pragma unroll
-      for (int i = 0; i < 2; ++i) J.addq(0, base + i + j * s1, Fx[i] * sy[j]);
+      for (int i = 0; i < 2; ++i) J.addq2(0, base + i + j * s1, Fx[i], sy[j]);
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int i = 0; i < 3; ++i) J.addq(1, base + i + j * s1, Fy[j] * sx[i]);
+      for (int i = 0; i < 3; ++i) J.addq2(1, base + i + j * s1, Fy[j], sx[i]);
 #pragma unroll
     for (int j = 0; j < 3; ++j)
 #pragma unroll
@@ -344,7 +361,7 @@ __device__ inline void deposit3(const StepParams<float>& P, const Acc& J, const 
       for (int j = 0; j < 3; ++j) {
         const float T = __builtin_fmaf(G[1][j], S0[2][k], H[1][j] * S1[2][k]);
 #pragma unroll
-        for (int i = 0; i < 2; ++i) J.addq(0, base + i + j * s1 + k * s2, F[0][i] * T);
+        for (int i = 0; i < 2; ++i) J.addq2(0, base + i + j * s1 + k * s2, F[0][i], T);
       }
 #pragma unroll
     for (int k = 0; k < 3; ++k)
@@ -352,7 +369,7 @@ __device__ inline void deposit3(const StepParams<float>& P, const Acc& J, const 
       for (int i = 0; i < 3; ++i) {
         const float T = __builtin_fmaf(G[0][i], S0[2][k], H[0][i] * S1[2][k]);
 #pragma unroll
-        for (int j = 0; j < 2; ++j) J.addq(1, base + i + j * s1 + k * s2, F[1][j] * T);
+        for (int j = 0; j < 2; ++j) J.addq2(1, base + i + j * s1 + k * s2, F[1][j], T);
       }
 #pragma unroll
     for (int j = 0; j < 3; ++j)
@@ -360,7 +377,7 @@ __device__ inline void deposit3(const StepParams<float>& P, const Acc& J, const 
       for (int i = 0; i < 3; ++i) {
         const float T = __builtin_fmaf(G[0][i], S0[1][j], H[0][i] * S1[1][j]);
 #pragma unroll
-        for (int k = 0; k < 2; ++k) J.addq(2, base + i + j * s1 + k * s2, F[2][k] * T);
+        for (int k = 0; k < 2; ++k) J.addq2(2, base + i + j * s1 + k * s2, F[2][k], T);
       }
   }
 }
@@ -740,6 +757,28 @@ __device__ inline void electron_deposit(const StepParams<R>& P, const JA& cur, c
   else deposit<R, D>(P, cur, mv.x0, mv.x1, mv.v, wgt);
 }
 
+// Minimum over the 64 lanes of two packed 16-bit integers per lane (DPP row
+// shifts and broadcasts; the result is read from lane 63).  Call with every
+// lane of the wave active.
+__device__ inline uint32_t wave_min_pk16(uint32_t v) {
+  typedef short S2 __attribute__((ext_vector_type(2)));
+  auto mn = [](uint32_t a, uint32_t b) {
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_min(__builtin_bit_cast(S2, a), __builtin_bit_cast(S2, b)));
+  };
+  constexpr int kId = 0x7fff7fff;
+  v = mn(v, (uint32_t)__builtin_amdgcn_update_dpp(kId, (int)v, 0x111, 0xf, 0xf, false));  // row_shr:1
+  v = mn(v, (uint32_t)__builtin_amdgcn_update_dpp(kId, (int)v, 0x112, 0xf, 0xf, false));  // row_shr:2
+  v = mn(v, (uint32_t)__builtin_amdgcn_update_dpp(kId, (int)v, 0x114, 0xf, 0xf, false));  // row_shr:4
+  v = mn(v, (uint32_t)__builtin_amdgcn_update_dpp(kId, (int)v, 0x118, 0xf, 0xf, false));  // row_shr:8
+  v = mn(v, (uint32_t)__builtin_amdgcn_update_dpp(kId, (int)v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+  v = mn(v, (uint32_t)__builtin_amdgcn_update_dpp(kId, (int)v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+__device__ inline uint32_t pk16(int lo, int hi) { return ((uint32_t)lo & 0xffffu) | ((uint32_t)hi << 16); }
+__device__ inline int lo16(uint32_t w) { return (int)(short)(w & 0xffffu); }
+__device__ inline int hi16(uint32_t w) { return (int)(short)(w >> 16); }
+
 // One workgroup = one chunk of 256 consecutive electrons of the (tile-sorted)
 // SoA (chunk_of_block spreads the chunks over the XCDs); lane t of the
 // workgroup takes electron t of the chunk.
@@ -748,8 +787,7 @@ __device__ inline void electron_deposit(const StepParams<R>& P, const JA& cur, c
 // FP32: int32 in units of 2^-jbits); otherwise both go to global memory.
 template <class R, int D>
 __device__ __forceinline__ void step_chunk(const StepParams<R>& P, const uint32_t chunk,
-                                           unsigned char* smem, int* s_lo, int* s_hi,
-                                           uint32_t* s_spec) {
+                                           unsigned char* smem, uint32_t* s_box, uint32_t* s_spec) {
   constexpr bool kF32 = sizeof(R) == 4;
   using JT = typename std::conditional<kF32, int, unsigned long long>::type;
   const uint32_t t = threadIdx.x;
@@ -807,29 +845,61 @@ __device__ __forceinline__ void step_chunk(const StepParams<R>& P, const uint32_
     }
   }
   // ---- the chunk's box of nodes (deposit windows cover the gathers) --------
-  if (t < 3) { s_lo[t] = 0x7fffffff; s_hi[t] = -0x7fffffff; }
+  // Per lane the window [bb, bb + 3] of each axis; the minimum of bb and of
+  // -(bb + 3) over the chunk give the box.  Each wave reduces them as packed
+  // 16-bit pairs (one word per two values) and leaves its words in LDS; the
+  // chunk's box is the minimum over the four waves' words.  A cell index
+  // beyond +-32000 (grids that large) widens the box to the whole 16-bit
+  // range, which no LDS box holds: such a chunk takes the global path.
   if (t < 2 * PIC_SPECTRUM_BINS) s_spec[t] = 0u;
-  __syncthreads();
-  if (live && !frozen) {
+  {
+    constexpr int kW = (2 * D + 1) / 2;  // packed words: 1 (1D), 2 (2D), 3 (3D)
+    int v[6] = {32767, 32767, 32767, 32767, 32767, 32767};
+    if (live && !frozen) {
 #pragma unroll
-    for (int a = 0; a < D; ++a) {
-      atomicMin(&s_lo[a], bb[a]);
-      atomicMax(&s_hi[a], bb[a] + 3);
+      for (int a = 0; a < D; ++a) {
+        const bool in = bb[a] >= -32000 && bb[a] <= 32000;
+        v[a] = in ? bb[a] : -32768;             // lower end
+        v[D + a] = in ? -(bb[a] + 3) : -32767;  // minus the upper end
+      }
+    }
+    const uint32_t wv = t >> 6;
+#pragma unroll
+    for (int k = 0; k < kW; ++k) {
+      const uint32_t m = wave_min_pk16(pk16(v[2 * k], v[2 * k + 1]));
+      if ((t & 63u) == 0u) s_box[4 * k + wv] = m;
     }
   }
   __syncthreads();
   int lo[3] = {0, 0, 0}, ext[3] = {1, 1, 1};
   int nodes = 0;
   bool tiled = false;
-  if (!frozen && P.lds_nodes > 0 && s_lo[0] <= s_hi[0]) {
-    nodes = 1;
+  {
+    typedef short S2 __attribute__((ext_vector_type(2)));
+    auto mn = [](uint32_t a, uint32_t b) {
+      return __builtin_bit_cast(uint32_t, __builtin_elementwise_min(__builtin_bit_cast(S2, a), __builtin_bit_cast(S2, b)));
+    };
+    constexpr int kW = (2 * D + 1) / 2;
+    int u[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
-    for (int a = 0; a < D; ++a) {
-      lo[a] = s_lo[a];
-      ext[a] = s_hi[a] - s_lo[a] + 1;
-      nodes *= ext[a];
+    for (int k = 0; k < kW; ++k) {
+      const uint4 w4 = *reinterpret_cast<const uint4*>(s_box + 4 * k);
+      const uint32_t m = mn(mn(w4.x, w4.y), mn(w4.z, w4.w));
+      u[2 * k] = lo16(m);
+      u[2 * k + 1] = hi16(m);
     }
-    tiled = nodes <= P.lds_nodes;
+    // u[a] = lowest bb, -u[D + a] = highest bb + 3 (empty chunk: lo > hi)
+    if (!frozen && P.lds_nodes > 0 && u[0] <= -u[D]) {
+      int64_t nn = 1;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        lo[a] = u[a];
+        ext[a] = -u[D + a] - u[a] + 1;
+        nn *= ext[a];
+      }
+      tiled = nn <= P.lds_nodes;
+      nodes = (int)(nn < (1 << 30) ? nn : (1 << 30));
+    }
   }
   constexpr bool kFL = FieldsInLds<R, D>::value;
   // 1D/2D boxes too large for fields + current may still fit the current
@@ -999,15 +1069,16 @@ __device__ __forceinline__ void step_chunk(const StepParams<R>& P, const uint32_
   const int any_rec = __syncthreads_or((int)(rec0 || rec1));
   if (tiled || jtiled) {  // flush the LDS current: one global atomic per touched node
     for (int l = t; l < nodes; l += kBlock) {
+      const JT qs[3] = {sJ[l], sJ[nodes + l], sJ[2 * nodes + l]};
+      if ((qs[0] | qs[1] | qs[2]) == JT(0)) continue;  // untouched node: no index needed
       int i, j, k;
       decode(l, i, j, k);
       const int64_t m = I(i, j, k);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const JT q = sJ[c * nodes + l];
-        if (q != JT(0)) {
-          if constexpr (kF32) atomicAdd(P.J[c] + m, (unsigned long long)((long long)q << (40 - P.jbits)));
-          else atomicAdd(P.J[c] + m, q);
+        if (qs[c] != JT(0)) {
+          if constexpr (kF32) atomicAdd(P.J[c] + m, (unsigned long long)((long long)qs[c] << (40 - P.jbits)));
+          else atomicAdd(P.J[c] + m, qs[c]);
         }
       }
     }
@@ -1037,9 +1108,9 @@ __device__ inline uint32_t chunk_of_block(uint32_t b) {
 template <class R, int D>
 __global__ __launch_bounds__(kBlock) void k_electron_step(const StepParams<R> P) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ int s_lo[3], s_hi[3];
+  __shared__ __align__(16) uint32_t s_box[12];
   __shared__ uint32_t s_spec[2 * PIC_SPECTRUM_BINS];
-  step_chunk<R, D>(P, chunk_of_block(blockIdx.x), smem, s_lo, s_hi, s_spec);
+  step_chunk<R, D>(P, chunk_of_block(blockIdx.x), smem, s_box, s_spec);
 }
 
 // Batched form for several runs: the chunks of every run are laid end to end
@@ -1054,7 +1125,7 @@ __global__ __launch_bounds__(kBlock) void k_electron_step_batch(const StepParams
                                                                 const uint32_t* __restrict__ first,
                                                                 int njobs) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ int s_lo[3], s_hi[3];
+  __shared__ __align__(16) uint32_t s_box[12];
   __shared__ uint32_t s_spec[2 * PIC_SPECTRUM_BINS];
   const uint32_t w = chunk_of_block(blockIdx.x);
   if (w >= first[njobs]) return;  // padding of the grid to a multiple of kGridQuantum
@@ -1063,7 +1134,7 @@ __global__ __launch_bounds__(kBlock) void k_electron_step_batch(const StepParams
     const int mid = (lo + hi + 1) >> 1;
     if (first[mid] <= w) lo = mid; else hi = mid - 1;
   }
-  step_chunk<R, D>(tab[lo], w - first[lo], smem, s_lo, s_hi, s_spec);
+  step_chunk<R, D>(tab[lo], w - first[lo], smem, s_box, s_spec);
 }
 
 template <class R, int D>
