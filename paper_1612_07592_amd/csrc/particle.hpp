@@ -8,14 +8,26 @@
 
 namespace pic {
 
+// FP64: the fixed-order series of fpmath.hpp (the same bits as the oracle).
+// FP32: the hardware's transcendental unit (v_sqrt_f32, v_log_f32 and
+// v_exp_f32, each within a few ulp), a few instructions where the
+// correctly rounded library forms take 11-24; the FP32 path's results are
+// judged statistically against the FP64 path.  expm1 keeps its relative
+// accuracy for small arguments (the per-step bremsstrahlung probability
+// 1 - exp(-X)) with four terms of its series below 2^-7 (relative error
+// under x^3/120 < 4e-9).
 __device__ inline double m_sqrt(double v) { return sqrt(v); }
-__device__ inline float m_sqrt(float v) { return sqrtf(v); }
+__device__ inline float m_sqrt(float v) { return __builtin_amdgcn_sqrtf(v); }
 __device__ inline double m_log(double v) { return fp_log(v); }
-__device__ inline float m_log(float v) { return logf(v); }
+__device__ inline float m_log(float v) { return __logf(v); }
 __device__ inline double m_exp(double v) { return fp_exp(v); }
-__device__ inline float m_exp(float v) { return expf(v); }
+__device__ inline float m_exp(float v) { return __expf(v); }
 __device__ inline double m_expm1(double v) { return fp_expm1(v); }
-__device__ inline float m_expm1(float v) { return expm1f(v); }
+__device__ inline float m_expm1(float v) {
+  if (fabsf(v) < 0.0078125f)
+    return v * __builtin_fmaf(v, __builtin_fmaf(v, __builtin_fmaf(v, 1.f / 24.f, 1.f / 6.f), 0.5f), 1.f);
+  return __expf(v) - 1.f;
+}
 __device__ inline double m_floor(double v) { return floor(v); }
 __device__ inline float m_floor(float v) { return floorf(v); }
 __device__ inline double m_sin(double v) { return sin(v); }

@@ -148,6 +148,35 @@ __device__ inline float gather_q(const F& f, int c, const Splits& s) {
   return lerp_f(a2, b2, f2);
 }
 
+// 3D FP32 gather in two rounds: the eight nodes of the three E components
+// are loaded before any is interpolated, then those of B, so that twelve
+// node-pair loads of an electron are in flight together (interleaved with
+// the interpolation, the compiler waited for each component's loads in
+// turn; all six components at once need 81 VGPRs).  Measured on the 3D gold
+// slab: 3.24 -> 2.83 ms per launch before the laser arrives, 8.45 -> 8.12 ms
+// at its peak.  The interpolation is gather_q's, in the same order.
+template <int SX, int SY, int SZ, class F>
+__device__ inline void gather_load8(const F& f, int c, const Splits& s, float v[8]) {
+  const int l = f.lin(s.i[0][SX], s.i[1][SY], s.i[2][SZ]);
+  const int s1 = f.s1(), s2 = f.s2();
+  v[0] = f.at(c, l);
+  v[1] = f.at(c, l + 1);
+  v[2] = f.at(c, l + s1);
+  v[3] = f.at(c, l + s1 + 1);
+  v[4] = f.at(c, l + s2);
+  v[5] = f.at(c, l + s2 + 1);
+  v[6] = f.at(c, l + s2 + s1);
+  v[7] = f.at(c, l + s2 + s1 + 1);
+}
+
+template <int SX, int SY, int SZ>
+__device__ inline float interp8(const float v[8], const Splits& s) {
+  const float f0 = s.f[0][SX], f1 = s.f[1][SY], f2 = s.f[2][SZ];
+  const float a2 = lerp_f(lerp_f(v[0], v[1], f0), lerp_f(v[2], v[3], f0), f1);
+  const float b2 = lerp_f(lerp_f(v[4], v[5], f0), lerp_f(v[6], v[7], f0), f1);
+  return lerp_f(a2, b2, f2);
+}
+
 // Inverse of one NCS cumulative row: ln(xi) at uniform u.
 template <class R>
 __device__ inline R ncs_inverse(const R* __restrict__ C, const R* __restrict__ lnxi, int n, R u,
@@ -389,10 +418,25 @@ __device__ inline void neumaier(double* s, double* c, double v) {
   *s = t;
 }
 
+// Sum over the 64 lanes in a fixed order: DPP row shifts and broadcasts
+// collect it in lane 63 (the halves of each double moved together), from
+// where it is read as a wave-uniform value.  Call with every lane active.
+template <int kCtrl, int kRows>
+__device__ inline double dpp_add(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), kCtrl, kRows, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), kCtrl, kRows, 0xf, false);
+  return v + __hiloint2double(hi, lo);
+}
+
 __device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v = dpp_add<0x111, 0xf>(v);  // row_shr:1
+  v = dpp_add<0x112, 0xf>(v);  // row_shr:2
+  v = dpp_add<0x114, 0xf>(v);  // row_shr:4
+  v = dpp_add<0x118, 0xf>(v);  // row_shr:8
+  v = dpp_add<0x142, 0xa>(v);  // row_bcast:15
+  v = dpp_add<0x143, 0xc>(v);  // row_bcast:31
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
+                          __builtin_amdgcn_readlane(__double2loint(v), 63));
 }
 
 __device__ inline uint32_t lane_offset(unsigned long long mask) {
@@ -555,12 +599,28 @@ __device__ inline void electron_push(const StepParams<R>& P, int64_t e, uint32_t
     }
   } else if constexpr (kF32) {
     const Splits sp = make_splits<D>(qin, P.fb, P.iqs);
-    E0 = gather_q<D, 1, 0, 0>(fld, 0, sp);
-    E1 = gather_q<D, 0, 1, 0>(fld, 1, sp);
-    E2 = gather_q<D, 0, 0, 1>(fld, 2, sp);
-    B0 = gather_q<D, 0, 1, 1>(fld, 3, sp);
-    B1 = gather_q<D, 1, 0, 1>(fld, 4, sp);
-    B2 = gather_q<D, 1, 1, 0>(fld, 5, sp);
+    if constexpr (D == 3) {
+      float nv[6][8];
+      gather_load8<1, 0, 0>(fld, 0, sp, nv[0]);
+      gather_load8<0, 1, 0>(fld, 1, sp, nv[1]);
+      gather_load8<0, 0, 1>(fld, 2, sp, nv[2]);
+      E0 = interp8<1, 0, 0>(nv[0], sp);
+      E1 = interp8<0, 1, 0>(nv[1], sp);
+      E2 = interp8<0, 0, 1>(nv[2], sp);
+      gather_load8<0, 1, 1>(fld, 3, sp, nv[3]);
+      gather_load8<1, 0, 1>(fld, 4, sp, nv[4]);
+      gather_load8<1, 1, 0>(fld, 5, sp, nv[5]);
+      B0 = interp8<0, 1, 1>(nv[3], sp);
+      B1 = interp8<1, 0, 1>(nv[4], sp);
+      B2 = interp8<1, 1, 0>(nv[5], sp);
+    } else {
+      E0 = gather_q<D, 1, 0, 0>(fld, 0, sp);
+      E1 = gather_q<D, 0, 1, 0>(fld, 1, sp);
+      E2 = gather_q<D, 0, 0, 1>(fld, 2, sp);
+      B0 = gather_q<D, 0, 1, 1>(fld, 3, sp);
+      B1 = gather_q<D, 1, 0, 1>(fld, 4, sp);
+      B2 = gather_q<D, 1, 1, 0>(fld, 5, sp);
+    }
   } else {
     R g[3] = {R(0), R(0), R(0)};
 #pragma unroll
@@ -1105,8 +1165,14 @@ __device__ inline uint32_t chunk_of_block(uint32_t b) {
   return ((t / kXcdGroup) * 8u + x) * kXcdGroup + (t % kXcdGroup);
 }
 
+// The 3D FP32 kernel runs at most 6 workgroups per CU (its LDS box), so it
+// is compiled for 6 waves per SIMD: 80 VGPRs, room for the gather's loads
+// to be in flight together.
 template <class R, int D>
-__global__ __launch_bounds__(kBlock) void k_electron_step(const StepParams<R> P) {
+constexpr int kStepMinWaves = (sizeof(R) == 4 && D == 3) ? 6 : 1;
+
+template <class R, int D>
+__global__ __launch_bounds__(kBlock, (kStepMinWaves<R, D>)) void k_electron_step(const StepParams<R> P) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ __align__(16) uint32_t s_box[12];
   __shared__ uint32_t s_spec[2 * PIC_SPECTRUM_BINS];
@@ -1121,7 +1187,7 @@ __global__ __launch_bounds__(kBlock) void k_electron_step(const StepParams<R> P)
 // grid-stride loop over chunks raises the kernel from 68 to 106 VGPRs and
 // drops occupancy from 7 to 4 waves per SIMD.)
 template <class R, int D>
-__global__ __launch_bounds__(kBlock) void k_electron_step_batch(const StepParams<R>* __restrict__ tab,
+__global__ __launch_bounds__(kBlock, (kStepMinWaves<R, D>)) void k_electron_step_batch(const StepParams<R>* __restrict__ tab,
                                                                 const uint32_t* __restrict__ first,
                                                                 int njobs) {
   extern __shared__ __align__(16) unsigned char smem[];
