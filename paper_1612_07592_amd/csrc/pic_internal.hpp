@@ -110,8 +110,10 @@ inline uint64_t pair_tables_checksum(const pic_pair_tables& t) {
 // index j <= n - 2 with C[j] <= b / kGuide (0 if none).  A uniform u then has
 // its bracket (the largest j <= n - 2 with C[j] <= u) between entries
 // floor(u kGuide) and that + 1, plus one, so the search covers a few points
-// instead of the whole row and returns the same bracket.
-constexpr int kGuide = 64;
+// instead of the whole row and returns the same bracket.  With as many
+// guide entries as row points (256) the search takes at most a step or two,
+// which keeps the chain of dependent table loads of an emission short.
+constexpr int kGuide = 256;
 
 struct DevTables {
   int n_eta = 0, n_xi = 0, n_T = 0, n_y = 0;

@@ -177,23 +177,6 @@ __device__ inline float interp8(const float v[8], const Splits& s) {
   return lerp_f(a2, b2, f2);
 }
 
-// Inverse of one NCS cumulative row: ln(xi) at uniform u.
-template <class R>
-__device__ inline R ncs_inverse(const R* __restrict__ C, const R* __restrict__ lnxi, int n, R u,
-                               const uint8_t* __restrict__ G) {
-  if (u < C[0]) return lnxi[0] + R(3) * m_log(m_div(u, C[0]));
-  // bracket search between the row guide's entries (same bracket as a
-  // search over the whole row)
-  const int b = (int)(u * R(kGuide));
-  int lo = G[b], hi = min((int)G[b + 1] + 1, n - 1);
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (C[mid] <= u) lo = mid; else hi = mid;
-  }
-  const R t = m_div(u - C[lo], C[lo + 1] - C[lo]);
-  return lnxi[lo] + t * (lnxi[lo + 1] - lnxi[lo]);
-}
-
 // Inverse of one bremsstrahlung cumulative row: scaled coordinate in [0,1].
 template <class R>
 __device__ inline R brem_inverse(const R* __restrict__ S, int n, R u, R iny1,
@@ -517,6 +500,43 @@ struct Move {
   R v[3] = {R(0), R(0), R(0)};               // velocity of the move
 };
 
+// Inverse of the two NCS cumulative rows around eta at the same uniform u:
+// ln(xi) of each row, linear in its bracket (the largest j <= n - 2 with
+// C[j] <= u, found between the row guide's entries), and below the row's
+// first point the small-xi form of the row, C proportional to xi^(1/3).  The two searches
+// run side by side so that their dependent table loads overlap.
+template <class R>
+__device__ inline void ncs_inverse2(const R* __restrict__ Ca, const R* __restrict__ Cb,
+                                    const R* __restrict__ lnxi, int n, R u, const uint8_t* __restrict__ Ga,
+                                    const uint8_t* __restrict__ Gb, R& la, R& lb) {
+  const int b = (int)(u * R(kGuide));
+  const R ca0 = Ca[0], cb0 = Cb[0];
+  int loa = Ga[b], hia = min((int)Ga[b + 1] + 1, n - 1);
+  int lob = Gb[b], hib = min((int)Gb[b + 1] + 1, n - 1);
+  while (hia - loa > 1 || hib - lob > 1) {
+    if (hia - loa > 1) {
+      const int mid = (loa + hia) >> 1;
+      if (Ca[mid] <= u) loa = mid; else hia = mid;
+    }
+    if (hib - lob > 1) {
+      const int mid = (lob + hib) >> 1;
+      if (Cb[mid] <= u) lob = mid; else hib = mid;
+    }
+  }
+  if (u < ca0) {
+    la = lnxi[0] + R(3) * m_log(m_div(u, ca0));
+  } else {
+    const R t = m_div(u - Ca[loa], Ca[loa + 1] - Ca[loa]);
+    la = lnxi[loa] + t * (lnxi[loa + 1] - lnxi[loa]);
+  }
+  if (u < cb0) {
+    lb = lnxi[0] + R(3) * m_log(m_div(u, cb0));
+  } else {
+    const R t = m_div(u - Cb[lob], Cb[lob + 1] - Cb[lob]);
+    lb = lnxi[lob] + t * (lnxi[lob + 1] - lnxi[lob]);
+  }
+}
+
 // Photon energy of an NCS emission: each of the two rows around eta inverted
 // at the uniform, blended in ln eta, xi = exp(.), eps = xi gamma capped at the
 // kinetic energy.
@@ -527,8 +547,9 @@ __device__ inline R ncs_eps(const StepParams<R>& P, int i, R f, R u2, R gamma) {
   const R* ncs = C->ncs;
   const R* lnxi = C->lnxi;
   const uint8_t* gn = C->gncs;
-  const R la = ncs_inverse<R>(ncs + (int64_t)i * nxi, lnxi, nxi, u2, gn + i * (kGuide + 1));
-  const R lb = ncs_inverse<R>(ncs + (int64_t)(i + 1) * nxi, lnxi, nxi, u2, gn + (i + 1) * (kGuide + 1));
+  R la, lb;
+  ncs_inverse2<R>(ncs + (int64_t)i * nxi, ncs + (int64_t)(i + 1) * nxi, lnxi, nxi, u2,
+                  gn + i * (kGuide + 1), gn + (i + 1) * (kGuide + 1), la, lb);
   const R lx = la + f * (lb - la);
   const R xi = m_exp(lx);
   R eps = xi * gamma;
@@ -714,16 +735,21 @@ __device__ inline void electron_move(const StepParams<R>& P, int64_t e, uint32_t
         q = q < 0 ? 0 : (q > P.n[a] - 1 ? P.n[a] - 1 : q);
         ci[a] = q;
       }
+      // the density n_i of the cell and the two sigma(T) rows are loaded
+      // together: neither address depends on the other load
       const double ni = P.ni[ci[0] + (int64_t)P.n[0] * (ci[1] + (int64_t)P.n[1] * ci[2])];
+      const R lt = m_log(T);
+      const R sl = (lt - R(P.ln_T0)) * R(P.idln_T);
+      int i = 0;
+      R f = R(0);
+      const bool top = sl >= R(P.n_T - 1);
+      if (top) { i = P.n_T - 2; f = R(1); }
+      else if (sl >= R(0)) { i = (int)sl; f = sl - R(i); }
+      const R sg0 = P.sig[i], sg1 = P.sig[i + 1];
       if (ni > 0.0) {
-        const R lt = m_log(T);
-        const R sl = (lt - R(P.ln_T0)) * R(P.idln_T);
         if (sl >= R(0)) {
-          int i;
-          R f;
-          if (sl >= R(P.n_T - 1)) { i = P.n_T - 2; f = R(1); out.clamped = true; }
-          else { i = (int)sl; f = sl - R(i); }
-          const R sig = P.sig[i] + f * (P.sig[i + 1] - P.sig[i]);
+          if (top) out.clamped = true;
+          const R sig = sg0 + f * (sg1 - sg0);
           if (sig > R(0)) {
             const R pm = m_sqrt(px * px + py * py + pz * pz);
             const R v = m_div(pm, gamma);
