@@ -59,6 +59,8 @@ HBM_PEAK_GBS = 8000.0
 # Non-packed FP32 (and FP64) VALU issue of MI355X: 256 CU x 4 SIMD x 16 lanes
 # x 2.4 GHz, one lane operation per lane and cycle (packed FP32 is disabled).
 ALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+# wave64 VALU instructions per second: 256 CUs x 4 SIMDs, one instruction per SIMD every 4 cycles
+VALU_PEAK_WAVE_INSTS = 256 * 4 * 2.4e9 / 4
 # algorithmic lane operations per electron-step that every live electron
 # executes (gather, Boris, eta, NCS decrement, move, deposit, stats), quarter-
 # rate operations counted 4; the conditional brem test and event sampling are
@@ -367,7 +369,15 @@ def roofline_leg(name, k, tables, torch, with_fp64=True):
             "alu_lane_ops": {"estimate_per_electron_step": ALU_OPS[dims],
                              "achieved_per_s": lane_ops, "peak_per_s": ALU_PEAK_LANE_OPS,
                              "frac": lane_ops / ALU_PEAK_LANE_OPS,
-                             "note": "lane operations counted from the method, not counters"}}
+                             "note": "lane operations counted from the method with the general "
+                                     "(cell-crossing) deposit for every electron-step: an upper "
+                                     "bound; valu_issue holds the counter figure"},
+            "valu_issue": ({"valu_instructions_per_launch": tr["valu_instructions_per_launch"],
+                            "achieved_per_s": tr["valu_instructions_per_launch"] / (avg_us * 1e-6),
+                            "peak_per_s": VALU_PEAK_WAVE_INSTS,
+                            "frac": tr["valu_instructions_per_launch"] / (avg_us * 1e-6) / VALU_PEAK_WAVE_INSTS,
+                            "source": "SQ_INSTS_VALU averaged over the launches, profiles/traffic.json"}
+                           if tr and tr.get("valu_instructions_per_launch") else None)}
     log(f"roofline {w['name']}: {avg_us:.1f} us per launch, {achieved:.0f} GB/s "
         f"(frac {roof['frac']:.3f}); window {roof['window_kernel_avg_us']:.1f} us")
     out = {"roofline": roof}
