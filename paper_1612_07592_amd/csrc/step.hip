@@ -674,30 +674,33 @@ __device__ inline void electron_push(const StepParams<R>& P, int64_t e, uint32_t
   L.gamma = m_fsqrt(R(1) + (L.px * L.px + L.py * L.py + L.pz * L.pz));
 
   // ---- quantum parameter eta (Lorentz invariant, Sec. II.A) -----------------
-  // eta^2 E_S^2 = |gamma E + p x B|^2 - (p.E)^2 (units m c = 1).  FP32 writes
-  // the same invariant as gamma^2 |F_perp|^2 + F_par^2, F = E + v x B split
-  // across and along p: the difference of the two squares cancels when p is
-  // nearly parallel to the force (its FP32 error grows like gamma^4 relative
-  // to eta^2, noise that the clip at zero turns into excess emission); the
-  // split form has no such cancellation.  FP64 keeps the form above.
-  R q2;
+  // eta^2 E_S^2 = |gamma E + p x B|^2 - (p.E)^2 (units m c = 1).  For
+  // |p| >= 1 FP32 writes the same invariant as gamma^2 |F_perp|^2 + F_par^2,
+  // F = E + v x B split across and along p: the difference of the two
+  // squares cancels when p is nearly parallel to the force (its FP32 error
+  // grows like gamma^4 relative to eta^2, noise that the clip at zero turns
+  // into excess emission); the split form has no such cancellation.  Below
+  // |p| = 1 (gamma < 1.42) the difference loses little, and the split form's
+  // 1/p^2 is not safe (a denormal p^2 has an infinite hardware reciprocal).
+  // FP64 keeps the difference.
+  const R cx = L.gamma * E0 + (L.py * B2 - L.pz * B1);
+  const R cy = L.gamma * E1 + (L.pz * B0 - L.px * B2);
+  const R cz = L.gamma * E2 + (L.px * B1 - L.py * B0);
+  const R pe = L.px * E0 + L.py * E1 + L.pz * E2;
+  R q2 = (cx * cx + cy * cy + cz * cz) - pe * pe;
+  if (q2 < R(0)) q2 = R(0);
   if constexpr (kF32) {
-    const R ig = m_div(R(1), L.gamma);
-    const R Fx = E0 + ig * (L.py * B2 - L.pz * B1);
-    const R Fy = E1 + ig * (L.pz * B0 - L.px * B2);
-    const R Fz = E2 + ig * (L.px * B1 - L.py * B0);
     const R pp = L.px * L.px + L.py * L.py + L.pz * L.pz;
-    const R Fp = Fx * L.px + Fy * L.py + Fz * L.pz;
-    const R sp = pp > R(0) ? m_div(Fp, pp) : R(0);  // F.p / p^2
-    const R ux = Fx - sp * L.px, uy = Fy - sp * L.py, uz = Fz - sp * L.pz;
-    q2 = L.gamma * L.gamma * (ux * ux + uy * uy + uz * uz) + Fp * sp;
-  } else {
-    const R cx = L.gamma * E0 + (L.py * B2 - L.pz * B1);
-    const R cy = L.gamma * E1 + (L.pz * B0 - L.px * B2);
-    const R cz = L.gamma * E2 + (L.px * B1 - L.py * B0);
-    const R pe = L.px * E0 + L.py * E1 + L.pz * E2;
-    q2 = (cx * cx + cy * cy + cz * cz) - pe * pe;
-    if (q2 < R(0)) q2 = R(0);
+    if (pp >= R(1)) {
+      const R ig = m_div(R(1), L.gamma);
+      const R Fx = E0 + ig * (L.py * B2 - L.pz * B1);
+      const R Fy = E1 + ig * (L.pz * B0 - L.px * B2);
+      const R Fz = E2 + ig * (L.px * B1 - L.py * B0);
+      const R Fp = Fx * L.px + Fy * L.py + Fz * L.pz;
+      const R sp = m_div(Fp, pp);  // F.p / p^2
+      const R ux = Fx - sp * L.px, uy = Fy - sp * L.py, uz = Fz - sp * L.pz;
+      q2 = L.gamma * L.gamma * (ux * ux + uy * uy + uz * uz) + Fp * sp;
+    }
   }
   const R eta = m_fsqrt(q2) * R(P.iES);
 

@@ -115,3 +115,35 @@ def test_fp32_full_pic_2d_gold_a270_ensemble(gpu_lib, tables_au):
     assert abs(d.mean()) <= t_one * se
     assert abs(rel.mean()) <= 0.01
     assert np.all(np.abs(fd.mean(0)) <= t_deciles * fse)
+
+
+def test_fp32_full_pic_3d_gold_narrow(gpu_lib, tables_au):
+    """The 3D configuration (lambda/32 cells, Au q = 69 at 200 n_c, 64
+    electrons per cell, a0 = 854) on a 512x32x32 box (2,097,152 electrons)
+    through the laser peak (450 steps): the FP32 3D kernel, with its own
+    gather, deposit and eta forms, against the FP64 kernel on the same
+    Philox streams.  Every FP32 momentum finite; emission events, kept
+    photons and the electrons' kinetic energy within 3% of FP64 (the
+    interaction is chaotic, so the bar is the run-to-run spread with room,
+    not a rounding bound; it fails a broken FP32 path by orders of
+    magnitude)."""
+    w = dict(W.c5(), n=[512, 32, 32], photon_capacity=1 << 24)
+    res = {}
+    for prec in ("fp64", "fp32"):
+        s = gpu_lib.Sim(dict(w, precision=prec), tables_au)
+        s.pic_step(450)
+        st = s.stats()
+        e = s.electrons()
+        res[prec] = (st, e)
+        s.close()
+    (s64, e64), (s32, e32) = res["fp64"], res["fp32"]
+    assert np.isfinite(e32["p"][e32["alive"]]).all()
+    rel = lambda a, b: abs(a - b) / max(abs(b), 1e-300)
+    ev = rel(s32["events"][0], s64["events"][0])
+    kp = rel(sum(s32["kept"]), sum(s64["kept"]))
+    ek = rel(s32["e_kin_e"], s64["e_kin_e"])
+    print(f"\n[fp32-vs-fp64] 3D narrow gold, 450 steps: events {s32['events'][0]} vs {s64['events'][0]} "
+          f"({ev:.2e}), kept {sum(s32['kept'])} vs {sum(s64['kept'])} ({kp:.2e}), "
+          f"kinetic energy {s32['e_kin_e']:.6e} vs {s64['e_kin_e']:.6e} ({ek:.2e})", flush=True)
+    assert s64["events"][0] > 100000
+    assert ev <= 0.03 and kp <= 0.03 and ek <= 0.03
