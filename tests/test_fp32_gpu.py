@@ -147,3 +147,29 @@ def test_fp32_full_pic_3d_gold_narrow(gpu_lib, tables_au):
           f"kinetic energy {s32['e_kin_e']:.6e} vs {s64['e_kin_e']:.6e} ({ek:.2e})", flush=True)
     assert s64["events"][0] > 100000
     assert ev <= 0.03 and kp <= 0.03 and ek <= 0.03
+
+
+def test_fp32_full_pic_1d_laser_slab(gpu_lib, tables_au):
+    """1D full PIC, a gold-like slab at 100 n_c under a0 = 855 (500 steps,
+    tens of thousands of emissions): the FP32 1D kernel against FP64 on the
+    same Philox streams, with the 3D test's bar (every FP32 momentum finite;
+    events, kept photons and kinetic energy within 3%)."""
+    w = S.ions_1d(steps=500)
+    w.update(ion_ppc=0, a0=855.0, ne_over_nc=100.0, photon_cut_mc2=1.0, photon_capacity=1 << 22)
+    res = {}
+    for prec in ("fp64", "fp32"):
+        s = gpu_lib.Sim(dict(w, precision=prec), tables_au)
+        s.pic_step(500)
+        res[prec] = (s.stats(), s.electrons())
+        s.close()
+    (s64, _), (s32, e32) = res["fp64"], res["fp32"]
+    assert np.isfinite(e32["p"][e32["alive"]]).all()
+    rel = lambda a, b: abs(a - b) / max(abs(b), 1e-300)
+    ev = rel(s32["events"][0], s64["events"][0])
+    kp = rel(sum(s32["kept"]), sum(s64["kept"]))
+    ek = rel(s32["e_kin_e"], s64["e_kin_e"])
+    print(f"\n[fp32-vs-fp64] 1D laser slab a0 = 855, 500 steps: events {s32['events'][0]} vs "
+          f"{s64['events'][0]} ({ev:.2e}), kept {sum(s32['kept'])} vs {sum(s64['kept'])} ({kp:.2e}), "
+          f"kinetic energy {s32['e_kin_e']:.6e} vs {s64['e_kin_e']:.6e} ({ek:.2e})", flush=True)
+    assert s64["events"][0] > 10000
+    assert ev <= 0.03 and kp <= 0.03 and ek <= 0.03
