@@ -631,8 +631,8 @@ def main():
                     help="jobs of the Poisson stream served (0 = none)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU split is a "
-                                   "design note, not implemented", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only; splitting the run over "
+                                   "several GPUs is described, not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
     legs = {"roofline": not args.no_roofline, "full": not args.no_full_run and not args.no_fp64,
             "cpu": not args.no_cpu_baseline, "serving": not args.no_serving,
