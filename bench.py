@@ -540,7 +540,7 @@ def serving(args):
 
 
 def host_cpu():
-    """Host processor as the GPU machine reports it."""
+    """Host processor of the machine the benchmark runs on, as the OS reports it."""
     info = {"nproc": None, "affinity": None, "model": None, "lscpu_cpus": None}
     try:
         info["nproc"] = int(subprocess.run(["nproc"], capture_output=True, text=True).stdout.strip())
