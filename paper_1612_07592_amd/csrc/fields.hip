@@ -72,6 +72,29 @@ __device__ inline bool in_range(const FieldArgs& A, bool isB, int c, int i, int 
 // step uses).  Each is formed exactly as a separate half step forms it.  Bn
 // gets every node (invalid B nodes copy B, which never changes there).  J is
 // cleared for the step's deposit.
+// The two half steps of one B component: b1 = b - tm + tp, b2 = b1 - tm + tp,
+// each term present only where its axis is active.
+template <class R>
+__device__ __forceinline__ void b_halves(R b, R tm, bool hm, R tp, bool hp, R& b1, R& b2) {
+  b1 = b;
+  if (hm) b1 = b1 - tm;
+  if (hp) b1 = b1 + tp;
+  b2 = b1;
+  if (hm) b2 = b2 - tm;
+  if (hp) b2 = b2 + tp;
+}
+
+// Every B component of node (i, j, k) is a valid node: 0 <= index <= n - 1 on
+// each active axis, 0 on the others.
+__device__ inline bool b_inner(const FieldArgs& A, int i, int j, int k) {
+  const int ijk[3] = {i, j, k};
+  bool in = true;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    in = in && (A.act[a] ? (ijk[a] >= 0 && ijk[a] <= A.n[a] - 1) : ijk[a] == 0);
+  return in;
+}
+
 template <class R>
 __device__ __forceinline__ void b_both_node(const FieldArgs& A, const R* __restrict__ Ex,
                                             const R* __restrict__ Ey, const R* __restrict__ Ez,
@@ -79,10 +102,46 @@ __device__ __forceinline__ void b_both_node(const FieldArgs& A, const R* __restr
                                             unsigned long long* Jx, unsigned long long* Jy,
                                             unsigned long long* Jz, const int64_t m) {
   if (m >= A.nfield) return;
-  Jx[m] = 0ull; Jy[m] = 0ull; Jz[m] = 0ull;
   int i, j, k;
   decode(A, m, i, j, k);
   const int64_t s1 = A.sz[0], s2 = (int64_t)A.sz[0] * A.sz[1];  // +1 along y, z
+  if (b_inner(A, i, j, k)) {
+    // All three components valid (nearly every node): every load is issued
+    // before the first store, so a thread waits on memory once rather than
+    // once per component and term.  The arithmetic is the general path's.
+    const bool ay = A.act[1] != 0, az = A.act[2] != 0;
+    const R bx = Bx[m], by = By[m], bz = Bz[m];
+    const R ex = Ex[m], ey = Ey[m], ez = Ez[m];
+    const R ey_x = Ey[m + 1], ez_x = Ez[m + 1];
+    R ex_y = R(0), ez_y = R(0), ex_z = R(0), ey_z = R(0);
+    if (ay) { ex_y = Ex[m + s1]; ez_y = Ez[m + s1]; }
+    if (az) { ex_z = Ex[m + s2]; ey_z = Ey[m + s2]; }
+    R b1, b2;
+    {  // dBx/dt = -dEz/dy + dEy/dz
+      const R ty = ay ? R(A.hd[1]) * (ez_y - ez) : R(0);
+      const R tz = az ? R(A.hd[2]) * (ey_z - ey) : R(0);
+      b_halves(bx, ty, ay, tz, az, b1, b2);
+      Bnx[m] = b1;
+      Bx[m] = b2;
+    }
+    {  // dBy/dt = -dEx/dz + dEz/dx
+      const R tz = az ? R(A.hd[2]) * (ex_z - ex) : R(0);
+      const R tx = R(A.hd[0]) * (ez_x - ez);
+      b_halves(by, tz, az, tx, true, b1, b2);
+      Bny[m] = b1;
+      By[m] = b2;
+    }
+    {  // dBz/dt = -dEy/dx + dEx/dy
+      const R tx = R(A.hd[0]) * (ey_x - ey);
+      const R ty = ay ? R(A.hd[1]) * (ex_y - ex) : R(0);
+      b_halves(bz, tx, true, ty, ay, b1, b2);
+      Bnz[m] = b1;
+      Bz[m] = b2;
+    }
+    Jx[m] = 0ull; Jy[m] = 0ull; Jz[m] = 0ull;
+    return;
+  }
+  Jx[m] = 0ull; Jy[m] = 0ull; Jz[m] = 0ull;
   {  // dBx/dt = -dEz/dy + dEy/dz
     const R b = Bx[m];
     if (in_range(A, true, 0, i, j, k)) {
@@ -198,13 +257,76 @@ __global__ __launch_bounds__(kBlock) void k_b_both(FieldArgs A, const R* __restr
                  (int64_t)blockIdx.x * kBlock + threadIdx.x);
 }
 
+// Every E component of node (i, j, k) is an interior Ampere node: 1 <= index
+// <= n - 1 on each active axis (no tangential face, no guard), 0 on the others.
+__device__ inline bool e_inner(const FieldArgs& A, int i, int j, int k) {
+  const int ijk[3] = {i, j, k};
+  bool in = true;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    in = in && (A.act[a] ? (ijk[a] >= 1 && ijk[a] <= A.n[a] - 1) : ijk[a] == 0);
+  return in;
+}
+
+// E^{n+1} at all three components of a node.  At an interior node (nearly
+// every node) the loads of all three updates are issued before the first
+// store, so a thread waits on memory once rather than once per component and
+// term; each value is e_interior's, in its operation order.  Other nodes take
+// e_full_node per component.
+template <class R>
+__device__ __forceinline__ void e_full_all(const FieldArgs& A, const EPtrs& P, double lsin,
+                                           double lcos, const int64_t m) {
+  if (m >= A.nfield) return;
+  int i, j, k;
+  decode(A, m, i, j, k);
+  if (!e_inner(A, i, j, k)) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) e_full_node<R>(A, P, lsin, lcos, c, m);
+    return;
+  }
+  const int64_t s1 = A.sz[0], s2 = (int64_t)A.sz[0] * A.sz[1];  // -1 along y, z
+  const bool ay = A.act[1] != 0, az = A.act[2] != 0;
+  const R* Bx = (const R*)P.B[0];
+  const R* By = (const R*)P.B[1];
+  const R* Bz = (const R*)P.B[2];
+  const R e0 = ((const R*)P.E[0])[m], e1 = ((const R*)P.E[1])[m], e2 = ((const R*)P.E[2])[m];
+  const long long j0 = (long long)P.J[0][m], j1 = (long long)P.J[1][m], j2 = (long long)P.J[2][m];
+  const R bx = Bx[m], by = By[m], bz = Bz[m];
+  const R by_x = By[m - 1], bz_x = Bz[m - 1];
+  R bx_y = R(0), bz_y = R(0), bx_z = R(0), by_z = R(0);
+  if (ay) { bx_y = Bx[m - s1]; bz_y = Bz[m - s1]; }
+  if (az) { bx_z = Bx[m - s2]; by_z = By[m - s2]; }
+  // dEx/dt = dBz/dy - dBy/dz - Jx
+  R x = e0;
+  if (ay) x = x + R(A.cd[1]) * (bz - bz_y);
+  if (az) x = x - R(A.cd[2]) * (by - by_z);
+  x = x - R(A.dt * ((double)j0 * kJInv));
+  // dEy/dt = dBx/dz - dBz/dx - Jy, plus the laser sheet
+  R y = e1;
+  if (az) y = y + R(A.cd[2]) * (bx - bx_z);
+  y = y - R(A.cd[0]) * (bz - bz_x);
+  double jy = (double)j1 * kJInv;
+  if (i == A.i_src) {
+    const int64_t s = j + (int64_t)A.nsrc_y * k;
+    const double v = lsin * P.srcC[s] + lcos * P.srcS[s];
+    jy = jy + A.srcfac * (P.srcA[s] * v);
+  }
+  y = y - R(A.dt * jy);
+  // dEz/dt = dBy/dx - dBx/dy - Jz
+  R z = e2;
+  z = z + R(A.cd[0]) * (by - by_x);
+  if (ay) z = z - R(A.cd[1]) * (bx - bx_y);
+  z = z - R(A.dt * ((double)j2 * kJInv));
+  ((R*)P.En[0])[m] = x;
+  ((R*)P.En[1])[m] = y;
+  ((R*)P.En[2])[m] = z;
+}
+
 // One thread updates the three components of its node, so each B value is
 // fetched by the threads of one pass instead of two component passes.
 template <class R>
 __global__ __launch_bounds__(kBlock) void k_e_full(FieldArgs A, EPtrs P, double lsin, double lcos) {
-  const int64_t m = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-#pragma unroll
-  for (int c = 0; c < 3; ++c) e_full_node<R>(A, P, lsin, lcos, c, m);
+  e_full_all<R>(A, P, lsin, lcos, (int64_t)blockIdx.x * kBlock + threadIdx.x);
 }
 
 // Batched forms: the workgroups of every run laid end to end (run j owns
@@ -235,9 +357,7 @@ __global__ __launch_bounds__(kBlock) void k_e_full_batch(const FieldJob* __restr
                                                          int njobs) {
   const int j = batch_job(first, njobs, blockIdx.x);
   const FieldJob& F = tab[j];
-  const int64_t m = (int64_t)(blockIdx.x - first[j]) * kBlock + threadIdx.x;
-#pragma unroll
-  for (int c = 0; c < 3; ++c) e_full_node<R>(F.A, F.P, F.lsin, F.lcos, c, m);
+  e_full_all<R>(F.A, F.P, F.lsin, F.lcos, (int64_t)(blockIdx.x - first[j]) * kBlock + threadIdx.x);
 }
 
 uint32_t field_blocks(const Ctx& c) { return (uint32_t)((c.g.nfield + kBlock - 1) / kBlock); }
