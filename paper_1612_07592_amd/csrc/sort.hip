@@ -52,18 +52,44 @@ constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 
 __device__ inline int hash_slot(uint32_t key) { return (int)((key * 2654435761u) >> 23) & (kHash - 1); }
 
-// Insert key; returns its slot and, through rank, the electron's rank among
-// the workgroup's electrons of that key.
-__device__ inline int hash_insert(uint32_t* hkey, uint32_t* hcnt, uint32_t key, uint32_t& rank) {
+// Add n electrons of key to the workgroup's table; returns its slot and,
+// through before, the key's count before the addition.  (At most kBlock
+// distinct keys in 2 kBlock slots: the probe always ends.)
+__device__ inline int hash_add(uint32_t* hkey, uint32_t* hcnt, uint32_t key, uint32_t n,
+                               uint32_t& before) {
   int h = hash_slot(key);
   for (;;) {
     const uint32_t prev = atomicCAS(&hkey[h], kEmpty, key);
     if (prev == kEmpty || prev == key) {
-      rank = atomicAdd(&hcnt[h], 1u);
+      before = atomicAdd(&hcnt[h], n);
       return h;
     }
     h = (h + 1) & (kHash - 1);
   }
+}
+
+// The lanes of the wave that are active and hold this lane's key: one pass
+// per distinct key of the wave.  A wave of a tile-sorted array nearly always
+// holds one or two tiles, so its electrons enter the table with one or two
+// LDS atomics instead of one per electron (same-address LDS atomics of a
+// whole wave serialise).  Called by every lane of the wave.
+__device__ inline uint64_t same_key_lanes(uint32_t key, bool active) {
+  uint64_t todo = __ballot(active);
+  uint64_t mine = 0ull;
+  while (todo) {
+    const int leader = __builtin_ctzll(todo);
+    const uint32_t lk = (uint32_t)__builtin_amdgcn_readlane((int)key, leader);
+    const bool eq = active && key == lk;
+    const uint64_t m = __ballot(eq);
+    if (eq) mine = m;
+    todo &= ~m;
+  }
+  return mine;
+}
+
+// number of the set bits of mask below this lane
+__device__ inline uint32_t lanes_below(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
 template <class R>
@@ -88,8 +114,8 @@ __global__ __launch_bounds__(kBlock) void k_sort_key(SortArgs A) {
     }
   }
   const bool valid = e < (int64_t)A.n_active[0];
+  uint32_t key = A.nkeys - 1;  // absorbed electrons: last bucket
   if (valid) {
-    uint32_t key = A.nkeys - 1;  // absorbed electrons: last bucket
     if (!(idv & kDead)) {
       uint32_t tt[3] = {0u, 0u, 0u};
 #pragma unroll
@@ -113,8 +139,11 @@ __global__ __launch_bounds__(kBlock) void k_sort_key(SortArgs A) {
       }
     }
     A.key[e] = key;
-    uint32_t rank;
-    hash_insert(hkey, hcnt, key, rank);
+  }
+  const uint64_t mine = same_key_lanes(key, valid);
+  if (valid && lanes_below(mine) == 0u) {  // the first lane of each key counts its lanes
+    uint32_t before;
+    hash_add(hkey, hcnt, key, (uint32_t)__popcll(mine), before);
   }
   __syncthreads();
   for (int i = t; i < kHash; i += kBlock)
@@ -207,9 +236,15 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(SortArgs A) {
     idv = A.id[e];
   }
   const bool valid = e < (int64_t)A.n_active[0];
+  // rank among the workgroup's electrons of the same key: the wave's range
+  // for the key (taken by its first lane) plus the lanes of the key below
+  const uint64_t mine = same_key_lanes(kv, valid);
+  const int leader = valid ? __builtin_ctzll(mine) : (int)__lane_id();
   int h = 0;
-  uint32_t rank = 0;
-  if (valid) h = hash_insert(hkey, hcnt, kv, rank);
+  uint32_t before = 0u;
+  if (valid && (int)__lane_id() == leader) h = hash_add(hkey, hcnt, kv, (uint32_t)__popcll(mine), before);
+  h = __shfl(h, leader, 64);
+  const uint32_t rank = (uint32_t)__shfl((int)before, leader, 64) + lanes_below(mine);
   __syncthreads();
   // one cursor atomic per distinct key of the workgroup; the slot's count is
   // replaced by the base of the workgroup's range for that key
