@@ -218,11 +218,15 @@ __device__ inline void deposit3(const StepParams<float>& P, const Acc& J, const 
     split_q(q1[a], 0, P.fb[a], P.iqs[a], i1s[a], f1s[a]);
     cross = cross || i0s[a] != i1s[a];
   }
-  // 3D: the form is chosen per wave.  The general form is exact for a move
-  // that stays in its cell too, and a wave whose lanes took both forms would
-  // issue the atomics of both (12 + 54).  (In 2D the per-wave choice raises
-  // the kernel from 69 to 81 VGPRs, 7 to 5 waves per SIMD; 3D stays at 5.)
-  const bool fast = D == 3 ? __ballot(cross) == 0ull : !cross;
+  // 2D and 3D: the form is chosen per wave.  A wave whose lanes took both
+  // forms would issue the atomics of both (8 + 21 in 2D, 12 + 54 in 3D).  For
+  // a move that stays in its cell the general form below yields exactly the
+  // single-cell form's contributions: a position has at most 24 fraction
+  // bits, so every node weight 1 - f is exact, the first face flux
+  // -q ((1 - f1) - (1 - f0)) is q (f1 - f0) and the second is exactly 0.  An
+  // electron's current therefore does not depend on which electrons share
+  // its wave.
+  const bool fast = D >= 2 ? __ballot(cross) == 0ull : !cross;
   if (fast) {
     // The move stays inside one cell on every axis: every node weight is
     // linear between the same two nodes, so the flux through the window's
