@@ -72,29 +72,6 @@ __device__ inline bool in_range(const FieldArgs& A, bool isB, int c, int i, int 
 // step uses).  Each is formed exactly as a separate half step forms it.  Bn
 // gets every node (invalid B nodes copy B, which never changes there).  J is
 // cleared for the step's deposit.
-// The two half steps of one B component: b1 = b - tm + tp, b2 = b1 - tm + tp,
-// each term present only where its axis is active.
-template <class R>
-__device__ __forceinline__ void b_halves(R b, R tm, bool hm, R tp, bool hp, R& b1, R& b2) {
-  b1 = b;
-  if (hm) b1 = b1 - tm;
-  if (hp) b1 = b1 + tp;
-  b2 = b1;
-  if (hm) b2 = b2 - tm;
-  if (hp) b2 = b2 + tp;
-}
-
-// Every B component of node (i, j, k) is a valid node: 0 <= index <= n - 1 on
-// each active axis, 0 on the others.
-__device__ inline bool b_inner(const FieldArgs& A, int i, int j, int k) {
-  const int ijk[3] = {i, j, k};
-  bool in = true;
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-    in = in && (A.act[a] ? (ijk[a] >= 0 && ijk[a] <= A.n[a] - 1) : ijk[a] == 0);
-  return in;
-}
-
 template <class R>
 __device__ __forceinline__ void b_both_node(const FieldArgs& A, const R* __restrict__ Ex,
                                             const R* __restrict__ Ey, const R* __restrict__ Ez,
@@ -105,42 +82,6 @@ __device__ __forceinline__ void b_both_node(const FieldArgs& A, const R* __restr
   int i, j, k;
   decode(A, m, i, j, k);
   const int64_t s1 = A.sz[0], s2 = (int64_t)A.sz[0] * A.sz[1];  // +1 along y, z
-  if (b_inner(A, i, j, k)) {
-    // All three components valid (nearly every node): every load is issued
-    // before the first store, so a thread waits on memory once rather than
-    // once per component and term.  The arithmetic is the general path's.
-    const bool ay = A.act[1] != 0, az = A.act[2] != 0;
-    const R bx = Bx[m], by = By[m], bz = Bz[m];
-    const R ex = Ex[m], ey = Ey[m], ez = Ez[m];
-    const R ey_x = Ey[m + 1], ez_x = Ez[m + 1];
-    R ex_y = R(0), ez_y = R(0), ex_z = R(0), ey_z = R(0);
-    if (ay) { ex_y = Ex[m + s1]; ez_y = Ez[m + s1]; }
-    if (az) { ex_z = Ex[m + s2]; ey_z = Ey[m + s2]; }
-    R b1, b2;
-    {  // dBx/dt = -dEz/dy + dEy/dz
-      const R ty = ay ? R(A.hd[1]) * (ez_y - ez) : R(0);
-      const R tz = az ? R(A.hd[2]) * (ey_z - ey) : R(0);
-      b_halves(bx, ty, ay, tz, az, b1, b2);
-      Bnx[m] = b1;
-      Bx[m] = b2;
-    }
-    {  // dBy/dt = -dEx/dz + dEz/dx
-      const R tz = az ? R(A.hd[2]) * (ex_z - ex) : R(0);
-      const R tx = R(A.hd[0]) * (ez_x - ez);
-      b_halves(by, tz, az, tx, true, b1, b2);
-      Bny[m] = b1;
-      By[m] = b2;
-    }
-    {  // dBz/dt = -dEy/dx + dEx/dy
-      const R tx = R(A.hd[0]) * (ey_x - ey);
-      const R ty = ay ? R(A.hd[1]) * (ex_y - ex) : R(0);
-      b_halves(bz, tx, true, ty, ay, b1, b2);
-      Bnz[m] = b1;
-      Bz[m] = b2;
-    }
-    Jx[m] = 0ull; Jy[m] = 0ull; Jz[m] = 0ull;
-    return;
-  }
   Jx[m] = 0ull; Jy[m] = 0ull; Jz[m] = 0ull;
   {  // dBx/dt = -dEz/dy + dEy/dz
     const R b = Bx[m];
