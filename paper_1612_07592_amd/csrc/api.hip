@@ -181,7 +181,7 @@ std::string derive(const pic_config& cfg, Ctx& c) {
   }
   // cell tiles for the sort and the LDS box of the step kernel
   if (cfg.reserved0 != 0) return "reserved0 must be 0";
-  const int dflt_every[4] = {0, 16, 8, 6};
+  const int dflt_every[4] = {0, 16, 8, 4};
   const int tiles[4] = {0, 16, 4, 2};
   // LDS box capacity in nodes (2D: fields + current, 36 B/node in FP32;
   // 3D: current only, 12 B/node); chosen by measurement on the 2D and 3D
